@@ -1,0 +1,143 @@
+"""Plain complex128 CPU oracle for the batched transfer-matrix method.
+
+TEST INFRASTRUCTURE ONLY: the test-suite, the smoke check and the CPU-baseline
+leg of the benchmark are the only callers.  The product path never imports
+this package, and this package imports nothing from the product path.
+
+The arithmetic lives in ``tmm_oracle.c`` (plain C, ``double complex``, built
+without fast-math, OpenMP over stacks); this module only builds it with gcc and
+marshals numpy arrays.  See the header of ``tmm_oracle.c`` for the equations it
+follows, the readings it takes, and which pins hold it.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "tmm_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle_tmm.so")
+_lib = None
+
+
+def compile_source(src: str, out: str) -> str:
+    """gcc, C11, no fast-math, no FMA contraction, OpenMP."""
+    tmp = out + ".tmp%d" % os.getpid()
+    cmd = ["gcc", "-std=c11", "-O2", "-fopenmp", "-fPIC", "-shared",
+           "-fno-fast-math", "-ffp-contract=off", src, "-o", tmp, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, out)
+    return out
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle into ``liboracle_tmm.so``."""
+    if force or not os.path.exists(_LIB):
+        compile_source(_SRC, _LIB)
+    return _LIB
+
+
+class using:
+    """Context manager that points this module at another build of the oracle
+    source (the pin-strength tests load deliberately broken copies)."""
+
+    def __init__(self, path: str):
+        self.path = path
+
+    def __enter__(self):
+        global _lib
+        self.saved = _lib
+        _lib = _bind(ctypes.CDLL(self.path))
+        return self
+
+    def __exit__(self, *exc):
+        global _lib
+        _lib = self.saved
+        return False
+
+
+def _bind(lib):
+    P = ctypes.c_void_p
+    lib.oracle_rt.restype = ctypes.c_int
+    lib.oracle_rt.argtypes = [ctypes.c_int] * 4 + [P, P, ctypes.c_int, ctypes.c_int,
+                                                    P, P, P, P, ctypes.c_uint,
+                                                    P, P, P, P, P]
+    lib.oracle_max_threads.restype = ctypes.c_int
+    return lib
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=False)
+        lib = ctypes.CDLL(_LIB)
+        _lib = _bind(lib)
+    return _lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def rt(d, nk, wl, sin_t, cos_t, *, mat=None, dispersive=None, pol="both",
+       want_amplitudes=True, flip=None):
+    """Evaluate R, T (and r, t) for a batch of stacks.
+
+    d        [B, L] float64 thicknesses (same length unit as ``wl``)
+    nk       complex table: [n_mat, n_wl] (dispersive) or [n_mat] (constant)
+    mat      [B, L+2] int32 row ids into ``nk``; None means row = b*(L+2)+j
+    wl       [n_wl] vacuum wavelengths; sin_t, cos_t [n_theta]
+    pol      's', 'p' or 'both' (output polarisation axis: s then p)
+    Returns a dict with 'R', 'T' [B, P, n_theta, n_wl] float64 and, when
+    requested, 'r', 't' complex128 of the same shape, plus 'threads'.
+    """
+    lib = _load()
+    d = np.ascontiguousarray(d, dtype=np.float64)
+    if d.ndim != 2:
+        raise ValueError("d must be [B, L]")
+    B, L = d.shape
+    nk = np.ascontiguousarray(nk, dtype=np.complex128)
+    wl = np.ascontiguousarray(wl, dtype=np.float64).ravel()
+    sin_t = np.ascontiguousarray(sin_t, dtype=np.float64).ravel()
+    cos_t = np.ascontiguousarray(cos_t, dtype=np.float64).ravel()
+    if sin_t.shape != cos_t.shape:
+        raise ValueError("sin_t and cos_t differ in length")
+    if dispersive is None:
+        dispersive = nk.ndim == 2
+    if dispersive and (nk.ndim != 2 or nk.shape[1] != wl.size):
+        raise ValueError("dispersive nk must be [n_mat, n_wl]")
+    n_mat = nk.shape[0]
+    if mat is not None:
+        mat = np.ascontiguousarray(mat, dtype=np.int32)
+        if mat.shape != (B, L + 2):
+            raise ValueError("mat must be [B, L+2]")
+    mask = {"s": 1, "p": 2, "both": 3}[pol]
+    P = 2 if mask == 3 else 1
+    shape = (B, P, sin_t.size, wl.size)
+    R = np.empty(shape)
+    T = np.empty(shape)
+    r = np.empty(shape, np.complex128) if want_amplitudes else None
+    t = np.empty(shape, np.complex128) if want_amplitudes else None
+    if flip is not None:
+        flip = np.ascontiguousarray(flip, dtype=np.uint8)
+        if flip.shape != (L + 2,):
+            raise ValueError("flip must be [L+2]")
+    th = lib.oracle_rt(B, L, wl.size, sin_t.size, _ptr(d), _ptr(nk), n_mat,
+                       int(bool(dispersive)), _ptr(mat), _ptr(wl), _ptr(sin_t),
+                       _ptr(cos_t), mask, _ptr(R), _ptr(T), _ptr(r), _ptr(t),
+                       _ptr(flip))
+    if th < 0:
+        raise ValueError("oracle_rt rejected its arguments")
+    out = {"R": R, "T": T, "threads": th}
+    if want_amplitudes:
+        out["r"] = r
+        out["t"] = t
+    return out
+
+
+def max_threads() -> int:
+    return _load().oracle_max_threads()

@@ -1,0 +1,193 @@
+"""Seeded synthetic workloads shaped like the paper's random thin-film stacks.
+
+This module only draws inputs: thicknesses, refractive-index tables (including
+the Cauchy material model n(lambda) = A + B / lambda^2 that defines the
+dispersive materials), material ids and the wavelength / angle grids.  It holds
+none of the transfer-matrix arithmetic, so both the HIP path and the CPU oracle
+consume its output.  Every array is drawn in float64 from
+``numpy.random.default_rng(seed)`` in a fixed order.  Lengths are in nm; Cauchy
+B coefficients are in um^2.
+
+The paper measures on random stacks it draws itself (speed-up section: random
+21-layer films; appendix examples: uniform thicknesses and indices), and names no
+public dataset; these generators stand in for them.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, replace
+from typing import Optional
+
+import numpy as np
+
+
+@dataclass
+class Workload:
+    """One batch: B stacks of L finite layers over n_wl wavelengths x n_theta angles.
+
+    d      [B, L] float64 thicknesses (nm)
+    nk     complex128 index table, [n_mat, n_wl] if ``dispersive`` else [n_mat]
+    mat    [B, L+2] int32 row ids into ``nk`` (media 0 and L+1 are the ambient and
+           the substrate) or None, meaning row = b*(L+2)+j
+    wl     [n_wl] vacuum wavelengths (nm)
+    theta  [n_theta] incidence angles in the ambient (rad)
+    sin_t, cos_t  [n_theta] float64 sine / cosine of ``theta``
+    """
+    name: str
+    d: np.ndarray
+    nk: np.ndarray
+    mat: Optional[np.ndarray]
+    wl: np.ndarray
+    theta: np.ndarray
+    sin_t: np.ndarray
+    cos_t: np.ndarray
+
+    @property
+    def B(self) -> int:
+        return self.d.shape[0]
+
+    @property
+    def L(self) -> int:
+        return self.d.shape[1]
+
+    @property
+    def dispersive(self) -> bool:
+        return self.nk.ndim == 2
+
+    @property
+    def n_points(self) -> int:
+        return self.B * self.wl.size * self.theta.size * 2
+
+    def take(self, stacks) -> "Workload":
+        """Subset of stacks (index array or slice); per-layer tables are re-packed."""
+        idx = np.arange(self.B)[stacks]
+        d = self.d[idx]
+        if self.mat is not None:
+            return replace(self, d=d, mat=np.ascontiguousarray(self.mat[idx]))
+        L2 = self.L + 2
+        rows = (idx[:, None] * L2 + np.arange(L2)[None, :]).ravel()
+        return replace(self, d=d, nk=np.ascontiguousarray(self.nk[rows]))
+
+    def rounded_f32(self) -> "Workload":
+        """Every real input rounded to float32 and widened back to float64.
+
+        The oracle is fed these when it checks the float32 kernels, so that the
+        rounding of the inputs is not charged to the kernel."""
+        f = lambda a: a.astype(np.float32).astype(np.float64)
+        nk = (self.nk.real.astype(np.float32).astype(np.float64)
+              + 1j * self.nk.imag.astype(np.float32).astype(np.float64))
+        return replace(self, d=f(self.d), nk=nk, wl=f(self.wl),
+                       sin_t=f(self.sin_t), cos_t=f(self.cos_t))
+
+
+def angles(theta: np.ndarray):
+    theta = np.asarray(theta, dtype=np.float64)
+    return np.sin(theta), np.cos(theta)
+
+
+def cauchy(A, Bc, k, wl_nm):
+    """n_m(lambda) = A_m + B_m / lambda^2 + i k_m with lambda in um; [n_mat, n_wl]."""
+    lam_um = np.asarray(wl_nm, dtype=np.float64) / 1000.0
+    A = np.asarray(A, dtype=np.float64)[:, None]
+    Bc = np.asarray(Bc, dtype=np.float64)[:, None]
+    k = np.asarray(k, dtype=np.float64)[:, None]
+    return (A + Bc / lam_um[None, :] ** 2) + 1j * k * np.ones_like(lam_um)[None, :]
+
+
+def _per_layer_table(n_inner: np.ndarray, n_amb: complex, n_sub: complex) -> np.ndarray:
+    """Per-layer constant indices packed as rows b*(L+2)+j, j = 0..L+1."""
+    B, L = n_inner.shape
+    tab = np.empty((B, L + 2), dtype=np.complex128)
+    tab[:, 0] = n_amb
+    tab[:, 1:L + 1] = n_inner
+    tab[:, L + 1] = n_sub
+    return tab.ravel()
+
+
+def small_batch(seed: int = 0, B: int = 16, L: int = 10, n_wl: int = 128,
+                n_theta: int = 8) -> Workload:
+    """Small complex128 batch: 16 stacks x 10 layers, d ~ U[10,300] nm,
+    n ~ U[1.3,2.5] + i U[0,0.01] per layer (constant in lambda), ambient 1.0,
+    substrate 1.52, 128 wavelengths 400-900 nm, 8 angles 0-60 deg."""
+    rng = np.random.default_rng(seed)
+    d = rng.uniform(10.0, 300.0, (B, L))
+    nr = rng.uniform(1.3, 2.5, (B, L))
+    k = rng.uniform(0.0, 0.01, (B, L))
+    nk = _per_layer_table(nr + 1j * k, 1.0, 1.52)
+    wl = np.linspace(400.0, 900.0, n_wl)
+    theta = np.deg2rad(np.linspace(0.0, 60.0, n_theta))
+    s, c = angles(theta)
+    return Workload("small_batch_16x10", d, nk, None, wl, theta, s, c)
+
+
+def large_batch(seed: int = 0, B: int = 4096, L: int = 40, n_wl: int = 1024,
+                n_theta: int = 91) -> Workload:
+    """Large batch: 4096 stacks x 40 layers from a 4-material Cauchy pool
+    (A ~ U[1.4,2.4], B ~ U[0.003,0.03] um^2, k = 0, 1e-3, 0, 1e-3), d ~ U[20,250] nm,
+    1024 wavelengths 300-1200 nm, 91 angles 0-90 deg in 1 deg steps (grazing
+    incidence included), ambient 1.0, substrate 1.52.  Table rows 0-3 are the
+    pool, row 4 the ambient, row 5 the substrate."""
+    rng = np.random.default_rng(seed)
+    A = rng.uniform(1.4, 2.4, 4)
+    Bc = rng.uniform(0.003, 0.03, 4)
+    k = np.array([0.0, 1e-3, 0.0, 1e-3])
+    mat_inner = rng.integers(0, 4, (B, L))
+    d = rng.uniform(20.0, 250.0, (B, L))
+    wl = np.linspace(300.0, 1200.0, n_wl)
+    nk = np.empty((6, n_wl), dtype=np.complex128)
+    nk[:4] = cauchy(A, Bc, k, wl)
+    nk[4] = 1.0
+    nk[5] = 1.52
+    mat = np.empty((B, L + 2), dtype=np.int32)
+    mat[:, 0] = 4
+    mat[:, 1:L + 1] = mat_inner
+    mat[:, L + 1] = 5
+    theta = np.deg2rad(np.arange(0, n_theta, dtype=np.float64))
+    s, c = angles(theta)
+    return Workload("large_batch_4096x40", d, nk, mat, wl, theta, s, c)
+
+
+def appendix_example(seed: int = 0, B: int = 1, n_media: int = 12, n_wl: int = 301,
+                     n_theta: int = 301) -> Workload:
+    """Shape of the paper's appendix TMM-Fast example: 12 media including the two
+    semi-infinite ones, d ~ U[20,150] nm, n ~ U[1.2,5] constant (the first draw is
+    the injection medium), exit medium n = 1, 301 wavelengths 500-900 nm and 301
+    angles 0-90 deg.  Light goes from a dense into a thin medium, so total
+    internal reflection and evanescent layers occur."""
+    rng = np.random.default_rng(seed)
+    L = n_media - 2
+    d = rng.uniform(20.0, 150.0, (B, L))
+    n = rng.uniform(1.2, 5.0, (B, n_media))
+    n[:, -1] = 1.0
+    nk = n.astype(np.complex128).ravel()
+    wl = np.linspace(500.0, 900.0, n_wl)
+    theta = np.deg2rad(np.linspace(0.0, 90.0, n_theta))
+    s, c = angles(theta)
+    return Workload("appendix_example_12media", d, nk, None, wl, theta, s, c)
+
+
+def random_stacks(seed: int, B: int, L: int, n_wl: int, n_theta: int, *,
+                  dispersive: bool = False, lossy: bool = True, theta_max_deg=89.0,
+                  n_amb: float = 1.0, n_sub: complex = 1.52) -> Workload:
+    """Generic random per-layer stacks for parity edge cases (ragged tails, L = 0,
+    L = 1, dispersive per-layer tables)."""
+    rng = np.random.default_rng(seed)
+    d = rng.uniform(5.0, 300.0, (B, L))
+    wl = np.sort(rng.uniform(350.0, 1100.0, n_wl))
+    theta = np.sort(rng.uniform(0.0, np.deg2rad(theta_max_deg), n_theta))
+    s, c = angles(theta)
+    if dispersive:
+        A = rng.uniform(1.3, 2.6, (B, L))
+        Bc = rng.uniform(0.0, 0.03, (B, L))
+        k = rng.uniform(0.0, 0.02, (B, L)) if lossy else np.zeros((B, L))
+        lam = wl / 1000.0
+        inner = A[..., None] + Bc[..., None] / lam ** 2 + 1j * k[..., None]
+        tab = np.empty((B, L + 2, n_wl), dtype=np.complex128)
+        tab[:, 0, :] = n_amb
+        tab[:, 1:L + 1, :] = inner
+        tab[:, L + 1, :] = n_sub
+        nk = tab.reshape(B * (L + 2), n_wl)
+    else:
+        nr = rng.uniform(1.3, 2.6, (B, L))
+        k = rng.uniform(0.0, 0.02, (B, L)) if lossy else np.zeros((B, L))
+        nk = _per_layer_table(nr + 1j * k, n_amb, n_sub)
+    return Workload(f"random_{B}x{L}", d, nk, None, wl, theta, s, c)
