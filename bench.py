@@ -1,0 +1,191 @@
+"""Throughput of the batched transfer-matrix forward pass on one MI355X.
+
+One step = one tmm_rt call over the large batch: 4096 stacks x 40 layers from a
+4-material Cauchy pool, 1024 wavelengths (300-1200 nm) x 91 angles (0-90 deg),
+s and p, R and T written to HBM.  Inputs and outputs are resident in device
+memory before the timed region starts.  Prints one JSON line.
+
+    python bench.py [--steps K] [--warmup W] [--dtype f64|f32] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "TMM points/s (stack·λ·θ·pol) at 40 layers; surrogate vs TMM at 1e-3 R error"
+
+# Algorithmic arithmetic of the division-free layer step (complex products and
+# sums of the Fresnel/phase/chain update, FMA counted as 2 flops; elementary
+# functions not counted): 55 flops for s and 73 for p per layer step, i.e. 64
+# per (point, interface) on average; a point of an L-layer stack crosses L+1
+# interfaces.
+FLOPS_PER_POINT_STEP = 64.0
+PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}   # MI355X vector FP64 / FP32
+PEAK_HBM_GBS = 8000.0
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def time_gpu(w, dtype: str, steps: int, warmup: int, amplitudes: bool = False):
+    import torch
+    from paper_2111_13667_amd import tmm
+
+    real = torch.float64 if dtype == "f64" else torch.float32
+    cplx = torch.complex128 if dtype == "f64" else torch.complex64
+    dev = "cuda"
+    d = torch.as_tensor(w.d, dtype=real, device=dev)
+    nk = torch.as_tensor(w.nk, dtype=cplx, device=dev)
+    mat = torch.as_tensor(w.mat, dtype=torch.int32, device=dev)
+    wl = torch.as_tensor(w.wl, dtype=real, device=dev)
+    s = torch.as_tensor(w.sin_t, dtype=real, device=dev)
+    c = torch.as_tensor(w.cos_t, dtype=real, device=dev)
+    shape = (w.B, 2, w.theta.size, w.wl.size)
+    R = torch.empty(shape, dtype=real, device=dev)
+    T = torch.empty(shape, dtype=real, device=dev)
+    r = torch.empty(shape, dtype=cplx, device=dev) if amplitudes else None
+    t = torch.empty(shape, dtype=cplx, device=dev) if amplitudes else None
+
+    def step():
+        tmm.tmm_rt(d, nk, wl, s, c, mat=mat, pol_mask=3, R=R, T=T, r=r, t=t)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()  # tmm_rt launches on this stream
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(steps):
+        step()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kernel_ms = ev0.elapsed_time(ev1) / steps
+    out_bytes = sum(x.numel() * x.element_size() for x in (R, T, r, t) if x is not None)
+    del R, T, r, t
+    torch.cuda.empty_cache()
+    return kernel_ms, wall, out_bytes
+
+
+def roofline(w, dtype, kernel_ms, out_bytes, traffic=None):
+    flops = w.n_points * (w.L + 1) * FLOPS_PER_POINT_STEP
+    achieved = flops / (kernel_ms * 1e-3) / 1e12
+    peak = PEAK_TFLOPS[dtype]
+    return {"bound": "alu", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+            "frac": round(achieved / peak, 4), "traffic": traffic,
+            "algorithmic_flops_per_launch": flops,
+            "output_GBps": round(out_bytes / (kernel_ms * 1e-3) / 1e9, 1),
+            "output_frac_of_hbm": round(out_bytes / (kernel_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)}
+
+
+def cpu_baseline(w, n_stacks: int):
+    """The CPU oracle (complex128, OpenMP over stacks) on the first n_stacks
+    stacks of the same workload, all wavelengths, angles and polarisations."""
+    import oracle
+    sub = w.take(slice(0, n_stacks))
+    oracle.rt(sub.d[:1], sub.nk[:, :8], sub.wl[:8], sub.sin_t[:2], sub.cos_t[:2], mat=sub.mat[:1],
+              want_amplitudes=False)  # load + warm
+    t0 = time.perf_counter()
+    out = oracle.rt(sub.d, sub.nk, sub.wl, sub.sin_t, sub.cos_t, mat=sub.mat, want_amplitudes=False)
+    dt = time.perf_counter() - t0
+    pts = sub.n_points
+    return {"value": round(pts / dt, 1), "unit": "points/s", "cores": int(out["threads"]),
+            "kind": "oracle",
+            "sample": f"first {n_stacks} of {w.B} stacks, all {w.wl.size} wavelengths x "
+                      f"{w.theta.size} angles x 2 pol ({pts} points) in {dt:.2f} s",
+            "cpu_model": cpu_model()}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--dtype", choices=["f64", "f32"], default="f64")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra", action="store_true", help="skip the f32 and amplitude variants")
+    ap.add_argument("--cpu-stacks", type=int, default=64)
+    ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"))
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this build measures one GPU only; every point is independent and "
+              "stacks would shard across GPUs with no exchange, but no multi-GPU run is "
+              "provided. Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        sys.exit(1)
+
+    from paper_2111_13667_amd import workloads
+    w = workloads.large_batch()
+
+    traffic = None
+    if os.path.exists(args.traffic_json):
+        try:
+            traffic = json.load(open(args.traffic_json)).get(args.dtype)
+        except (OSError, ValueError):
+            traffic = None
+
+    kernel_ms, wall, out_bytes = time_gpu(w, args.dtype, args.steps, args.warmup)
+    value = w.n_points / (kernel_ms * 1e-3)
+    rec = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "points/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(kernel_ms, 4),
+        "wall_ms_per_step": round(wall * 1e3 / args.steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.dtype,
+        "data": "synthetic",
+        "config": {"workload": "large_batch: 4096 stacks x 40 layers (4-material Cauchy pool), "
+                               "1024 wavelengths 300-1200 nm x 91 angles 0-90 deg, s+p, R and T",
+                   "stacks": w.B, "layers": w.L, "n_wl": int(w.wl.size), "n_theta": int(w.theta.size),
+                   "points": w.n_points, "outputs": "R,T"},
+        "roofline": roofline(w, args.dtype, kernel_ms, out_bytes, traffic),
+    }
+    if not args.no_extra:
+        extra = {}
+        other = "f32" if args.dtype == "f64" else "f64"
+        ms, _, ob = time_gpu(w, other, max(3, args.steps // 2), 1)
+        extra[other] = {"value": round(w.n_points / (ms * 1e-3), 1), "ms_per_step": round(ms, 4),
+                        "roofline": roofline(w, other, ms, ob)}
+        ms, _, ob = time_gpu(w, args.dtype, max(3, args.steps // 2), 1, amplitudes=True)
+        extra[args.dtype + "_with_r_t"] = {"value": round(w.n_points / (ms * 1e-3), 1),
+                                           "ms_per_step": round(ms, 4),
+                                           "roofline": roofline(w, args.dtype, ms, ob)}
+        rec["extra"] = extra
+    if not args.no_cpu_baseline:
+        rec["cpu_baseline"] = cpu_baseline(w, args.cpu_stacks)
+    rec["gpu"] = torch.cuda.get_device_name(0)
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,610 @@
+// Forward transfer-matrix kernels (gfx950) and the tmm_rt entry point.
+//
+// Work decomposition: one lane = one (stack, wavelength, angle) with both
+// polarisations, so the pol-independent work (q_j, the phase factor e^{2 i delta_j})
+// is done once for s and p.  A 256-thread workgroup covers one angle and a
+// tile of 64 consecutive wavelengths (lanes = wavelengths, so every store of a
+// wave is 64 consecutive elements), and its four waves walk a chunk of stacks,
+// one stack per wave at a time: the stack index, the layer loop, thicknesses
+// and material ids are wave-uniform and stay on the scalar unit.
+//
+// Two ways to obtain q_j and eta_j for the layer loop:
+//   table  : when a material-id array is given and the table has at most
+//            kMaxTableMat rows, the workgroup computes q, eta, |q|^2, |eta|^2 of
+//            every material for its 64 wavelengths once (complex sqrt and one
+//            division per entry) into LDS, and the layer loop only reads them.
+//            Stacks whose ambient differs from the one the table was built for
+//            fall back to the inline source.
+//   inline : otherwise each step loads n_j and computes q_j, eta_j itself.
+// The recursion itself is described in tmm_device.hpp.
+#include <math.h>
+#include <string.h>
+
+#include "tmm_device.hpp"
+#include "tmm_host.hpp"
+
+namespace tmm {
+
+constexpr int kBlock = 256;
+constexpr int kWavesPerBlock = kBlock / kWave;
+constexpr int kMaxTableMat = 16;
+
+template <typename R>
+struct FwdParams {
+    int B, L, n_wl, n_theta;
+    const R* d;
+    const R* nk;
+    int n_mat, dispersive;
+    const int32_t* mat;
+    const R* wl;
+    const R* sin_t;
+    const R* cos_t;
+    R* R_out;
+    R* T_out;
+    R* r_out;
+    R* t_out;
+    int n_tiles, chunk;
+};
+
+// Renormalisation period of the layer loop (steps).  Per-step growth of the
+// state is bounded by 2(|alpha| + |beta|); 16 double steps or 4 float steps
+// stay far from overflow for any physical index.
+template <typename R> struct RenormPeriod;
+template <> struct RenormPeriod<double> { static constexpr int value = 16; };
+template <> struct RenormPeriod<float> { static constexpr int value = 4; };
+
+// ---------------------------------------------------------------------------
+// Ambient medium (j = 0), per lane: q_0 = n_0 cos(theta_0), eta_0 = n_0 / cos(theta_0)
+// from the given cosine (no square root, so grazing incidence keeps its tiny
+// cosine), the Snell invariant kx and the flux constants of T_s, T_p.
+struct Ambient {
+    double n0r, n0i, q0r, q0i, e0r, e0i, kx, Ks, Kp;
+    bool ok;
+};
+
+__device__ __forceinline__ Ambient make_ambient(double n0r, double n0i, double st, double ct) {
+    Ambient a;
+    a.n0r = n0r;
+    a.n0i = n0i;
+    a.ok = (n0i == 0.0) || (st == 0.0);
+    a.kx = n0r * st;
+    a.q0r = n0r * ct;
+    a.q0i = n0i * ct;
+    const double ic = 1.0 / ct;
+    a.e0r = n0r * ic;
+    a.e0i = n0i * ic;
+    const double nn = n0r * n0r + n0i * n0i;
+    a.Ks = nn * ct / n0r;
+    a.Kp = nn * ic / n0r;
+    return a;
+}
+
+template <typename R>
+__device__ __forceinline__ void load_n(const R* nk, int dispersive, int n_wl, int64_t row, int i,
+                                       double& nr, double& ni) {
+    const int64_t idx = dispersive ? row * (int64_t)n_wl + i : row;
+    nr = (double)nk[2 * idx];
+    ni = (double)nk[2 * idx + 1];
+}
+
+// ---------------------------------------------------------------------------
+// Media table in LDS, structure-of-arrays, one entry per (material, lane).
+template <typename R> struct Table;
+
+template <>
+struct Table<double> {
+    static constexpr int kEntryBytes = 48;
+    double2* q;
+    double2* e;
+    double2* n2;
+    __device__ Table(unsigned char* base, int n_mat) {
+        const int n = n_mat * kWave;
+        q = reinterpret_cast<double2*>(base);
+        e = q + n;
+        n2 = e + n;
+    }
+    __device__ __forceinline__ void put(int m, int lane, const Medium& md) {
+        const int x = m * kWave + lane;
+        q[x] = make_double2(md.qr, md.qi);
+        e[x] = make_double2(md.er, md.ei);
+        n2[x] = make_double2(md.q2, md.e2);
+    }
+    __device__ __forceinline__ Layer<double> get(int m, int lane) const {
+        const int x = m * kWave + lane;
+        const double2 a = q[x], b = e[x], c = n2[x];
+        Layer<double> v;
+        v.q = {a.x, a.y};
+        v.e = {b.x, b.y};
+        v.q2 = c.x;
+        v.e2 = c.y;
+        v.pr = a.x;
+        v.pi = a.y;
+        return v;
+    }
+};
+
+template <>
+struct Table<float> {
+    static constexpr int kEntryBytes = 40;
+    double2* pd;
+    float2* q;
+    float2* e;
+    float2* n2;
+    __device__ Table(unsigned char* base, int n_mat) {
+        const int n = n_mat * kWave;
+        pd = reinterpret_cast<double2*>(base);
+        q = reinterpret_cast<float2*>(pd + n);
+        e = q + n;
+        n2 = e + n;
+    }
+    __device__ __forceinline__ void put(int m, int lane, const Medium& md) {
+        const int x = m * kWave + lane;
+        pd[x] = make_double2(md.qr, md.qi);
+        q[x] = make_float2((float)md.qr, (float)md.qi);
+        e[x] = make_float2((float)md.er, (float)md.ei);
+        n2[x] = make_float2((float)md.q2, (float)md.e2);
+    }
+    __device__ __forceinline__ Layer<float> get(int m, int lane) const {
+        const int x = m * kWave + lane;
+        const double2 p = pd[x];
+        const float2 a = q[x], b = e[x], c = n2[x];
+        Layer<float> v;
+        v.q = {a.x, a.y};
+        v.e = {b.x, b.y};
+        v.q2 = c.x;
+        v.e2 = c.y;
+        v.pr = p.x;
+        v.pi = p.y;
+        return v;
+    }
+};
+
+template <typename R>
+__host__ __device__ constexpr size_t table_bytes(int n_mat) {
+    return (size_t)n_mat * kWave * Table<R>::kEntryBytes + 4 * kMaxTableMat;
+}
+
+// Sources of per-layer values for the chain.  Row ids are wave-uniform.
+template <typename R>
+struct TableSource {
+    const Table<R>* tab;
+    const int32_t* mrow;
+    int lane, n_mat;
+    uint32_t lossy_mask;
+    __device__ __forceinline__ bool row_bad(int j) const { return (uint32_t)mrow[j] >= (uint32_t)n_mat; }
+    __device__ __forceinline__ Layer<R> layer(int j, bool& lossy) const {
+        int m = mrow[j];
+        m = m < 0 ? 0 : (m >= n_mat ? n_mat - 1 : m);
+        lossy = (lossy_mask >> m) & 1u;
+        return tab->get(m, lane);
+    }
+};
+
+template <typename R>
+struct InlineSource {
+    const R* nk;
+    const int32_t* mrow;   // NULL: implicit rows implicit_base + j
+    int64_t implicit_base;
+    int n_mat, dispersive, n_wl, i;
+    double kx;
+    __device__ __forceinline__ bool row_bad(int j) const {
+        return mrow ? (uint32_t)mrow[j] >= (uint32_t)n_mat : false;
+    }
+    __device__ __forceinline__ Layer<R> layer(int j, bool& lossy) const {
+        int64_t row;
+        if (mrow) {
+            int m = mrow[j];
+            row = m < 0 ? 0 : (m >= n_mat ? n_mat - 1 : m);
+        } else {
+            row = implicit_base + j;
+        }
+        double nr, ni;
+        load_n(nk, dispersive, n_wl, row, i, nr, ni);
+        const Medium md = make_medium(nr, ni, kx);
+        lossy = __any(md.qi != 0.0);
+        return to_layer<R>(md);
+    }
+};
+
+// ---------------------------------------------------------------------------
+// The layer recursion (see tmm_device.hpp).
+template <typename R, int POL, bool AMP>
+struct Chain {
+    cx<R> ss, ts, sp, tp;  // sigma, tau of s and p
+    int es, ep;            // power-of-two exponents taken out of (ss, ts), (sp, tp)
+    R pis, pip;            // prod |q_j|^2, prod |eta_j|^2 (R, T only)
+    int epis, epip;
+    cx<R> Pq, Pe;          // prod q_j, prod eta_j (amplitudes wanted)
+    int ePq, ePe;
+    double S;              // sum Im(phi_j)
+    double F;              // sum Re(phi_j), reduced modulo 4 (amplitudes wanted)
+
+    __device__ __forceinline__ void init() {
+        ss = ts = sp = tp = {(R)1, (R)0};
+        es = ep = 0;
+        pis = pip = (R)1;
+        epis = epip = 0;
+        Pq = Pe = {(R)1, (R)0};
+        ePq = ePe = 0;
+        S = 0.0;
+        F = 0.0;
+    }
+
+    __device__ __forceinline__ void step(const Layer<R>& cur, const Layer<R>& nxt, double cd, bool lossy) {
+        const double phr = cd * cur.pr;
+        const double phi = cd * cur.pi;
+        const cx<R> E = phase_factor<R>(phr, phi, lossy);
+        if (POL & 1) {
+            const cx<R> A = cmul(cur.q, ss), Bv = cmul(nxt.q, ts);
+            const cx<R> a = cadd(A, Bv), b = csub(A, Bv);
+            const cx<R> Eb = cmul(E, b);
+            ss = cadd(a, Eb);
+            ts = csub(a, Eb);
+        }
+        if (POL & 2) {
+            const cx<R> A = cmul(nxt.e, sp), Bv = cmul(cur.e, tp);
+            const cx<R> a = cadd(A, Bv), b = csub(A, Bv);
+            const cx<R> Eb = cmul(E, b);
+            sp = cadd(a, Eb);
+            tp = csub(a, Eb);
+        }
+        if (AMP) {
+            if (POL & 1) Pq = cmul(Pq, cur.q);
+            if (POL & 2) Pe = cmul(Pe, cur.e);
+            S += phi;
+            F = reduce4(F + phr);
+        } else {
+            if (POL & 1) pis *= cur.q2;
+            if (POL & 2) pip *= cur.e2;
+            if (lossy) S += phi;
+        }
+    }
+
+    __device__ __forceinline__ void renorm() {
+        if (POL & 1) renorm_pair(ss, ts, es);
+        if (POL & 2) renorm_pair(sp, tp, ep);
+        if (AMP) {
+            if (POL & 1) renorm_cx(Pq, ePq);
+            if (POL & 2) renorm_cx(Pe, ePe);
+        } else {
+            if (POL & 1) renorm_one(pis, epis);
+            if (POL & 2) renorm_one(pip, epip);
+        }
+    }
+};
+
+struct PointOut {
+    double R, T;
+    cx<double> r, t;
+};
+
+// Ambient step (j = 0, no phase) and extraction of r, t, R, T (Eq. (3), (7)).
+template <typename R, int POL, bool AMP>
+__device__ __forceinline__ void finish(const Chain<R, POL, AMP>& c, const Ambient& amb,
+                                       const Layer<R>& first, const Layer<R>& sub,
+                                       double nsub_r, double nsub_i, int L, PointOut* out) {
+    const double eS = exp2(c.S * kNegPiLog2e);
+    const int two_L1 = 2 * (L + 1);
+    if (POL & 1) {
+        const cx<double> q0 = {amb.q0r, amb.q0i};
+        const cx<double> q1 = {first.pr, first.pi};
+        const cx<double> A = cmul(q0, widen(c.ss)), Bv = cmul(q1, widen(c.ts));
+        const cx<double> a = cadd(A, Bv), b = csub(A, Bv);
+        const double na = cnorm(a);
+        PointOut& o = out[0];
+        o.R = cnorm(b) / na;
+        double prod;
+        int eprod;
+        if (AMP) {
+            prod = cnorm(widen(c.Pq));
+            eprod = 2 * c.ePq;
+        } else {
+            prod = (double)c.pis;
+            eprod = c.epis;
+        }
+        o.T = ldexp(amb.Ks * prod * sub.pr * eS / na, two_L1 + eprod - 2 * c.es);
+        if (AMP) {
+            o.r = cdiv(b, a);
+            double sn, cs;
+            sincospi(0.5 * c.F, &sn, &cs);
+            const double m = exp2(0.5 * c.S * kNegPiLog2e);
+            const cx<double> ph = {m * cs, m * sn};
+            cx<double> num = cmul(cmul(q0, widen(c.Pq)), ph);
+            cx<double> tt = cdiv(num, a);
+            const int e = (L + 1) + c.ePq - c.es;
+            o.t = {ldexp(tt.re, e), ldexp(tt.im, e)};
+        }
+    }
+    if (POL & 2) {
+        const cx<double> e0 = {amb.e0r, amb.e0i};
+        const cx<double> e1 = widen(first.e);
+        const cx<double> A = cmul(e1, widen(c.sp)), Bv = cmul(e0, widen(c.tp));
+        const cx<double> a = cadd(A, Bv), b = csub(A, Bv);
+        const double na = cnorm(a);
+        PointOut& o = out[(POL & 1) ? 1 : 0];
+        o.R = cnorm(b) / na;
+        double prod;
+        int eprod;
+        if (AMP) {
+            prod = cnorm(widen(c.Pe));
+            eprod = 2 * c.ePe;
+        } else {
+            prod = (double)c.pip;
+            eprod = c.epip;
+        }
+        o.T = ldexp(amb.Kp * prod * (double)sub.e.re * eS / na, two_L1 + eprod - 2 * c.ep);
+        if (AMP) {
+            o.r = cdiv(b, a);
+            double sn, cs;
+            sincospi(0.5 * c.F, &sn, &cs);
+            const double m = exp2(0.5 * c.S * kNegPiLog2e);
+            const cx<double> ph = {m * cs, m * sn};
+            // P_p = 2^{L+1} n_0 n_sub / q_sub prod eta_j
+            const cx<double> n0 = {amb.n0r, amb.n0i};
+            const cx<double> nsub = {nsub_r, nsub_i};
+            const cx<double> qsub = {sub.pr, sub.pi};
+            const cx<double> num = cmul(cmul(cdiv(cmul(n0, nsub), qsub), widen(c.Pe)), ph);
+            const cx<double> tt = cdiv(num, a);
+            const int e = (L + 1) + c.ePe - c.ep;
+            o.t = {ldexp(tt.re, e), ldexp(tt.im, e)};
+        }
+    }
+}
+
+}  // namespace tmm
+
+namespace tmm {
+
+template <typename R>
+__device__ __forceinline__ void store_point(const FwdParams<R>& p, int b, int k, int i, int pol_slot,
+                                            int P, const PointOut& o, bool valid) {
+    const int64_t idx = (((int64_t)b * P + pol_slot) * p.n_theta + k) * p.n_wl + i;
+    const double nan = __builtin_nan("");
+    if (p.R_out) p.R_out[idx] = (R)(valid ? o.R : nan);
+    if (p.T_out) p.T_out[idx] = (R)(valid ? o.T : nan);
+    if (p.r_out) {
+        p.r_out[2 * idx] = (R)(valid ? o.r.re : nan);
+        p.r_out[2 * idx + 1] = (R)(valid ? o.r.im : nan);
+    }
+    if (p.t_out) {
+        p.t_out[2 * idx] = (R)(valid ? o.t.re : nan);
+        p.t_out[2 * idx + 1] = (R)(valid ? o.t.im : nan);
+    }
+}
+
+// One stack for this lane's (wavelength, angle): layer loop from the substrate
+// to the ambient, then extraction and coalesced stores.
+template <typename R, int POL, bool AMP, class Src>
+__device__ __forceinline__ void run_stack(const FwdParams<R>& p, const Src& src, const Ambient& amb,
+                                          int b, int k, int i, bool active, bool lane_ok,
+                                          double c4lam, double nsub_r, double nsub_i) {
+    const int L = p.L;
+    const R* drow = p.d + (int64_t)b * L;
+    bool bad = src.row_bad(0) || src.row_bad(L + 1);
+    bool lossy;
+    const Layer<R> sub = src.layer(L + 1, lossy);
+    Layer<R> nxt = sub;
+    Chain<R, POL, AMP> c;
+    c.init();
+    int cnt = 0;
+    for (int j = L; j >= 1; --j) {
+        const R dj = drow[j - 1];
+        bad = bad || bad_thickness(dj) || src.row_bad(j);
+        const Layer<R> cur = src.layer(j, lossy);
+        c.step(cur, nxt, (double)dj * c4lam, lossy);
+        nxt = cur;
+        if (++cnt == RenormPeriod<R>::value) {
+            cnt = 0;
+            c.renorm();
+        }
+    }
+    c.renorm();
+    PointOut out[2];
+    finish<R, POL, AMP>(c, amb, nxt, sub, nsub_r, nsub_i, L, out);
+    if (active) {
+        const bool valid = lane_ok && !bad;
+        constexpr int P = (POL == 3) ? 2 : 1;
+        store_point(p, b, k, i, 0, P, out[0], valid);
+        if (POL == 3) store_point(p, b, k, i, 1, P, out[1], valid);
+    }
+}
+
+template <typename R, int POL, bool AMP, bool TABLE>
+__global__ void __launch_bounds__(kBlock) fwd_kernel(FwdParams<R> p) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    int bid = blockIdx.x;
+    const int tile = bid % p.n_tiles;
+    bid /= p.n_tiles;
+    const int k = bid % p.n_theta;
+    bid /= p.n_theta;
+    const int b0 = bid * p.chunk;
+    const int b1 = min(b0 + p.chunk, p.B);
+    const int i_raw = tile * kWave + lane;
+    const bool active = i_raw < p.n_wl;
+    const int i = active ? i_raw : p.n_wl - 1;  // ragged tail: compute a valid point, store nothing
+    const double lam = (double)p.wl[i];
+    const bool lam_ok = lam > 0.0 && lam < __builtin_inf();
+    const double c4lam = 4.0 / lam;  // phi_j = 4 d_j q_j / lambda half-turns = 2 delta_j / pi
+    const double st = (double)p.sin_t[k], ct = (double)p.cos_t[k];
+    const int L2 = p.L + 2;
+
+    if (TABLE) {
+        int amb_row = p.mat[(int64_t)b0 * L2];
+        amb_row = amb_row < 0 ? 0 : (amb_row >= p.n_mat ? p.n_mat - 1 : amb_row);
+        double n0r, n0i;
+        load_n(p.nk, p.dispersive, p.n_wl, amb_row, i, n0r, n0i);
+        const Ambient amb = make_ambient(n0r, n0i, st, ct);
+        Table<R> tab(smem, p.n_mat);
+        int* flags = reinterpret_cast<int*>(smem + (size_t)p.n_mat * kWave * Table<R>::kEntryBytes);
+        for (int m = wave; m < p.n_mat; m += kWavesPerBlock) {
+            double nr, ni;
+            load_n(p.nk, p.dispersive, p.n_wl, m, i, nr, ni);
+            const Medium md = make_medium(nr, ni, amb.kx);
+            tab.put(m, lane, md);
+            const bool lossy = __any(md.qi != 0.0);
+            if (lane == 0) flags[m] = lossy ? 1 : 0;
+        }
+        __syncthreads();
+        uint32_t mask = 0;
+        for (int m = 0; m < p.n_mat; ++m) mask |= (uint32_t)flags[m] << m;
+        mask = __builtin_amdgcn_readfirstlane(mask);
+        for (int b = b0 + wave; b < b1; b += kWavesPerBlock) {
+            const int32_t* mrow = p.mat + (int64_t)b * L2;
+            int sub_row = mrow[p.L + 1];
+            sub_row = sub_row < 0 ? 0 : (sub_row >= p.n_mat ? p.n_mat - 1 : sub_row);
+            double nsr = 0.0, nsi = 0.0;
+            if (AMP) load_n(p.nk, p.dispersive, p.n_wl, sub_row, i, nsr, nsi);
+            if (mrow[0] == amb_row) {
+                TableSource<R> src{&tab, mrow, lane, p.n_mat, mask};
+                run_stack<R, POL, AMP>(p, src, amb, b, k, i, active, lam_ok && amb.ok, c4lam, nsr, nsi);
+            } else {
+                int a_row = mrow[0];
+                a_row = a_row < 0 ? 0 : (a_row >= p.n_mat ? p.n_mat - 1 : a_row);
+                double ar, ai;
+                load_n(p.nk, p.dispersive, p.n_wl, a_row, i, ar, ai);
+                const Ambient amb_b = make_ambient(ar, ai, st, ct);
+                InlineSource<R> src{p.nk, mrow, 0, p.n_mat, p.dispersive, p.n_wl, i, amb_b.kx};
+                run_stack<R, POL, AMP>(p, src, amb_b, b, k, i, active, lam_ok && amb_b.ok, c4lam, nsr, nsi);
+            }
+        }
+    } else {
+        for (int b = b0 + wave; b < b1; b += kWavesPerBlock) {
+            const int32_t* mrow = p.mat ? p.mat + (int64_t)b * L2 : nullptr;
+            const int64_t base = (int64_t)b * L2;
+            auto row_of = [&](int j) -> int64_t {
+                if (!mrow) return base + j;
+                const int m = mrow[j];
+                return m < 0 ? 0 : (m >= p.n_mat ? p.n_mat - 1 : m);
+            };
+            double n0r, n0i;
+            load_n(p.nk, p.dispersive, p.n_wl, row_of(0), i, n0r, n0i);
+            const Ambient amb = make_ambient(n0r, n0i, st, ct);
+            double nsr = 0.0, nsi = 0.0;
+            if (AMP) load_n(p.nk, p.dispersive, p.n_wl, row_of(p.L + 1), i, nsr, nsi);
+            InlineSource<R> src{p.nk, mrow, base, p.n_mat, p.dispersive, p.n_wl, i, amb.kx};
+            run_stack<R, POL, AMP>(p, src, amb, b, k, i, active, lam_ok && amb.ok, c4lam, nsr, nsi);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Host side.
+
+template <typename R, int POL, bool AMP, bool TABLE>
+static hipError_t launch_fwd(const FwdParams<R>& p, int blocks, size_t lds, hipStream_t s) {
+    hipLaunchKernelGGL((fwd_kernel<R, POL, AMP, TABLE>), dim3(blocks), dim3(kBlock), lds, s, p);
+    return hipGetLastError();
+}
+
+template <typename R, bool TABLE>
+static hipError_t dispatch_pol(const FwdParams<R>& p, unsigned pol, bool amp, int blocks, size_t lds,
+                               hipStream_t s) {
+    if (amp) {
+        if (pol == 1) return launch_fwd<R, 1, true, TABLE>(p, blocks, lds, s);
+        if (pol == 2) return launch_fwd<R, 2, true, TABLE>(p, blocks, lds, s);
+        return launch_fwd<R, 3, true, TABLE>(p, blocks, lds, s);
+    }
+    if (pol == 1) return launch_fwd<R, 1, false, TABLE>(p, blocks, lds, s);
+    if (pol == 2) return launch_fwd<R, 2, false, TABLE>(p, blocks, lds, s);
+    return launch_fwd<R, 3, false, TABLE>(p, blocks, lds, s);
+}
+
+// Stacks per workgroup: enough workgroups to fill 256 CUs many times over,
+// and as many stacks per workgroup as that allows, to amortise the table.
+static int pick_chunk(int64_t B, int64_t tiles_x_angles) {
+    const int64_t target_blocks = 32768;
+    int64_t chunk = ceil_div(B * tiles_x_angles, target_blocks);
+    chunk = ceil_div(chunk, kWavesPerBlock) * kWavesPerBlock;
+    if (chunk < kWavesPerBlock) chunk = kWavesPerBlock;
+    if (chunk > 64) chunk = 64;
+    return (int)chunk;
+}
+
+template <typename R>
+static tmm_status run_fwd(const tmm_rt_args* a, hipStream_t s) {
+    FwdParams<R> p;
+    p.B = a->B;
+    p.L = a->L;
+    p.n_wl = a->n_wl;
+    p.n_theta = a->n_theta;
+    p.d = static_cast<const R*>(a->d);
+    p.nk = static_cast<const R*>(a->nk);
+    p.n_mat = a->n_mat;
+    p.dispersive = a->dispersive;
+    p.mat = a->mat;
+    p.wl = static_cast<const R*>(a->wl);
+    p.sin_t = static_cast<const R*>(a->sin_theta);
+    p.cos_t = static_cast<const R*>(a->cos_theta);
+    p.R_out = static_cast<R*>(a->R);
+    p.T_out = static_cast<R*>(a->T);
+    p.r_out = static_cast<R*>(a->r);
+    p.t_out = static_cast<R*>(a->t);
+    p.n_tiles = (int)ceil_div(a->n_wl, kWave);
+    p.chunk = pick_chunk(a->B, (int64_t)p.n_tiles * a->n_theta);
+    const int64_t blocks = (int64_t)p.n_tiles * a->n_theta * ceil_div(a->B, p.chunk);
+    if (blocks > 0x7fffffff) return fail(TMM_ERR_UNSUPPORTED, "tmm_rt: grid of %lld workgroups is too large",
+                                         (long long)blocks);
+    const bool table = a->mat != nullptr && a->n_mat <= kMaxTableMat;
+    const bool amp = a->r != nullptr || a->t != nullptr;
+    const size_t lds = table ? table_bytes<R>(a->n_mat) : 0;
+    (void)hipGetLastError();
+    hipError_t e = table ? dispatch_pol<R, true>(p, a->pol_mask, amp, (int)blocks, lds, s)
+                         : dispatch_pol<R, false>(p, a->pol_mask, amp, (int)blocks, lds, s);
+    if (e != hipSuccess) return fail(TMM_ERR_HIP, "tmm_rt: launch failed: %s", hipGetErrorString(e));
+    return ok();
+}
+
+char* last_error_buffer() {
+    static thread_local char buf[512];
+    return buf;
+}
+
+}  // namespace tmm
+
+extern "C" {
+
+const char* tmm_status_string(tmm_status s) {
+    switch (s) {
+        case TMM_OK: return "ok";
+        case TMM_ERR_INVALID_ARG: return "invalid argument";
+        case TMM_ERR_UNSUPPORTED: return "unsupported request";
+        case TMM_ERR_HIP: return "HIP runtime error";
+        case TMM_ERR_WORKSPACE: return "workspace missing or too small";
+    }
+    return "unknown status";
+}
+
+const char* tmm_last_error(void) { return tmm::last_error_buffer(); }
+
+const char* tmm_version(void) { return "0.1.0"; }
+
+tmm_status tmm_rt(const tmm_rt_args* a, tmm_dtype dtype, void* stream) {
+    using tmm::fail;
+    if (!a) return fail(TMM_ERR_INVALID_ARG, "tmm_rt: args is NULL");
+    if (dtype != TMM_F64 && dtype != TMM_F32) return fail(TMM_ERR_INVALID_ARG, "tmm_rt: unknown dtype %d", (int)dtype);
+    if (a->B < 0 || a->L < 0 || a->n_wl < 0 || a->n_theta < 0)
+        return fail(TMM_ERR_INVALID_ARG, "tmm_rt: negative size (B=%d L=%d n_wl=%d n_theta=%d)", a->B, a->L,
+                    a->n_wl, a->n_theta);
+    if (a->L > (1 << 20)) return fail(TMM_ERR_INVALID_ARG, "tmm_rt: L=%d exceeds 1<<20", a->L);
+    if (a->pol_mask < 1u || a->pol_mask > 3u)
+        return fail(TMM_ERR_INVALID_ARG, "tmm_rt: pol_mask must be 1 (s), 2 (p) or 3 (both), got %u", a->pol_mask);
+    if (a->dispersive != 0 && a->dispersive != 1) return fail(TMM_ERR_INVALID_ARG, "tmm_rt: dispersive must be 0 or 1");
+    if (a->B == 0 || a->n_wl == 0 || a->n_theta == 0) return tmm::ok();  // nothing to compute
+    if (a->n_mat < 1) return fail(TMM_ERR_INVALID_ARG, "tmm_rt: n_mat must be >= 1");
+    if (!a->nk || !a->wl || !a->sin_theta || !a->cos_theta)
+        return fail(TMM_ERR_INVALID_ARG, "tmm_rt: nk, wl, sin_theta and cos_theta must be non-NULL");
+    if (a->L > 0 && a->B > 0 && !a->d) return fail(TMM_ERR_INVALID_ARG, "tmm_rt: d is NULL with L > 0");
+    if (!a->mat && (int64_t)a->n_mat < (int64_t)a->B * (a->L + 2))
+        return fail(TMM_ERR_INVALID_ARG, "tmm_rt: without mat, nk needs B*(L+2)=%lld rows, has %d",
+                    (long long)a->B * (a->L + 2), a->n_mat);
+    const int P = (a->pol_mask == 3u) ? 2 : 1;
+    const double elems = (double)a->B * P * (double)a->n_theta * (double)a->n_wl;
+    if (elems > 4.0e18) return fail(TMM_ERR_INVALID_ARG, "tmm_rt: output too large");
+    if (!a->R && !a->T && !a->r && !a->t) return fail(TMM_ERR_INVALID_ARG, "tmm_rt: no output requested");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    return dtype == TMM_F64 ? tmm::run_fwd<double>(a, s) : tmm::run_fwd<float>(a, s);
+}
+
+}  // extern "C"

@@ -1,0 +1,209 @@
+"""Thin ctypes binding of libtmm_rt (include/tmm_rt.h).
+
+Argument marshalling only: torch tensors supply device memory and the current
+HIP stream; every step of the computation runs in the library's HIP kernels.
+There is no fallback: if the library is missing or a call fails, an exception
+is raised.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtmm_rt.so")
+
+TMM_OK = 0
+TMM_ERR_INVALID_ARG = 1
+TMM_ERR_UNSUPPORTED = 2
+TMM_ERR_HIP = 4
+TMM_ERR_WORKSPACE = 5
+TMM_F64 = 0
+TMM_F32 = 1
+POL = {"s": 1, "p": 2, "both": 3}
+
+
+class TmmError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"[{status}] {message}")
+        self.status = status
+
+
+class TmmRtArgs(ctypes.Structure):
+    _fields_ = [
+        ("B", ctypes.c_int32), ("L", ctypes.c_int32),
+        ("n_wl", ctypes.c_int32), ("n_theta", ctypes.c_int32),
+        ("d", ctypes.c_void_p), ("nk", ctypes.c_void_p),
+        ("n_mat", ctypes.c_int32), ("dispersive", ctypes.c_int32),
+        ("mat", ctypes.c_void_p), ("wl", ctypes.c_void_p),
+        ("sin_theta", ctypes.c_void_p), ("cos_theta", ctypes.c_void_p),
+        ("pol_mask", ctypes.c_uint32),
+        ("R", ctypes.c_void_p), ("T", ctypes.c_void_p),
+        ("r", ctypes.c_void_p), ("t", ctypes.c_void_p),
+    ]
+
+
+_lib = None
+
+
+def library() -> ctypes.CDLL:
+    """Open libtmm_rt.so (built in-tree by __graft_entry__.build())."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+        lib = ctypes.CDLL(LIB_PATH)
+        lib.tmm_rt.restype = ctypes.c_int
+        lib.tmm_rt.argtypes = [ctypes.POINTER(TmmRtArgs), ctypes.c_int, ctypes.c_void_p]
+        lib.tmm_status_string.restype = ctypes.c_char_p
+        lib.tmm_status_string.argtypes = [ctypes.c_int]
+        lib.tmm_last_error.restype = ctypes.c_char_p
+        lib.tmm_version.restype = ctypes.c_char_p
+        _lib = lib
+    return _lib
+
+
+def _check(status: int):
+    if status != TMM_OK:
+        lib = library()
+        raise TmmError(status, lib.tmm_last_error().decode() or lib.tmm_status_string(status).decode())
+
+
+def _stream_handle(stream) -> int:
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream
+
+
+def _ptr(x) -> Optional[int]:
+    return None if x is None else x.data_ptr()
+
+
+def tmm_rt(d, nk, wl, sin_theta, cos_theta, *, mat=None, n_mat=None, dispersive=None,
+           pol_mask: int = 3, R=None, T=None, r=None, t=None, stream=None) -> None:
+    """Launch tmm_rt on device tensors (see include/tmm_rt.h for the layout).
+
+    d [B, L] real; nk complex [n_mat, n_wl] or [n_mat]; mat [B, L+2] int32 or None;
+    wl [n_wl], sin_theta / cos_theta [n_theta]; R, T real and r, t complex
+    [B, P, n_theta, n_wl] outputs (any may be None).  All real tensors share one
+    dtype (float64 or float32); complex ones are the matching complex dtype.
+    """
+    import torch
+    real = d.dtype
+    if real == torch.float64:
+        dt, cdt = TMM_F64, torch.complex128
+    elif real == torch.float32:
+        dt, cdt = TMM_F32, torch.complex64
+    else:
+        raise TypeError("d must be float64 or float32")
+    for name, x in (("wl", wl), ("sin_theta", sin_theta), ("cos_theta", cos_theta), ("R", R), ("T", T)):
+        if x is not None and x.dtype != real:
+            raise TypeError(f"{name} must be {real}")
+    for name, x in (("nk", nk), ("r", r), ("t", t)):
+        if x is not None and x.dtype != cdt:
+            raise TypeError(f"{name} must be {cdt}")
+    tensors = [d, nk, wl, sin_theta, cos_theta, mat, R, T, r, t]
+    for x in tensors:
+        if x is not None and (not x.is_cuda or not x.is_contiguous()):
+            raise ValueError("every tensor must be a contiguous device tensor")
+    if mat is not None and mat.dtype != torch.int32:
+        raise TypeError("mat must be int32")
+    B, L = d.shape
+    if dispersive is None:
+        dispersive = nk.dim() == 2
+    if n_mat is None:
+        n_mat = nk.shape[0]
+    P = 2 if pol_mask == 3 else 1
+    shape = (B, P, sin_theta.numel(), wl.numel())
+    for name, x in (("R", R), ("T", T), ("r", r), ("t", t)):
+        if x is not None and tuple(x.shape) != shape:
+            raise ValueError(f"{name} must have shape {shape}")
+    a = TmmRtArgs(B, L, wl.numel(), sin_theta.numel(), _ptr(d), _ptr(nk), n_mat, int(dispersive),
+                  _ptr(mat), _ptr(wl), _ptr(sin_theta), _ptr(cos_theta), pol_mask,
+                  _ptr(R), _ptr(T), _ptr(r), _ptr(t))
+    _check(library().tmm_rt(ctypes.byref(a), dt, _stream_handle(stream)))
+
+
+# ---------------------------------------------------------------------------
+# Convenience layer in the style of the paper's API.
+
+def _dev(x, dtype, device):
+    import torch
+    if isinstance(x, torch.Tensor):
+        return x.to(device=device, dtype=dtype).contiguous()
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=dtype, device=device)
+
+
+def evaluate(d, nk, wl, sin_theta, cos_theta, *, mat=None, pol: str = "both", dtype="f64",
+             amplitudes: bool = False, device="cuda"):
+    """Allocate outputs on the device and run tmm_rt; returns a dict of tensors
+    'R', 'T' (and 'r', 't') shaped [B, P, n_theta, n_wl]."""
+    import torch
+    real = torch.float64 if dtype in ("f64", torch.float64) else torch.float32
+    cplx = torch.complex128 if real == torch.float64 else torch.complex64
+    d_t = _dev(np.asarray(d) if not isinstance(d, torch.Tensor) else d, real, device)
+    if d_t.dim() == 1:
+        d_t = d_t.reshape(1, -1)
+    nk_t = _dev(nk, cplx, device)
+    wl_t = _dev(wl, real, device)
+    s_t = _dev(sin_theta, real, device)
+    c_t = _dev(cos_theta, real, device)
+    mat_t = None if mat is None else _dev(mat, torch.int32, device)
+    B = d_t.shape[0]
+    P = 2 if pol == "both" else 1
+    shape = (B, P, s_t.numel(), wl_t.numel())
+    out = {"R": torch.empty(shape, dtype=real, device=device),
+           "T": torch.empty(shape, dtype=real, device=device)}
+    if amplitudes:
+        out["r"] = torch.empty(shape, dtype=cplx, device=device)
+        out["t"] = torch.empty(shape, dtype=cplx, device=device)
+    tmm_rt(d_t, nk_t, wl_t, s_t, c_t, mat=mat_t, pol_mask=POL[pol], R=out["R"], T=out["T"],
+           r=out.get("r"), t=out.get("t"))
+    return out
+
+
+def evaluate_workload(w, *, dtype="f64", amplitudes=False, pol="both", device="cuda"):
+    """Run a workloads.Workload through tmm_rt."""
+    return evaluate(w.d, w.nk, w.wl, w.sin_t, w.cos_t, mat=w.mat, pol=pol, dtype=dtype,
+                    amplitudes=amplitudes, device=device)
+
+
+def coh_tmm(pol: str, n, d, theta, wl, *, dtype="f64", amplitudes=True, device="cuda"):
+    """Paper-style call: ``coh_tmm(pol, n, d, theta, wl)``.
+
+    n  [L+2] or [N, L+2] indices (constant) or [N, L+2, n_wl] (dispersive), media
+       0 and L+1 semi-infinite; d [L+2] or [N, L+2] thicknesses with +-inf (or any
+       value) in the two semi-infinite slots, same length unit as wl; theta in
+       rad; pol 's', 'p' or 'both'.  Returns a dict like the paper's
+       ('R', 'T', 'r', 't' as [N, P, n_theta, n_wl]; P is squeezed out for a
+       single polarisation).  sin/cos of theta are taken in float64 here.
+    """
+    import torch
+    n = np.asarray(n.cpu() if isinstance(n, torch.Tensor) else n)
+    d = np.asarray(d.detach().cpu() if isinstance(d, torch.Tensor) else d, dtype=np.float64)
+    if d.ndim == 1:
+        d = d[None]
+    if n.ndim == 1 or (n.ndim == 2 and n.shape[0] != d.shape[0]):
+        n = n[None]
+    N, M = d.shape
+    d_fin = np.ascontiguousarray(d[:, 1:M - 1])
+    theta = np.atleast_1d(np.asarray(theta, dtype=np.float64))
+    wl = np.atleast_1d(np.asarray(wl, dtype=np.float64))
+    if n.ndim == 3:
+        nk = n.reshape(N * M, wl.size).astype(np.complex128)
+    else:
+        nk = n.reshape(N * M).astype(np.complex128)
+    out = evaluate(d_fin, nk, wl, np.sin(theta), np.cos(theta), pol=pol, dtype=dtype,
+                   amplitudes=amplitudes, device=device)
+    if pol != "both":
+        out = {k: v[:, 0] for k, v in out.items()}
+    return out
+
+
+def unpolarised(out):
+    """(X_s + X_p) / 2 over the polarisation axis of a pol='both' result."""
+    return {k: 0.5 * (v[:, 0] + v[:, 1]) for k, v in out.items() if k in ("R", "T")}

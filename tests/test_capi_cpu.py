@@ -1,0 +1,92 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function that
+include/*.h declares, and rejects bad arguments on the host with the documented
+status codes (no HIP call is made before validation passes)."""
+import ctypes
+import glob
+import os
+import re
+
+import pytest
+
+from paper_2111_13667_amd import tmm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = set()
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        src = open(h).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        for m in re.finditer(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\**\s*(tmm_[a-z_0-9]+)\s*\(", src, flags=re.M):
+            names.add(m.group(1))
+    return sorted(names)
+
+
+def test_header_declares_entry_points():
+    names = declared_functions()
+    assert "tmm_rt" in names and "tmm_status_string" in names
+
+
+@pytest.mark.parametrize("name", declared_functions())
+def test_library_exports_declared_symbol(name):
+    lib = tmm.library()
+    assert hasattr(lib, name), f"{name} declared in include/ but not exported"
+
+
+def test_version_and_status_strings():
+    lib = tmm.library()
+    assert re.match(rb"^\d+\.\d+\.\d+$", lib.tmm_version())
+    for s in (0, 1, 2, 4, 5):
+        assert lib.tmm_status_string(s)
+
+
+FAKE = 0x1000  # never dereferenced: validation fails before any device access
+
+
+def args(**kw):
+    base = dict(B=2, L=3, n_wl=4, n_theta=5, d=FAKE, nk=FAKE, n_mat=6, dispersive=1, mat=FAKE,
+                wl=FAKE, sin_theta=FAKE, cos_theta=FAKE, pol_mask=3, R=FAKE, T=None, r=None, t=None)
+    base.update(kw)
+    return tmm.TmmRtArgs(**base)
+
+
+BAD = [
+    ("negative B", dict(B=-1)),
+    ("negative L", dict(L=-2)),
+    ("negative n_wl", dict(n_wl=-1)),
+    ("L too large", dict(L=(1 << 20) + 1)),
+    ("pol_mask 0", dict(pol_mask=0)),
+    ("pol_mask 4", dict(pol_mask=4)),
+    ("no outputs", dict(R=None)),
+    ("n_mat 0", dict(n_mat=0)),
+    ("dispersive 2", dict(dispersive=2)),
+    ("nk NULL", dict(nk=None)),
+    ("wl NULL", dict(wl=None)),
+    ("cos NULL", dict(cos_theta=None)),
+    ("d NULL", dict(d=None)),
+    ("implicit rows missing", dict(mat=None, n_mat=9)),
+]
+
+
+@pytest.mark.parametrize("case", BAD, ids=[c[0] for c in BAD])
+def test_invalid_arguments_rejected_on_host(case):
+    lib = tmm.library()
+    a = args(**case[1])
+    st = lib.tmm_rt(ctypes.byref(a), tmm.TMM_F64, None)
+    assert st == tmm.TMM_ERR_INVALID_ARG
+    assert lib.tmm_last_error()
+
+
+def test_null_args_and_bad_dtype():
+    lib = tmm.library()
+    assert lib.tmm_rt(None, tmm.TMM_F64, None) == tmm.TMM_ERR_INVALID_ARG
+    a = args()
+    assert lib.tmm_rt(ctypes.byref(a), 7, None) == tmm.TMM_ERR_INVALID_ARG
+
+
+def test_empty_batch_is_a_no_op():
+    lib = tmm.library()
+    for kw in (dict(B=0), dict(n_wl=0), dict(n_theta=0)):
+        a = args(**kw)
+        assert lib.tmm_rt(ctypes.byref(a), tmm.TMM_F64, None) == tmm.TMM_OK

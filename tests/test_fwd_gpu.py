@@ -1,0 +1,230 @@
+"""GPU parity of the forward kernels against the CPU oracle (element by element).
+
+Tolerances: float64 kernels agree with the complex128 oracle to 1e-12 absolute
+on R and T and 1e-12 * max(1, |ref|) on r and t; float32 kernels agree to 2e-5
+absolute on R and T with the oracle fed the float32-rounded inputs.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2111_13667_amd import workloads
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+TOL32 = 2e-5
+
+
+def run_gpu(w, dtype="f64", amplitudes=False, pol="both"):
+    from paper_2111_13667_amd import tmm
+    out = tmm.evaluate_workload(w, dtype=dtype, amplitudes=amplitudes, pol=pol)
+    torch.cuda.synchronize()
+    return {k: v.cpu().numpy() for k, v in out.items()}
+
+
+def run_oracle(w, amplitudes=False, pol="both"):
+    return oracle.rt(w.d, w.nk, w.wl, w.sin_t, w.cos_t, mat=w.mat, pol=pol,
+                     want_amplitudes=amplitudes)
+
+
+def assert_close64(got, ref, keys=("R", "T")):
+    for k in keys:
+        g, r = got[k], ref[k]
+        assert g.shape == r.shape, k
+        if k in ("r", "t"):
+            err = np.abs(g - r) / np.maximum(1.0, np.abs(r))
+        else:
+            err = np.abs(g - r)
+        assert np.isfinite(g).all(), f"{k}: non-finite GPU values"
+        assert err.max() <= TOL64, f"{k}: max error {err.max():.3e}"
+
+
+def assert_close32(got, ref):
+    for k in ("R", "T"):
+        err = np.abs(got[k].astype(np.float64) - ref[k])
+        assert np.isfinite(got[k]).all(), f"{k}: non-finite GPU values"
+        assert err.max() <= TOL32, f"{k}: max error {err.max():.3e}"
+
+
+def test_small_batch_f64_with_amplitudes():
+    w = workloads.small_batch()
+    assert_close64(run_gpu(w, amplitudes=True), run_oracle(w, amplitudes=True), ("R", "T", "r", "t"))
+
+
+def test_small_batch_f32():
+    w = workloads.small_batch()
+    assert_close32(run_gpu(w, dtype="f32"), run_oracle(w.rounded_f32()))
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_large_batch_first_stacks_full_grid(dtype):
+    # Material-pool table path: 8 stacks x 40 layers x 1024 wl x 91 angles (grazing included).
+    w = workloads.large_batch().take(slice(0, 8))
+    if dtype == "f64":
+        assert_close64(run_gpu(w), run_oracle(w))
+    else:
+        assert_close32(run_gpu(w, dtype="f32"), run_oracle(w.rounded_f32()))
+
+
+def test_large_batch_amplitudes_f64():
+    w = workloads.large_batch().take(slice(8, 11))
+    assert_close64(run_gpu(w, amplitudes=True), run_oracle(w, amplitudes=True), ("R", "T", "r", "t"))
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_large_batch_full_size_sampled(dtype):
+    # The full 4096 x 40 x 1024 x 91 x 2 batch in the benchmark's launch
+    # configuration, checked on 2000 seeded random points against the oracle.
+    from paper_2111_13667_amd import tmm
+    w = workloads.large_batch()
+    out = tmm.evaluate_workload(w, dtype=dtype)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(1234)
+    n = 2000
+    b = rng.integers(0, w.B, n)
+    p = rng.integers(0, 2, n)
+    k = rng.integers(0, w.theta.size, n)
+    i = rng.integers(0, w.wl.size, n)
+    idx = [torch.as_tensor(x, device="cuda") for x in (b, p, k, i)]
+    got = {key: out[key][idx].cpu().numpy().astype(np.float64) for key in ("R", "T")}
+    del out
+    wr = w.rounded_f32() if dtype == "f32" else w
+    tol = TOL64 if dtype == "f64" else TOL32
+    for j in range(n):
+        ref = oracle.rt(wr.d[b[j]:b[j] + 1], wr.nk[:, i[j]:i[j] + 1], wr.wl[i[j]:i[j] + 1],
+                        wr.sin_t[k[j]:k[j] + 1], wr.cos_t[k[j]:k[j] + 1],
+                        mat=wr.mat[b[j]:b[j] + 1], want_amplitudes=False)
+        for key in ("R", "T"):
+            assert abs(got[key][j] - ref[key][0, p[j], 0, 0]) <= tol, (key, b[j], p[j], k[j], i[j])
+
+
+@pytest.mark.parametrize("L", [0, 1, 2, 7])
+def test_few_layers_ragged_grids(L):
+    # Bare interface and thin stacks; wavelength counts that leave ragged tiles.
+    w = workloads.random_stacks(10 + L, B=5, L=L, n_wl=67, n_theta=3)
+    assert_close64(run_gpu(w, amplitudes=True), run_oracle(w, amplitudes=True), ("R", "T", "r", "t"))
+
+
+def test_single_wavelength_single_angle():
+    w = workloads.random_stacks(3, B=3, L=5, n_wl=1, n_theta=1)
+    assert_close64(run_gpu(w, amplitudes=True), run_oracle(w, amplitudes=True), ("R", "T", "r", "t"))
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_dispersive_per_layer_table(dtype):
+    w = workloads.random_stacks(21, B=6, L=23, n_wl=130, n_theta=4, dispersive=True)
+    if dtype == "f64":
+        assert_close64(run_gpu(w, amplitudes=True), run_oracle(w, amplitudes=True), ("R", "T", "r", "t"))
+    else:
+        assert_close32(run_gpu(w, dtype="f32"), run_oracle(w.rounded_f32()))
+
+
+def test_appendix_example_total_internal_reflection():
+    # Dense injection medium, exit into air: evanescent layers and TIR.
+    w = workloads.appendix_example(B=2, n_wl=101, n_theta=91)
+    assert_close64(run_gpu(w, amplitudes=True), run_oracle(w, amplitudes=True), ("R", "T", "r", "t"))
+
+
+@pytest.mark.parametrize("pol", ["s", "p"])
+def test_single_polarisation(pol):
+    w = workloads.large_batch(B=5, L=9, n_wl=70, n_theta=6)
+    assert_close64(run_gpu(w, amplitudes=True, pol=pol), run_oracle(w, amplitudes=True, pol=pol),
+                   ("R", "T", "r", "t"))
+
+
+def test_table_path_with_mixed_ambients():
+    # Stacks whose ambient differs from the first stack's take the inline source.
+    w = workloads.large_batch(B=9, L=12, n_wl=64, n_theta=5)
+    w.mat[3, 0] = 5
+    w.mat[5, 0] = 2
+    w.mat[5, -1] = 4
+    assert_close64(run_gpu(w, amplitudes=True), run_oracle(w, amplitudes=True), ("R", "T", "r", "t"))
+
+
+def test_large_material_table_inline_with_ids():
+    # More rows than the LDS table holds: inline source with material ids.
+    rng = np.random.default_rng(5)
+    w = workloads.large_batch(B=7, L=15, n_wl=90, n_theta=4)
+    n_mat = 40
+    nk = np.empty((n_mat, w.wl.size), np.complex128)
+    nk[:] = workloads.cauchy(rng.uniform(1.3, 2.5, n_mat), rng.uniform(0, 0.03, n_mat),
+                             rng.uniform(0, 0.01, n_mat), w.wl)
+    nk[0] = 1.0
+    mat = rng.integers(1, n_mat, w.mat.shape).astype(np.int32)
+    mat[:, 0] = 0
+    from dataclasses import replace
+    w = replace(w, nk=nk, mat=mat)
+    assert_close64(run_gpu(w, amplitudes=True), run_oracle(w, amplitudes=True), ("R", "T", "r", "t"))
+
+
+def test_zero_thickness_layers():
+    w = workloads.random_stacks(8, B=4, L=9, n_wl=40, n_theta=5)
+    w.d[:, ::3] = 0.0
+    assert_close64(run_gpu(w, amplitudes=True), run_oracle(w, amplitudes=True), ("R", "T", "r", "t"))
+
+
+def test_grazing_incidence_finite():
+    w = workloads.large_batch(B=3, L=40, n_wl=64, n_theta=91)
+    got = run_gpu(w, amplitudes=True)
+    for k in ("R", "T", "r", "t"):
+        assert np.isfinite(got[k]).all()
+    np.testing.assert_allclose(got["R"][:, :, -1], 1.0, atol=1e-12)
+
+
+def test_invalid_values_give_nan_not_fault():
+    w = workloads.large_batch(B=4, L=6, n_wl=64, n_theta=3)
+    w.d[1, 2] = -5.0
+    w.d[2, 0] = np.nan
+    w.mat[3, 4] = 99
+    got = run_gpu(w, amplitudes=True)
+    assert np.isfinite(got["R"][0]).all()
+    for b in (1, 2, 3):
+        assert np.isnan(got["R"][b]).all() and np.isnan(got["r"][b]).all()
+    ref = run_oracle(w)
+    assert np.isnan(ref["R"][1:]).all()
+
+
+def test_absorbing_ambient_only_at_normal_incidence():
+    w = workloads.random_stacks(9, B=2, L=3, n_wl=20, n_theta=3, n_amb=1.2 + 0.05j)
+    w.sin_t[0], w.cos_t[0] = 0.0, 1.0
+    got = run_gpu(w)
+    ref = run_oracle(w)
+    assert np.isfinite(got["R"][:, :, 0]).all()
+    assert np.isnan(got["R"][:, :, 1:]).all() and np.isnan(ref["R"][:, :, 1:]).all()
+    assert np.abs(got["R"][:, :, 0] - ref["R"][:, :, 0]).max() <= TOL64
+
+
+def test_empty_batch():
+    from paper_2111_13667_amd import tmm
+    w = workloads.small_batch(B=1)
+    d = torch.zeros((0, w.L), dtype=torch.float64, device="cuda")
+    R = torch.empty((0, 2, 8, 128), dtype=torch.float64, device="cuda")
+    nk = torch.ones(1, dtype=torch.complex128, device="cuda")
+    wl = torch.as_tensor(w.wl, device="cuda")
+    s = torch.as_tensor(w.sin_t, device="cuda")
+    c = torch.as_tensor(w.cos_t, device="cuda")
+    tmm.tmm_rt(d, nk, wl, s, c, R=R)
+
+
+def test_bitwise_deterministic():
+    w = workloads.large_batch().take(slice(0, 16))
+    a = run_gpu(w, amplitudes=True)
+    b = run_gpu(w, amplitudes=True)
+    for k in a:
+        assert np.array_equal(a[k].view(np.uint8), b[k].view(np.uint8)), k
+
+
+def test_paper_style_call():
+    from paper_2111_13667_amd import tmm
+    rng = np.random.default_rng(2)
+    d = rng.uniform(20, 150, 12)
+    d[0] = d[-1] = np.inf
+    n = rng.uniform(1.2, 5, 12)
+    n[-1] = 1.0
+    wl = np.linspace(500, 900, 31)
+    th = np.deg2rad(np.linspace(0, 90, 17))
+    out = tmm.coh_tmm("s", n, d, th, wl)
+    ref = oracle.rt(d[None, 1:-1], n.astype(complex), wl, np.sin(th), np.cos(th), pol="s")
+    assert np.abs(out["R"].cpu().numpy() - ref["R"][:, 0]).max() <= TOL64
