@@ -34,6 +34,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "tmm_math.hpp"
+
 namespace tmm {
 
 constexpr int kWave = 64;
@@ -139,9 +141,9 @@ __device__ __forceinline__ cx<R> phase_factor(double phr, double phi_im, bool lo
 template <>
 __device__ __forceinline__ cx<double> phase_factor<double>(double phr, double phi_im, bool lossy) {
     double s, c;
-    sincospi(phr, &s, &c);
+    sincospi_d(phr, s, c);
     if (lossy) {
-        const double rho = exp2(phi_im * kNegPiLog2e);
+        const double rho = exp2_d(phi_im * kNegPiLog2e);
         s *= rho;
         c *= rho;
     }
@@ -152,11 +154,11 @@ template <>
 __device__ __forceinline__ cx<float> phase_factor<float>(double phr, double phi_im, bool lossy) {
     // Exact reduction by a multiple of the period (2 half-turns) in double, then
     // a float sin/cos of |x| <= 1 half-turn.
-    const float x = (float)(phr - 2.0 * rint(0.5 * phr));
+    const float x = (float)__builtin_fma(-2.0, __builtin_rint(0.5 * phr), phr);
     float s, c;
-    sincospif(x, &s, &c);
+    sincospi_f(x, s, c);
     if (lossy) {
-        const float rho = exp2f((float)(phi_im * kNegPiLog2e));
+        const float rho = exp2_f((float)(phi_im * kNegPiLog2e));
         s *= rho;
         c *= rho;
     }

@@ -91,27 +91,24 @@ __device__ __forceinline__ void load_n(const R* nk, int dispersive, int n_wl, in
 // Media table in LDS, structure-of-arrays, one entry per (material, lane).
 template <typename R> struct Table;
 
+// Layout: one block per material, arrays of that material one after another,
+// so that a single address (block + lane) reaches every array through the
+// immediate offset of the LDS read.
 template <>
 struct Table<double> {
-    static constexpr int kEntryBytes = 48;
-    double2* q;
-    double2* e;
-    double2* n2;
-    __device__ Table(unsigned char* base, int n_mat) {
-        const int n = n_mat * kWave;
-        q = reinterpret_cast<double2*>(base);
-        e = q + n;
-        n2 = e + n;
-    }
+    static constexpr int kEntryBytes = 48;               // per (material, lane)
+    static constexpr int kBlockBytes = kWave * kEntryBytes;
+    unsigned char* base;
+    __device__ Table(unsigned char* b, int) : base(b) {}
     __device__ __forceinline__ void put(int m, int lane, const Medium& md) {
-        const int x = m * kWave + lane;
-        q[x] = make_double2(md.qr, md.qi);
-        e[x] = make_double2(md.er, md.ei);
-        n2[x] = make_double2(md.q2, md.e2);
+        double2* blk = reinterpret_cast<double2*>(base + m * kBlockBytes);
+        blk[lane] = make_double2(md.qr, md.qi);
+        blk[kWave + lane] = make_double2(md.er, md.ei);
+        blk[2 * kWave + lane] = make_double2(md.q2, md.e2);
     }
     __device__ __forceinline__ Layer<double> get(int m, int lane) const {
-        const int x = m * kWave + lane;
-        const double2 a = q[x], b = e[x], c = n2[x];
+        const double2* blk = reinterpret_cast<const double2*>(base + m * kBlockBytes) + lane;
+        const double2 a = blk[0], b = blk[kWave], c = blk[2 * kWave];
         Layer<double> v;
         v.q = {a.x, a.y};
         v.e = {b.x, b.y};
@@ -126,28 +123,22 @@ struct Table<double> {
 template <>
 struct Table<float> {
     static constexpr int kEntryBytes = 40;
-    double2* pd;
-    float2* q;
-    float2* e;
-    float2* n2;
-    __device__ Table(unsigned char* base, int n_mat) {
-        const int n = n_mat * kWave;
-        pd = reinterpret_cast<double2*>(base);
-        q = reinterpret_cast<float2*>(pd + n);
-        e = q + n;
-        n2 = e + n;
-    }
+    static constexpr int kBlockBytes = kWave * kEntryBytes;
+    unsigned char* base;
+    __device__ Table(unsigned char* b, int) : base(b) {}
     __device__ __forceinline__ void put(int m, int lane, const Medium& md) {
-        const int x = m * kWave + lane;
-        pd[x] = make_double2(md.qr, md.qi);
-        q[x] = make_float2((float)md.qr, (float)md.qi);
-        e[x] = make_float2((float)md.er, (float)md.ei);
-        n2[x] = make_float2((float)md.q2, (float)md.e2);
+        unsigned char* blk = base + m * kBlockBytes;
+        reinterpret_cast<double2*>(blk)[lane] = make_double2(md.qr, md.qi);
+        float2* f = reinterpret_cast<float2*>(blk + kWave * 16);
+        f[lane] = make_float2((float)md.qr, (float)md.qi);
+        f[kWave + lane] = make_float2((float)md.er, (float)md.ei);
+        f[2 * kWave + lane] = make_float2((float)md.q2, (float)md.e2);
     }
     __device__ __forceinline__ Layer<float> get(int m, int lane) const {
-        const int x = m * kWave + lane;
-        const double2 p = pd[x];
-        const float2 a = q[x], b = e[x], c = n2[x];
+        const unsigned char* blk = base + m * kBlockBytes;
+        const double2 p = reinterpret_cast<const double2*>(blk)[lane];
+        const float2* f = reinterpret_cast<const float2*>(blk + kWave * 16) + lane;
+        const float2 a = f[0], b = f[kWave], c = f[2 * kWave];
         Layer<float> v;
         v.q = {a.x, a.y};
         v.e = {b.x, b.y};
@@ -161,7 +152,9 @@ struct Table<float> {
 
 template <typename R>
 __host__ __device__ constexpr size_t table_bytes(int n_mat) {
-    return (size_t)n_mat * kWave * Table<R>::kEntryBytes + 4 * kMaxTableMat;
+    // media table, lossy flags, per-wave layer staging (d: 8 B, code: 4 B per layer)
+    return (size_t)n_mat * kWave * Table<R>::kEntryBytes + 4 * kMaxTableMat +
+           (size_t)kWavesPerBlock * kWave * 12;
 }
 
 // Sources of per-layer values for the chain.  Row ids are wave-uniform.
@@ -409,6 +402,80 @@ __device__ __forceinline__ void run_stack(const FwdParams<R>& p, const Src& src,
     }
 }
 
+// Per-wave LDS staging of one stack's layers: thickness and table row of up to
+// kWave layers at a time, written by one lane each and read back as
+// wave-uniform values by the layer loop.
+struct Stage {
+    double d[kWave];
+    int code[kWave];  // table row | lossy flag << 16
+};
+
+__device__ __forceinline__ void wave_sync_lds() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Table path: one stack, layers staged through LDS in chunks of kWave, loop
+// unrolled by two so that the current/next medium values rotate in registers.
+template <typename R, int POL, bool AMP>
+__device__ __forceinline__ void run_stack_table(const FwdParams<R>& p, const Table<R>& tab, uint32_t lossy_mask,
+                                                Stage& stg, const Ambient& amb, int b, int k, int i, int lane,
+                                                bool active, bool lane_ok, double c4lam, double nsub_r,
+                                                double nsub_i) {
+    const int L = p.L;
+    const int n_mat = p.n_mat;
+    const R* drow = p.d + (int64_t)b * L;
+    const int32_t* mrow = p.mat + (int64_t)b * (L + 2);
+    const int m_sub_raw = mrow[L + 1];
+    bool bad = (uint32_t)m_sub_raw >= (uint32_t)n_mat;
+    const int m_sub = bad ? 0 : m_sub_raw;
+    const Layer<R> sub = tab.get(m_sub, lane);
+    Layer<R> nxt = sub;
+    Chain<R, POL, AMP> c;
+    c.init();
+    int cnt = 0;
+    for (int top = L; top >= 1; top -= kWave) {
+        const int lo = top - kWave + 1 > 1 ? top - kWave + 1 : 1;
+        // stage layers lo..top
+        const int j = lo + lane;
+        bool lane_bad = false;
+        if (j <= top) {
+            const R dj = drow[j - 1];
+            const int m = mrow[j];
+            const bool mbad = (uint32_t)m >= (uint32_t)n_mat;
+            lane_bad = mbad || bad_thickness(dj);
+            const int mc = mbad ? 0 : m;
+            stg.d[lane] = (double)dj;
+            stg.code[lane] = mc | (int)(((lossy_mask >> mc) & 1u) << 16);
+        }
+        bad = bad || __any(lane_bad);
+        wave_sync_lds();
+#pragma unroll 2
+        for (int jj = top; jj >= lo; --jj) {
+            const int code = __builtin_amdgcn_readfirstlane(stg.code[jj - lo]);
+            const double dj = stg.d[jj - lo];
+            const Layer<R> cur = tab.get(code & 0xffff, lane);
+            c.step(cur, nxt, dj * c4lam, (code >> 16) != 0);
+            nxt = cur;
+            if (++cnt == RenormPeriod<R>::value) {
+                cnt = 0;
+                c.renorm();
+            }
+        }
+        wave_sync_lds();
+    }
+    c.renorm();
+    PointOut out[2];
+    finish<R, POL, AMP>(c, amb, nxt, sub, nsub_r, nsub_i, L, out);
+    if (active) {
+        const bool valid = lane_ok && !bad;
+        constexpr int P = (POL == 3) ? 2 : 1;
+        store_point(p, b, k, i, 0, P, out[0], valid);
+        if (POL == 3) store_point(p, b, k, i, 1, P, out[1], valid);
+    }
+}
+
 template <typename R, int POL, bool AMP, bool TABLE>
 __global__ void __launch_bounds__(kBlock) fwd_kernel(FwdParams<R> p) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -438,6 +505,8 @@ __global__ void __launch_bounds__(kBlock) fwd_kernel(FwdParams<R> p) {
         const Ambient amb = make_ambient(n0r, n0i, st, ct);
         Table<R> tab(smem, p.n_mat);
         int* flags = reinterpret_cast<int*>(smem + (size_t)p.n_mat * kWave * Table<R>::kEntryBytes);
+        Stage* stages = reinterpret_cast<Stage*>(smem + (size_t)p.n_mat * kWave * Table<R>::kEntryBytes +
+                                                 4 * kMaxTableMat);
         for (int m = wave; m < p.n_mat; m += kWavesPerBlock) {
             double nr, ni;
             load_n(p.nk, p.dispersive, p.n_wl, m, i, nr, ni);
@@ -457,8 +526,8 @@ __global__ void __launch_bounds__(kBlock) fwd_kernel(FwdParams<R> p) {
             double nsr = 0.0, nsi = 0.0;
             if (AMP) load_n(p.nk, p.dispersive, p.n_wl, sub_row, i, nsr, nsi);
             if (mrow[0] == amb_row) {
-                TableSource<R> src{&tab, mrow, lane, p.n_mat, mask};
-                run_stack<R, POL, AMP>(p, src, amb, b, k, i, active, lam_ok && amb.ok, c4lam, nsr, nsi);
+                run_stack_table<R, POL, AMP>(p, tab, mask, stages[wave], amb, b, k, i, lane, active,
+                                             lam_ok && amb.ok, c4lam, nsr, nsi);
             } else {
                 int a_row = mrow[0];
                 a_row = a_row < 0 ? 0 : (a_row >= p.n_mat ? p.n_mat - 1 : a_row);
