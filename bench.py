@@ -124,6 +124,8 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="skip the f32 and amplitude variants")
     ap.add_argument("--cpu-stacks", type=int, default=64)
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"))
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="first run a plain N-MiB elementwise copy kernel (profiler calibration)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -140,6 +142,16 @@ def main():
 
     from paper_2111_13667_amd import workloads
     w = workloads.large_batch()
+
+    if args.calibrate_copy_mib > 0:
+        # A plain elementwise kernel of known traffic (reads and writes N bytes),
+        # for scaling the FETCH_SIZE / WRITE_SIZE counters of a profiler run.
+        n = args.calibrate_copy_mib * (1 << 20) // 8
+        x = torch.ones(n, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(x)
+        torch.neg(x, out=y)
+        torch.cuda.synchronize()
+        del x, y
 
     traffic = None
     if os.path.exists(args.traffic_json):
