@@ -112,6 +112,40 @@ typedef struct tmm_rt_args {
  */
 tmm_status tmm_rt(const tmm_rt_args *a, tmm_dtype dtype, void *stream);
 
+/*
+ * Workspace bytes that tmm_rt_grad needs for these arguments (0 if there is
+ * nothing to compute).  Depends on B, L, n_wl and n_theta only.
+ */
+size_t tmm_rt_grad_workspace_size(const tmm_rt_args *a);
+
+/*
+ * Reverse-mode gradients of a loss l(R, T) w.r.t. the layer thicknesses and
+ * the layer refractive indices -- the gradients the paper obtains through
+ * PyTorch autograd (section "TMM-Torch", appendix example: dl/dd of an MSE
+ * against a target reflectance), computed here by a hand-written adjoint of
+ * the forward recursion (Eq. (1)-(7)).  float64 only.
+ *  a            the forward arguments (as for tmm_rt).  r and t must be NULL;
+ *               R and T, if given, receive the forward values as a by-product.
+ *  dl_dR, dl_dT [B][P][n_theta][n_wl] upstream gradients (device; either may
+ *               be NULL, meaning zero; not both).
+ *  grad_d       [B][L] real: dl/dd_j of every finite layer (device, or NULL).
+ *  grad_n       [B][L] complex interleaved: dl/dRe n_j + i dl/dIm n_j, where
+ *               n_j is shifted at every wavelength (for a constant index this
+ *               is the derivative w.r.t. that index) (device, or NULL).
+ *               The ambient and substrate get no gradient.
+ *  workspace    device scratch of at least tmm_rt_grad_workspace_size(a)
+ *               bytes, owned by the caller, contents irrelevant on entry.
+ *  dtype        TMM_F64 (TMM_F32 returns TMM_ERR_UNSUPPORTED).
+ * The gradient outputs are overwritten (zeroed, then accumulated with atomic
+ * adds, so the last bits may differ from run to run).  Points that are invalid
+ * (see the NaN rules above) make their stack's gradients NaN.
+ * Returns TMM_OK, TMM_ERR_INVALID_ARG, TMM_ERR_UNSUPPORTED, TMM_ERR_WORKSPACE
+ * or TMM_ERR_HIP.
+ */
+tmm_status tmm_rt_grad(const tmm_rt_args *a, const void *dl_dR, const void *dl_dT, void *grad_d,
+                       void *grad_n, void *workspace, size_t workspace_bytes, tmm_dtype dtype,
+                       void *stream);
+
 /* Static description of a status code (never NULL). */
 const char *tmm_status_string(tmm_status s);
 

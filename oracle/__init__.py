@@ -66,6 +66,9 @@ def _bind(lib):
                                                     P, P, P, P, ctypes.c_uint,
                                                     P, P, P, P, P]
     lib.oracle_max_threads.restype = ctypes.c_int
+    lib.oracle_rt_dir_cs.restype = ctypes.c_int
+    lib.oracle_rt_dir_cs.argtypes = [ctypes.c_int] * 4 + [P, P, ctypes.c_int, P, P, P, ctypes.c_uint,
+                                                           P, P, P, P, P]
     return lib
 
 
@@ -137,6 +140,60 @@ def rt(d, nk, wl, sin_t, cos_t, *, mat=None, dispersive=None, pol="both",
         out["r"] = r
         out["t"] = t
     return out
+
+
+def rt_dir_cs(d, nk, wl, sin_t, cos_t, *, gR=None, gT=None, vd=None, vn=None, pol="both",
+              dispersive=None):
+    """Complex-step directional derivative, per stack, of
+    sum(gR * R + gT * T) along d -> d + e vd, n_j -> n_j + e vn (finite layers).
+
+    Per-layer index table only: nk has rows b*(L+2)+j ([B*(L+2)] or
+    [B*(L+2), n_wl]).  gR, gT: [B, P, n_theta, n_wl]; vd: [B, L] real;
+    vn: [B, L] complex.  Returns D [B].
+    """
+    lib = _load()
+    d = np.ascontiguousarray(d, dtype=np.float64)
+    B, L = d.shape
+    nk = np.ascontiguousarray(nk, dtype=np.complex128)
+    wl = np.ascontiguousarray(wl, dtype=np.float64).ravel()
+    sin_t = np.ascontiguousarray(sin_t, dtype=np.float64).ravel()
+    cos_t = np.ascontiguousarray(cos_t, dtype=np.float64).ravel()
+    if dispersive is None:
+        dispersive = nk.ndim == 2
+    if nk.shape[0] != B * (L + 2):
+        raise ValueError("nk must have one row per medium of every stack")
+    mask = {"s": 1, "p": 2, "both": 3}[pol]
+    P = 2 if mask == 3 else 1
+    shape = (B, P, sin_t.size, wl.size)
+    conv = lambda a, dt, shp: None if a is None else np.ascontiguousarray(np.broadcast_to(a, shp), dtype=dt)
+    gR = conv(gR, np.float64, shape)
+    gT = conv(gT, np.float64, shape)
+    vd = conv(vd, np.float64, (B, L))
+    vn = conv(vn, np.complex128, (B, L))
+    D = np.empty(B)
+    th = lib.oracle_rt_dir_cs(B, L, wl.size, sin_t.size, _ptr(d), _ptr(nk), int(bool(dispersive)),
+                              _ptr(wl), _ptr(sin_t), _ptr(cos_t), mask, _ptr(gR), _ptr(gT),
+                              _ptr(vd), _ptr(vn), _ptr(D))
+    if th < 0:
+        raise ValueError("oracle_rt_dir_cs rejected its arguments")
+    return D
+
+
+def rt_grad_cs(d, nk, wl, sin_t, cos_t, *, gR=None, gT=None, pol="both"):
+    """Full gradient per stack by one complex-step pass per parameter:
+    returns (grad_d [B, L], grad_n [B, L] complex = dl/dRe n + i dl/dIm n)."""
+    d = np.asarray(d, dtype=np.float64)
+    B, L = d.shape
+    gd = np.empty((B, L))
+    gn = np.empty((B, L), np.complex128)
+    for j in range(L):
+        e = np.zeros((B, L))
+        e[:, j] = 1.0
+        gd[:, j] = rt_dir_cs(d, nk, wl, sin_t, cos_t, gR=gR, gT=gT, vd=e, pol=pol)
+        re = rt_dir_cs(d, nk, wl, sin_t, cos_t, gR=gR, gT=gT, vn=e.astype(complex), pol=pol)
+        im = rt_dir_cs(d, nk, wl, sin_t, cos_t, gR=gR, gT=gT, vn=1j * e, pol=pol)
+        gn[:, j] = re + 1j * im
+    return gd, gn
 
 
 def max_threads() -> int:

@@ -42,6 +42,11 @@
  * independent Abeles characteristic-matrix formulation.
  * Parity unpinned: T_p when the exit medium is absorbing or evanescent (only
  * the passivity inequality applies there).
+ *
+ * oracle_rt_dir_cs (bottom of this file) repeats the same steps in bicomplex
+ * arithmetic to give complex-step directional derivatives of R and T; it is
+ * pinned against central finite differences of oracle_rt
+ * (tests/test_oracle_grad_pins.py).
  */
 #include <complex.h>
 #include <math.h>
@@ -238,4 +243,183 @@ int oracle_max_threads(void) {
 #else
     return 1;
 #endif
+}
+
+/* ===========================================================================
+ * Complex-step derivative oracle (bicomplex arithmetic).
+ *
+ * The same steps as oracle_point, carried out on bicomplex numbers
+ * z = z1 + z2 j (z1, z2 complex in i, j^2 = -1, i j = j i).  A real parameter p
+ * of the stack is replaced by p + h v j with h = 1e-20; every output quantity
+ * then has a j-part equal to h times its derivative along v, free of
+ * cancellation (complex-step differentiation in its multicomplex form).  R and
+ * T are formed from the i-real and i-imaginary parts treated as j-complex
+ * numbers, so their j-parts are h dR/de and h dT/de.
+ * Used to check the adjoint kernel's gradients (TMM-Torch section: gradients
+ * of R, T w.r.t. thicknesses and refractive indices).
+ * =========================================================================== */
+
+typedef struct { cplx a, b; } bicplx; /* a + b j */
+
+static bicplx bc(cplx a, cplx b) { bicplx r = {a, b}; return r; }
+static bicplx bc_add(bicplx x, bicplx y) { return bc(x.a + y.a, x.b + y.b); }
+static bicplx bc_sub(bicplx x, bicplx y) { return bc(x.a - y.a, x.b - y.b); }
+static bicplx bc_mul(bicplx x, bicplx y) {
+    return bc(x.a * y.a - x.b * y.b, x.a * y.b + x.b * y.a);
+}
+static bicplx bc_scale(cplx s, bicplx x) { return bc(s * x.a, s * x.b); }
+static bicplx bc_div(bicplx x, bicplx y) {
+    /* x / y = x * (y.a - y.b j) / (y.a^2 + y.b^2) */
+    cplx den = y.a * y.a + y.b * y.b;
+    bicplx c = bc(y.a, -y.b);
+    bicplx n = bc_mul(x, c);
+    return bc(n.a / den, n.b / den);
+}
+/* sqrt with the same principal branch on the value part; w1^2 - w2^2 = z1,
+ * 2 w1 w2 = z2.  The j-part is O(h), so w1 = sqrt(z1 + w2^2) = sqrt(z1) to
+ * double precision. */
+static bicplx bc_sqrt(bicplx z) {
+    cplx w1 = csqrt(z.a);
+    cplx w2 = z.b / (2.0 * w1);
+    return bc(w1, w2);
+}
+/* exp(z1 + z2 j) = exp(z1) (cos z2 + j sin z2) */
+static bicplx bc_exp(bicplx z) {
+    cplx e = cexp(z.a);
+    return bc(e * ccos(z.b), e * csin(z.b));
+}
+
+/* One point in bicomplex arithmetic; n[j], d[j] already carry their j-parts.
+ * Outputs R, T as j-complex numbers (value, j-part). */
+static int oracle_point_bc(int L, const bicplx *n, const bicplx *d, double lam,
+                           double sin_t, double cos_t, int pol, bicplx *cos_buf,
+                           double R_out[2], double T_out[2]) {
+    if (cimag(n[0].a) != 0.0 && sin_t != 0.0) return -1;
+    bicplx kx = bc_scale(sin_t, n[0]);
+    cos_buf[0] = bc(cos_t, 0.0);
+    for (int j = 1; j <= L + 1; ++j) {
+        bicplx s = bc_div(kx, n[j]);
+        bicplx c = bc_sqrt(bc_sub(bc(1.0, 0.0), bc_mul(s, s)));
+        if (!is_forward(n[j].a * c.a)) c = bc_scale(-1.0, c);
+        cos_buf[j] = c;
+    }
+    bicplx M[4] = {bc(1.0, 0.0), bc(0.0, 0.0), bc(0.0, 0.0), bc(1.0, 0.0)};
+    for (int j = 0; j <= L; ++j) {
+        bicplx n1 = n[j], n2 = n[j + 1], c1 = cos_buf[j], c2 = cos_buf[j + 1];
+        bicplx r, t, den;
+        if (pol == 0) {
+            den = bc_add(bc_mul(n1, c1), bc_mul(n2, c2));
+            t = bc_div(bc_scale(2.0, bc_mul(n1, c1)), den);
+            r = bc_div(bc_sub(bc_mul(n1, c1), bc_mul(n2, c2)), den);
+        } else {
+            den = bc_add(bc_mul(n2, c1), bc_mul(n1, c2));
+            t = bc_div(bc_scale(2.0, bc_mul(n1, c1)), den);
+            r = bc_div(bc_sub(bc_mul(n2, c1), bc_mul(n1, c2)), den);
+        }
+        bicplx delta = bc(0.0, 0.0);
+        if (j > 0) {
+            delta = bc_scale(2.0 * ORACLE_PI / lam, bc_mul(bc_mul(n1, d[j - 1]), c1));
+            if (cimag(delta.a) > ORACLE_IM_DELTA_CAP) return -1;
+        }
+        bicplx em = bc_exp(bc_scale(-I, delta)), ep = bc_exp(bc_scale(I, delta));
+        bicplx it = bc_div(bc(1.0, 0.0), t);
+        bicplx Mj[4] = {bc_mul(em, it), bc_mul(bc_mul(em, r), it), bc_mul(bc_mul(ep, r), it),
+                        bc_mul(ep, it)};
+        bicplx C[4];
+        C[0] = bc_add(bc_mul(M[0], Mj[0]), bc_mul(M[1], Mj[2]));
+        C[1] = bc_add(bc_mul(M[0], Mj[1]), bc_mul(M[1], Mj[3]));
+        C[2] = bc_add(bc_mul(M[2], Mj[0]), bc_mul(M[3], Mj[2]));
+        C[3] = bc_add(bc_mul(M[2], Mj[1]), bc_mul(M[3], Mj[3]));
+        for (int q = 0; q < 4; ++q) M[q] = C[q];
+    }
+    bicplx r = bc_div(M[2], M[0]);
+    bicplx t = bc_div(bc(1.0, 0.0), M[0]);
+    /* i-real / i-imaginary parts as j-complex numbers (value, j-part), squared. */
+    double rr0 = creal(r.a), rr1 = creal(r.b), ri0 = cimag(r.a), ri1 = cimag(r.b);
+    double tr0 = creal(t.a), tr1 = creal(t.b), ti0 = cimag(t.a), ti1 = cimag(t.b);
+    double R0 = rr0 * rr0 + ri0 * ri0, R1 = 2.0 * (rr0 * rr1 + ri0 * ri1);
+    double tt0 = tr0 * tr0 + ti0 * ti0, tt1 = 2.0 * (tr0 * tr1 + ti0 * ti1);
+    /* flux ratio f = Re(num) / Re(den), each a j-complex number */
+    bicplx num, den;
+    if (pol == 0) {
+        num = bc_mul(n[L + 1], cos_buf[L + 1]);
+        den = bc_mul(n[0], cos_buf[0]);
+    } else {
+        bicplx cc = bc(conj(cos_buf[L + 1].a), conj(cos_buf[L + 1].b));
+        bicplx c0 = bc(conj(cos_buf[0].a), conj(cos_buf[0].b));
+        num = bc_mul(n[L + 1], cc);
+        den = bc_mul(n[0], c0);
+    }
+    double nu0 = creal(num.a), nu1 = creal(num.b), de0 = creal(den.a), de1 = creal(den.b);
+    double f0 = nu0 / de0, f1 = (nu1 * de0 - nu0 * de1) / (de0 * de0);
+    R_out[0] = R0; R_out[1] = R1;
+    T_out[0] = tt0 * f0; T_out[1] = tt1 * f0 + tt0 * f1;
+    return 0;
+}
+
+/*
+ * Directional derivative of a weighted sum of outputs, per stack:
+ *   D[b] = sum over (pol, theta, lambda) of gR * dR/de + gT * dT/de
+ * for the perturbation d_j -> d_j + e vd[b][j], n_j -> n_j + e vn[b][j] of the
+ * finite layers j = 1..L (vn complex; n_j shifted at every wavelength).
+ * Per-layer index table only (row b*(L+2)+j), as in oracle_rt with mat = NULL.
+ *   gR, gT  [B][P][n_theta][n_wl] weights (either may be NULL = 0)
+ *   vd      [B][L] real, vn [B][L] complex interleaved (either may be NULL = 0)
+ * Returns the number of threads used, or -1 on a bad argument.
+ */
+int oracle_rt_dir_cs(int B, int L, int n_wl, int n_theta, const double *d, const double *nk,
+                     int dispersive, const double *wl, const double *sin_t,
+                     const double *cos_t, unsigned pol_mask, const double *gR,
+                     const double *gT, const double *vd, const double *vn, double *D) {
+    if (B < 0 || L < 0 || n_wl < 0 || n_theta < 0 || (pol_mask & ~3u) || !pol_mask) return -1;
+    const double h = 1e-20;
+    int P = (pol_mask & 1u) + ((pol_mask >> 1) & 1u);
+    int threads = 1;
+#pragma omp parallel
+    {
+#ifdef _OPENMP
+#pragma omp single
+        threads = omp_get_num_threads();
+#endif
+        bicplx *nb = (bicplx *)malloc(sizeof(bicplx) * (size_t)(L + 2));
+        bicplx *db = (bicplx *)malloc(sizeof(bicplx) * (size_t)(L + 1));
+        bicplx *cb = (bicplx *)malloc(sizeof(bicplx) * (size_t)(L + 2));
+#pragma omp for schedule(dynamic, 1)
+        for (int b = 0; b < B; ++b) {
+            double acc = 0.0;
+            for (int j = 0; j < L; ++j)
+                db[j] = bc(d[(int64_t)b * L + j], vd ? h * vd[(int64_t)b * L + j] : 0.0);
+            for (int i = 0; i < n_wl; ++i) {
+                for (int j = 0; j < L + 2; ++j) {
+                    cplx v = nk_at(nk, dispersive, n_wl, b * (L + 2) + j, i);
+                    cplx dv = 0.0;
+                    if (vn && j >= 1 && j <= L) {
+                        int64_t q = (int64_t)b * L + (j - 1);
+                        dv = h * (vn[2 * q] + I * vn[2 * q + 1]);
+                    }
+                    nb[j] = bc(v, dv);
+                }
+                for (int k = 0; k < n_theta; ++k) {
+                    int pi = 0;
+                    for (int pol = 0; pol < 2; ++pol) {
+                        if (!(pol_mask & (1u << pol))) continue;
+                        double R[2], T[2];
+                        int64_t o = (((int64_t)b * P + pi) * n_theta + k) * n_wl + i;
+                        if (oracle_point_bc(L, nb, db, wl[i], sin_t[k], cos_t[k], pol, cb, R, T) == 0) {
+                            if (gR) acc += gR[o] * R[1] / h;
+                            if (gT) acc += gT[o] * T[1] / h;
+                        } else {
+                            acc = NAN;
+                        }
+                        ++pi;
+                    }
+                }
+            }
+            D[b] = acc;
+        }
+        free(nb);
+        free(db);
+        free(cb);
+    }
+    return threads;
 }

@@ -209,4 +209,38 @@ __device__ __forceinline__ bool bad_thickness(float d) {
     return neg || nonfinite;
 }
 
+// ---------------------------------------------------------------------------
+// Ambient medium (j = 0), per lane: q_0 = n_0 cos(theta_0), eta_0 = n_0 / cos(theta_0)
+// from the given cosine (no square root, so grazing incidence keeps its tiny
+// cosine), the Snell invariant kx and the flux constants of T_s, T_p.
+struct Ambient {
+    double n0r, n0i, q0r, q0i, e0r, e0i, kx, Ks, Kp;
+    bool ok;
+};
+
+__device__ __forceinline__ Ambient make_ambient(double n0r, double n0i, double st, double ct) {
+    Ambient a;
+    a.n0r = n0r;
+    a.n0i = n0i;
+    a.ok = (n0i == 0.0) || (st == 0.0);
+    a.kx = n0r * st;
+    a.q0r = n0r * ct;
+    a.q0i = n0i * ct;
+    const double ic = 1.0 / ct;
+    a.e0r = n0r * ic;
+    a.e0i = n0i * ic;
+    const double nn = n0r * n0r + n0i * n0i;
+    a.Ks = nn * ct / n0r;
+    a.Kp = nn * ic / n0r;
+    return a;
+}
+
+template <typename R>
+__device__ __forceinline__ void load_n(const R* nk, int dispersive, int n_wl, int64_t row, int i,
+                                       double& nr, double& ni) {
+    const int64_t idx = dispersive ? row * (int64_t)n_wl + i : row;
+    nr = (double)nk[2 * idx];
+    ni = (double)nk[2 * idx + 1];
+}
+
 }  // namespace tmm

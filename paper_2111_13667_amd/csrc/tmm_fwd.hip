@@ -54,40 +54,6 @@ template <> struct RenormPeriod<double> { static constexpr int value = 16; };
 template <> struct RenormPeriod<float> { static constexpr int value = 4; };
 
 // ---------------------------------------------------------------------------
-// Ambient medium (j = 0), per lane: q_0 = n_0 cos(theta_0), eta_0 = n_0 / cos(theta_0)
-// from the given cosine (no square root, so grazing incidence keeps its tiny
-// cosine), the Snell invariant kx and the flux constants of T_s, T_p.
-struct Ambient {
-    double n0r, n0i, q0r, q0i, e0r, e0i, kx, Ks, Kp;
-    bool ok;
-};
-
-__device__ __forceinline__ Ambient make_ambient(double n0r, double n0i, double st, double ct) {
-    Ambient a;
-    a.n0r = n0r;
-    a.n0i = n0i;
-    a.ok = (n0i == 0.0) || (st == 0.0);
-    a.kx = n0r * st;
-    a.q0r = n0r * ct;
-    a.q0i = n0i * ct;
-    const double ic = 1.0 / ct;
-    a.e0r = n0r * ic;
-    a.e0i = n0i * ic;
-    const double nn = n0r * n0r + n0i * n0i;
-    a.Ks = nn * ct / n0r;
-    a.Kp = nn * ic / n0r;
-    return a;
-}
-
-template <typename R>
-__device__ __forceinline__ void load_n(const R* nk, int dispersive, int n_wl, int64_t row, int i,
-                                       double& nr, double& ni) {
-    const int64_t idx = dispersive ? row * (int64_t)n_wl + i : row;
-    nr = (double)nk[2 * idx];
-    ni = (double)nk[2 * idx + 1];
-}
-
-// ---------------------------------------------------------------------------
 // Media table in LDS, structure-of-arrays, one entry per (material, lane).
 template <typename R> struct Table;
 
@@ -625,6 +591,32 @@ static tmm_status run_fwd(const tmm_rt_args* a, hipStream_t s) {
     return ok();
 }
 
+tmm_status check_rt_args(const tmm_rt_args* a, const char* who, bool need_output) {
+    if (!a) return fail(TMM_ERR_INVALID_ARG, "%s: args is NULL", who);
+    if (a->B < 0 || a->L < 0 || a->n_wl < 0 || a->n_theta < 0)
+        return fail(TMM_ERR_INVALID_ARG, "%s: negative size (B=%d L=%d n_wl=%d n_theta=%d)", who, a->B, a->L,
+                    a->n_wl, a->n_theta);
+    if (a->L > (1 << 20)) return fail(TMM_ERR_INVALID_ARG, "%s: L=%d exceeds 1<<20", who, a->L);
+    if (a->pol_mask < 1u || a->pol_mask > 3u)
+        return fail(TMM_ERR_INVALID_ARG, "%s: pol_mask must be 1 (s), 2 (p) or 3 (both), got %u", who, a->pol_mask);
+    if (a->dispersive != 0 && a->dispersive != 1)
+        return fail(TMM_ERR_INVALID_ARG, "%s: dispersive must be 0 or 1", who);
+    if (a->B == 0 || a->n_wl == 0 || a->n_theta == 0) return ok();  // nothing to compute
+    if (a->n_mat < 1) return fail(TMM_ERR_INVALID_ARG, "%s: n_mat must be >= 1", who);
+    if (!a->nk || !a->wl || !a->sin_theta || !a->cos_theta)
+        return fail(TMM_ERR_INVALID_ARG, "%s: nk, wl, sin_theta and cos_theta must be non-NULL", who);
+    if (a->L > 0 && !a->d) return fail(TMM_ERR_INVALID_ARG, "%s: d is NULL with L > 0", who);
+    if (!a->mat && (int64_t)a->n_mat < (int64_t)a->B * (a->L + 2))
+        return fail(TMM_ERR_INVALID_ARG, "%s: without mat, nk needs B*(L+2)=%lld rows, has %d", who,
+                    (long long)a->B * (a->L + 2), a->n_mat);
+    const int P = (a->pol_mask == 3u) ? 2 : 1;
+    const double elems = (double)a->B * P * (double)a->n_theta * (double)a->n_wl;
+    if (elems > 4.0e18) return fail(TMM_ERR_INVALID_ARG, "%s: output too large", who);
+    if (need_output && !a->R && !a->T && !a->r && !a->t)
+        return fail(TMM_ERR_INVALID_ARG, "%s: no output requested", who);
+    return ok();
+}
+
 char* last_error_buffer() {
     static thread_local char buf[512];
     return buf;
@@ -651,27 +643,10 @@ const char* tmm_version(void) { return "0.1.0"; }
 
 tmm_status tmm_rt(const tmm_rt_args* a, tmm_dtype dtype, void* stream) {
     using tmm::fail;
-    if (!a) return fail(TMM_ERR_INVALID_ARG, "tmm_rt: args is NULL");
+    tmm_status st = tmm::check_rt_args(a, "tmm_rt", true);
+    if (st != TMM_OK) return st;
     if (dtype != TMM_F64 && dtype != TMM_F32) return fail(TMM_ERR_INVALID_ARG, "tmm_rt: unknown dtype %d", (int)dtype);
-    if (a->B < 0 || a->L < 0 || a->n_wl < 0 || a->n_theta < 0)
-        return fail(TMM_ERR_INVALID_ARG, "tmm_rt: negative size (B=%d L=%d n_wl=%d n_theta=%d)", a->B, a->L,
-                    a->n_wl, a->n_theta);
-    if (a->L > (1 << 20)) return fail(TMM_ERR_INVALID_ARG, "tmm_rt: L=%d exceeds 1<<20", a->L);
-    if (a->pol_mask < 1u || a->pol_mask > 3u)
-        return fail(TMM_ERR_INVALID_ARG, "tmm_rt: pol_mask must be 1 (s), 2 (p) or 3 (both), got %u", a->pol_mask);
-    if (a->dispersive != 0 && a->dispersive != 1) return fail(TMM_ERR_INVALID_ARG, "tmm_rt: dispersive must be 0 or 1");
     if (a->B == 0 || a->n_wl == 0 || a->n_theta == 0) return tmm::ok();  // nothing to compute
-    if (a->n_mat < 1) return fail(TMM_ERR_INVALID_ARG, "tmm_rt: n_mat must be >= 1");
-    if (!a->nk || !a->wl || !a->sin_theta || !a->cos_theta)
-        return fail(TMM_ERR_INVALID_ARG, "tmm_rt: nk, wl, sin_theta and cos_theta must be non-NULL");
-    if (a->L > 0 && a->B > 0 && !a->d) return fail(TMM_ERR_INVALID_ARG, "tmm_rt: d is NULL with L > 0");
-    if (!a->mat && (int64_t)a->n_mat < (int64_t)a->B * (a->L + 2))
-        return fail(TMM_ERR_INVALID_ARG, "tmm_rt: without mat, nk needs B*(L+2)=%lld rows, has %d",
-                    (long long)a->B * (a->L + 2), a->n_mat);
-    const int P = (a->pol_mask == 3u) ? 2 : 1;
-    const double elems = (double)a->B * P * (double)a->n_theta * (double)a->n_wl;
-    if (elems > 4.0e18) return fail(TMM_ERR_INVALID_ARG, "tmm_rt: output too large");
-    if (!a->R && !a->T && !a->r && !a->t) return fail(TMM_ERR_INVALID_ARG, "tmm_rt: no output requested");
     hipStream_t s = static_cast<hipStream_t>(stream);
     return dtype == TMM_F64 ? tmm::run_fwd<double>(a, s) : tmm::run_fwd<float>(a, s);
 }

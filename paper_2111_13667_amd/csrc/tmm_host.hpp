@@ -35,4 +35,8 @@ inline tmm_status check_launch(const char* what) {
 
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+// Shared host checks of the tmm_rt_args fields (sizes, pointers, ranges);
+// need_output: at least one of R, T, r, t must be given.
+tmm_status check_rt_args(const tmm_rt_args* a, const char* who, bool need_output);
+
 }  // namespace tmm

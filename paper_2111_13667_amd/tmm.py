@@ -62,6 +62,11 @@ def library() -> ctypes.CDLL:
         lib.tmm_status_string.argtypes = [ctypes.c_int]
         lib.tmm_last_error.restype = ctypes.c_char_p
         lib.tmm_version.restype = ctypes.c_char_p
+        lib.tmm_rt_grad_workspace_size.restype = ctypes.c_size_t
+        lib.tmm_rt_grad_workspace_size.argtypes = [ctypes.POINTER(TmmRtArgs)]
+        lib.tmm_rt_grad.restype = ctypes.c_int
+        lib.tmm_rt_grad.argtypes = [ctypes.POINTER(TmmRtArgs)] + [ctypes.c_void_p] * 5 + \
+            [ctypes.c_size_t, ctypes.c_int, ctypes.c_void_p]
         _lib = lib
     return _lib
 
@@ -126,6 +131,56 @@ def tmm_rt(d, nk, wl, sin_theta, cos_theta, *, mat=None, n_mat=None, dispersive=
                   _ptr(mat), _ptr(wl), _ptr(sin_theta), _ptr(cos_theta), pol_mask,
                   _ptr(R), _ptr(T), _ptr(r), _ptr(t))
     _check(library().tmm_rt(ctypes.byref(a), dt, _stream_handle(stream)))
+
+
+def _rt_args(d, nk, wl, sin_theta, cos_theta, mat, n_mat, dispersive, pol_mask, R=None, T=None,
+             r=None, t=None):
+    B, L = d.shape
+    if dispersive is None:
+        dispersive = nk.dim() == 2
+    if n_mat is None:
+        n_mat = nk.shape[0]
+    return TmmRtArgs(B, L, wl.numel(), sin_theta.numel(), _ptr(d), _ptr(nk), n_mat, int(dispersive),
+                     _ptr(mat), _ptr(wl), _ptr(sin_theta), _ptr(cos_theta), pol_mask,
+                     _ptr(R), _ptr(T), _ptr(r), _ptr(t))
+
+
+def grad_workspace_size(d, nk, wl, sin_theta, cos_theta, *, mat=None, pol_mask=3) -> int:
+    a = _rt_args(d, nk, wl, sin_theta, cos_theta, mat, None, None, pol_mask)
+    return int(library().tmm_rt_grad_workspace_size(ctypes.byref(a)))
+
+
+def tmm_rt_grad(d, nk, wl, sin_theta, cos_theta, *, mat=None, n_mat=None, dispersive=None,
+                pol_mask: int = 3, dl_dR=None, dl_dT=None, grad_d=None, grad_n=None,
+                workspace=None, R=None, T=None, stream=None) -> None:
+    """Launch tmm_rt_grad (float64): gradients of sum(dl_dR * R + dl_dT * T) w.r.t.
+    d [B, L] into grad_d [B, L] and w.r.t. the finite layers' indices into
+    grad_n [B, L] complex128.  workspace: a uint8 device tensor of at least
+    grad_workspace_size(...) bytes (allocated here if None)."""
+    import torch
+    if d.dtype != torch.float64:
+        raise TypeError("tmm_rt_grad is float64 only")
+    for x in (d, nk, wl, sin_theta, cos_theta, mat, dl_dR, dl_dT, grad_d, grad_n, R, T):
+        if x is not None and (not x.is_cuda or not x.is_contiguous()):
+            raise ValueError("every tensor must be a contiguous device tensor")
+    B, L = d.shape
+    P = 2 if pol_mask == 3 else 1
+    shape = (B, P, sin_theta.numel(), wl.numel())
+    for name, x in (("dl_dR", dl_dR), ("dl_dT", dl_dT), ("R", R), ("T", T)):
+        if x is not None and (tuple(x.shape) != shape or x.dtype != torch.float64):
+            raise ValueError(f"{name} must be float64 {shape}")
+    if grad_d is not None and (tuple(grad_d.shape) != (B, L) or grad_d.dtype != torch.float64):
+        raise ValueError("grad_d must be float64 [B, L]")
+    if grad_n is not None and (tuple(grad_n.shape) != (B, L) or grad_n.dtype != torch.complex128):
+        raise ValueError("grad_n must be complex128 [B, L]")
+    a = _rt_args(d, nk, wl, sin_theta, cos_theta, mat, n_mat, dispersive, pol_mask, R, T)
+    lib = library()
+    need = int(lib.tmm_rt_grad_workspace_size(ctypes.byref(a)))
+    if workspace is None:
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=d.device)
+    _check(lib.tmm_rt_grad(ctypes.byref(a), _ptr(dl_dR), _ptr(dl_dT), _ptr(grad_d), _ptr(grad_n),
+                           _ptr(workspace), workspace.numel() * workspace.element_size(), TMM_F64,
+                           _stream_handle(stream)))
 
 
 # ---------------------------------------------------------------------------
@@ -207,3 +262,88 @@ def coh_tmm(pol: str, n, d, theta, wl, *, dtype="f64", amplitudes=True, device="
 def unpolarised(out):
     """(X_s + X_p) / 2 over the polarisation axis of a pol='both' result."""
     return {k: 0.5 * (v[:, 0] + v[:, 1]) for k, v in out.items() if k in ("R", "T")}
+
+
+# ---------------------------------------------------------------------------
+# Differentiable evaluation: forward through tmm_rt, backward through tmm_rt_grad.
+
+def _autograd_function():
+    import torch
+
+    class TMMFunction(torch.autograd.Function):
+        """R, T of B stacks with per-layer constant indices; differentiable w.r.t.
+        the thicknesses d [B, L] and the layer indices n [B, L] (complex).  The
+        ambient and substrate indices are constants."""
+
+        @staticmethod
+        def forward(ctx, d, n_layers, n_amb, n_sub, wl, sin_t, cos_t, pol_mask):
+            B, L = d.shape
+            nk = torch.cat([n_amb.reshape(1, 1).expand(B, 1), n_layers,
+                            n_sub.reshape(1, 1).expand(B, 1)], dim=1).reshape(-1).contiguous()
+            P = 2 if pol_mask == 3 else 1
+            shape = (B, P, sin_t.numel(), wl.numel())
+            R = torch.empty(shape, dtype=torch.float64, device=d.device)
+            T = torch.empty(shape, dtype=torch.float64, device=d.device)
+            d = d.contiguous()
+            tmm_rt(d, nk, wl, sin_t, cos_t, pol_mask=pol_mask, R=R, T=T)
+            ctx.save_for_backward(d, nk, wl, sin_t, cos_t)
+            ctx.pol_mask = pol_mask
+            return R, T
+
+        @staticmethod
+        def backward(ctx, gR, gT):
+            d, nk, wl, sin_t, cos_t = ctx.saved_tensors
+            B, L = d.shape
+            want_d, want_n = ctx.needs_input_grad[0], ctx.needs_input_grad[1]
+            gd = torch.empty((B, L), dtype=torch.float64, device=d.device)
+            gn = torch.empty((B, L), dtype=torch.complex128, device=d.device)
+            tmm_rt_grad(d, nk, wl, sin_t, cos_t, pol_mask=ctx.pol_mask,
+                        dl_dR=None if gR is None else gR.contiguous(),
+                        dl_dT=None if gT is None else gT.contiguous(),
+                        grad_d=gd, grad_n=gn)
+            return (gd if want_d else None, gn if want_n else None) + (None,) * 6
+
+    return TMMFunction
+
+
+_TMMFunction = None
+
+
+def rt_differentiable(d, n_layers, n_amb, n_sub, wl, sin_theta, cos_theta, pol: str = "both"):
+    """(R, T) as differentiable torch tensors [B, P, n_theta, n_wl] (float64).
+    d [B, L] float64 and n_layers [B, L] complex128 on the device (either may
+    require grad); n_amb, n_sub complex scalars; sin/cos of the angles in float64."""
+    import torch
+    global _TMMFunction
+    if _TMMFunction is None:
+        _TMMFunction = _autograd_function()
+    dev = d.device
+    as_c = lambda x: torch.as_tensor(x, dtype=torch.complex128, device=dev)
+    return _TMMFunction.apply(d, n_layers.to(torch.complex128), as_c(n_amb), as_c(n_sub),
+                              wl.contiguous(), sin_theta.contiguous(), cos_theta.contiguous(), POL[pol])
+
+
+def coh_tmm_torch(pol: str, n, d, theta, wl, device="cuda"):
+    """Paper-style differentiable call (App. A.3): n [L+2] or [N, L+2] indices,
+    d [L+2] or [N, L+2] thicknesses (the two semi-infinite slots are ignored; a
+    torch tensor with requires_grad gets gradients on its finite entries), theta
+    in rad, wl in the unit of d.  Returns {'R', 'T'} differentiable tensors."""
+    import torch
+    if not isinstance(d, torch.Tensor):
+        d = torch.as_tensor(np.asarray(d, dtype=np.float64))
+    d2 = d if d.dim() == 2 else d.unsqueeze(0)
+    N, M = d2.shape
+    d_fin = d2[:, 1:M - 1].to(device=device, dtype=torch.float64)
+    n_t = torch.as_tensor(n) if not isinstance(n, torch.Tensor) else n
+    n_t = n_t.to(device=device, dtype=torch.complex128)
+    if n_t.dim() == 1:
+        n_t = n_t.unsqueeze(0).expand(N, M)
+    theta = np.atleast_1d(np.asarray(theta, dtype=np.float64))
+    wl_t = torch.as_tensor(np.atleast_1d(np.asarray(wl, dtype=np.float64)), device=device)
+    s = torch.as_tensor(np.sin(theta), device=device)
+    c = torch.as_tensor(np.cos(theta), device=device)
+    # the semi-infinite media must be the same for every stack here
+    R, T = rt_differentiable(d_fin, n_t[:, 1:M - 1].contiguous(), n_t[0, 0], n_t[0, M - 1], wl_t, s, c, pol)
+    if pol != "both":
+        R, T = R[:, 0], T[:, 0]
+    return {"R": R, "T": T}

@@ -67,6 +67,13 @@ class Workload:
         rows = (idx[:, None] * L2 + np.arange(L2)[None, :]).ravel()
         return replace(self, d=d, nk=np.ascontiguousarray(self.nk[rows]))
 
+    def per_layer(self) -> "Workload":
+        """Same stacks with one index-table row per medium (row b*(L+2)+j, mat None)."""
+        if self.mat is None:
+            return self
+        nk = np.ascontiguousarray(self.nk[self.mat.ravel()])
+        return replace(self, nk=nk, mat=None)
+
     def rounded_f32(self) -> "Workload":
         """Every real input rounded to float32 and widened back to float64.
 
@@ -144,6 +151,30 @@ def large_batch(seed: int = 0, B: int = 4096, L: int = 40, n_wl: int = 1024,
     theta = np.deg2rad(np.arange(0, n_theta, dtype=np.float64))
     s, c = angles(theta)
     return Workload("large_batch_4096x40", d, nk, mat, wl, theta, s, c)
+
+
+def adjoint_batch(seed: int = 0, B: int = 1024, L: int = 60, n_wl: int = 512,
+                  n_theta: int = 31) -> Workload:
+    """Gradient workload: 1024 stacks x 60 alternating high/low layers (high first,
+    n_H = 2.35, n_L = 1.46, k = 0), d ~ U[30,200] nm, 512 wavelengths 400-800 nm x
+    31 angles 0-60 deg, ambient 1.0, substrate 1.52.  Table rows: 0 high, 1 low,
+    2 ambient, 3 substrate."""
+    rng = np.random.default_rng(seed)
+    d = rng.uniform(30.0, 200.0, (B, L))
+    nk = np.array([2.35, 1.46, 1.0, 1.52], dtype=np.complex128)
+    mat = np.empty((B, L + 2), dtype=np.int32)
+    mat[:, 0] = 2
+    mat[:, 1:L + 1] = np.arange(L) % 2
+    mat[:, L + 1] = 3
+    wl = np.linspace(400.0, 800.0, n_wl)
+    theta = np.deg2rad(np.linspace(0.0, 60.0, n_theta))
+    s, c = angles(theta)
+    return Workload("adjoint_batch_1024x60", d, nk, mat, wl, theta, s, c)
+
+
+def longpass_target(wl: np.ndarray, edge_nm: float = 600.0) -> np.ndarray:
+    """Target reflectance of the gradient workload: 1 below the edge, 0 above."""
+    return (np.asarray(wl) < edge_nm).astype(np.float64)
 
 
 def appendix_example(seed: int = 0, B: int = 1, n_media: int = 12, n_wl: int = 301,
