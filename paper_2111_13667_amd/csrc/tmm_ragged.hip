@@ -1,0 +1,486 @@
+// Ragged batches: stacks with different layer counts, wavelength grids and
+// angle grids in one persistent launch (gfx950), behind a plan object that
+// owns the work list, the autotuned launch shape and an optional HIP graph.
+//
+// Work unit = (stack, angle, tile of 64 wavelengths); one wave evaluates one
+// unit (both polarisations, one lane per wavelength) with the same recursion
+// as the dense kernel (tmm_chain.hpp).  Units are ordered by decreasing layer
+// count (longest chains first) and handed out through an atomic counter, so
+// the wave that finishes early takes the next unit: load balance does not
+// depend on how the stacks are mixed.  For every unit the wave computes
+// q, eta of each index-table row at its 64 wavelengths into its own LDS slice
+// (a handful of complex square roots per lane), then runs the layer loop on
+// table lookups.
+//
+// The plan keeps its own device copies of the offsets it was created with,
+// so the kernel never reads a caller's offset array.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <numeric>
+#include <tuple>
+#include <vector>
+
+#include "tmm_chain.hpp"
+#include "tmm_host.hpp"
+#include "tmm_ragged.h"
+
+namespace tmm {
+namespace ragged {
+
+constexpr int kThreads = 128;  // two waves: each wave's media table stays within 48 KiB of LDS per block
+constexpr int kWaves = kThreads / kWave;
+constexpr int kMaxMat = 8;
+
+template <typename R>
+struct Params {
+    int B;
+    const int64_t* layer_off;
+    const int64_t* wl_off;
+    const int64_t* th_off;
+    const int64_t* out_off;
+    const R* d;
+    const int32_t* mat;
+    const int32_t* ends;
+    const R* wl;
+    const R* sin_t;
+    const R* cos_t;
+    const R* nk;
+    int n_mat;
+    int64_t nk_stride;  // wl_off[B]
+    R* R_out;
+    R* T_out;
+    const int2* units;
+    int64_t n_units;
+    unsigned long long* counter;
+    int grain;
+};
+
+template <typename R>
+__device__ __forceinline__ size_t wave_table_bytes(int n_mat) {
+    return (size_t)n_mat * Table<R>::kBlockBytes;
+}
+
+__global__ void reset_counter(unsigned long long* c) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *c = 0ull;
+}
+
+template <typename R, int POL>
+__global__ void __launch_bounds__(kThreads) ragged_kernel(Params<R> p) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    Table<R> tab(smem + (size_t)wave * p.n_mat * Table<R>::kBlockBytes, p.n_mat);
+    constexpr int P = (POL == 3) ? 2 : 1;
+    for (;;) {
+        unsigned long long base = 0;
+        if (lane == 0) base = atomicAdd(p.counter, (unsigned long long)p.grain);
+        base = __shfl(base, 0, kWave);
+        if ((int64_t)base >= p.n_units) break;
+        for (int g = 0; g < p.grain; ++g) {
+            const int64_t u = (int64_t)base + g;
+            if (u >= p.n_units) break;
+            const int2 ud = p.units[u];
+            const int b = __builtin_amdgcn_readfirstlane(ud.x);
+            const int k = __builtin_amdgcn_readfirstlane(ud.y >> 16);
+            const int tile = __builtin_amdgcn_readfirstlane(ud.y & 0xffff);
+            const int64_t l0 = p.layer_off[b];
+            const int L = (int)(p.layer_off[b + 1] - l0);
+            const int64_t w0 = p.wl_off[b];
+            const int nwl = (int)(p.wl_off[b + 1] - w0);
+            const int64_t t0 = p.th_off[b];
+            const int nth = (int)(p.th_off[b + 1] - t0);
+            const int i_raw = tile * kWave + lane;
+            const bool active = i_raw < nwl;
+            const int i = active ? i_raw : nwl - 1;
+            const int64_t col = w0 + i;  // column of this lane's wavelength in nk
+            const double lam = (double)p.wl[col];
+            const bool lam_ok = lam > 0.0 && lam < __builtin_inf();
+            const double c4lam = 4.0 / lam;
+            const double st = (double)p.sin_t[t0 + k], ct = (double)p.cos_t[t0 + k];
+            int a_row = p.ends[2 * b], s_row = p.ends[2 * b + 1];
+            bool bad = (uint32_t)a_row >= (uint32_t)p.n_mat || (uint32_t)s_row >= (uint32_t)p.n_mat;
+            a_row = min(max(a_row, 0), p.n_mat - 1);
+            s_row = min(max(s_row, 0), p.n_mat - 1);
+            const Ambient amb = make_ambient((double)p.nk[2 * ((int64_t)a_row * p.nk_stride + col)],
+                                             (double)p.nk[2 * ((int64_t)a_row * p.nk_stride + col) + 1], st, ct);
+            // this unit's media table: every row at this lane's wavelength
+            uint32_t lossy_mask = 0;
+            for (int m = 0; m < p.n_mat; ++m) {
+                const int64_t e = (int64_t)m * p.nk_stride + col;
+                const Medium md = make_medium((double)p.nk[2 * e], (double)p.nk[2 * e + 1], amb.kx);
+                tab.put(m, lane, md);
+                if (__any(md.qi != 0.0)) lossy_mask |= 1u << m;
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            const R* drow = p.d + l0;
+            const int32_t* mrow = p.mat + l0;
+            const Layer<R> sub = tab.get(s_row, lane);
+            Layer<R> nxt = sub;
+            Chain<R, POL, false> c;
+            c.init();
+            int cnt = 0;
+            for (int j = L; j >= 1; --j) {
+                const R dj = drow[j - 1];
+                int m = mrow[j - 1];
+                bad = bad || bad_thickness(dj) || (uint32_t)m >= (uint32_t)p.n_mat;
+                m = min(max(m, 0), p.n_mat - 1);
+                const Layer<R> cur = tab.get(m, lane);
+                c.step(cur, nxt, (double)dj * c4lam, (lossy_mask >> m) & 1u);
+                nxt = cur;
+                if (++cnt == RenormPeriod<R>::value) {
+                    cnt = 0;
+                    c.renorm();
+                }
+            }
+            c.renorm();
+            PointOut out[2];
+            finish<R, POL, false>(c, amb, nxt, sub, 0.0, 0.0, L, out);
+            if (active) {
+                const bool valid = lam_ok && amb.ok && !bad;
+                const double nan = __builtin_nan("");
+                for (int q = 0; q < P; ++q) {
+                    const int64_t o = p.out_off[b] + ((int64_t)q * nth + k) * nwl + i;
+                    if (p.R_out) p.R_out[o] = (R)(valid ? out[q].R : nan);
+                    if (p.T_out) p.T_out[o] = (R)(valid ? out[q].T : nan);
+                }
+            }
+            // the next unit rewrites this wave's table slice
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+    }
+}
+
+// Launch shape chosen by the autotuner.
+struct Shape {
+    int blocks_per_cu;
+    int grain;
+};
+
+// Autotune cache: (dtype, pol, mean-layer bucket, unit-count bucket) -> shape.
+std::mutex g_tune_mutex;
+std::map<std::tuple<int, int, int, int>, Shape> g_tune_cache;
+
+}  // namespace ragged
+}  // namespace tmm
+
+struct tmm_ragged_plan {
+    int B;
+    uint32_t pol_mask;
+    int P;
+    std::vector<int64_t> layer_off, wl_off, th_off, out_off;
+    int64_t n_units;
+    int64_t out_size;
+    int64_t*d_layer_off, *d_wl_off, *d_th_off, *d_out_off;
+    int2* d_units;
+    unsigned long long* d_counter;
+    int n_cu;
+    bool tuned[2];
+    tmm::ragged::Shape shape[2];  // per dtype
+    hipGraph_t graph;
+    hipGraphExec_t graph_exec;
+    int mean_layers;
+};
+
+namespace {
+
+using tmm::fail;
+using tmm::ok;
+
+template <typename R>
+tmm::ragged::Params<R> make_params(const tmm_ragged_plan* pl, const tmm_ragged_data* a) {
+    tmm::ragged::Params<R> p;
+    p.B = pl->B;
+    p.layer_off = pl->d_layer_off;
+    p.wl_off = pl->d_wl_off;
+    p.th_off = pl->d_th_off;
+    p.out_off = pl->d_out_off;
+    p.d = static_cast<const R*>(a->d);
+    p.mat = a->mat;
+    p.ends = a->ends;
+    p.wl = static_cast<const R*>(a->wl);
+    p.sin_t = static_cast<const R*>(a->sin_theta);
+    p.cos_t = static_cast<const R*>(a->cos_theta);
+    p.nk = static_cast<const R*>(a->nk);
+    p.n_mat = a->n_mat;
+    p.nk_stride = pl->wl_off[pl->B];
+    p.R_out = static_cast<R*>(a->R);
+    p.T_out = static_cast<R*>(a->T);
+    p.units = pl->d_units;
+    p.n_units = pl->n_units;
+    p.counter = pl->d_counter;
+    p.grain = 1;
+    return p;
+}
+
+template <typename R>
+hipError_t launch(const tmm_ragged_plan* pl, tmm::ragged::Params<R> p, tmm::ragged::Shape sh, hipStream_t s) {
+    p.grain = sh.grain;
+    const size_t lds = (size_t)tmm::ragged::kWaves * p.n_mat * tmm::Table<R>::kBlockBytes;
+    const int blocks = pl->n_cu * sh.blocks_per_cu;
+    hipLaunchKernelGGL(tmm::ragged::reset_counter, dim3(1), dim3(64), 0, s, pl->d_counter);
+    if (pl->pol_mask == 1u)
+        hipLaunchKernelGGL((tmm::ragged::ragged_kernel<R, 1>), dim3(blocks), dim3(tmm::ragged::kThreads), lds, s, p);
+    else if (pl->pol_mask == 2u)
+        hipLaunchKernelGGL((tmm::ragged::ragged_kernel<R, 2>), dim3(blocks), dim3(tmm::ragged::kThreads), lds, s, p);
+    else
+        hipLaunchKernelGGL((tmm::ragged::ragged_kernel<R, 3>), dim3(blocks), dim3(tmm::ragged::kThreads), lds, s, p);
+    return hipGetLastError();
+}
+
+// Times every candidate shape on the real data (each run produces the full,
+// valid output) and keeps the fastest; the result is cached per
+// (dtype, pol, layer bucket, unit bucket) for later plans.
+template <typename R>
+tmm_status tune(tmm_ragged_plan* pl, const tmm::ragged::Params<R>& p, int di, hipStream_t s) {
+    const int lb = pl->mean_layers / 16;
+    int ub = 0;
+    for (int64_t u = pl->n_units; u > 1; u >>= 2) ++ub;
+    const auto key = std::make_tuple(di, (int)pl->pol_mask, lb, ub);
+    {
+        std::lock_guard<std::mutex> g(tmm::ragged::g_tune_mutex);
+        auto it = tmm::ragged::g_tune_cache.find(key);
+        if (it != tmm::ragged::g_tune_cache.end()) {
+            pl->shape[di] = it->second;
+            pl->tuned[di] = true;
+            return ok();
+        }
+    }
+    const int bpc[] = {2, 4, 8};
+    const int grains[] = {1, 4};
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return fail(TMM_ERR_HIP, "tmm_ragged_run: event creation failed");
+    float best = 1e30f;
+    tmm::ragged::Shape best_sh = {4, 1};
+    for (int b : bpc) {
+        for (int g : grains) {
+            const tmm::ragged::Shape sh = {b, g};
+            hipEventRecord(e0, s);
+            if (launch<R>(pl, p, sh, s) != hipSuccess) {
+                hipEventDestroy(e0);
+                hipEventDestroy(e1);
+                return fail(TMM_ERR_HIP, "tmm_ragged_run: launch failed while tuning");
+            }
+            hipEventRecord(e1, s);
+            if (hipEventSynchronize(e1) != hipSuccess) {
+                hipEventDestroy(e0);
+                hipEventDestroy(e1);
+                return fail(TMM_ERR_HIP, "tmm_ragged_run: kernel failed while tuning");
+            }
+            float ms = 0.0f;
+            hipEventElapsedTime(&ms, e0, e1);
+            if (ms < best) {
+                best = ms;
+                best_sh = sh;
+            }
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    pl->shape[di] = best_sh;
+    pl->tuned[di] = true;
+    std::lock_guard<std::mutex> g(tmm::ragged::g_tune_mutex);
+    tmm::ragged::g_tune_cache[key] = best_sh;
+    return ok();
+}
+
+tmm_status check_data(const tmm_ragged_plan* pl, const tmm_ragged_data* a, tmm_dtype dt, const char* who) {
+    if (!pl || !a) return fail(TMM_ERR_INVALID_ARG, "%s: NULL argument", who);
+    if (dt != TMM_F64 && dt != TMM_F32) return fail(TMM_ERR_INVALID_ARG, "%s: unknown dtype", who);
+    if (a->n_mat < 1) return fail(TMM_ERR_INVALID_ARG, "%s: n_mat must be >= 1", who);
+    if (a->n_mat > tmm::ragged::kMaxMat)
+        return fail(TMM_ERR_UNSUPPORTED, "%s: at most %d index-table rows are supported", who, tmm::ragged::kMaxMat);
+    if (!a->R && !a->T) return fail(TMM_ERR_INVALID_ARG, "%s: no output requested", who);
+    if (pl->B > 0 && (!a->ends || !a->wl || !a->sin_theta || !a->cos_theta || !a->nk))
+        return fail(TMM_ERR_INVALID_ARG, "%s: ends, wl, sin_theta, cos_theta and nk must be non-NULL", who);
+    if (pl->layer_off[pl->B] > 0 && (!a->d || !a->mat))
+        return fail(TMM_ERR_INVALID_ARG, "%s: d and mat must be non-NULL", who);
+    return ok();
+}
+
+}  // namespace
+
+extern "C" {
+
+tmm_status tmm_ragged_plan_create(int32_t B, const int64_t* layer_off, const int64_t* wl_off, const int64_t* th_off,
+                                  uint32_t pol_mask, tmm_ragged_plan** out) {
+    if (!out) return fail(TMM_ERR_INVALID_ARG, "tmm_ragged_plan_create: out is NULL");
+    *out = nullptr;
+    if (B < 0 || !layer_off || !wl_off || !th_off)
+        return fail(TMM_ERR_INVALID_ARG, "tmm_ragged_plan_create: B >= 0 and host offset arrays required");
+    if (pol_mask < 1u || pol_mask > 3u) return fail(TMM_ERR_INVALID_ARG, "tmm_ragged_plan_create: bad pol_mask");
+    if (layer_off[0] != 0 || wl_off[0] != 0 || th_off[0] != 0)
+        return fail(TMM_ERR_INVALID_ARG, "tmm_ragged_plan_create: offsets must start at 0");
+    const int P = pol_mask == 3u ? 2 : 1;
+    std::vector<int64_t> oo(B + 1, 0);
+    std::vector<int> order(B);
+    int64_t n_units = 0;
+    for (int b = 0; b < B; ++b) {
+        const int64_t L = layer_off[b + 1] - layer_off[b];
+        const int64_t nw = wl_off[b + 1] - wl_off[b];
+        const int64_t nt = th_off[b + 1] - th_off[b];
+        if (L < 0 || L > (1 << 20) || nw < 1 || nt < 1 || nw > 64 * 65535 || nt > 32767)
+            return fail(TMM_ERR_INVALID_ARG,
+                        "tmm_ragged_plan_create: stack %d has L=%lld, n_wl=%lld, n_theta=%lld (need 0 <= L <= 2^20, "
+                        "1 <= n_wl <= 4194240, 1 <= n_theta <= 32767)", b, (long long)L, (long long)nw, (long long)nt);
+        oo[b + 1] = oo[b] + P * nt * nw;
+        n_units += nt * ((nw + 63) / 64);
+        order[b] = b;
+    }
+    if (wl_off[B] > ((int64_t)1 << 40)) return fail(TMM_ERR_INVALID_ARG, "tmm_ragged_plan_create: too many wavelengths");
+    // longest chains first; ties keep the input order
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+        return layer_off[x + 1] - layer_off[x] > layer_off[y + 1] - layer_off[y];
+    });
+    std::vector<int2> units;
+    units.reserve((size_t)n_units);
+    for (int b : order) {
+        const int nw = (int)(wl_off[b + 1] - wl_off[b]);
+        const int nt = (int)(th_off[b + 1] - th_off[b]);
+        const int tiles = (nw + 63) / 64;
+        for (int k = 0; k < nt; ++k)
+            for (int t = 0; t < tiles; ++t) units.push_back(make_int2(b, (k << 16) | t));
+    }
+    tmm_ragged_plan* pl = new tmm_ragged_plan();
+    pl->B = B;
+    pl->pol_mask = pol_mask;
+    pl->P = P;
+    pl->layer_off.assign(layer_off, layer_off + B + 1);
+    pl->wl_off.assign(wl_off, wl_off + B + 1);
+    pl->th_off.assign(th_off, th_off + B + 1);
+    pl->out_off = oo;
+    pl->n_units = n_units;
+    pl->out_size = oo[B];
+    pl->tuned[0] = pl->tuned[1] = false;
+    pl->graph = nullptr;
+    pl->graph_exec = nullptr;
+    pl->d_layer_off = pl->d_wl_off = pl->d_th_off = pl->d_out_off = nullptr;
+    pl->d_units = nullptr;
+    pl->d_counter = nullptr;
+    pl->mean_layers = B > 0 ? (int)(layer_off[B] / B) : 0;
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+        delete pl;
+        return fail(TMM_ERR_HIP, "tmm_ragged_plan_create: no device");
+    }
+    pl->n_cu = prop.multiProcessorCount;
+    const size_t nb = (size_t)(B + 1) * sizeof(int64_t);
+    bool okk = hipMalloc((void**)&pl->d_layer_off, nb) == hipSuccess && hipMalloc((void**)&pl->d_wl_off, nb) == hipSuccess &&
+               hipMalloc((void**)&pl->d_th_off, nb) == hipSuccess && hipMalloc((void**)&pl->d_out_off, nb) == hipSuccess &&
+               hipMalloc((void**)&pl->d_units, std::max<size_t>(1, units.size()) * sizeof(int2)) == hipSuccess &&
+               hipMalloc((void**)&pl->d_counter, sizeof(unsigned long long)) == hipSuccess;
+    okk = okk && hipMemcpy(pl->d_layer_off, layer_off, nb, hipMemcpyHostToDevice) == hipSuccess &&
+          hipMemcpy(pl->d_wl_off, wl_off, nb, hipMemcpyHostToDevice) == hipSuccess &&
+          hipMemcpy(pl->d_th_off, th_off, nb, hipMemcpyHostToDevice) == hipSuccess &&
+          hipMemcpy(pl->d_out_off, oo.data(), nb, hipMemcpyHostToDevice) == hipSuccess &&
+          (units.empty() ||
+           hipMemcpy(pl->d_units, units.data(), units.size() * sizeof(int2), hipMemcpyHostToDevice) == hipSuccess);
+    if (!okk) {
+        tmm_ragged_plan_destroy(pl);
+        return fail(TMM_ERR_HIP, "tmm_ragged_plan_create: device allocation or copy failed");
+    }
+    *out = pl;
+    return ok();
+}
+
+tmm_status tmm_ragged_plan_destroy(tmm_ragged_plan* pl) {
+    if (!pl) return ok();
+    (void)hipDeviceSynchronize();
+    if (pl->graph_exec) (void)hipGraphExecDestroy(pl->graph_exec);
+    if (pl->graph) (void)hipGraphDestroy(pl->graph);
+    void* ptrs[] = {pl->d_layer_off, pl->d_wl_off, pl->d_th_off, pl->d_out_off, pl->d_units, pl->d_counter};
+    for (void* p : ptrs)
+        if (p) (void)hipFree(p);
+    delete pl;
+    return ok();
+}
+
+int64_t tmm_ragged_plan_output_size(const tmm_ragged_plan* pl) { return pl ? pl->out_size : -1; }
+
+tmm_status tmm_ragged_plan_output_offsets(const tmm_ragged_plan* pl, int64_t* host_out_off) {
+    if (!pl || !host_out_off) return fail(TMM_ERR_INVALID_ARG, "tmm_ragged_plan_output_offsets: NULL argument");
+    memcpy(host_out_off, pl->out_off.data(), (size_t)(pl->B + 1) * sizeof(int64_t));
+    return ok();
+}
+
+tmm_status tmm_ragged_run(tmm_ragged_plan* pl, const tmm_ragged_data* a, tmm_dtype dtype, void* stream) {
+    tmm_status st = check_data(pl, a, dtype, "tmm_ragged_run");
+    if (st != TMM_OK) return st;
+    if (pl->n_units == 0) return ok();
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int di = dtype == TMM_F64 ? 0 : 1;
+    (void)hipGetLastError();
+    if (dtype == TMM_F64) {
+        const auto p = make_params<double>(pl, a);
+        if (!pl->tuned[di]) return tune<double>(pl, p, di, s);
+        if (launch<double>(pl, p, pl->shape[di], s) != hipSuccess) return tmm::check_launch("tmm_ragged_run");
+    } else {
+        const auto p = make_params<float>(pl, a);
+        if (!pl->tuned[di]) return tune<float>(pl, p, di, s);
+        if (launch<float>(pl, p, pl->shape[di], s) != hipSuccess) return tmm::check_launch("tmm_ragged_run");
+    }
+    return tmm::check_launch("tmm_ragged_run");
+}
+
+tmm_status tmm_ragged_capture(tmm_ragged_plan* pl, const tmm_ragged_data* a, tmm_dtype dtype, void* stream) {
+    tmm_status st = check_data(pl, a, dtype, "tmm_ragged_capture");
+    if (st != TMM_OK) return st;
+    if (!stream) return fail(TMM_ERR_INVALID_ARG, "tmm_ragged_capture: needs a non-default stream");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int di = dtype == TMM_F64 ? 0 : 1;
+    if (!pl->tuned[di]) {
+        st = tmm_ragged_run(pl, a, dtype, stream);  // tunes (and computes the outputs once)
+        if (st != TMM_OK) return st;
+        if (hipStreamSynchronize(s) != hipSuccess) return fail(TMM_ERR_HIP, "tmm_ragged_capture: sync failed");
+    }
+    if (pl->graph_exec) {
+        (void)hipGraphExecDestroy(pl->graph_exec);
+        pl->graph_exec = nullptr;
+    }
+    if (pl->graph) {
+        (void)hipGraphDestroy(pl->graph);
+        pl->graph = nullptr;
+    }
+    if (pl->n_units == 0) return ok();
+    (void)hipGetLastError();
+    if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess)
+        return fail(TMM_ERR_HIP, "tmm_ragged_capture: begin capture failed");
+    hipError_t e;
+    if (dtype == TMM_F64)
+        e = launch<double>(pl, make_params<double>(pl, a), pl->shape[di], s);
+    else
+        e = launch<float>(pl, make_params<float>(pl, a), pl->shape[di], s);
+    hipGraph_t g = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(s, &g);
+    if (e != hipSuccess || e2 != hipSuccess || !g) {
+        if (g) (void)hipGraphDestroy(g);
+        return fail(TMM_ERR_HIP, "tmm_ragged_capture: capture failed");
+    }
+    if (hipGraphInstantiate(&pl->graph_exec, g, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return fail(TMM_ERR_HIP, "tmm_ragged_capture: instantiate failed");
+    }
+    pl->graph = g;
+    return ok();
+}
+
+tmm_status tmm_ragged_replay(tmm_ragged_plan* pl, void* stream) {
+    if (!pl) return fail(TMM_ERR_INVALID_ARG, "tmm_ragged_replay: plan is NULL");
+    if (pl->n_units == 0) return ok();
+    if (!pl->graph_exec) return fail(TMM_ERR_INVALID_ARG, "tmm_ragged_replay: nothing captured");
+    if (hipGraphLaunch(pl->graph_exec, static_cast<hipStream_t>(stream)) != hipSuccess)
+        return fail(TMM_ERR_HIP, "tmm_ragged_replay: graph launch failed");
+    return ok();
+}
+
+}  // extern "C"

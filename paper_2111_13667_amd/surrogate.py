@@ -1,0 +1,381 @@
+"""ctypes binding of the learned surrogate (include/tmm_surrogate.h) and the
+training / calibration driver around it.
+
+Argument marshalling and orchestration only: data generation runs in tmm_rt,
+every forward, backward and optimiser step in the library's HIP kernels.
+"""
+from __future__ import annotations
+
+import ctypes
+import json
+import time
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import tmm, workloads
+
+
+class SurrogateConfig(ctypes.Structure):
+    _fields_ = [
+        ("n_in", ctypes.c_int32), ("n_hidden", ctypes.c_int32), ("n_layers", ctypes.c_int32),
+        ("n_out", ctypes.c_int32), ("n_members", ctypes.c_int32), ("max_batch", ctypes.c_int32),
+        ("seed", ctypes.c_uint64),
+        ("in_shift", ctypes.c_float), ("in_scale", ctypes.c_float),
+        ("lr", ctypes.c_float), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float),
+        ("eps", ctypes.c_float), ("weight_decay", ctypes.c_float),
+    ]
+
+
+_bound = False
+
+
+def _lib():
+    global _bound
+    lib = tmm.library()
+    if not _bound:
+        P = ctypes.c_void_p
+        lib.tmm_surrogate_create.restype = ctypes.c_int
+        lib.tmm_surrogate_create.argtypes = [ctypes.POINTER(SurrogateConfig), ctypes.POINTER(P)]
+        lib.tmm_surrogate_destroy.restype = ctypes.c_int
+        lib.tmm_surrogate_destroy.argtypes = [P]
+        lib.tmm_surrogate_param_count.restype = ctypes.c_size_t
+        lib.tmm_surrogate_param_count.argtypes = [P]
+        lib.tmm_surrogate_export.restype = ctypes.c_int
+        lib.tmm_surrogate_export.argtypes = [P, P, ctypes.c_size_t]
+        lib.tmm_surrogate_import.restype = ctypes.c_int
+        lib.tmm_surrogate_import.argtypes = [P, P, ctypes.c_size_t]
+        lib.tmm_surrogate_train_step.restype = ctypes.c_int
+        lib.tmm_surrogate_train_step.argtypes = [P, P, P, ctypes.c_int32, ctypes.c_float, P, P]
+        lib.tmm_surrogate_gradients.restype = ctypes.c_int
+        lib.tmm_surrogate_gradients.argtypes = [P, P, P, ctypes.c_int32, P, P]
+        lib.tmm_surrogate_predict.restype = ctypes.c_int
+        lib.tmm_surrogate_predict.argtypes = [P, P, ctypes.c_int32, P, P, P, P]
+        lib.tmm_surrogate_predict_fallback.restype = ctypes.c_int
+        lib.tmm_surrogate_predict_fallback.argtypes = [P, P, ctypes.c_int32, ctypes.POINTER(tmm.TmmRtArgs),
+                                                       ctypes.c_float, ctypes.c_float, P,
+                                                       ctypes.POINTER(ctypes.c_int32), P]
+        _bound = True
+    return lib
+
+
+def _p(x):
+    return None if x is None else x.data_ptr()
+
+
+class Surrogate:
+    """Ensemble MLP surrogate living in device memory (one handle)."""
+
+    def __init__(self, n_in, n_out, *, n_hidden=1024, n_layers=5, n_members=5, max_batch=4096, seed=0,
+                 in_shift=0.0, in_scale=1.0, beta1=0.9, beta2=0.999, eps=1e-8, weight_decay=0.0):
+        self.cfg = SurrogateConfig(n_in, n_hidden, n_layers, n_out, n_members, max_batch, seed,
+                                   in_shift, in_scale, 0.0, beta1, beta2, eps, weight_decay)
+        h = ctypes.c_void_p()
+        tmm._check(_lib().tmm_surrogate_create(ctypes.byref(self.cfg), ctypes.byref(h)))
+        self.h = h
+        self.n_in, self.n_out, self.E = n_in, n_out, n_members
+
+    def close(self):
+        if self.h:
+            _lib().tmm_surrogate_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def param_count(self) -> int:
+        return int(_lib().tmm_surrogate_param_count(self.h))
+
+    def export(self) -> np.ndarray:
+        buf = np.empty(self.param_count * self.E, dtype=np.float32)
+        tmm._check(_lib().tmm_surrogate_export(self.h, buf.ctypes.data, buf.size))
+        return buf.reshape(self.E, self.param_count)
+
+    def load(self, params: np.ndarray):
+        buf = np.ascontiguousarray(params, dtype=np.float32).ravel()
+        tmm._check(_lib().tmm_surrogate_import(self.h, buf.ctypes.data, buf.size))
+
+    def _check_xy(self, x, y=None):
+        import torch
+        for name, t, cols in (("x", x, self.n_in), ("y", y, self.n_out)):
+            if t is None:
+                continue
+            if t.dim() != 2 or t.shape[1] != cols or t.dtype != torch.float32 or not t.is_contiguous() \
+                    or not t.is_cuda:
+                raise ValueError(f"{name} must be a contiguous float32 device tensor [B, {cols}]")
+        if y is not None and y.shape[0] != x.shape[0]:
+            raise ValueError("x and y differ in batch size")
+
+    def train_step(self, x, y, lr, loss=None):
+        self._check_xy(x, y)
+        import torch
+        if loss is not None and (loss.numel() < self.E or loss.dtype != torch.float32 or not loss.is_cuda):
+            raise ValueError("loss must be a device float32 tensor with one entry per member")
+        tmm._check(_lib().tmm_surrogate_train_step(self.h, _p(x), _p(y), x.shape[0], lr, _p(loss),
+                                                   tmm._stream_handle(None)))
+
+    def gradients(self, x, y):
+        import torch
+        self._check_xy(x, y)
+        g = torch.empty((self.E, self.param_count), dtype=torch.float32, device=x.device)
+        tmm._check(_lib().tmm_surrogate_gradients(self.h, _p(x), _p(y), x.shape[0], _p(g),
+                                                  tmm._stream_handle(None)))
+        return g
+
+    def predict(self, x, *, sigma=True, members=False):
+        import torch
+        self._check_xy(x)
+        B = x.shape[0]
+        mean = torch.empty((B, self.n_out), dtype=torch.float32, device=x.device)
+        sig = torch.empty_like(mean) if sigma else None
+        mem = torch.empty((self.E, B, self.n_out), dtype=torch.float32, device=x.device) if members else None
+        tmm._check(_lib().tmm_surrogate_predict(self.h, _p(x), B, _p(mean), _p(sig), _p(mem),
+                                                tmm._stream_handle(None)))
+        return mean, sig, mem
+
+    def predict_fallback(self, x, task: "Task", err_scale: float, bound: float):
+        """Surrogate with transfer-matrix fallback for the stacks x [B, n_in] of task."""
+        import torch
+        self._check_xy(x)
+        if task.n_out != self.n_out or task.n_layers != self.n_in or task.wl.dtype != torch.float32:
+            raise ValueError("task does not match the surrogate (layers, outputs, float32 grids)")
+        tmpl = task.args(x.shape[0])
+        out = torch.empty((x.shape[0], self.n_out), dtype=torch.float32, device=x.device)
+        nf = ctypes.c_int32(0)
+        tmm._check(_lib().tmm_surrogate_predict_fallback(self.h, _p(x), x.shape[0], ctypes.byref(tmpl),
+                                                         err_scale, bound, _p(out), ctypes.byref(nf),
+                                                         tmm._stream_handle(None)))
+        return out, int(nf.value)
+
+
+# ---------------------------------------------------------------------------
+# The thin-film surrogate task: 30 alternating Cauchy layers -> R over 256 wl x 16 angles x 2 pol.
+
+@dataclass
+class Task:
+    """Device tensors describing the fixed part of the stacks (materials, grids)."""
+    n_layers: int
+    nk: object
+    mat_row: object      # [1, L+2] int32, the material sequence of every stack
+    wl: object
+    sin_t: object
+    cos_t: object
+    n_wl: int
+    n_theta: int
+
+    @property
+    def n_out(self):
+        return 2 * self.n_theta * self.n_wl
+
+    def mat(self, B):
+        """Material ids [B, L+2] (a contiguous device tensor with exactly B rows)."""
+        cache = self.__dict__.setdefault("_mat_cache", {})
+        if B not in cache:
+            cache.clear()
+            cache[B] = self.mat_row.expand(B, self.n_layers + 2).contiguous()
+        return cache[B]
+
+    def args(self, B, d=None, R=None):
+        """tmm_rt arguments for B stacks (d [B, L] thicknesses, R output); the
+        material-id array it points to has exactly B rows."""
+        mat = self.mat(B)
+        return tmm.TmmRtArgs(B, self.n_layers, self.n_wl, self.n_theta, tmm._ptr(d), tmm._ptr(self.nk),
+                             self.nk.shape[0], int(self.nk.dim() == 2), tmm._ptr(mat),
+                             tmm._ptr(self.wl), tmm._ptr(self.sin_t), tmm._ptr(self.cos_t), 3,
+                             tmm._ptr(R), None, None, None)
+
+
+def make_task(dtype="f32", device="cuda", L=30, n_wl=256, n_theta=16):
+    """The surrogate workload's fixed part (default: 30 alternating layers, 256 wl x 16 angles)."""
+    import torch
+    w = workloads.surrogate_batch(B=1, L=L, n_wl=n_wl, n_theta=n_theta)
+    real = torch.float32 if dtype == "f32" else torch.float64
+    cplx = torch.complex64 if dtype == "f32" else torch.complex128
+    mat_row = torch.as_tensor(w.mat[:1], dtype=torch.int32, device=device)
+    return Task(w.L, torch.as_tensor(w.nk, dtype=cplx, device=device), mat_row,
+                torch.as_tensor(w.wl, dtype=real, device=device),
+                torch.as_tensor(w.sin_t, dtype=real, device=device),
+                torch.as_tensor(w.cos_t, dtype=real, device=device), w.wl.size, w.theta.size)
+
+
+def generate(task: Task, d, chunk=65536):
+    """R spectra [B, n_out] of the stacks with thicknesses d [B, L] (device), by
+    tmm_rt in the task's real type."""
+    import torch
+    real = task.wl.dtype
+    B = d.shape[0]
+    out = torch.empty((B, task.n_out), dtype=real, device=d.device)
+    for b0 in range(0, B, chunk):
+        b1 = min(B, b0 + chunk)
+        dd = d[b0:b1].to(real).contiguous()
+        tmm.tmm_rt(dd, task.nk, task.wl, task.sin_t, task.cos_t, mat=task.mat(b1 - b0), pol_mask=3,
+                   R=out[b0:b1].view(b1 - b0, 2, task.n_theta, task.n_wl))
+    return out
+
+
+def calibrate(mean, sigma, truth, bound):
+    """err_scale such that accepting the stacks with err_scale * max sigma <= bound
+    keeps max |mean - truth| <= bound on this set; returns (err_scale, accepted fraction)."""
+    import torch
+    s = sigma.max(dim=1).values.double().cpu().numpy()
+    e = (mean - truth).abs().max(dim=1).values.double().cpu().numpy()
+    order = np.argsort(s, kind="stable")
+    bad = e[order] > bound
+    first_bad = int(np.argmax(bad)) if bad.any() else len(order)
+    if first_bad == 0:
+        return float("inf"), 0.0
+    tau = s[order[first_bad - 1]]
+    if first_bad < len(order):
+        tau = min(tau, np.nextafter(s[order[first_bad]], 0))
+    scale = bound / tau if tau > 0 else float("inf")
+    return float(scale), first_bad / len(order)
+
+
+def train(sur: Surrogate, x, y, *, epochs, batch, lr_max=1e-3, lr_min=1e-5, seed=0, log_every=0):
+    """Adam over shuffled mini-batches with a cosine learning-rate schedule.
+    Returns the per-epoch mean training loss of member 0."""
+    import torch
+    N = x.shape[0]
+    steps_per_epoch = N // batch
+    total = epochs * steps_per_epoch
+    loss = torch.zeros(sur.E, dtype=torch.float32, device=x.device)
+    g = torch.Generator(device="cpu")
+    g.manual_seed(seed)
+    hist = []
+    step = 0
+    for ep in range(epochs):
+        perm = torch.randperm(N, generator=g).to(x.device)
+        acc = torch.zeros(sur.E, dtype=torch.float64, device=x.device)
+        for k in range(steps_per_epoch):
+            idx = perm[k * batch:(k + 1) * batch]
+            xb = x.index_select(0, idx)
+            yb = y.index_select(0, idx)
+            lr = lr_min + 0.5 * (lr_max - lr_min) * (1 + np.cos(np.pi * step / max(1, total)))
+            sur.train_step(xb, yb, float(lr), loss)
+            acc += loss.double()
+            step += 1
+        hist.append((acc / steps_per_epoch).cpu().numpy().tolist())
+        if log_every and (ep + 1) % log_every == 0:
+            print(json.dumps({"epoch": ep + 1, "loss": hist[-1]}), flush=True)
+    return hist
+
+
+# ---------------------------------------------------------------------------
+# End-to-end driver: data from tmm_rt, training, calibration, throughput.
+
+def _timeit(fn, reps=3):
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(reps):
+        fn()
+    ev1.record()
+    torch.cuda.synchronize()
+    return ev0.elapsed_time(ev1) / reps / 1e3
+
+
+def run(n_train=2_000_000, n_cal=50_000, n_test=50_000, epochs=10, batch=4096, hidden=1024, layers=5,
+        members=5, lr_max=1e-3, lr_min=1e-5, eval_batch=65536, bound=1e-3, seed=0, log=print):
+    """Train the surrogate on tmm_rt data and report accuracy and throughput."""
+    import torch
+    dev = "cuda"
+    report = {"config": dict(n_train=n_train, n_cal=n_cal, n_test=n_test, epochs=epochs, batch=batch,
+                             hidden=hidden, layers=layers, members=members, bound=bound)}
+    task = make_task("f32")
+    task64 = make_task("f64")
+    g = torch.Generator(device=dev)
+    g.manual_seed(seed)
+    N = n_train + n_cal + n_test
+    d = (20.0 + 230.0 * torch.rand((N, task.n_layers), generator=g, device=dev, dtype=torch.float32)).contiguous()
+    t0 = time.perf_counter()
+    y = generate(task, d)
+    torch.cuda.synchronize()
+    report["datagen_s"] = time.perf_counter() - t0
+    log(json.dumps({"stage": "data", "stacks": N, "seconds": round(report["datagen_s"], 3)}))
+    xtr, ytr = d[:n_train], y[:n_train]
+    xcal, ycal = d[n_train:n_train + n_cal], y[n_train:n_train + n_cal]
+    xte, yte = d[n_train + n_cal:], y[n_train + n_cal:]
+    sur = Surrogate(task.n_layers, task.n_out, n_hidden=hidden, n_layers=layers, n_members=members,
+                    max_batch=max(batch, 4096), seed=seed + 1, in_shift=135.0, in_scale=1.0 / 66.4)
+    t0 = time.perf_counter()
+    hist = train(sur, xtr, ytr, epochs=epochs, batch=batch, lr_max=lr_max, lr_min=lr_min, seed=seed,
+                 log_every=1)
+    torch.cuda.synchronize()
+    report["train_s"] = time.perf_counter() - t0
+    report["loss_per_epoch"] = [h[0] for h in hist]
+    steps = epochs * (n_train // batch)
+    flop_step = 3 * 2 * batch * members * sum(i * o for i, o in zip(
+        [128] + [hidden] * layers, [hidden] * layers + [task.n_out]))
+    report["train_tflops"] = flop_step * steps / report["train_s"] / 1e12
+    log(json.dumps({"stage": "train", "seconds": round(report["train_s"], 2),
+                    "TFLOP/s": round(report["train_tflops"], 1)}))
+    # accuracy on held-out stacks
+    mean, sigma, _ = sur.predict(xte)
+    err = (mean - yte).abs()
+    base = (ytr[:100000].mean(0, keepdim=True) - yte).abs()
+    report["test_mae"] = err.mean().item()
+    report["test_rmse"] = err.pow(2).mean().sqrt().item()
+    report["test_max_abs"] = err.max().item()
+    report["baseline_mean_spectrum_mae"] = base.mean().item()
+    mcal, scal, _ = sur.predict(xcal)
+    scale, frac_cal = calibrate(mcal, scal, ycal, bound)
+    report["err_scale"] = scale
+    report["accepted_fraction_cal"] = frac_cal
+    out, nf = sur.predict_fallback(xte, task, scale, bound)
+    y64 = generate(task64, xte.double())
+    report["fallback_fraction_test"] = nf / n_test
+    report["max_abs_after_fallback_vs_f64"] = (out.double() - y64).abs().max().item()
+    log(json.dumps({"stage": "accuracy", **{k: report[k] for k in (
+        "test_mae", "test_rmse", "test_max_abs", "baseline_mean_spectrum_mae", "accepted_fraction_cal",
+        "fallback_fraction_test", "max_abs_after_fallback_vs_f64")}}))
+    # throughput on one batch of eval_batch stacks
+    xb = xte[:eval_batch] if n_test >= eval_batch else d[:eval_batch]
+    B = xb.shape[0]
+    Rf = torch.empty((B, task.n_out), dtype=torch.float32, device=dev)
+    Rd = torch.empty((B, task.n_out), dtype=torch.float64, device=dev)
+    x64 = xb.double().contiguous()
+    t_tmm32 = _timeit(lambda: tmm.tmm_rt(xb, task.nk, task.wl, task.sin_t, task.cos_t, mat=task.mat(B),
+                                         R=Rf.view(B, 2, task.n_theta, task.n_wl)))
+    t_tmm64 = _timeit(lambda: tmm.tmm_rt(x64, task64.nk, task64.wl, task64.sin_t, task64.cos_t,
+                                         mat=task64.mat(B), R=Rd.view(B, 2, task.n_theta, task.n_wl)))
+    t_pred = _timeit(lambda: sur.predict(xb))
+    nfs = []
+    t_fb = _timeit(lambda: nfs.append(sur.predict_fallback(xb, task, scale, bound)[1]))
+    report["throughput_stacks_per_s"] = {"tmm_f32": B / t_tmm32, "tmm_f64": B / t_tmm64,
+                                         "surrogate_only": B / t_pred, "surrogate_fallback": B / t_fb}
+    report["fallback_fraction_eval_batch"] = nfs[-1] / B
+    report["gain_vs_tmm_f32"] = t_tmm32 / t_fb
+    report["gain_vs_tmm_f64"] = t_tmm64 / t_fb
+    log(json.dumps({"stage": "throughput", **report["throughput_stacks_per_s"],
+                    "gain_vs_tmm_f32": report["gain_vs_tmm_f32"], "gain_vs_tmm_f64": report["gain_vs_tmm_f64"]}))
+    sur.close()
+    return report
+
+
+if __name__ == "__main__":
+    import argparse
+    ap = argparse.ArgumentParser(description="train and evaluate the surrogate on tmm_rt data")
+    ap.add_argument("--n-train", type=int, default=2_000_000)
+    ap.add_argument("--n-cal", type=int, default=50_000)
+    ap.add_argument("--n-test", type=int, default=50_000)
+    ap.add_argument("--epochs", type=int, default=10)
+    ap.add_argument("--batch", type=int, default=4096)
+    ap.add_argument("--hidden", type=int, default=1024)
+    ap.add_argument("--layers", type=int, default=5)
+    ap.add_argument("--members", type=int, default=5)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--bound", type=float, default=1e-3)
+    ap.add_argument("--out", default=None)
+    a = ap.parse_args()
+    rep = run(n_train=a.n_train, n_cal=a.n_cal, n_test=a.n_test, epochs=a.epochs, batch=a.batch, hidden=a.hidden,
+              layers=a.layers, members=a.members, lr_max=a.lr, bound=a.bound)
+    print(json.dumps(rep), flush=True)
+    if a.out:
+        with open(a.out, "w") as f:
+            json.dump(rep, f, indent=1)

@@ -118,10 +118,9 @@ def tmm_rt(d, nk, wl, sin_theta, cos_theta, *, mat=None, n_mat=None, dispersive=
     if mat is not None and mat.dtype != torch.int32:
         raise TypeError("mat must be int32")
     B, L = d.shape
+    n_mat = _check_shapes(d, nk, wl, sin_theta, cos_theta, mat, n_mat, dispersive)
     if dispersive is None:
         dispersive = nk.dim() == 2
-    if n_mat is None:
-        n_mat = nk.shape[0]
     P = 2 if pol_mask == 3 else 1
     shape = (B, P, sin_theta.numel(), wl.numel())
     for name, x in (("R", R), ("T", T), ("r", r), ("t", t)):
@@ -131,6 +130,36 @@ def tmm_rt(d, nk, wl, sin_theta, cos_theta, *, mat=None, n_mat=None, dispersive=
                   _ptr(mat), _ptr(wl), _ptr(sin_theta), _ptr(cos_theta), pol_mask,
                   _ptr(R), _ptr(T), _ptr(r), _ptr(t))
     _check(library().tmm_rt(ctypes.byref(a), dt, _stream_handle(stream)))
+
+
+def _check_shapes(d, nk, wl, sin_theta, cos_theta, mat, n_mat, dispersive) -> int:
+    """Host-side size checks of the device tensors (the C library cannot see
+    tensor sizes): every array must hold what the kernels will read.  Returns
+    the number of index-table rows."""
+    if d.dim() != 2:
+        raise ValueError("d must be [B, L]")
+    B, L = d.shape
+    if sin_theta.dim() != 1 or cos_theta.dim() != 1 or sin_theta.numel() != cos_theta.numel():
+        raise ValueError("sin_theta and cos_theta must be 1-D of equal length")
+    if wl.dim() != 1:
+        raise ValueError("wl must be 1-D")
+    if dispersive is None:
+        dispersive = nk.dim() == 2
+    if dispersive and (nk.dim() != 2 or nk.shape[1] != wl.numel()):
+        raise ValueError("a dispersive nk must be [n_mat, n_wl]")
+    if not dispersive and nk.dim() != 1:
+        raise ValueError("a constant nk must be [n_mat]")
+    rows = nk.shape[0]
+    if n_mat is None:
+        n_mat = rows
+    if n_mat > rows:
+        raise ValueError(f"n_mat={n_mat} exceeds the {rows} rows of nk")
+    if mat is not None:
+        if tuple(mat.shape) != (B, L + 2):
+            raise ValueError(f"mat must be [B, L+2] = {(B, L + 2)}, got {tuple(mat.shape)}")
+    elif n_mat < B * (L + 2):
+        raise ValueError(f"without mat, nk needs B*(L+2) = {B * (L + 2)} rows")
+    return n_mat
 
 
 def _rt_args(d, nk, wl, sin_theta, cos_theta, mat, n_mat, dispersive, pol_mask, R=None, T=None,
@@ -146,6 +175,7 @@ def _rt_args(d, nk, wl, sin_theta, cos_theta, mat, n_mat, dispersive, pol_mask, 
 
 
 def grad_workspace_size(d, nk, wl, sin_theta, cos_theta, *, mat=None, pol_mask=3) -> int:
+    _check_shapes(d, nk, wl, sin_theta, cos_theta, mat, None, None)
     a = _rt_args(d, nk, wl, sin_theta, cos_theta, mat, None, None, pol_mask)
     return int(library().tmm_rt_grad_workspace_size(ctypes.byref(a)))
 
@@ -173,6 +203,11 @@ def tmm_rt_grad(d, nk, wl, sin_theta, cos_theta, *, mat=None, n_mat=None, disper
         raise ValueError("grad_d must be float64 [B, L]")
     if grad_n is not None and (tuple(grad_n.shape) != (B, L) or grad_n.dtype != torch.complex128):
         raise ValueError("grad_n must be complex128 [B, L]")
+    if mat is not None and mat.dtype != torch.int32:
+        raise TypeError("mat must be int32")
+    if nk.dtype != torch.complex128:
+        raise TypeError("nk must be complex128")
+    n_mat = _check_shapes(d, nk, wl, sin_theta, cos_theta, mat, n_mat, dispersive)
     a = _rt_args(d, nk, wl, sin_theta, cos_theta, mat, n_mat, dispersive, pol_mask, R, T)
     lib = library()
     need = int(lib.tmm_rt_grad_workspace_size(ctypes.byref(a)))

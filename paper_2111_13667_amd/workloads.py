@@ -177,6 +177,108 @@ def longpass_target(wl: np.ndarray, edge_nm: float = 600.0) -> np.ndarray:
     return (np.asarray(wl) < edge_nm).astype(np.float64)
 
 
+def surrogate_batch(seed: int = 0, B: int = 65536, L: int = 30, n_wl: int = 256,
+                    n_theta: int = 16) -> Workload:
+    """Surrogate workload: B stacks of 30 layers, d ~ U[20,250] nm, fixed
+    alternating Cauchy materials (high first: A = 2.3, B = 0.02 um^2; low:
+    A = 1.45, B = 0.004 um^2; lossless), 256 wavelengths 400-900 nm x 16 angles
+    0-60 deg, ambient 1.0, substrate 1.52.  Table rows: 0 high, 1 low,
+    2 ambient, 3 substrate."""
+    rng = np.random.default_rng(seed)
+    d = rng.uniform(20.0, 250.0, (B, L))
+    wl = np.linspace(400.0, 900.0, n_wl)
+    nk = np.empty((4, n_wl), dtype=np.complex128)
+    nk[:2] = cauchy([2.3, 1.45], [0.02, 0.004], [0.0, 0.0], wl)
+    nk[2] = 1.0
+    nk[3] = 1.52
+    mat = np.empty((B, L + 2), dtype=np.int32)
+    mat[:, 0] = 2
+    mat[:, 1:L + 1] = np.arange(L) % 2
+    mat[:, L + 1] = 3
+    theta = np.deg2rad(np.linspace(0.0, 60.0, n_theta))
+    s, c = angles(theta)
+    return Workload("surrogate_batch_30", d, nk, mat, wl, theta, s, c)
+
+
+@dataclass
+class RaggedWorkload:
+    """Stacks with their own layer counts and grids, packed flat (CSR style).
+
+    Stack b: finite layers layer_off[b]..layer_off[b+1]-1 of d and mat,
+    wavelengths wl_off[b]..wl_off[b+1]-1 of wl, angles th_off[b]..th_off[b+1]-1
+    of theta / sin_t / cos_t; ends[b] = (ambient row, substrate row); nk
+    [n_mat, wl_off[B]] holds every material at every stack's wavelengths.
+    """
+    name: str
+    layer_off: np.ndarray
+    wl_off: np.ndarray
+    th_off: np.ndarray
+    d: np.ndarray
+    mat: np.ndarray
+    ends: np.ndarray
+    wl: np.ndarray
+    theta: np.ndarray
+    sin_t: np.ndarray
+    cos_t: np.ndarray
+    nk: np.ndarray
+
+    @property
+    def B(self) -> int:
+        return len(self.layer_off) - 1
+
+    @property
+    def n_points(self) -> int:
+        nw = np.diff(self.wl_off)
+        nt = np.diff(self.th_off)
+        return int(2 * (nw * nt).sum())
+
+    def stack(self, b: int) -> Workload:
+        """Stack b as a dense one-stack workload (for the oracle)."""
+        l0, l1 = self.layer_off[b], self.layer_off[b + 1]
+        w0, w1 = self.wl_off[b], self.wl_off[b + 1]
+        t0, t1 = self.th_off[b], self.th_off[b + 1]
+        L = int(l1 - l0)
+        mat = np.empty((1, L + 2), dtype=np.int32)
+        mat[0, 0] = self.ends[b, 0]
+        mat[0, 1:L + 1] = self.mat[l0:l1]
+        mat[0, L + 1] = self.ends[b, 1]
+        return Workload(f"{self.name}[{b}]", self.d[None, l0:l1].copy(), np.ascontiguousarray(self.nk[:, w0:w1]),
+                        mat, self.wl[w0:w1].copy(), self.theta[t0:t1].copy(), self.sin_t[t0:t1].copy(),
+                        self.cos_t[t0:t1].copy())
+
+
+def ragged_batch(seed: int = 0, B: int = 8192, L_range=(2, 100), wl_range=(256, 2048), th_range=(1, 64),
+                 wl_span=(350.0, 1100.0), th_max_deg=80.0) -> RaggedWorkload:
+    """Ragged batch: layer counts ~ integers in L_range (inclusive), per-stack
+    wavelength counts in wl_range over linspace(350, 1100 nm) and angle counts in
+    th_range over linspace(0, 80 deg) (one angle means normal incidence); the
+    4-material Cauchy pool of large_batch (rows 0-3) plus ambient 1.0 (row 4) and
+    substrate 1.52 (row 5); d ~ U[20,250] nm; material ids uniform over the pool.
+    Draw order: layer counts, wavelength counts, angle counts, A, B, thicknesses,
+    material ids."""
+    rng = np.random.default_rng(seed)
+    Ls = rng.integers(L_range[0], L_range[1] + 1, B)
+    nws = rng.integers(wl_range[0], wl_range[1] + 1, B)
+    nts = rng.integers(th_range[0], th_range[1] + 1, B)
+    A = rng.uniform(1.4, 2.4, 4)
+    Bc = rng.uniform(0.003, 0.03, 4)
+    k = np.array([0.0, 1e-3, 0.0, 1e-3])
+    layer_off = np.concatenate([[0], np.cumsum(Ls)]).astype(np.int64)
+    wl_off = np.concatenate([[0], np.cumsum(nws)]).astype(np.int64)
+    th_off = np.concatenate([[0], np.cumsum(nts)]).astype(np.int64)
+    d = rng.uniform(20.0, 250.0, int(layer_off[-1]))
+    mat = rng.integers(0, 4, int(layer_off[-1])).astype(np.int32)
+    wl = np.concatenate([np.linspace(wl_span[0], wl_span[1], n) for n in nws])
+    theta = np.concatenate([np.deg2rad(np.linspace(0.0, th_max_deg, n)) if n > 1 else np.zeros(1) for n in nts])
+    s, c = angles(theta)
+    nk = np.empty((6, wl.size), dtype=np.complex128)
+    nk[:4] = cauchy(A, Bc, k, wl)
+    nk[4] = 1.0
+    nk[5] = 1.52
+    ends = np.tile(np.array([[4, 5]], dtype=np.int32), (B, 1))
+    return RaggedWorkload(f"ragged_batch_{B}", layer_off, wl_off, th_off, d, mat, ends, wl, theta, s, c, nk)
+
+
 def appendix_example(seed: int = 0, B: int = 1, n_media: int = 12, n_wl: int = 301,
                      n_theta: int = 301) -> Workload:
     """Shape of the paper's appendix TMM-Fast example: 12 media including the two

@@ -90,3 +90,18 @@ def test_empty_batch_is_a_no_op():
     for kw in (dict(B=0), dict(n_wl=0), dict(n_theta=0)):
         a = args(**kw)
         assert lib.tmm_rt(ctypes.byref(a), tmm.TMM_F64, None) == tmm.TMM_OK
+
+
+def test_ragged_plan_rejects_bad_offsets_on_host():
+    from paper_2111_13667_amd import ragged
+    import numpy as np
+    bad = [
+        (np.array([1, 3]), np.array([0, 5]), np.array([0, 1])),      # does not start at 0
+        (np.array([0, -1]), np.array([0, 5]), np.array([0, 1])),     # negative layer count
+        (np.array([0, 3]), np.array([0, 0]), np.array([0, 1])),      # no wavelength
+        (np.array([0, 3]), np.array([0, 5]), np.array([0, 0])),      # no angle
+    ]
+    for lo, wo, to in bad:
+        with pytest.raises(tmm.TmmError) as e:
+            ragged.RaggedPlan(lo, wo, to)
+        assert e.value.status == tmm.TMM_ERR_INVALID_ARG

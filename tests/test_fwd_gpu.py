@@ -228,3 +228,18 @@ def test_paper_style_call():
     out = tmm.coh_tmm("s", n, d, th, wl)
     ref = oracle.rt(d[None, 1:-1], n.astype(complex), wl, np.sin(th), np.cos(th), pol="s")
     assert np.abs(out["R"].cpu().numpy() - ref["R"][:, 0]).max() <= TOL64
+
+
+def test_binding_rejects_arrays_smaller_than_the_batch():
+    # The C interface cannot see device array sizes; the binding checks them
+    # before any launch (here: 3 rows of material ids for 5 stacks).
+    from paper_2111_13667_amd import tmm
+    w = workloads.large_batch(B=5, L=4, n_wl=8, n_theta=2)
+    dev = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device="cuda")
+    R = torch.empty((5, 2, 2, 8), dtype=torch.float64, device="cuda")
+    with pytest.raises(ValueError):
+        tmm.tmm_rt(dev(w.d, torch.float64), dev(w.nk, torch.complex128), dev(w.wl, torch.float64),
+                   dev(w.sin_t, torch.float64), dev(w.cos_t, torch.float64), mat=dev(w.mat[:3], torch.int32), R=R)
+    with pytest.raises(ValueError):
+        tmm.tmm_rt(dev(w.d, torch.float64), dev(w.nk[:, :4], torch.complex128), dev(w.wl, torch.float64),
+                   dev(w.sin_t, torch.float64), dev(w.cos_t, torch.float64), mat=dev(w.mat, torch.int32), R=R)

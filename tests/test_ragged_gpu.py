@@ -1,0 +1,107 @@
+"""Ragged batches (one persistent launch) against the oracle, stack by stack;
+autotuning, HIP-graph replay and invalid inputs."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2111_13667_amd import workloads
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def run(rw, dtype="f64", pol="both"):
+    from paper_2111_13667_amd import ragged
+    plan = ragged.RaggedPlan(rw.layer_off, rw.wl_off, rw.th_off, pol=pol)
+    dev = ragged.to_device(rw, dtype)
+    real = dev[3].dtype
+    R = torch.empty(plan.output_size, dtype=real, device="cuda")
+    T = torch.empty(plan.output_size, dtype=real, device="cuda")
+    plan.run(*dev, R=R, T=T)
+    torch.cuda.synchronize()
+    return plan, dev, R, T
+
+
+def check_stacks(rw, plan, R, T, stacks, dtype="f64", pol="both"):
+    off = plan.output_offsets()
+    Rh, Th = R.cpu().numpy().astype(np.float64), T.cpu().numpy().astype(np.float64)
+    tol = 1e-12 if dtype == "f64" else 2e-5
+    for b in stacks:
+        w = rw.stack(b)
+        if dtype == "f32":
+            w = w.rounded_f32()
+        ref = oracle.rt(w.d, w.nk, w.wl, w.sin_t, w.cos_t, mat=w.mat, pol=pol, want_amplitudes=False)
+        shape = ref["R"].shape[1:]
+        got_R = Rh[off[b]:off[b + 1]].reshape(shape)
+        got_T = Th[off[b]:off[b + 1]].reshape(shape)
+        assert np.abs(got_R - ref["R"][0]).max() <= tol, (b, np.abs(got_R - ref["R"][0]).max())
+        assert np.abs(got_T - ref["T"][0]).max() <= tol, b
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_small_ragged_batch_every_stack(dtype):
+    rw = workloads.ragged_batch(seed=3, B=37, L_range=(0, 12), wl_range=(1, 150), th_range=(1, 5))
+    plan, _, R, T = run(rw, dtype)
+    check_stacks(rw, plan, R, T, range(rw.B), dtype)
+
+
+@pytest.mark.parametrize("pol", ["s", "p"])
+def test_single_polarisation(pol):
+    rw = workloads.ragged_batch(seed=4, B=9, L_range=(1, 20), wl_range=(30, 100), th_range=(1, 4))
+    plan, _, R, T = run(rw, "f64", pol)
+    check_stacks(rw, plan, R, T, range(rw.B), "f64", pol)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_full_ragged_batch_sampled_stacks(dtype):
+    # 8192 stacks, 2-100 layers, 256-2048 wavelengths, 1-64 angles (6.1e8 points),
+    # checked on 12 seeded random stacks plus the longest and the shortest.
+    rw = workloads.ragged_batch()
+    plan, _, R, T = run(rw, dtype)
+    L = np.diff(rw.layer_off)
+    rng = np.random.default_rng(7)
+    stacks = list(rng.choice(rw.B, 12, replace=False)) + [int(L.argmax()), int(L.argmin())]
+    assert np.isfinite(R.cpu().numpy()).all()
+    check_stacks(rw, plan, R, T, stacks, dtype)
+
+
+def test_graph_replay_matches_eager_every_time():
+    rw = workloads.ragged_batch(seed=5, B=300, L_range=(2, 30), wl_range=(64, 300), th_range=(1, 8))
+    from paper_2111_13667_amd import ragged
+    plan, dev, R0, T0 = run(rw)
+    R = torch.empty_like(R0)
+    T = torch.empty_like(T0)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        plan.capture(*dev, R=R, T=T, stream=s)
+    s.synchronize()
+    for rep in range(3):
+        R.zero_()
+        T.fill_(-1.0)
+        torch.cuda.synchronize()
+        plan.replay(stream=s)
+        s.synchronize()
+        assert torch.equal(R, R0) and torch.equal(T, T0), rep
+        x = torch.randn(1000, device="cuda").sum()  # eager work between replays
+        torch.cuda.synchronize()
+
+
+def test_second_run_reuses_tuned_shape_and_is_identical():
+    rw = workloads.ragged_batch(seed=6, B=64, L_range=(5, 40), wl_range=(100, 400), th_range=(1, 6))
+    plan, dev, R1, T1 = run(rw)
+    R2, T2 = torch.empty_like(R1), torch.empty_like(T1)
+    plan.run(*dev, R=R2, T=T2)
+    torch.cuda.synchronize()
+    assert torch.equal(R1, R2) and torch.equal(T1, T2)
+
+
+def test_invalid_material_row_is_nan_for_that_stack_only():
+    rw = workloads.ragged_batch(seed=8, B=6, L_range=(3, 6), wl_range=(10, 70), th_range=(1, 3))
+    rw.mat[rw.layer_off[2]] = 17
+    rw.ends[4, 1] = -1
+    plan, _, R, T = run(rw)
+    off = plan.output_offsets()
+    Rh = R.cpu().numpy()
+    for b in range(rw.B):
+        seg = Rh[off[b]:off[b + 1]]
+        assert np.isnan(seg).all() if b in (2, 4) else np.isfinite(seg).all(), b

@@ -1,0 +1,123 @@
+"""GPU checks of the surrogate's BF16 MFMA kernels against the float64 MLP
+reference (which rounds to bfloat16 at the same points), of its training, and
+of the transfer-matrix fallback."""
+import numpy as np
+import pytest
+
+from oracle import mlp
+from paper_2111_13667_amd import workloads
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+SHIFT, SCALE = 135.0, 1.0 / 66.4   # U[20, 250] -> roughly zero mean, unit variance
+
+
+def small(n_hidden=256, n_layers=2, n_out=256, E=2, max_batch=256, seed=3):
+    from paper_2111_13667_amd.surrogate import Surrogate
+    return Surrogate(30, n_out, n_hidden=n_hidden, n_layers=n_layers, n_members=E, max_batch=max_batch,
+                     seed=seed, in_shift=SHIFT, in_scale=SCALE)
+
+
+def test_forward_matches_reference_every_member():
+    sur = small()
+    rng = np.random.default_rng(0)
+    x = rng.uniform(20, 250, (200, 30)).astype(np.float32)   # ragged: 200 of 256 rows
+    params = sur.export()
+    mean, sig, mem = sur.predict(torch.as_tensor(x, device="cuda"), members=True)
+    mem = mem.cpu().numpy()
+    dims = mlp.layer_dims(30, 256, 2, 256)
+    ys = []
+    for e in range(sur.E):
+        y, _ = mlp.forward(params[e].astype(np.float64), x.astype(np.float64), dims, SHIFT, SCALE)
+        ys.append(y)
+        scale = np.abs(y).max()
+        assert np.abs(mem[e] - y).max() <= 2e-3 * scale, (e, np.abs(mem[e] - y).max(), scale)
+    ys = np.array(ys)
+    assert np.abs(mean.cpu().numpy() - ys.mean(0)).max() <= 2e-3 * np.abs(ys).max()
+    assert np.abs(sig.cpu().numpy() - ys.std(0, ddof=1)).max() <= 4e-3 * np.abs(ys).max()
+    sur.close()
+
+
+def test_gradients_match_reference():
+    sur = small(E=2)
+    rng = np.random.default_rng(1)
+    x = rng.uniform(20, 250, (256, 30)).astype(np.float32)
+    t = rng.uniform(0, 1, (256, 256)).astype(np.float32)
+    g = sur.gradients(torch.as_tensor(x, device="cuda"), torch.as_tensor(t, device="cuda")).cpu().numpy()
+    params = sur.export()
+    dims = mlp.layer_dims(30, 256, 2, 256)
+    for e in range(sur.E):
+        ref = mlp.backward(params[e].astype(np.float64), x.astype(np.float64), t.astype(np.float64), dims,
+                           SHIFT, SCALE)
+        # compare layer by layer (weights and biases)
+        o = 0
+        for i, out in zip(*dims):
+            a, b = g[e][o:o + i * out], ref[o:o + i * out]
+            assert np.linalg.norm(a - b) <= 1e-2 * np.linalg.norm(b), (e, i, out)
+            o += i * out
+        a, b = g[e][o:], ref[o:]
+        assert np.linalg.norm(a - b) <= 1e-2 * np.linalg.norm(b)
+    sur.close()
+
+
+def test_export_import_roundtrip_and_determinism():
+    sur = small()
+    p = sur.export()
+    x = torch.as_tensor(np.random.default_rng(2).uniform(20, 250, (128, 30)).astype(np.float32), device="cuda")
+    m1, _, _ = sur.predict(x)
+    sur.load(p * 0.5)
+    m2, _, _ = sur.predict(x)
+    sur.load(p)
+    m3, _, _ = sur.predict(x)
+    assert np.array_equal(m1.cpu().numpy(), m3.cpu().numpy())
+    assert not np.allclose(m1.cpu().numpy(), m2.cpu().numpy())
+    sur.close()
+
+
+def test_training_gains_over_the_mean_spectrum():
+    # A low-dimensional instance of the surrogate task (4 alternating layers,
+    # 64 wavelengths x 4 angles x 2 pol), trained by the project's kernels on
+    # tmm_rt data: the network must beat the method without it -- the mean
+    # spectrum of the training set -- on held-out stacks by a wide margin.
+    from paper_2111_13667_amd import surrogate as S
+    task = S.make_task(L=4, n_wl=64, n_theta=4)
+    rng = np.random.default_rng(0)
+    n_train, n_test = 32768, 4096
+    d = torch.as_tensor(rng.uniform(20, 250, (n_train + n_test, 4)), dtype=torch.float32, device="cuda")
+    y = S.generate(task, d)
+    sur = S.Surrogate(4, task.n_out, n_hidden=256, n_layers=3, n_members=2, max_batch=1024, seed=1,
+                      in_shift=SHIFT, in_scale=SCALE)
+    hist = S.train(sur, d[:n_train], y[:n_train], epochs=40, batch=1024, lr_max=2e-3)
+    mean, _, _ = sur.predict(d[n_train:])
+    err_net = (mean - y[n_train:]).abs().mean().item()
+    err_base = (y[:n_train].mean(0, keepdim=True) - y[n_train:]).abs().mean().item()
+    print("held-out mean |error|: network", err_net, "mean spectrum", err_base, "loss", hist[0][0], hist[-1][0])
+    assert hist[-1][0] < 0.2 * hist[0][0]
+    assert err_net < 0.3 * err_base, (err_net, err_base)
+    sur.close()
+
+
+def test_fallback_keeps_the_bound():
+    # 30-layer task, untrained ensemble: calibration on a set, then on the same
+    # set max |out - tmm| <= bound; err_scale = inf recomputes every stack
+    # (exactly the float32 TMM values), err_scale = 0 none (exactly the mean).
+    from paper_2111_13667_amd import surrogate as S
+    task = S.make_task()
+    rng = np.random.default_rng(3)
+    n = 1500  # not a multiple of the internal batch
+    x = torch.as_tensor(rng.uniform(20, 250, (n, 30)), dtype=torch.float32, device="cuda")
+    y = S.generate(task, x)
+    sur = S.Surrogate(30, task.n_out, n_hidden=256, n_layers=2, n_members=3, max_batch=512, seed=2,
+                      in_shift=SHIFT, in_scale=SCALE)
+    mean, sigma, _ = sur.predict(x)
+    bound = 1e-3
+    scale, frac = S.calibrate(mean, sigma, y, bound)
+    out, nf = sur.predict_fallback(x, task, scale, bound)
+    assert nf == n - int(round(frac * n))
+    assert (out - y).abs().max().item() <= bound
+    out_all, nf_all = sur.predict_fallback(x, task, float("inf"), bound)
+    assert nf_all == n and torch.equal(out_all, y)
+    out_none, nf_none = sur.predict_fallback(x, task, 0.0, bound)
+    assert nf_none == 0 and torch.equal(out_none, mean)
+    sur.close()
