@@ -85,6 +85,73 @@ def time_gpu(w, dtype: str, steps: int, warmup: int, amplitudes: bool = False):
     return kernel_ms, wall, out_bytes
 
 
+def _event_time(fn, steps, warmup, stream=None):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    stream = stream or torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def time_grad(steps=3):
+    """Adjoint gradients on the 1024 x 60-layer batch (512 wl x 31 angles, s+p):
+    dl/dd and dl/dn of an MSE against a long-pass target, float64."""
+    import torch
+    from paper_2111_13667_amd import tmm, workloads
+    w = workloads.adjoint_batch()
+    dev = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device="cuda")
+    d, nk, mat = dev(w.d, torch.float64), dev(w.nk, torch.complex128), dev(w.mat, torch.int32)
+    wl, s, c = dev(w.wl, torch.float64), dev(w.sin_t, torch.float64), dev(w.cos_t, torch.float64)
+    shape = (w.B, 2, w.theta.size, w.wl.size)
+    R = torch.empty(shape, dtype=torch.float64, device="cuda")
+    tmm.tmm_rt(d, nk, wl, s, c, mat=mat, R=R)
+    gR = 2.0 * (R - dev(workloads.longpass_target(w.wl), torch.float64)) / R.numel()
+    gd = torch.empty((w.B, w.L), dtype=torch.float64, device="cuda")
+    gn = torch.empty((w.B, w.L), dtype=torch.complex128, device="cuda")
+    ws = torch.empty(tmm.grad_workspace_size(d, nk, wl, s, c, mat=mat), dtype=torch.uint8, device="cuda")
+    ms = _event_time(lambda: tmm.tmm_rt_grad(d, nk, wl, s, c, mat=mat, dl_dR=gR, grad_d=gd, grad_n=gn,
+                                             workspace=ws), steps, 1)
+    fwd_ms = _event_time(lambda: tmm.tmm_rt(d, nk, wl, s, c, mat=mat, R=R), steps, 1)
+    return {"workload": "adjoint_batch: 1024 stacks x 60 layers, 512 wl x 31 angles, s+p, float64",
+            "points": w.n_points, "grad_ms": round(ms, 3), "forward_ms": round(fwd_ms, 3),
+            "grad_points_per_s": round(w.n_points / (ms * 1e-3), 1), "grad_over_forward": round(ms / fwd_ms, 2),
+            "workspace_MB": round(ws.numel() / 1e6, 1)}
+
+
+def time_ragged(dtype="f64", steps=3):
+    """Ragged batch: 8192 stacks, 2-100 layers, 256-2048 wl, 1-64 angles, s+p, R and T,
+    one persistent launch (autotuned on the first run) and its HIP-graph replay."""
+    import torch
+    from paper_2111_13667_amd import ragged, workloads
+    rw = workloads.ragged_batch()
+    plan = ragged.RaggedPlan(rw.layer_off, rw.wl_off, rw.th_off)
+    dev = ragged.to_device(rw, dtype)
+    real = dev[3].dtype
+    R = torch.empty(plan.output_size, dtype=real, device="cuda")
+    T = torch.empty(plan.output_size, dtype=real, device="cuda")
+    plan.run(*dev, R=R, T=T)  # tunes
+    torch.cuda.synchronize()
+    ms = _event_time(lambda: plan.run(*dev, R=R, T=T), steps, 1)
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        plan.capture(*dev, R=R, T=T, stream=st)
+    st.synchronize()
+    gms = _event_time(lambda: plan.replay(stream=st), steps, 1, stream=st)
+    layer_steps = int(((np.diff(rw.layer_off) + 1) * np.diff(rw.wl_off) * np.diff(rw.th_off)).sum()) * 2
+    plan.close()
+    return {"workload": f"ragged_batch: 8192 stacks, 2-100 layers, 256-2048 wl, 1-64 angles, s+p, {dtype}",
+            "points": rw.n_points, "ms": round(ms, 3), "graph_ms": round(gms, 3),
+            "points_per_s": round(rw.n_points / (ms * 1e-3), 1),
+            "algorithmic_TFLOPs": round(layer_steps * FLOPS_PER_POINT_STEP / (ms * 1e-3) / 1e12, 2)}
+
+
 def roofline(w, dtype, kernel_ms, out_bytes, traffic=None):
     flops = w.n_points * (w.L + 1) * FLOPS_PER_POINT_STEP
     achieved = flops / (kernel_ms * 1e-3) / 1e12
@@ -121,7 +188,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--dtype", choices=["f64", "f32"], default="f64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extra", action="store_true", help="skip the f32 and amplitude variants")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the other-precision, amplitude, adjoint and ragged measurements")
     ap.add_argument("--cpu-stacks", type=int, default=64)
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"))
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -192,6 +260,9 @@ def main():
         extra[args.dtype + "_with_r_t"] = {"value": round(w.n_points / (ms * 1e-3), 1),
                                            "ms_per_step": round(ms, 4),
                                            "roofline": roofline(w, args.dtype, ms, ob)}
+        extra["adjoint_f64"] = time_grad()
+        extra["ragged_f64"] = time_ragged("f64")
+        extra["ragged_f32"] = time_ragged("f32")
         rec["extra"] = extra
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(w, args.cpu_stacks)
