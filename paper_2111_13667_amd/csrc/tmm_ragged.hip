@@ -32,7 +32,7 @@
 namespace tmm {
 namespace ragged {
 
-constexpr int kThreads = 128;  // two waves: each wave's media table stays within 48 KiB of LDS per block
+constexpr int kThreads = 256;  // four waves, each with its own media table and layer staging
 constexpr int kWaves = kThreads / kWave;
 constexpr int kMaxMat = 8;
 
@@ -60,9 +60,72 @@ struct Params {
     int grain;
 };
 
-template <typename R>
-__device__ __forceinline__ size_t wave_table_bytes(int n_mat) {
-    return (size_t)n_mat * Table<R>::kBlockBytes;
+// Per-wave media table: q and eta of every index-table row at the wave's 64
+// wavelengths (|q|^2 and |eta|^2 are recomputed in the loop, which keeps the
+// slice at 32 bytes per (row, lane) and the occupancy up).  One block per row:
+// FP64 [q (double2)][eta (double2)]; FP32 [q in double (double2)][q (float2)][eta (float2)].
+template <typename R> struct WaveTable;
+
+template <>
+struct WaveTable<double> {
+    static constexpr int kBlockBytes = kWave * 32;
+    unsigned char* base;
+    __device__ WaveTable(unsigned char* b) : base(b) {}
+    __device__ __forceinline__ void put(int m, int lane, const Medium& md) {
+        double2* blk = reinterpret_cast<double2*>(base + m * kBlockBytes);
+        blk[lane] = make_double2(md.qr, md.qi);
+        blk[kWave + lane] = make_double2(md.er, md.ei);
+    }
+    __device__ __forceinline__ Layer<double> get(int m, int lane) const {
+        const double2* blk = reinterpret_cast<const double2*>(base + m * kBlockBytes) + lane;
+        const double2 a = blk[0], b = blk[kWave];
+        Layer<double> v;
+        v.q = {a.x, a.y};
+        v.e = {b.x, b.y};
+        v.q2 = a.x * a.x + a.y * a.y;
+        v.e2 = b.x * b.x + b.y * b.y;
+        v.pr = a.x;
+        v.pi = a.y;
+        return v;
+    }
+};
+
+template <>
+struct WaveTable<float> {
+    static constexpr int kBlockBytes = kWave * 32;
+    unsigned char* base;
+    __device__ WaveTable(unsigned char* b) : base(b) {}
+    __device__ __forceinline__ void put(int m, int lane, const Medium& md) {
+        unsigned char* blk = base + m * kBlockBytes;
+        reinterpret_cast<double2*>(blk)[lane] = make_double2(md.qr, md.qi);
+        float2* f = reinterpret_cast<float2*>(blk + kWave * 16);
+        f[lane] = make_float2((float)md.qr, (float)md.qi);
+        f[kWave + lane] = make_float2((float)md.er, (float)md.ei);
+    }
+    __device__ __forceinline__ Layer<float> get(int m, int lane) const {
+        const unsigned char* blk = base + m * kBlockBytes;
+        const double2 p = reinterpret_cast<const double2*>(blk)[lane];
+        const float2* f = reinterpret_cast<const float2*>(blk + kWave * 16) + lane;
+        const float2 a = f[0], b = f[kWave];
+        Layer<float> v;
+        v.q = {a.x, a.y};
+        v.e = {b.x, b.y};
+        v.q2 = a.x * a.x + a.y * a.y;
+        v.e2 = b.x * b.x + b.y * b.y;
+        v.pr = p.x;
+        v.pi = p.y;
+        return v;
+    }
+};
+
+// Per-wave staging of a unit's layers (thickness, table row), kWave at a time.
+struct WaveStage {
+    double d[kWave];
+    int m[kWave];
+};
+
+__host__ __device__ constexpr size_t wave_lds_bytes(int n_mat) {
+    return (size_t)n_mat * kWave * 32 + sizeof(WaveStage);
 }
 
 __global__ void reset_counter(unsigned long long* c) {
@@ -74,7 +137,9 @@ __global__ void __launch_bounds__(kThreads) ragged_kernel(Params<R> p) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-    Table<R> tab(smem + (size_t)wave * p.n_mat * Table<R>::kBlockBytes, p.n_mat);
+    unsigned char* my = smem + (size_t)wave * wave_lds_bytes(p.n_mat);
+    WaveTable<R> tab(my);
+    WaveStage& stg = *reinterpret_cast<WaveStage*>(my + (size_t)p.n_mat * kWave * 32);
     constexpr int P = (POL == 3) ? 2 : 1;
     for (;;) {
         unsigned long long base = 0;
@@ -126,18 +191,35 @@ __global__ void __launch_bounds__(kThreads) ragged_kernel(Params<R> p) {
             Chain<R, POL, false> c;
             c.init();
             int cnt = 0;
-            for (int j = L; j >= 1; --j) {
-                const R dj = drow[j - 1];
-                int m = mrow[j - 1];
-                bad = bad || bad_thickness(dj) || (uint32_t)m >= (uint32_t)p.n_mat;
-                m = min(max(m, 0), p.n_mat - 1);
-                const Layer<R> cur = tab.get(m, lane);
-                c.step(cur, nxt, (double)dj * c4lam, (lossy_mask >> m) & 1u);
-                nxt = cur;
-                if (++cnt == RenormPeriod<R>::value) {
-                    cnt = 0;
-                    c.renorm();
+            for (int top = L; top >= 1; top -= kWave) {
+                const int lo = top - kWave + 1 > 1 ? top - kWave + 1 : 1;
+                const int j = lo + lane;  // stage layers lo..top, one per lane
+                bool lane_bad = false;
+                if (j <= top) {
+                    const R dj = drow[j - 1];
+                    const int m = mrow[j - 1];
+                    lane_bad = bad_thickness(dj) || (uint32_t)m >= (uint32_t)p.n_mat;
+                    stg.d[lane] = (double)dj;
+                    stg.m[lane] = min(max(m, 0), p.n_mat - 1);
                 }
+                bad = bad || __any(lane_bad);
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll 2
+                for (int jj = top; jj >= lo; --jj) {
+                    const int m = __builtin_amdgcn_readfirstlane(stg.m[jj - lo]);
+                    const Layer<R> cur = tab.get(m, lane);
+                    c.step(cur, nxt, stg.d[jj - lo] * c4lam, (lossy_mask >> m) & 1u);
+                    nxt = cur;
+                    if (++cnt == RenormPeriod<R>::value) {
+                        cnt = 0;
+                        c.renorm();
+                    }
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             }
             c.renorm();
             PointOut out[2];
@@ -224,7 +306,7 @@ tmm::ragged::Params<R> make_params(const tmm_ragged_plan* pl, const tmm_ragged_d
 template <typename R>
 hipError_t launch(const tmm_ragged_plan* pl, tmm::ragged::Params<R> p, tmm::ragged::Shape sh, hipStream_t s) {
     p.grain = sh.grain;
-    const size_t lds = (size_t)tmm::ragged::kWaves * p.n_mat * tmm::Table<R>::kBlockBytes;
+    const size_t lds = (size_t)tmm::ragged::kWaves * tmm::ragged::wave_lds_bytes(p.n_mat);
     const int blocks = pl->n_cu * sh.blocks_per_cu;
     hipLaunchKernelGGL(tmm::ragged::reset_counter, dim3(1), dim3(64), 0, s, pl->d_counter);
     if (pl->pol_mask == 1u)
@@ -254,13 +336,13 @@ tmm_status tune(tmm_ragged_plan* pl, const tmm::ragged::Params<R>& p, int di, hi
             return ok();
         }
     }
-    const int bpc[] = {2, 4, 8};
+    const int bpc[] = {1, 2, 4};
     const int grains[] = {1, 4};
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
         return fail(TMM_ERR_HIP, "tmm_ragged_run: event creation failed");
     float best = 1e30f;
-    tmm::ragged::Shape best_sh = {4, 1};
+    tmm::ragged::Shape best_sh = {2, 1};
     for (int b : bpc) {
         for (int g : grains) {
             const tmm::ragged::Shape sh = {b, g};
