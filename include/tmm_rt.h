@@ -113,10 +113,19 @@ typedef struct tmm_rt_args {
 tmm_status tmm_rt(const tmm_rt_args *a, tmm_dtype dtype, void *stream);
 
 /*
- * Workspace bytes that tmm_rt_grad needs for these arguments (0 if there is
- * nothing to compute).  Depends on B, L, n_wl and n_theta only.
+ * Preferred workspace bytes of tmm_rt_grad for these arguments (0 if there is
+ * nothing to compute): checkpoints of the persistent grid plus partial sums for
+ * all stacks, or for as many stacks as fit in 512 MiB of partial sums (the
+ * batch then runs in several launches).  Depends on B, L, n_wl, n_theta only.
  */
 size_t tmm_rt_grad_workspace_size(const tmm_rt_args *a);
+
+/*
+ * Smallest workspace tmm_rt_grad accepts (partial sums for four stacks per
+ * launch).  Any size between this and tmm_rt_grad_workspace_size works; a
+ * smaller workspace means more launches, the results are the same bits.
+ */
+size_t tmm_rt_grad_workspace_min_size(const tmm_rt_args *a);
 
 /*
  * Reverse-mode gradients of a loss l(R, T) w.r.t. the layer thicknesses and
@@ -133,11 +142,13 @@ size_t tmm_rt_grad_workspace_size(const tmm_rt_args *a);
  *               n_j is shifted at every wavelength (for a constant index this
  *               is the derivative w.r.t. that index) (device, or NULL).
  *               The ambient and substrate get no gradient.
- *  workspace    device scratch of at least tmm_rt_grad_workspace_size(a)
- *               bytes, owned by the caller, contents irrelevant on entry.
+ *  workspace    device scratch of at least tmm_rt_grad_workspace_min_size(a)
+ *               bytes (tmm_rt_grad_workspace_size(a) preferred), owned by the
+ *               caller, contents irrelevant on entry; too small: TMM_ERR_WORKSPACE.
  *  dtype        TMM_F64 (TMM_F32 returns TMM_ERR_UNSUPPORTED).
- * The gradient outputs are overwritten (zeroed, then accumulated with atomic
- * adds, so the last bits may differ from run to run).  Points that are invalid
+ * The gradient outputs are overwritten.  Each gradient is a sum over the
+ * (wavelength, angle) points taken in a fixed order, so repeated calls give the
+ * same bits (also with a smaller workspace).  Points that are invalid
  * (see the NaN rules above) make their stack's gradients NaN.
  * Returns TMM_OK, TMM_ERR_INVALID_ARG, TMM_ERR_UNSUPPORTED, TMM_ERR_WORKSPACE
  * or TMM_ERR_HIP.

@@ -13,8 +13,18 @@
 //   pass B  segments from the ambient back to the substrate: reload the
 //           segment's checkpoint, recompute its kSeg steps keeping the inputs
 //           in registers, then run the adjoint of each step (layer j
-//           ascending), form dl/dd_j and dl/dn_j, reduce them over the wave's
-//           64 wavelengths and add them to the outputs with float64 atomics.
+//           ascending) and form the lane's share of dl/dd_j and dl/dn_j.  The
+//           3 kSeg shares of a segment go through a per-wave LDS transpose and
+//           are summed over the wave's 64 wavelengths; one partial sum per
+//           (column, stack, layer) goes to the workspace, where column =
+//           (wavelength tile, angle).
+//   reduce  a second kernel sums the partials over the columns in a fixed
+//           order, so the gradients are the same bits on every run.
+//
+// Launch: persistent blocks of four waves walk a static range of tasks
+// (column, group of four stacks); the block keeps an LDS table of the index
+// table's rows at its column (q, eta and the per-material adjoint factors)
+// and rebuilds it when the column or the ambient row changes.
 //
 // Adjoint conventions: for a complex intermediate z the adjoint is
 // zb = dl/dRe z + i dl/dIm z, so w = c z gives zb = conj(c) wb.  Per step
@@ -28,7 +38,12 @@
 // db_j = 2 pi / lambda Re(conj(deltab) q_j) and qb_j += 2 pi d_j / lambda deltab;
 // finally nb_j = conj(n/q) qb_j + conj((n/q)(2 - eta/q)) etab_j since
 // dq/dn = n/q and d(eta)/dn = (n/q)(2 - eta/q).
+#include <limits.h>
 #include <math.h>
+
+#include <map>
+#include <mutex>
+#include <type_traits>
 
 #include "tmm_device.hpp"
 #include "tmm_host.hpp"
@@ -37,10 +52,13 @@ namespace tmm {
 
 constexpr int kGradBlock = 256;
 constexpr int kGradWaves = kGradBlock / kWave;
-constexpr int kSeg = 4;                  // layers per checkpoint segment
+constexpr int kSeg = 3;                  // layers per checkpoint segment
+constexpr int kRed = 3 * kSeg;           // shares per segment: dl/dd, dl/dRe n, dl/dIm n per layer
 constexpr int kGradMaxTableMat = 16;
+constexpr int kTabFields = 6;            // q, eta, n/q, (n/q)(2 - eta/q), 2q/|q|^2, 2 eta/|eta|^2
 constexpr int kCkptDoubles = 8;          // (sigma, tau) of s and p, complex
-constexpr int kGradMaxBlocks = 2048;     // bounds the workspace
+constexpr int kGradMaxBlocks = 1024;     // persistent grid bound (and checkpoint slots)
+constexpr size_t kPartialCap = (size_t)1 << 29;  // partial-sum bytes of the preferred workspace
 
 struct GradParams {
     int B, L, n_wl, n_theta;
@@ -55,53 +73,85 @@ struct GradParams {
     const double* gT;
     double* R_out;
     double* T_out;
-    double* grad_d;
-    double* grad_n;
-    double* ws;
-    int n_tiles, chunk, n_seg;
-    int use_table;
+    double* ws;        // checkpoints: [block][wave][n_seg + 1][kCkptDoubles][kWave]
+    double* partial;   // [column][stack - b_begin][L][3]
+    int b_begin, b_end;
+    int n_tiles, n_seg;
+    int64_t n_tasks;   // columns * ceil((b_end - b_begin) / kGradWaves)
+    int64_t per_block;
 };
 
-struct GLayer {
-    cx<double> q, e, n;
+// Per-stack layer data is read-only during the launch and read at
+// wave-uniform indices: through these pointers it is fetched with scalar loads
+// and the row arithmetic stays on the scalar unit.
+typedef const __attribute__((address_space(4))) double* cdptr;
+typedef const __attribute__((address_space(4))) int32_t* ciptr;
+
+// Forward values of a medium: q and eta.
+struct FL {
+    cx<double> q, e;
+};
+// Adjoint factors of a medium (see the header comment).
+struct AL {
+    cx<double> nq, de, wq, we;
 };
 
-__device__ __forceinline__ GLayer glayer_from(double nr, double ni, double kx) {
-    const Medium m = make_medium(nr, ni, kx);
-    GLayer g;
-    g.q = {m.qr, m.qi};
-    g.e = {m.er, m.ei};
-    g.n = {nr, ni};
-    return g;
+__device__ __forceinline__ FL fl_from(const Medium& m) { return FL{{m.qr, m.qi}, {m.er, m.ei}}; }
+
+__device__ __forceinline__ AL al_from(double nr, double ni, const FL& f) {
+    const double iq2 = 1.0 / cnorm(f.q);
+    const cx<double> nq = {(nr * f.q.re + ni * f.q.im) * iq2, (ni * f.q.re - nr * f.q.im) * iq2};
+    const cx<double> eq = {(f.e.re * f.q.re + f.e.im * f.q.im) * iq2, (f.e.im * f.q.re - f.e.re * f.q.im) * iq2};
+    AL a;
+    a.nq = nq;
+    a.de = cmul(nq, cx<double>{2.0 - eq.re, -eq.im});
+    a.wq = cscale(2.0 * iq2, f.q);
+    a.we = cscale(2.0 / cnorm(f.e), f.e);
+    return a;
 }
 
-// Layer values: from the LDS table (material ids, small table, same ambient)
-// or computed in place.
-struct GSource {
-    const double2* tab;  // [m][3][lane] double2, or NULL
-    const double* nk;
-    const int32_t* mrow;  // NULL: implicit rows
-    int64_t base;
-    int n_mat, dispersive, n_wl, i, lane;
-    double kx;
+// Media from the block's LDS table (material ids, at most kGradMaxTableMat rows).
+struct TabSrc {
+    const double2* tab;   // this lane's entries: tab[(m * kTabFields + f) * kWave]
+    ciptr mrow;  // the stack's rows [L + 2]
+    int n_mat;
     __device__ __forceinline__ int row(int j) const {
-        if (!mrow) return (int)(base + j);
         const int m = mrow[j];
         return m < 0 ? 0 : (m >= n_mat ? n_mat - 1 : m);
     }
-    __device__ __forceinline__ bool row_bad(int j) const {
-        return mrow ? (uint32_t)mrow[j] >= (uint32_t)n_mat : false;
+    __device__ __forceinline__ FL fwd(int j) const {
+        const double2* e = tab + row(j) * kTabFields * kWave;
+        const double2 a = e[0], b = e[kWave];
+        return FL{{a.x, a.y}, {b.x, b.y}};
     }
-    __device__ __forceinline__ GLayer get(int j) const {
-        if (tab) {
-            const double2* blk = tab + (size_t)row(j) * 3 * kWave + lane;
-            const double2 a = blk[0], b = blk[kWave], c = blk[2 * kWave];
-            return GLayer{{a.x, a.y}, {b.x, b.y}, {c.x, c.y}};
-        }
-        const int64_t r = mrow ? (int64_t)row(j) : base + j;
+    __device__ __forceinline__ AL adj(int j, const FL&) const {
+        const double2* e = tab + row(j) * kTabFields * kWave;
+        const double2 a = e[2 * kWave], b = e[3 * kWave], c = e[4 * kWave], d = e[5 * kWave];
+        return AL{{a.x, a.y}, {b.x, b.y}, {c.x, c.y}, {d.x, d.y}};
+    }
+};
+
+// Media computed in place (per-layer rows, or tables too large for LDS).
+struct InlSrc {
+    const double* nk;
+    ciptr mrow;  // NULL: implicit rows base + j
+    int64_t base;
+    int n_mat, dispersive, n_wl, i;
+    double kx;
+    __device__ __forceinline__ int64_t row(int j) const {
+        if (!mrow) return base + j;
+        const int m = mrow[j];
+        return m < 0 ? 0 : (m >= n_mat ? n_mat - 1 : m);
+    }
+    __device__ __forceinline__ FL fwd(int j) const {
         double nr, ni;
-        load_n(nk, dispersive, n_wl, r, i, nr, ni);
-        return glayer_from(nr, ni, kx);
+        load_n(nk, dispersive, n_wl, row(j), i, nr, ni);
+        return fl_from(make_medium(nr, ni, kx));
+    }
+    __device__ __forceinline__ AL adj(int j, const FL& f) const {
+        double nr, ni;
+        load_n(nk, dispersive, n_wl, row(j), i, nr, ni);
+        return al_from(nr, ni, f);
     }
 };
 
@@ -110,7 +160,7 @@ struct State {
 };
 
 template <int POL>
-__device__ __forceinline__ void fwd_step(State& z, const GLayer& cur, const GLayer& nxt, const cx<double>& E) {
+__device__ __forceinline__ void fwd_step(State& z, const FL& cur, const FL& nxt, const cx<double>& E) {
     if (POL & 1) {
         const cx<double> A = cmul(cur.q, z.ss), Bv = cmul(nxt.q, z.ts);
         const cx<double> a = cadd(A, Bv), b = csub(A, Bv);
@@ -127,7 +177,6 @@ __device__ __forceinline__ void fwd_step(State& z, const GLayer& cur, const GLay
     }
 }
 
-__device__ __forceinline__ cx<double> cconj(cx<double> a) { return {a.re, -a.im}; }
 // conj(a) * b
 __device__ __forceinline__ cx<double> cmulc(cx<double> a, cx<double> b) {
     return {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re};
@@ -156,23 +205,43 @@ __device__ __forceinline__ int pair_exp(const cx<double>& a, const cx<double>& b
     return frexp_exp(m);
 }
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int o = kWave / 2; o >= 1; o >>= 1) v += __shfl_xor(v, o, kWave);
-    return v;
+// v + v of the lane whose index differs in bit 0 (CTRL 0xB1) or bit 1 (0x4E),
+// by DPP quad permutes; every lane of the wave must be active.
+template <int CTRL>
+__device__ __forceinline__ double quad_add(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+    return v + __hiloint2double(hi, lo);
 }
 
-template <int POL>
-__device__ void grad_stack(const GradParams& p, const GSource& src, const Ambient& amb, int b, int k, int i,
-                           bool active, bool lane_ok, double* ws) {
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// The stack's layer data is valid: finite non-negative thicknesses and row ids
+// inside the index table (wave-uniform result).
+__device__ __forceinline__ bool stack_bad(const GradParams& p, const double* drow, ciptr mrow, int lane) {
+    bool bad = false;
+    for (int j = lane; j < p.L; j += kWave) {
+        bad = bad || bad_thickness(drow[j]);
+        if (mrow) bad = bad || (uint32_t)mrow[j + 1] >= (uint32_t)p.n_mat;
+    }
+    if (mrow && lane == 0)
+        bad = bad || (uint32_t)mrow[0] >= (uint32_t)p.n_mat || (uint32_t)mrow[p.L + 1] >= (uint32_t)p.n_mat;
+    return __any(bad);
+}
+
+template <int POL, typename Src>
+__device__ void grad_stack(const GradParams& p, const Src& src, const Ambient& amb, int b, int k, int i, int lane,
+                           bool active, bool valid, double* ws, double* red, double* part) {
     const int L = p.L;
     constexpr int P = (POL == 3) ? 2 : 1;
     const double lam = p.wl[i];
     const double c4lam = 4.0 / lam;           // phi = c4lam d q (half-turns of 2 delta)
     const double two_pi_lam = 2.0 * M_PI / lam;
-    const double* drow = p.d + (int64_t)b * L;
-    const int lane = src.lane;
-    bool bad = src.row_bad(0) || src.row_bad(L + 1);
+    const cdptr drow = (cdptr)(p.d + (int64_t)b * L);
     auto ck = [&](int c, int comp) -> double& { return ws[((size_t)c * kCkptDoubles + comp) * kWave + lane]; };
     auto save = [&](int c, const State& z) {
         ck(c, 0) = z.ss.re; ck(c, 1) = z.ss.im; ck(c, 2) = z.ts.re; ck(c, 3) = z.ts.im;
@@ -191,35 +260,32 @@ __device__ void grad_stack(const GradParams& p, const GSource& src, const Ambien
     int es = 0, ep = 0, epis = 0, epip = 0;
     double pis = 1.0, pip = 1.0, S = 0.0;
     save(0, z);
-    const GLayer sub = src.get(L + 1);
-    GLayer nxt = sub;
+    const FL sub = src.fwd(L + 1);
+    FL nxt = sub;
     for (int s = 0; s < p.n_seg; ++s) {
         const int top = L - s * kSeg;
         const int lo = top - kSeg + 1 > 1 ? top - kSeg + 1 : 1;
         for (int j = top; j >= lo; --j) {
-            const double dj = drow[j - 1];
-            bad = bad || bad_thickness(dj) || src.row_bad(j);
-            const GLayer cur = src.get(j);
-            const double cd = dj * c4lam;
+            const FL cur = src.fwd(j);
+            const double cd = drow[j - 1] * c4lam;
             const double phi = cd * cur.q.im;
             const bool lossy = __any(phi != 0.0);
-            const cx<double> E = phase_factor<double>(cd * cur.q.re, phi, lossy);
+            const cx<double> E = phase_factor<double, true>(cd * cur.q.re, phi, lossy);
             fwd_step<POL>(z, cur, nxt, E);
-            pis *= cnorm(cur.q);
-            pip *= cnorm(cur.e);
+            if (POL & 1) pis *= cnorm(cur.q);
+            if (POL & 2) pip *= cnorm(cur.e);
             S += phi;
             nxt = cur;
         }
         if (POL & 1) renorm_pair(z.ss, z.ts, es);
         if (POL & 2) renorm_pair(z.sp, z.tp, ep);
-        renorm_one(pis, epis);
-        renorm_one(pip, epip);
+        if (POL & 1) renorm_one(pis, epis);
+        if (POL & 2) renorm_one(pip, epip);
         save(s + 1, z);
     }
-    const GLayer first = nxt;
+    const FL first = nxt;
     const double eS = exp2(S * kNegPiLog2e);
     const int two_L1 = 2 * (L + 1);
-    const bool valid = lane_ok && !bad;
     const double nan = __builtin_nan("");
     const double w_act = active ? 1.0 : 0.0;  // ragged-tail lanes contribute nothing
 
@@ -272,154 +338,236 @@ __device__ void grad_stack(const GradParams& p, const GSource& src, const Ambien
     }
 
     // ---- pass B: segments from the ambient side ----------------------------
+    const int v_red = lane >> 2 < kRed ? lane >> 2 : kRed - 1;  // share this lane sums
+    const double2* red_in = reinterpret_cast<const double2*>(red + v_red * kWave + (lane & 3) * 16);
+    // One segment of NST steps whose top layer is `top`: recompute from the
+    // checkpoint, then the adjoint of each step (no guards: NST is exact).
+    auto segment = [&](auto nst_c, int s, int top) {
+        constexpr int NST = decltype(nst_c)::value;
+        State zin[NST];
+        cx<double> Es[NST];
+        State zz = load(s);
+        FL nx = sub;
+        if (top != L) nx = src.fwd(top + 1);
+#pragma unroll
+        for (int t = 0; t < NST; ++t) {
+            const int j = top - t;
+            const FL cur = src.fwd(j);
+            const double cd = drow[j - 1] * c4lam;
+            const double phi = cd * cur.q.im;
+            const bool lossy = __any(phi != 0.0);
+            Es[t] = phase_factor<double, true>(cd * cur.q.re, phi, lossy);
+            zin[t] = zz;
+            fwd_step<POL>(zz, cur, nx, Es[t]);
+            nx = cur;
+        }
+        // the forward pass renormalised the segment's end state; undo on the adjoint
+        if (POL & 1) {
+            const double f = ldexp(1.0, -pair_exp(zz.ss, zz.ts));
+            sb_s = cscale(f, sb_s);
+            tb_s = cscale(f, tb_s);
+        }
+        if (POL & 2) {
+            const double f = ldexp(1.0, -pair_exp(zz.sp, zz.tp));
+            sb_p = cscale(f, sb_p);
+            tb_p = cscale(f, tb_p);
+        }
+        FL cur = nx;  // layer top - NST + 1
+#pragma unroll
+        for (int t = NST - 1; t >= 0; --t) {
+            const int j = top - t;
+            FL up = sub;
+            if (j != L) up = src.fwd(j + 1);
+            const AL ca = src.adj(j, cur);
+            const double dj = drow[j - 1];
+            cx<double> Eb = {0.0, 0.0};
+            cx<double> qb = pend_q, eb = pend_e;
+            if (POL & 1) {
+                cx<double> alphab, betab;
+                adj_step(zin[t].ss, zin[t].ts, cur.q, up.q, Es[t], sb_s, tb_s, alphab, betab, Eb);
+                qb = cadd(qb, alphab);  // alpha_j = q_j
+                pend_q = betab;         // beta_j = q_{j+1}
+                qb = cadd(qb, cscale(cT_s, ca.wq));  // T through |q_j|^2
+            }
+            if (POL & 2) {
+                cx<double> alphab, betab;
+                adj_step(zin[t].sp, zin[t].tp, up.e, cur.e, Es[t], sb_p, tb_p, alphab, betab, Eb);
+                eb = cadd(eb, betab);   // beta_j = eta_j
+                pend_e = alphab;        // alpha_j = eta_{j+1}
+                eb = cadd(eb, cscale(cT_p, ca.we));  // T through |eta_j|^2
+            }
+            // deltab = -2i conj(E) Eb - 2i cT  (chain and e^{-2 Im sum delta})
+            const cx<double> cE = cmulc(Es[t], Eb);
+            const cx<double> db = {2.0 * cE.im, -2.0 * cE.re - 2.0 * cT};
+            const double gd = two_pi_lam * (db.re * cur.q.re + db.im * cur.q.im);
+            qb = cadd(qb, cscale(two_pi_lam * dj, db));
+            const cx<double> nb = cadd(cmulc(ca.nq, qb), cmulc(ca.de, eb));
+            red[(3 * t + 0) * kWave + lane] = gd;
+            red[(3 * t + 1) * kWave + lane] = nb.re;
+            red[(3 * t + 2) * kWave + lane] = nb.im;
+            cur = up;
+        }
+    };
     for (int s = p.n_seg - 1; s >= 0; --s) {
         const int top = L - s * kSeg;
         const int lo = top - kSeg + 1 > 1 ? top - kSeg + 1 : 1;
         const int nst = top - lo + 1;
-        State zin[kSeg];
-        cx<double> Es[kSeg];
-        State zz = load(s);
-        GLayer nx = (top == L) ? sub : src.get(top + 1);
+        if (nst == kSeg) {
+            segment(std::integral_constant<int, kSeg>(), s, top);
+        } else {
+            static_assert(kSeg <= 4, "segment lengths below are spelled out");
+            if (nst == 1) segment(std::integral_constant<int, 1>(), s, top);
+            if (kSeg > 2 && nst == 2) segment(std::integral_constant<int, (kSeg > 2 ? 2 : 1)>(), s, top);
+            if (kSeg > 3 && nst == 3) segment(std::integral_constant<int, (kSeg > 3 ? 3 : 1)>(), s, top);
+        }
+        wave_sync();
+        // lane 4v + c sums quarter c of share v; quad permutes finish the sums
+        double acc = 0.0;
 #pragma unroll
-        for (int t = 0; t < kSeg; ++t) {
-            if (t < nst) {
-                const int j = top - t;
-                const GLayer cur = src.get(j);
-                const double cd = drow[j - 1] * c4lam;
-                const double phi = cd * cur.q.im;
-                const bool lossy = __any(phi != 0.0);
-                Es[t] = phase_factor<double>(cd * cur.q.re, phi, lossy);
-                zin[t] = zz;
-                fwd_step<POL>(zz, cur, nx, Es[t]);
-                nx = cur;
+        for (int u = 0; u < 8; ++u) {
+            const double2 x = red_in[u];
+            acc += x.x;
+            acc += x.y;
+        }
+        acc = quad_add<0xB1>(acc);
+        acc = quad_add<0x4E>(acc);
+        if ((lane & 3) == 0 && (lane >> 2) < 3 * nst) {
+            const int v = lane >> 2;
+            const int t = v / 3;
+            part[(top - t - 1) * 3 + (v - 3 * t)] = acc;
+        }
+        wave_sync();
+    }
+}
+
+// Fills the block's LDS table for one column and ambient row: every wave
+// computes rows wave, wave + 4, ... at its lanes' wavelength.
+__device__ void build_table(const GradParams& p, double2* tab, int amb_row, int i, double st, double ct, int wave,
+                            int lane) {
+    double n0r, n0i;
+    load_n(p.nk, p.dispersive, p.n_wl, amb_row, i, n0r, n0i);
+    const Ambient a = make_ambient(n0r, n0i, st, ct);
+    for (int m = wave; m < p.n_mat; m += kGradWaves) {
+        double nr, ni;
+        load_n(p.nk, p.dispersive, p.n_wl, m, i, nr, ni);
+        const FL f = fl_from(make_medium(nr, ni, a.kx));
+        const AL g = al_from(nr, ni, f);
+        double2* e = tab + m * kTabFields * kWave + lane;
+        e[0] = make_double2(f.q.re, f.q.im);
+        e[kWave] = make_double2(f.e.re, f.e.im);
+        e[2 * kWave] = make_double2(g.nq.re, g.nq.im);
+        e[3 * kWave] = make_double2(g.de.re, g.de.im);
+        e[4 * kWave] = make_double2(g.wq.re, g.wq.im);
+        e[5 * kWave] = make_double2(g.we.re, g.we.im);
+    }
+}
+
+// Task t = (column, group of kGradWaves stacks), column = (angle k, tile).
+struct Task {
+    int k, tile, b;
+};
+__device__ __forceinline__ Task task_of(const GradParams& p, int64_t t, int wave) {
+    const int64_t groups = (p.b_end - p.b_begin + kGradWaves - 1) / kGradWaves;
+    const int64_t col = t / groups;
+    Task r;
+    r.k = (int)(col / p.n_tiles);
+    r.tile = (int)(col - (int64_t)r.k * p.n_tiles);
+    r.b = p.b_begin + (int)(t - col * groups) * kGradWaves + wave;
+    return r;
+}
+
+template <int POL, bool TABLE>
+__global__ void __launch_bounds__(kGradBlock) __attribute__((amdgpu_waves_per_eu(2))) grad_kernel(GradParams p) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int s_rows[kGradWaves];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    double* red = reinterpret_cast<double*>(smem) + wave * kRed * kWave;
+    double2* tab = reinterpret_cast<double2*>(smem + (size_t)kGradWaves * kRed * kWave * sizeof(double));
+    double* ws = p.ws + ((size_t)blockIdx.x * kGradWaves + wave) * (size_t)(p.n_seg + 1) * kCkptDoubles * kWave;
+    const int L2 = p.L + 2;
+    const int64_t nbs = p.b_end - p.b_begin;
+    const int64_t t0 = (int64_t)blockIdx.x * p.per_block;
+    const int64_t t1 = t0 + p.per_block < p.n_tasks ? t0 + p.per_block : p.n_tasks;
+    int64_t tab_col = -1;
+    int tab_row = -1;
+    for (int64_t t = t0; t < t1; ++t) {
+        const Task tk = task_of(p, t, wave);
+        const int i_raw = tk.tile * kWave + lane;
+        const bool active = i_raw < p.n_wl;
+        const int i = active ? i_raw : p.n_wl - 1;
+        const double lam = p.wl[i];
+        const bool lam_ok = lam > 0.0 && lam < __builtin_inf();
+        const double st = p.sin_t[tk.k], ct = p.cos_t[tk.k];
+        const bool has = tk.b < p.b_end;
+        const int b = has ? tk.b : p.b_end - 1;
+        const ciptr mrow = p.mat ? (ciptr)(p.mat + (int64_t)b * L2) : nullptr;
+        const int64_t col = (int64_t)tk.k * p.n_tiles + tk.tile;
+        double* part = p.partial + ((size_t)col * nbs + (b - p.b_begin)) * (size_t)p.L * 3;
+        const bool bad = stack_bad(p, p.d + (int64_t)b * p.L, mrow, lane);
+        if (TABLE) {
+            int a_row = mrow[0];
+            a_row = a_row < 0 ? 0 : (a_row >= p.n_mat ? p.n_mat - 1 : a_row);
+            bool done = !has;
+            // one sub-round per distinct ambient row among the block's stacks
+            for (;;) {
+                __syncthreads();
+                if (lane == 0) s_rows[wave] = done ? INT_MAX : a_row;
+                __syncthreads();
+                int r = s_rows[0];
+                for (int w = 1; w < kGradWaves; ++w) r = min(r, s_rows[w]);
+                if (r == INT_MAX) break;
+                if (r != tab_row || col != tab_col) {
+                    build_table(p, tab, r, i, st, ct, wave, lane);
+                    tab_row = r;
+                    tab_col = col;
+                }
+                __syncthreads();
+                if (!done && a_row == r) {
+                    double n0r, n0i;
+                    load_n(p.nk, p.dispersive, p.n_wl, a_row, i, n0r, n0i);
+                    const Ambient amb = make_ambient(n0r, n0i, st, ct);
+                    TabSrc src;
+                    src.tab = tab + lane;
+                    src.mrow = mrow;
+                    src.n_mat = p.n_mat;
+                    grad_stack<POL>(p, src, amb, b, tk.k, i, lane, active, lam_ok && amb.ok && !bad, ws, red, part);
+                    done = true;
+                }
             }
-        }
-        // the forward pass renormalised the segment's end state; undo on the adjoint
-        if (POL & 1) {
-            const int e = pair_exp(zz.ss, zz.ts);
-            sb_s = cscale(ldexp(1.0, -e), sb_s);
-            tb_s = cscale(ldexp(1.0, -e), tb_s);
-        }
-        if (POL & 2) {
-            const int e = pair_exp(zz.sp, zz.tp);
-            sb_p = cscale(ldexp(1.0, -e), sb_p);
-            tb_p = cscale(ldexp(1.0, -e), tb_p);
-        }
-#pragma unroll
-        for (int t = kSeg - 1; t >= 0; --t) {
-            if (t < nst) {
-                const int j = top - t;
-                const GLayer cur = src.get(j);
-                const GLayer nxj = (j == L) ? sub : src.get(j + 1);
-                const double dj = drow[j - 1];
-                cx<double> Eb = {0.0, 0.0};
-                cx<double> qb = pend_q, eb = pend_e;
-                if (POL & 1) {
-                    cx<double> alphab, betab;
-                    adj_step(zin[t].ss, zin[t].ts, cur.q, nxj.q, Es[t], sb_s, tb_s, alphab, betab, Eb);
-                    qb = cadd(qb, alphab);  // alpha_j = q_j
-                    pend_q = betab;         // beta_j = q_{j+1}
-                    qb = cadd(qb, cscale(2.0 * cT_s / cnorm(cur.q), cur.q));  // T through |q_j|^2
-                }
-                if (POL & 2) {
-                    cx<double> alphab, betab;
-                    adj_step(zin[t].sp, zin[t].tp, nxj.e, cur.e, Es[t], sb_p, tb_p, alphab, betab, Eb);
-                    eb = cadd(eb, betab);   // beta_j = eta_j
-                    pend_e = alphab;        // alpha_j = eta_{j+1}
-                    eb = cadd(eb, cscale(2.0 * cT_p / cnorm(cur.e), cur.e));  // T through |eta_j|^2
-                }
-                // deltab = -2i conj(E) Eb - 2i cT  (chain and e^{-2 Im sum delta})
-                const cx<double> cE = cmulc(Es[t], Eb);
-                const cx<double> db = {2.0 * cE.im, -2.0 * cE.re - 2.0 * cT};
-                const double gd = two_pi_lam * (db.re * cur.q.re + db.im * cur.q.im);
-                qb = cadd(qb, cscale(two_pi_lam * dj, db));
-                // nb = conj(n/q) qb + conj((n/q)(2 - eta/q)) etab
-                const cx<double> nq = cdiv(cur.n, cur.q);
-                const cx<double> eq = cdiv(cur.e, cur.q);
-                const cx<double> de = cmul(nq, cx<double>{2.0 - eq.re, -eq.im});
-                const cx<double> nb = cadd(cmulc(nq, qb), cmulc(de, eb));
-                const double s0 = wave_sum(gd);
-                const double s1 = wave_sum(nb.re);
-                const double s2 = wave_sum(nb.im);
-                if (lane == 0) {
-                    const int64_t g = (int64_t)b * L + (j - 1);
-                    if (p.grad_d) atomicAdd(p.grad_d + g, s0);
-                    if (p.grad_n) {
-                        atomicAdd(p.grad_n + 2 * g, s1);
-                        atomicAdd(p.grad_n + 2 * g + 1, s2);
-                    }
-                }
-            }
+        } else if (has) {
+            InlSrc src;
+            src.nk = p.nk;
+            src.mrow = mrow;
+            src.base = (int64_t)b * L2;
+            src.n_mat = p.n_mat;
+            src.dispersive = p.dispersive;
+            src.n_wl = p.n_wl;
+            src.i = i;
+            double n0r, n0i;
+            load_n(p.nk, p.dispersive, p.n_wl, src.row(0), i, n0r, n0i);
+            const Ambient amb = make_ambient(n0r, n0i, st, ct);
+            src.kx = amb.kx;
+            grad_stack<POL>(p, src, amb, b, tk.k, i, lane, active, lam_ok && amb.ok && !bad, ws, red, part);
         }
     }
 }
 
-template <int POL>
-__global__ void __launch_bounds__(kGradBlock) grad_kernel(GradParams p) {
-    extern __shared__ __align__(16) unsigned char smem[];
-    const int lane = threadIdx.x & (kWave - 1);
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-    int bid = blockIdx.x;
-    const int tile = bid % p.n_tiles;
-    bid /= p.n_tiles;
-    const int k = bid % p.n_theta;
-    bid /= p.n_theta;
-    const int b0 = bid * p.chunk;
-    const int b1 = min(b0 + p.chunk, p.B);
-    const int i_raw = tile * kWave + lane;
-    const bool active = i_raw < p.n_wl;
-    const int i = active ? i_raw : p.n_wl - 1;
-    const double lam = p.wl[i];
-    const bool lam_ok = lam > 0.0 && lam < __builtin_inf();
-    const double st = p.sin_t[k], ct = p.cos_t[k];
-    const int L2 = p.L + 2;
-    double* ws = p.ws + ((size_t)blockIdx.x * kGradWaves + wave) * (size_t)(p.n_seg + 1) * kCkptDoubles * kWave;
-
-    double2* tab = nullptr;
-    int amb_row = 0;
-    Ambient amb_t;
-    if (p.use_table) {
-        amb_row = p.mat[(int64_t)b0 * L2];
-        amb_row = amb_row < 0 ? 0 : (amb_row >= p.n_mat ? p.n_mat - 1 : amb_row);
-        double n0r, n0i;
-        load_n(p.nk, p.dispersive, p.n_wl, amb_row, i, n0r, n0i);
-        amb_t = make_ambient(n0r, n0i, st, ct);
-        tab = reinterpret_cast<double2*>(smem);
-        for (int m = wave; m < p.n_mat; m += kGradWaves) {
-            double nr, ni;
-            load_n(p.nk, p.dispersive, p.n_wl, m, i, nr, ni);
-            const GLayer g = glayer_from(nr, ni, amb_t.kx);
-            double2* blk = tab + (size_t)m * 3 * kWave + lane;
-            blk[0] = make_double2(g.q.re, g.q.im);
-            blk[kWave] = make_double2(g.e.re, g.e.im);
-            blk[2 * kWave] = make_double2(g.n.re, g.n.im);
+// grad[g] = sum over the columns of partial[col][g] in column order (g runs
+// over the launch's stacks x layers x {d, Re n, Im n}).
+__global__ void grad_reduce(const double* partial, int64_t cols, int64_t n, int64_t g0, double* grad_d,
+                            double* grad_n) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += stride) {
+        double s = 0.0;
+        for (int64_t c = 0; c < cols; ++c) s += partial[c * n + t];
+        const int64_t g = g0 + t / 3;
+        const int comp = (int)(t % 3);
+        if (comp == 0) {
+            if (grad_d) grad_d[g] = s;
+        } else if (grad_n) {
+            grad_n[2 * g + comp - 1] = s;
         }
-        __syncthreads();
-    }
-    for (int b = b0 + wave; b < b1; b += kGradWaves) {
-        const int32_t* mrow = p.mat ? p.mat + (int64_t)b * L2 : nullptr;
-        GSource src;
-        src.nk = p.nk;
-        src.mrow = mrow;
-        src.base = (int64_t)b * L2;
-        src.n_mat = p.n_mat;
-        src.dispersive = p.dispersive;
-        src.n_wl = p.n_wl;
-        src.i = i;
-        src.lane = lane;
-        const int a_row = src.row(0);
-        Ambient amb;
-        if (p.use_table && mrow[0] == amb_row) {
-            amb = amb_t;
-            src.tab = tab;
-        } else {
-            double n0r, n0i;
-            load_n(p.nk, p.dispersive, p.n_wl, a_row, i, n0r, n0i);
-            amb = make_ambient(n0r, n0i, st, ct);
-            src.tab = nullptr;
-        }
-        src.kx = amb.kx;
-        grad_stack<POL>(p, src, amb, b, k, i, active, lam_ok && amb.ok, ws);
     }
 }
 
@@ -428,24 +576,72 @@ __global__ void zero_fill(double* x, int64_t n) {
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += stride) x[t] = 0.0;
 }
 
+// Workspace layout: checkpoint slots of the persistent grid, then the
+// partial sums of the stacks one launch covers (per_stack bytes per stack).
 struct GradShape {
-    int n_tiles, chunk, n_seg;
-    int64_t blocks;
-    size_t ws_bytes;
+    int n_tiles, n_seg;
+    int64_t cols;
+    size_t per_stack, ckpt_bytes;
 };
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 static GradShape grad_shape(const tmm_rt_args* a) {
     GradShape g;
     g.n_tiles = (int)ceil_div(a->n_wl, kWave);
     g.n_seg = (int)ceil_div(a->L, kSeg);
-    const int64_t cols = (int64_t)g.n_tiles * a->n_theta;
-    int64_t chunk = ceil_div((int64_t)a->B * cols, kGradMaxBlocks);
-    chunk = ceil_div(chunk, kGradWaves) * kGradWaves;
-    if (chunk < kGradWaves) chunk = kGradWaves;
-    g.chunk = (int)chunk;
-    g.blocks = cols * ceil_div(a->B, chunk);
-    g.ws_bytes = (size_t)g.blocks * kGradWaves * (size_t)(g.n_seg + 1) * kCkptDoubles * kWave * sizeof(double);
+    g.cols = (int64_t)g.n_tiles * a->n_theta;
+    g.per_stack = (size_t)g.cols * a->L * 3 * sizeof(double);
+    const int64_t tasks = g.cols * ceil_div(a->B, kGradWaves);
+    const int64_t blocks = tasks < kGradMaxBlocks ? tasks : kGradMaxBlocks;
+    g.ckpt_bytes = align256((size_t)blocks * kGradWaves * (size_t)(g.n_seg + 1) * kCkptDoubles * kWave * sizeof(double));
     return g;
+}
+
+static size_t ws_bytes(const GradShape& g, int64_t stacks) { return g.ckpt_bytes + align256((size_t)stacks * g.per_stack); }
+
+// Stacks per launch for a workspace of `bytes` (0 if it is too small): all B,
+// else a multiple of kGradWaves, at least min(B, kGradWaves).
+static int64_t stacks_per_launch(const GradShape& g, int64_t B, size_t bytes) {
+    if (bytes < g.ckpt_bytes) return 0;
+    int64_t n = (int64_t)((bytes - g.ckpt_bytes) / g.per_stack);
+    if (n >= B) return B;
+    n = n / kGradWaves * kGradWaves;
+    return n >= kGradWaves ? n : 0;
+}
+
+static int64_t preferred_stacks(const GradShape& g, int64_t B) {
+    int64_t n = (int64_t)(kPartialCap / g.per_stack);
+    if (n >= B) return B;
+    n = n / kGradWaves * kGradWaves;
+    const int64_t lo = B < kGradWaves ? B : kGradWaves;
+    return n > lo ? n : lo;
+}
+
+// Resident blocks per CU of one kernel variant at this LDS size (cached).
+template <int POL, bool TABLE>
+static int occupancy_blocks(size_t lds) {
+    static std::mutex mu;
+    static std::map<size_t, int> cache;
+    std::lock_guard<std::mutex> g(mu);
+    auto it = cache.find(lds);
+    if (it != cache.end()) return it->second;
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, grad_kernel<POL, TABLE>, kGradBlock, lds) != hipSuccess || n < 1)
+        n = 1;
+    cache[lds] = n;
+    return n;
+}
+
+template <int POL, bool TABLE>
+static hipError_t launch_grad(GradParams p, int n_cu, size_t lds, hipStream_t s) {
+    int64_t grid = (int64_t)n_cu * occupancy_blocks<POL, TABLE>(lds);
+    if (grid > kGradMaxBlocks) grid = kGradMaxBlocks;
+    if (grid > p.n_tasks) grid = p.n_tasks;
+    p.per_block = ceil_div(p.n_tasks, grid);
+    grid = ceil_div(p.n_tasks, p.per_block);
+    hipLaunchKernelGGL((grad_kernel<POL, TABLE>), dim3((unsigned)grid), dim3(kGradBlock), lds, s, p);
+    return hipGetLastError();
 }
 
 }  // namespace tmm
@@ -454,7 +650,14 @@ extern "C" {
 
 size_t tmm_rt_grad_workspace_size(const tmm_rt_args* a) {
     if (!a || a->B <= 0 || a->L <= 0 || a->n_wl <= 0 || a->n_theta <= 0) return 0;
-    return tmm::grad_shape(a).ws_bytes;
+    const tmm::GradShape g = tmm::grad_shape(a);
+    return tmm::ws_bytes(g, tmm::preferred_stacks(g, a->B));
+}
+
+size_t tmm_rt_grad_workspace_min_size(const tmm_rt_args* a) {
+    if (!a || a->B <= 0 || a->L <= 0 || a->n_wl <= 0 || a->n_theta <= 0) return 0;
+    const tmm::GradShape g = tmm::grad_shape(a);
+    return tmm::ws_bytes(g, a->B < tmm::kGradWaves ? a->B : tmm::kGradWaves);
 }
 
 tmm_status tmm_rt_grad(const tmm_rt_args* a, const void* dl_dR, const void* dl_dT, void* grad_d, void* grad_n,
@@ -477,9 +680,15 @@ tmm_status tmm_rt_grad(const tmm_rt_args* a, const void* dl_dR, const void* dl_d
         return tmm::check_launch("tmm_rt_grad");
     }
     const tmm::GradShape g = tmm::grad_shape(a);
-    if (!workspace || workspace_bytes < g.ws_bytes)
-        return fail(TMM_ERR_WORKSPACE, "tmm_rt_grad: workspace of %zu bytes needed, %zu given", g.ws_bytes,
-                    workspace_bytes);
+    const int64_t chunk = workspace ? tmm::stacks_per_launch(g, a->B, workspace_bytes) : 0;
+    if (chunk == 0)
+        return fail(TMM_ERR_WORKSPACE, "tmm_rt_grad: workspace of at least %zu bytes needed (%zu preferred), %zu given",
+                    tmm::ws_bytes(g, a->B < tmm::kGradWaves ? a->B : tmm::kGradWaves),
+                    tmm::ws_bytes(g, tmm::preferred_stacks(g, a->B)), workspace ? workspace_bytes : (size_t)0);
+    int dev = 0, n_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n_cu < 1)
+        return fail(TMM_ERR_HIP, "tmm_rt_grad: no device");
     tmm::GradParams p;
     p.B = a->B;
     p.L = a->L;
@@ -497,24 +706,32 @@ tmm_status tmm_rt_grad(const tmm_rt_args* a, const void* dl_dR, const void* dl_d
     p.gT = static_cast<const double*>(dl_dT);
     p.R_out = static_cast<double*>(a->R);
     p.T_out = static_cast<double*>(a->T);
-    p.grad_d = static_cast<double*>(grad_d);
-    p.grad_n = static_cast<double*>(grad_n);
     p.ws = static_cast<double*>(workspace);
+    p.partial = reinterpret_cast<double*>(static_cast<unsigned char*>(workspace) + g.ckpt_bytes);
     p.n_tiles = g.n_tiles;
-    p.chunk = g.chunk;
     p.n_seg = g.n_seg;
-    p.use_table = (a->mat != nullptr && a->n_mat <= tmm::kGradMaxTableMat) ? 1 : 0;
-    const size_t lds = p.use_table ? (size_t)a->n_mat * 3 * tmm::kWave * sizeof(double2) : 0;
+    const bool table = a->mat != nullptr && a->n_mat <= tmm::kGradMaxTableMat;
+    const size_t lds = (size_t)tmm::kGradWaves * tmm::kRed * tmm::kWave * sizeof(double) +
+                       (table ? (size_t)a->n_mat * tmm::kTabFields * tmm::kWave * sizeof(double2) : 0);
     (void)hipGetLastError();
-    if (grad_d) hipLaunchKernelGGL(tmm::zero_fill, dim3(256), dim3(256), 0, s, p.grad_d, n_grad);
-    if (grad_n) hipLaunchKernelGGL(tmm::zero_fill, dim3(256), dim3(256), 0, s, p.grad_n, 2 * n_grad);
-    const dim3 grid((unsigned)g.blocks), block(tmm::kGradBlock);
-    if (a->pol_mask == 1u)
-        hipLaunchKernelGGL(tmm::grad_kernel<1>, grid, block, lds, s, p);
-    else if (a->pol_mask == 2u)
-        hipLaunchKernelGGL(tmm::grad_kernel<2>, grid, block, lds, s, p);
-    else
-        hipLaunchKernelGGL(tmm::grad_kernel<3>, grid, block, lds, s, p);
+    for (int64_t b0 = 0; b0 < a->B; b0 += chunk) {
+        p.b_begin = (int)b0;
+        p.b_end = (int)(b0 + chunk < a->B ? b0 + chunk : a->B);
+        p.n_tasks = g.cols * tmm::ceil_div(p.b_end - p.b_begin, tmm::kGradWaves);
+        hipError_t e;
+        if (a->pol_mask == 1u)
+            e = table ? tmm::launch_grad<1, true>(p, n_cu, lds, s) : tmm::launch_grad<1, false>(p, n_cu, lds, s);
+        else if (a->pol_mask == 2u)
+            e = table ? tmm::launch_grad<2, true>(p, n_cu, lds, s) : tmm::launch_grad<2, false>(p, n_cu, lds, s);
+        else
+            e = table ? tmm::launch_grad<3, true>(p, n_cu, lds, s) : tmm::launch_grad<3, false>(p, n_cu, lds, s);
+        if (e != hipSuccess) return tmm::check_launch("tmm_rt_grad");
+        const int64_t n = (int64_t)(p.b_end - p.b_begin) * a->L * 3;
+        const int64_t blocks = tmm::ceil_div(n, 256) < 2048 ? tmm::ceil_div(n, 256) : 2048;
+        hipLaunchKernelGGL(tmm::grad_reduce, dim3((unsigned)blocks), dim3(256), 0, s, p.partial, g.cols, n,
+                           (int64_t)p.b_begin * a->L, static_cast<double*>(grad_d),
+                           static_cast<double*>(grad_n));
+    }
     return tmm::check_launch("tmm_rt_grad");
 }
 

@@ -38,36 +38,42 @@ constexpr float kExp2F[7] = {1.000000000e+00f, 6.931471825e-01f, 2.402265072e-01
 // coefficient in scalar registers (it is the same for every lane).  Written as
 // an instruction so that the compiler keeps the coefficients out of vector
 // registers and does not turn the step into a copy plus a two-operand FMA.
+// PIN = false leaves the register choice to the compiler, for kernels whose
+// scalar registers are needed elsewhere.
+template <bool PIN>
 __device__ __forceinline__ double fma3(double a, double x, double c) {
+    if (!PIN) return __builtin_fma(a, x, c);
     double r;
     asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(x), "s"(c));
     return r;
 }
+template <bool PIN>
 __device__ __forceinline__ float fma3(float a, float x, float c) {
+    if (!PIN) return __builtin_fmaf(a, x, c);
     float r;
     asm("v_fma_f32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(x), "s"(c));
     return r;
 }
 
-template <typename T, int N>
+template <bool PIN, typename T, int N>
 __device__ __forceinline__ T horner(const T (&c)[N], T x) {
     T acc = c[N - 1];
 #pragma unroll
-    for (int k = N - 2; k >= 0; --k) acc = fma3(acc, x, c[k]);
+    for (int k = N - 2; k >= 0; --k) acc = fma3<PIN>(acc, x, c[k]);
     return acc;
 }
 
 // Two polynomials in the same variable, Horner steps interleaved so that the
 // two dependency chains hide each other's latency (NA >= NB).
-template <typename T, int NA, int NB>
+template <bool PIN, typename T, int NA, int NB>
 __device__ __forceinline__ void horner2(const T (&a)[NA], const T (&b)[NB], T x, T& pa, T& pb) {
     static_assert(NA >= NB, "first polynomial must be the longer one");
     T A = a[NA - 1], Bc = b[NB - 1];
 #pragma unroll
     for (int k = NA - 2; k >= 0; --k) {
-        A = fma3(A, x, a[k]);
+        A = fma3<PIN>(A, x, a[k]);
         const int kb = k - (NA - NB);
-        if (kb >= 0) Bc = fma3(Bc, x, b[kb]);
+        if (kb >= 0) Bc = fma3<PIN>(Bc, x, b[kb]);
     }
     pa = A;
     pb = Bc;
@@ -84,13 +90,14 @@ __device__ __forceinline__ void rotate_quadrant(int k, T sr, T cr, T& s, T& c) {
 }
 
 // sin(pi x), cos(pi x) for finite x.  x - 2 round(x/2) and x - k/2 are exact.
+template <bool PIN = true>
 __device__ __forceinline__ void sincospi_d(double x, double& s, double& c) {
     x = __builtin_fma(-2.0, __builtin_rint(0.5 * x), x);
     const double k = __builtin_rint(2.0 * x);
     const double r = __builtin_fma(-0.5, k, x);
     const double r2 = r * r;
     double ps, pc;
-    horner2(kCosPiD, kSinPiD, r2, pc, ps);
+    horner2<PIN>(kCosPiD, kSinPiD, r2, pc, ps);
     rotate_quadrant((int)k, r * ps, pc, s, c);
 }
 
@@ -100,24 +107,25 @@ __device__ __forceinline__ void sincospi_f(float x, float& s, float& c) {
     const float r = __builtin_fmaf(-0.5f, k, x);
     const float r2 = r * r;
     float ps, pc;
-    horner2(kCosPiF, kSinPiF, r2, pc, ps);
+    horner2<true>(kCosPiF, kSinPiF, r2, pc, ps);
     rotate_quadrant((int)k, r * ps, pc, s, c);
 }
 
 // 2^y; y is clamped to [-1100, 1100] so that the exponent fits an int
 // (ldexp then gives 0 or inf, as 2^y itself would).
+template <bool PIN = true>
 __device__ __forceinline__ double exp2_d(double y) {
     y = __builtin_fmin(__builtin_fmax(y, -1100.0), 1100.0);
     const double k = __builtin_rint(y);
     const double f = y - k;
-    return __builtin_amdgcn_ldexp(horner(kExp2D, f), (int)k);
+    return __builtin_amdgcn_ldexp(horner<PIN>(kExp2D, f), (int)k);
 }
 
 __device__ __forceinline__ float exp2_f(float y) {
     y = __builtin_fminf(__builtin_fmaxf(y, -200.0f), 200.0f);
     const float k = __builtin_rintf(y);
     const float f = y - k;
-    return __builtin_amdgcn_ldexpf(horner(kExp2F, f), (int)k);
+    return __builtin_amdgcn_ldexpf(horner<true>(kExp2F, f), (int)k);
 }
 
 }  // namespace tmm

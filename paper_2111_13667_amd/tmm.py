@@ -64,6 +64,8 @@ def library() -> ctypes.CDLL:
         lib.tmm_version.restype = ctypes.c_char_p
         lib.tmm_rt_grad_workspace_size.restype = ctypes.c_size_t
         lib.tmm_rt_grad_workspace_size.argtypes = [ctypes.POINTER(TmmRtArgs)]
+        lib.tmm_rt_grad_workspace_min_size.restype = ctypes.c_size_t
+        lib.tmm_rt_grad_workspace_min_size.argtypes = [ctypes.POINTER(TmmRtArgs)]
         lib.tmm_rt_grad.restype = ctypes.c_int
         lib.tmm_rt_grad.argtypes = [ctypes.POINTER(TmmRtArgs)] + [ctypes.c_void_p] * 5 + \
             [ctypes.c_size_t, ctypes.c_int, ctypes.c_void_p]
@@ -174,10 +176,13 @@ def _rt_args(d, nk, wl, sin_theta, cos_theta, mat, n_mat, dispersive, pol_mask, 
                      _ptr(R), _ptr(T), _ptr(r), _ptr(t))
 
 
-def grad_workspace_size(d, nk, wl, sin_theta, cos_theta, *, mat=None, pol_mask=3) -> int:
+def grad_workspace_size(d, nk, wl, sin_theta, cos_theta, *, mat=None, pol_mask=3, minimum=False) -> int:
+    """Preferred (or, with minimum=True, smallest accepted) tmm_rt_grad workspace bytes."""
     _check_shapes(d, nk, wl, sin_theta, cos_theta, mat, None, None)
     a = _rt_args(d, nk, wl, sin_theta, cos_theta, mat, None, None, pol_mask)
-    return int(library().tmm_rt_grad_workspace_size(ctypes.byref(a)))
+    lib = library()
+    f = lib.tmm_rt_grad_workspace_min_size if minimum else lib.tmm_rt_grad_workspace_size
+    return int(f(ctypes.byref(a)))
 
 
 def tmm_rt_grad(d, nk, wl, sin_theta, cos_theta, *, mat=None, n_mat=None, dispersive=None,
@@ -186,7 +191,8 @@ def tmm_rt_grad(d, nk, wl, sin_theta, cos_theta, *, mat=None, n_mat=None, disper
     """Launch tmm_rt_grad (float64): gradients of sum(dl_dR * R + dl_dT * T) w.r.t.
     d [B, L] into grad_d [B, L] and w.r.t. the finite layers' indices into
     grad_n [B, L] complex128.  workspace: a uint8 device tensor of at least
-    grad_workspace_size(...) bytes (allocated here if None)."""
+    grad_workspace_size(..., minimum=True) bytes (the preferred size is
+    allocated here if None)."""
     import torch
     if d.dtype != torch.float64:
         raise TypeError("tmm_rt_grad is float64 only")
