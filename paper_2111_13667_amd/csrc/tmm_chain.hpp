@@ -38,10 +38,11 @@ struct Chain {
         F = 0.0;
     }
 
-    __device__ __forceinline__ void step(const Layer<R>& cur, const Layer<R>& nxt, double cd, bool lossy) {
+    __device__ __forceinline__ void step(const Layer<R>& cur, const Layer<R>& nxt, double cd, bool lossy,
+                                         const TabPhase<R>& phase) {
         const double phr = cd * cur.pr;
         const double phi = cd * cur.pi;
-        const cx<R> E = phase_factor<R>(phr, phi, lossy);
+        const cx<R> E = phase(phr, phi, lossy);
         if (POL & 1) {
             const cx<R> A = cmul(cur.q, ss), Bv = cmul(nxt.q, ts);
             const cx<R> a = cadd(A, Bv), b = csub(A, Bv);
@@ -64,7 +65,7 @@ struct Chain {
         } else {
             if (POL & 1) pis *= cur.q2;
             if (POL & 2) pip *= cur.e2;
-            if (lossy) S += phi;
+            S += phi;  // exactly 0 for a lossless row (Im q = 0 in every lane)
         }
     }
 

@@ -175,6 +175,66 @@ struct PhaseFactor<float, true> {
     }
 };
 
+// Phase factor through an LDS copy of the (cos, sin) table of tmm_math.hpp;
+// same contract as phase_factor.  Every workgroup fills its copy once
+// (fill_phase_tab, then a barrier) before the layer loops use it.
+template <typename R, bool PIN = true>
+struct TabPhase;
+
+template <bool PIN>
+struct TabPhase<double, PIN> {
+    const double2* tab;
+    __device__ __forceinline__ cx<double> operator()(double phr, double phi_im, bool lossy) const {
+        double s, c;
+        sincospi_tab<PIN>(phr, tab, s, c);
+        if (lossy) {
+            const double rho = exp2_d<PIN>(phi_im * kNegPiLog2e);
+            s *= rho;
+            c *= rho;
+        }
+        return {c, s};
+    }
+};
+
+template <>
+struct TabPhase<float, true> {
+    const float2* tab;
+    __device__ __forceinline__ cx<float> operator()(double phr, double phi_im, bool lossy) const {
+        float s, c;
+        sincospi_tab_f(phr, tab, s, c);
+        if (lossy) {
+            const float rho = exp2_f((float)(phi_im * kNegPiLog2e));
+            s *= rho;
+            c *= rho;
+        }
+        return {c, s};
+    }
+};
+
+// LDS bytes of the table copy (a multiple of 16).
+template <typename R>
+__host__ __device__ constexpr size_t phase_tab_bytes() {
+    return ((size_t)kScEntries * 2 * sizeof(R) + 15) / 16 * 16;
+}
+
+// Copy the table into LDS at `lds`; threads tid = 0..nthr-1 of the workgroup share the work.
+template <typename R>
+__device__ __forceinline__ void fill_phase_tab(unsigned char* lds, int tid, int nthr) {
+    for (int e = tid; e < kScEntries; e += nthr) {
+        if (sizeof(R) == 8)
+            reinterpret_cast<double2*>(lds)[e] = make_double2(kScTabD[e][0], kScTabD[e][1]);
+        else
+            reinterpret_cast<float2*>(lds)[e] = make_float2(kScTabF[e][0], kScTabF[e][1]);
+    }
+}
+
+template <typename R>
+__device__ __forceinline__ TabPhase<R> phase_of(const unsigned char* lds) {
+    TabPhase<R> t;
+    t.tab = reinterpret_cast<decltype(t.tab)>(lds);
+    return t;
+}
+
 // x - 4 round(x / 4): exact, keeps a running half-turn phase within [-2, 2].
 __device__ __forceinline__ double reduce4(double x) { return x - 4.0 * rint(0.25 * x); }
 

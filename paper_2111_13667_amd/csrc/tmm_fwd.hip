@@ -49,9 +49,8 @@ struct FwdParams {
 
 template <typename R>
 __host__ __device__ constexpr size_t table_bytes(int n_mat) {
-    // media table, lossy flags, per-wave layer staging (d: 8 B, code: 4 B per layer)
-    return (size_t)n_mat * kWave * Table<R>::kEntryBytes + 4 * kMaxTableMat +
-           (size_t)kWavesPerBlock * kWave * 12;
+    // phase table, media table, lossy flags
+    return phase_tab_bytes<R>() + (size_t)n_mat * kWave * Table<R>::kEntryBytes + 4 * kMaxTableMat;
 }
 
 // Sources of per-layer values for the chain.  Row ids are wave-uniform.
@@ -122,7 +121,7 @@ __device__ __forceinline__ void store_point(const FwdParams<R>& p, int b, int k,
 template <typename R, int POL, bool AMP, class Src>
 __device__ __forceinline__ void run_stack(const FwdParams<R>& p, const Src& src, const Ambient& amb,
                                           int b, int k, int i, bool active, bool lane_ok,
-                                          double c4lam, double nsub_r, double nsub_i) {
+                                          double c4lam, double nsub_r, double nsub_i, const TabPhase<R>& phase) {
     const int L = p.L;
     const R* drow = p.d + (int64_t)b * L;
     bool bad = src.row_bad(0) || src.row_bad(L + 1);
@@ -136,7 +135,7 @@ __device__ __forceinline__ void run_stack(const FwdParams<R>& p, const Src& src,
         const R dj = drow[j - 1];
         bad = bad || bad_thickness(dj) || src.row_bad(j);
         const Layer<R> cur = src.layer(j, lossy);
-        c.step(cur, nxt, (double)dj * c4lam, lossy);
+        c.step(cur, nxt, (double)dj * c4lam, lossy, phase);
         nxt = cur;
         if (++cnt == RenormPeriod<R>::value) {
             cnt = 0;
@@ -154,27 +153,14 @@ __device__ __forceinline__ void run_stack(const FwdParams<R>& p, const Src& src,
     }
 }
 
-// Per-wave LDS staging of one stack's layers: thickness and table row of up to
-// kWave layers at a time, written by one lane each and read back as
-// wave-uniform values by the layer loop.
-struct Stage {
-    double d[kWave];
-    int code[kWave];  // table row | lossy flag << 16
-};
-
-__device__ __forceinline__ void wave_sync_lds() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// Table path: one stack, layers staged through LDS in chunks of kWave, loop
-// unrolled by two so that the current/next medium values rotate in registers.
+// Table path: one stack.  The layers are read in chunks of kWave, one per lane
+// (coalesced), and the layer loop broadcasts them from the owning lane; whole
+// renormalisation blocks are unrolled, so no value is copied between steps.
 template <typename R, int POL, bool AMP>
 __device__ __forceinline__ void run_stack_table(const FwdParams<R>& p, const Table<R>& tab, uint32_t lossy_mask,
-                                                Stage& stg, const Ambient& amb, int b, int k, int i, int lane,
+                                                const Ambient& amb, int b, int k, int i, int lane,
                                                 bool active, bool lane_ok, double c4lam, double nsub_r,
-                                                double nsub_i) {
+                                                double nsub_i, const TabPhase<R>& phase) {
     const int L = p.L;
     const int n_mat = p.n_mat;
     const R* drow = p.d + (int64_t)b * L;
@@ -186,11 +172,14 @@ __device__ __forceinline__ void run_stack_table(const FwdParams<R>& p, const Tab
     Layer<R> nxt = sub;
     Chain<R, POL, AMP> c;
     c.init();
-    int cnt = 0;
+    static_assert(kWave % RenormPeriod<R>::value == 0, "chunks must hold whole renormalisation blocks");
+    constexpr int RP = RenormPeriod<R>::value;
     for (int top = L; top >= 1; top -= kWave) {
         const int lo = top - kWave + 1 > 1 ? top - kWave + 1 : 1;
-        // stage layers lo..top
+        // lane l holds layer lo + l: thickness and table row | lossy flag << 16
         const int j = lo + lane;
+        double my_d = 0.0;
+        int my_code = 0;
         bool lane_bad = false;
         if (j <= top) {
             const R dj = drow[j - 1];
@@ -198,24 +187,31 @@ __device__ __forceinline__ void run_stack_table(const FwdParams<R>& p, const Tab
             const bool mbad = (uint32_t)m >= (uint32_t)n_mat;
             lane_bad = mbad || bad_thickness(dj);
             const int mc = mbad ? 0 : m;
-            stg.d[lane] = (double)dj;
-            stg.code[lane] = mc | (int)(((lossy_mask >> mc) & 1u) << 16);
+            my_d = (double)dj;
+            my_code = mc | (int)(((lossy_mask >> mc) & 1u) << 16);
         }
         bad = bad || __any(lane_bad);
-        wave_sync_lds();
-#pragma unroll 2
-        for (int jj = top; jj >= lo; --jj) {
-            const int code = __builtin_amdgcn_readfirstlane(stg.code[jj - lo]);
-            const double dj = stg.d[jj - lo];
+        // one step: layer jj's values broadcast from lane jj - lo
+        auto step = [&](int jj) {
+            const int sl = jj - lo;
+            const int code = __builtin_amdgcn_readlane(my_code, sl);
+            const double dj = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(my_d), sl),
+                                               __builtin_amdgcn_readlane(__double2loint(my_d), sl));
             const Layer<R> cur = tab.get(code & 0xffff, lane);
-            c.step(cur, nxt, dj * c4lam, (code >> 16) != 0);
+            c.step(cur, nxt, dj * c4lam, (code >> 16) != 0, phase);
             nxt = cur;
-            if (++cnt == RenormPeriod<R>::value) {
-                cnt = 0;
+        };
+        // blocks of RP steps; chunks start at multiples of kWave steps, so the
+        // renormalisation points are those of a running step count
+        for (int bt = top; bt >= lo; bt -= RP) {
+            if (bt - lo >= RP - 1) {
+#pragma unroll 2
+                for (int u = 0; u < RP; ++u) step(bt - u);
                 c.renorm();
+            } else {
+                for (int jj = bt; jj >= lo; --jj) step(jj);
             }
         }
-        wave_sync_lds();
     }
     c.renorm();
     PointOut out[2];
@@ -248,6 +244,10 @@ __global__ void __launch_bounds__(kBlock) fwd_kernel(FwdParams<R> p) {
     const double c4lam = 4.0 / lam;  // phi_j = 4 d_j q_j / lambda half-turns = 2 delta_j / pi
     const double st = (double)p.sin_t[k], ct = (double)p.cos_t[k];
     const int L2 = p.L + 2;
+    fill_phase_tab<R>(smem, threadIdx.x, kBlock);
+    const TabPhase<R> phase = phase_of<R>(smem);
+    unsigned char* const lds = smem + phase_tab_bytes<R>();
+    if (!TABLE) __syncthreads();
 
     if (TABLE) {
         int amb_row = p.mat[(int64_t)b0 * L2];
@@ -255,10 +255,8 @@ __global__ void __launch_bounds__(kBlock) fwd_kernel(FwdParams<R> p) {
         double n0r, n0i;
         load_n(p.nk, p.dispersive, p.n_wl, amb_row, i, n0r, n0i);
         const Ambient amb = make_ambient(n0r, n0i, st, ct);
-        Table<R> tab(smem, p.n_mat);
-        int* flags = reinterpret_cast<int*>(smem + (size_t)p.n_mat * kWave * Table<R>::kEntryBytes);
-        Stage* stages = reinterpret_cast<Stage*>(smem + (size_t)p.n_mat * kWave * Table<R>::kEntryBytes +
-                                                 4 * kMaxTableMat);
+        Table<R> tab(lds, p.n_mat);
+        int* flags = reinterpret_cast<int*>(lds + (size_t)p.n_mat * kWave * Table<R>::kEntryBytes);
         for (int m = wave; m < p.n_mat; m += kWavesPerBlock) {
             double nr, ni;
             load_n(p.nk, p.dispersive, p.n_wl, m, i, nr, ni);
@@ -278,8 +276,8 @@ __global__ void __launch_bounds__(kBlock) fwd_kernel(FwdParams<R> p) {
             double nsr = 0.0, nsi = 0.0;
             if (AMP) load_n(p.nk, p.dispersive, p.n_wl, sub_row, i, nsr, nsi);
             if (mrow[0] == amb_row) {
-                run_stack_table<R, POL, AMP>(p, tab, mask, stages[wave], amb, b, k, i, lane, active,
-                                             lam_ok && amb.ok, c4lam, nsr, nsi);
+                run_stack_table<R, POL, AMP>(p, tab, mask, amb, b, k, i, lane, active,
+                                             lam_ok && amb.ok, c4lam, nsr, nsi, phase);
             } else {
                 int a_row = mrow[0];
                 a_row = a_row < 0 ? 0 : (a_row >= p.n_mat ? p.n_mat - 1 : a_row);
@@ -287,7 +285,7 @@ __global__ void __launch_bounds__(kBlock) fwd_kernel(FwdParams<R> p) {
                 load_n(p.nk, p.dispersive, p.n_wl, a_row, i, ar, ai);
                 const Ambient amb_b = make_ambient(ar, ai, st, ct);
                 InlineSource<R> src{p.nk, mrow, 0, p.n_mat, p.dispersive, p.n_wl, i, amb_b.kx};
-                run_stack<R, POL, AMP>(p, src, amb_b, b, k, i, active, lam_ok && amb_b.ok, c4lam, nsr, nsi);
+                run_stack<R, POL, AMP>(p, src, amb_b, b, k, i, active, lam_ok && amb_b.ok, c4lam, nsr, nsi, phase);
             }
         }
     } else {
@@ -305,7 +303,7 @@ __global__ void __launch_bounds__(kBlock) fwd_kernel(FwdParams<R> p) {
             double nsr = 0.0, nsi = 0.0;
             if (AMP) load_n(p.nk, p.dispersive, p.n_wl, row_of(p.L + 1), i, nsr, nsi);
             InlineSource<R> src{p.nk, mrow, base, p.n_mat, p.dispersive, p.n_wl, i, amb.kx};
-            run_stack<R, POL, AMP>(p, src, amb, b, k, i, active, lam_ok && amb.ok, c4lam, nsr, nsi);
+            run_stack<R, POL, AMP>(p, src, amb, b, k, i, active, lam_ok && amb.ok, c4lam, nsr, nsi, phase);
         }
     }
 }
@@ -369,7 +367,7 @@ static tmm_status run_fwd(const tmm_rt_args* a, hipStream_t s) {
                                          (long long)blocks);
     const bool table = a->mat != nullptr && a->n_mat <= kMaxTableMat;
     const bool amp = a->r != nullptr || a->t != nullptr;
-    const size_t lds = table ? table_bytes<R>(a->n_mat) : 0;
+    const size_t lds = table ? table_bytes<R>(a->n_mat) : phase_tab_bytes<R>();
     (void)hipGetLastError();
     hipError_t e = table ? dispatch_pol<R, true>(p, a->pol_mask, amp, (int)blocks, lds, s)
                          : dispatch_pol<R, false>(p, a->pol_mask, amp, (int)blocks, lds, s);

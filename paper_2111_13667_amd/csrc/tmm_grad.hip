@@ -235,7 +235,8 @@ __device__ __forceinline__ bool stack_bad(const GradParams& p, const double* dro
 
 template <int POL, typename Src>
 __device__ void grad_stack(const GradParams& p, const Src& src, const Ambient& amb, int b, int k, int i, int lane,
-                           bool active, bool valid, double* ws, double* red, double* part) {
+                           bool active, bool valid, double* ws, double* red, double* part,
+                           const TabPhase<double>& phase) {
     const int L = p.L;
     constexpr int P = (POL == 3) ? 2 : 1;
     const double lam = p.wl[i];
@@ -270,7 +271,7 @@ __device__ void grad_stack(const GradParams& p, const Src& src, const Ambient& a
             const double cd = drow[j - 1] * c4lam;
             const double phi = cd * cur.q.im;
             const bool lossy = __any(phi != 0.0);
-            const cx<double> E = phase_factor<double, true>(cd * cur.q.re, phi, lossy);
+            const cx<double> E = phase(cd * cur.q.re, phi, lossy);
             fwd_step<POL>(z, cur, nxt, E);
             if (POL & 1) pis *= cnorm(cur.q);
             if (POL & 2) pip *= cnorm(cur.e);
@@ -356,7 +357,7 @@ __device__ void grad_stack(const GradParams& p, const Src& src, const Ambient& a
             const double cd = drow[j - 1] * c4lam;
             const double phi = cd * cur.q.im;
             const bool lossy = __any(phi != 0.0);
-            Es[t] = phase_factor<double, true>(cd * cur.q.re, phi, lossy);
+            Es[t] = phase(cd * cur.q.re, phi, lossy);
             zin[t] = zz;
             fwd_step<POL>(zz, cur, nx, Es[t]);
             nx = cur;
@@ -482,8 +483,12 @@ __global__ void __launch_bounds__(kGradBlock) __attribute__((amdgpu_waves_per_eu
     __shared__ int s_rows[kGradWaves];
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-    double* red = reinterpret_cast<double*>(smem) + wave * kRed * kWave;
-    double2* tab = reinterpret_cast<double2*>(smem + (size_t)kGradWaves * kRed * kWave * sizeof(double));
+    fill_phase_tab<double>(smem, threadIdx.x, kGradBlock);
+    __syncthreads();
+    const TabPhase<double> phase = phase_of<double>(smem);
+    unsigned char* const lds = smem + phase_tab_bytes<double>();
+    double* red = reinterpret_cast<double*>(lds) + wave * kRed * kWave;
+    double2* tab = reinterpret_cast<double2*>(lds + (size_t)kGradWaves * kRed * kWave * sizeof(double));
     double* ws = p.ws + ((size_t)blockIdx.x * kGradWaves + wave) * (size_t)(p.n_seg + 1) * kCkptDoubles * kWave;
     const int L2 = p.L + 2;
     const int64_t nbs = p.b_end - p.b_begin;
@@ -531,7 +536,8 @@ __global__ void __launch_bounds__(kGradBlock) __attribute__((amdgpu_waves_per_eu
                     src.tab = tab + lane;
                     src.mrow = mrow;
                     src.n_mat = p.n_mat;
-                    grad_stack<POL>(p, src, amb, b, tk.k, i, lane, active, lam_ok && amb.ok && !bad, ws, red, part);
+                    grad_stack<POL>(p, src, amb, b, tk.k, i, lane, active, lam_ok && amb.ok && !bad, ws, red, part,
+                                    phase);
                     done = true;
                 }
             }
@@ -548,7 +554,7 @@ __global__ void __launch_bounds__(kGradBlock) __attribute__((amdgpu_waves_per_eu
             load_n(p.nk, p.dispersive, p.n_wl, src.row(0), i, n0r, n0i);
             const Ambient amb = make_ambient(n0r, n0i, st, ct);
             src.kx = amb.kx;
-            grad_stack<POL>(p, src, amb, b, tk.k, i, lane, active, lam_ok && amb.ok && !bad, ws, red, part);
+            grad_stack<POL>(p, src, amb, b, tk.k, i, lane, active, lam_ok && amb.ok && !bad, ws, red, part, phase);
         }
     }
 }
@@ -711,7 +717,7 @@ tmm_status tmm_rt_grad(const tmm_rt_args* a, const void* dl_dR, const void* dl_d
     p.n_tiles = g.n_tiles;
     p.n_seg = g.n_seg;
     const bool table = a->mat != nullptr && a->n_mat <= tmm::kGradMaxTableMat;
-    const size_t lds = (size_t)tmm::kGradWaves * tmm::kRed * tmm::kWave * sizeof(double) +
+    const size_t lds = tmm::phase_tab_bytes<double>() + (size_t)tmm::kGradWaves * tmm::kRed * tmm::kWave * sizeof(double) +
                        (table ? (size_t)a->n_mat * tmm::kTabFields * tmm::kWave * sizeof(double2) : 0);
     (void)hipGetLastError();
     for (int64_t b0 = 0; b0 < a->B; b0 += chunk) {

@@ -118,15 +118,7 @@ struct WaveTable<float> {
     }
 };
 
-// Per-wave staging of a unit's layers (thickness, table row), kWave at a time.
-struct WaveStage {
-    double d[kWave];
-    int m[kWave];
-};
-
-__host__ __device__ constexpr size_t wave_lds_bytes(int n_mat) {
-    return (size_t)n_mat * kWave * 32 + sizeof(WaveStage);
-}
+__host__ __device__ constexpr size_t wave_lds_bytes(int n_mat) { return (size_t)n_mat * kWave * 32; }
 
 __global__ void reset_counter(unsigned long long* c) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *c = 0ull;
@@ -137,9 +129,11 @@ __global__ void __launch_bounds__(kThreads) ragged_kernel(Params<R> p) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-    unsigned char* my = smem + (size_t)wave * wave_lds_bytes(p.n_mat);
+    fill_phase_tab<R>(smem, threadIdx.x, kThreads);
+    __syncthreads();
+    const TabPhase<R> phase = phase_of<R>(smem);
+    unsigned char* my = smem + phase_tab_bytes<R>() + (size_t)wave * wave_lds_bytes(p.n_mat);
     WaveTable<R> tab(my);
-    WaveStage& stg = *reinterpret_cast<WaveStage*>(my + (size_t)p.n_mat * kWave * 32);
     constexpr int P = (POL == 3) ? 2 : 1;
     for (;;) {
         unsigned long long base = 0;
@@ -190,36 +184,42 @@ __global__ void __launch_bounds__(kThreads) ragged_kernel(Params<R> p) {
             Layer<R> nxt = sub;
             Chain<R, POL, false> c;
             c.init();
-            int cnt = 0;
+            constexpr int RP = RenormPeriod<R>::value;
+            static_assert(kWave % RP == 0, "chunks must hold whole renormalisation blocks");
             for (int top = L; top >= 1; top -= kWave) {
                 const int lo = top - kWave + 1 > 1 ? top - kWave + 1 : 1;
-                const int j = lo + lane;  // stage layers lo..top, one per lane
+                // lane l holds layer lo + l (thickness, table row); the loop broadcasts them
+                const int j = lo + lane;
+                double my_d = 0.0;
+                int my_m = 0;
                 bool lane_bad = false;
                 if (j <= top) {
                     const R dj = drow[j - 1];
                     const int m = mrow[j - 1];
                     lane_bad = bad_thickness(dj) || (uint32_t)m >= (uint32_t)p.n_mat;
-                    stg.d[lane] = (double)dj;
-                    stg.m[lane] = min(max(m, 0), p.n_mat - 1);
+                    my_d = (double)dj;
+                    my_m = min(max(m, 0), p.n_mat - 1);
                 }
                 bad = bad || __any(lane_bad);
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-#pragma unroll 2
-                for (int jj = top; jj >= lo; --jj) {
-                    const int m = __builtin_amdgcn_readfirstlane(stg.m[jj - lo]);
+                auto step = [&](int jj) {
+                    const int sl = jj - lo;
+                    const int m = __builtin_amdgcn_readlane(my_m, sl);
+                    const double dj = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(my_d), sl),
+                                                       __builtin_amdgcn_readlane(__double2loint(my_d), sl));
                     const Layer<R> cur = tab.get(m, lane);
-                    c.step(cur, nxt, stg.d[jj - lo] * c4lam, (lossy_mask >> m) & 1u);
+                    c.step(cur, nxt, dj * c4lam, (lossy_mask >> m) & 1u, phase);
                     nxt = cur;
-                    if (++cnt == RenormPeriod<R>::value) {
-                        cnt = 0;
+                };
+                // renormalisation blocks at the points of a running step count
+                for (int bt = top; bt >= lo; bt -= RP) {
+                    if (bt - lo >= RP - 1) {
+#pragma unroll 2
+                        for (int u = 0; u < RP; ++u) step(bt - u);
                         c.renorm();
+                    } else {
+                        for (int jj = bt; jj >= lo; --jj) step(jj);
                     }
                 }
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             }
             c.renorm();
             PointOut out[2];
@@ -306,7 +306,7 @@ tmm::ragged::Params<R> make_params(const tmm_ragged_plan* pl, const tmm_ragged_d
 template <typename R>
 hipError_t launch(const tmm_ragged_plan* pl, tmm::ragged::Params<R> p, tmm::ragged::Shape sh, hipStream_t s) {
     p.grain = sh.grain;
-    const size_t lds = (size_t)tmm::ragged::kWaves * tmm::ragged::wave_lds_bytes(p.n_mat);
+    const size_t lds = tmm::phase_tab_bytes<R>() + (size_t)tmm::ragged::kWaves * tmm::ragged::wave_lds_bytes(p.n_mat);
     const int blocks = pl->n_cu * sh.blocks_per_cu;
     hipLaunchKernelGGL(tmm::ragged::reset_counter, dim3(1), dim3(64), 0, s, pl->d_counter);
     if (pl->pol_mask == 1u)
