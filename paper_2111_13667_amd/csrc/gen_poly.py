@@ -1,10 +1,9 @@
 """Generate the polynomial coefficients and tables of tmm_math.hpp.
 
 Near-minimax (Chebyshev) fits in 60-digit arithmetic with mpmath:
-  sin(pi r) = r * S(r^2),  cos(pi r) = C(r^2)   for |r| <= 1/4,
   2^f = E(f)                                     for |f| <= 1/2,
   sin(pi h) = h * Sh(h^2), cos(pi h) = Ch(h^2)  for |h| <= 1/128 (table residual).
-Degrees: double S 6, C 7, E 11, Sh 3, Ch 3; float S 3, C 4, E 6, Sh 1, Ch 2.
+Degrees: double E 11, Sh 3, Ch 3; float E 6, Sh 1, Ch 2.
 The printed fit errors are the approximation errors before rounding the
 coefficients.  The tables hold cos(pi k/64), sin(pi k/64) for k = -64..64,
 rounded to nearest from 60-digit values.
@@ -17,12 +16,8 @@ mp.mp.dps = 60
 sinc_pi = lambda s: mp.sinpi(mp.sqrt(s)) / mp.sqrt(s) if s != 0 else mp.pi
 cos_pi = lambda s: mp.cospi(mp.sqrt(s))
 exp2 = lambda x: mp.power(2, x)
-Q = mp.mpf(1) / 16
 H = mp.mpf(1) / (128 * 128)
-FITS = [("kSinPiD", sinc_pi, 0, Q, 6, "double"), ("kCosPiD", cos_pi, 0, Q, 7, "double"),
-        ("kExp2D", exp2, -0.5, 0.5, 11, "double"),
-        ("kSinPiF", sinc_pi, 0, Q, 3, "float"), ("kCosPiF", cos_pi, 0, Q, 4, "float"),
-        ("kExp2F", exp2, -0.5, 0.5, 6, "float"),
+FITS = [("kExp2D", exp2, -0.5, 0.5, 11, "double"), ("kExp2F", exp2, -0.5, 0.5, 6, "float"),
         ("kSinHD", sinc_pi, 0, H, 3, "double"), ("kCosHD", cos_pi, 0, H, 3, "double"),
         ("kSinHF", sinc_pi, 0, H, 1, "float"), ("kCosHF", cos_pi, 0, H, 2, "float")]
 

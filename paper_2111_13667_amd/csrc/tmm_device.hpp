@@ -133,51 +133,12 @@ __device__ __forceinline__ Layer<R> to_layer(const Medium& m) {
     return v;
 }
 
-// E = e^{i pi phi} for phi = phr + i phi_im (half-turns).  `lossy` is wave-uniform
-// and false only when phi_im == 0 in every lane, where the modulus is exactly 1.
-// PIN: polynomial coefficients pinned in scalar registers (see fma3).
-template <typename R, bool PIN = true>
-struct PhaseFactor;
-
-template <bool PIN>
-struct PhaseFactor<double, PIN> {
-    static __device__ __forceinline__ cx<double> eval(double phr, double phi_im, bool lossy) {
-        double s, c;
-        sincospi_d<PIN>(phr, s, c);
-        if (lossy) {
-            const double rho = exp2_d<PIN>(phi_im * kNegPiLog2e);
-            s *= rho;
-            c *= rho;
-        }
-        return {c, s};
-    }
-};
-
-template <typename R, bool PIN = true>
-__device__ __forceinline__ cx<R> phase_factor(double phr, double phi_im, bool lossy) {
-    return PhaseFactor<R, PIN>::eval(phr, phi_im, lossy);
-}
-
-template <>
-struct PhaseFactor<float, true> {
-    static __device__ __forceinline__ cx<float> eval(double phr, double phi_im, bool lossy) {
-        // Exact reduction by a multiple of the period (2 half-turns) in double, then
-        // a float sin/cos of |x| <= 1 half-turn.
-        const float x = (float)__builtin_fma(-2.0, __builtin_rint(0.5 * phr), phr);
-        float s, c;
-        sincospi_f(x, s, c);
-        if (lossy) {
-            const float rho = exp2_f((float)(phi_im * kNegPiLog2e));
-            s *= rho;
-            c *= rho;
-        }
-        return {c, s};
-    }
-};
-
-// Phase factor through an LDS copy of the (cos, sin) table of tmm_math.hpp;
-// same contract as phase_factor.  Every workgroup fills its copy once
-// (fill_phase_tab, then a barrier) before the layer loops use it.
+// E = e^{i pi phi} for phi = phr + i phi_im (half-turns), through an LDS copy
+// of the (cos, sin) table of tmm_math.hpp.  `lossy` is wave-uniform and false
+// only when phi_im == 0 in every lane, where the modulus is exactly 1.  Every
+// workgroup fills its copy once (fill_phase_tab, then a barrier) before the
+// layer loops use it.  PIN: polynomial coefficients pinned in scalar registers
+// (see fma3).
 template <typename R, bool PIN = true>
 struct TabPhase;
 
