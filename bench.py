@@ -192,6 +192,8 @@ def main():
                     help="skip the other-precision, amplitude, adjoint and ragged measurements")
     ap.add_argument("--cpu-stacks", type=int, default=64)
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"))
+    ap.add_argument("--only", choices=["adjoint", "ragged_f64", "ragged_f32"], default=None,
+                    help="run only this extra measurement and print its record (for profiling)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="first run a plain N-MiB elementwise copy kernel (profiler calibration)")
     args = ap.parse_args()
@@ -207,6 +209,14 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py: no GPU visible", file=sys.stderr)
         sys.exit(1)
+
+    if args.only:
+        if args.only == "adjoint":
+            rec = time_grad(max(1, args.steps))
+        else:
+            rec = time_ragged(args.only.split("_")[1], max(1, args.steps))
+        print(json.dumps({"only": args.only, **rec}), flush=True)
+        return
 
     from paper_2111_13667_amd import workloads
     w = workloads.large_batch()
