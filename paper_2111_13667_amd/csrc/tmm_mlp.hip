@@ -304,11 +304,18 @@ unsigned grid1(int64_t n) {
     return (unsigned)g;
 }
 
-// Launch one batched NT GEMM (all members) with the given epilogue.
+// Launch one batched NT GEMM (all members) with the given epilogue: 256 x 128
+// tiles when M allows, else 128 x 128 (every dimension is a multiple of 128).
 template <int EPI>
 void gemm(hipStream_t s, int E, const tmm::mlp::GemmArgs& g) {
-    dim3 grid(g.N / tmm::mlp::kBN, g.M / tmm::mlp::kBM, E);
-    hipLaunchKernelGGL(tmm::mlp::gemm_nt_bf16<EPI>, grid, dim3(tmm::mlp::kGemmThreads), 0, s, g);
+    constexpr int BN = 2 * tmm::mlp::kWN;
+    if (g.M % 256 == 0) {
+        dim3 grid(g.N / BN, g.M / 256, E);
+        hipLaunchKernelGGL((tmm::mlp::gemm_nt_bf16<EPI, 128>), grid, dim3(tmm::mlp::kGemmThreads), 0, s, g);
+    } else {
+        dim3 grid(g.N / BN, g.M / 128, E);
+        hipLaunchKernelGGL((tmm::mlp::gemm_nt_bf16<EPI, 64>), grid, dim3(tmm::mlp::kGemmThreads), 0, s, g);
+    }
 }
 
 tmm::mlp::GemmArgs gargs(int M, int N, int K, const __bf16* A, int lda, int64_t sA, const __bf16* B, int ldb,

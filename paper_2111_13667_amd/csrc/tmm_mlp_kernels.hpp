@@ -9,12 +9,14 @@
 // The transposed copies are written by the producers (optimizer, forward and
 // backward epilogues), not by separate transposes.
 //
-// Tile: 128 x 128 outputs per 256-thread workgroup, 32 reduction steps per LDS
-// stage, four waves each owning a 64 x 64 quadrant = 2 x 2 blocks of the
-// 32x32x16 BF16 MFMA (FP32 accumulation).  MFMA operand layout used: lane l
-// supplies row/column (l mod 32) and 8 consecutive reduction indices starting
-// at 8 (l / 32); accumulator element r of lane l is C[8 (r/4) + 4 (l/32) + r mod 4][l mod 32].
-// (Any consistent permutation of the 16 reduction indices gives the same sum.)
+// Tile: (2 WM) x (2 WN) outputs per 256-thread workgroup (WM = 128 or 64 rows,
+// WN = 64 columns per wave), 64 reduction steps per LDS stage (double-buffered,
+// rows padded by 16 bytes against bank conflicts; up to 108 KiB of LDS), four waves in a 2 x 2 grid,
+// each owning WM/32 x WN/32 blocks of the 32x32x16 BF16 MFMA (FP32
+// accumulation).  MFMA operand layout used: lane l supplies row/column (l mod
+// 32) and 8 consecutive reduction indices starting at 8 (l / 32); accumulator
+// element r of lane l is C[8 (r/4) + 4 (l/32) + r mod 4][l mod 32].  (Any
+// consistent permutation of the 16 reduction indices gives the same sum.)
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -26,10 +28,13 @@ namespace mlp {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));  // one 16-byte chunk
 
-constexpr int kBM = 128, kBN = 128, kBK = 32;
-constexpr int kLdsRow = kBK + 8;  // padded row (bf16 elements) against bank conflicts
+constexpr int kBK = 64;
+constexpr int kLdsRow = kBK + 8;  // padded row (bf16 elements): 144 B = 9 x 16 B, no ds_read_b128 bank conflicts
+constexpr int kChunksPerRow = kBK / 8;  // 16-byte chunks per tile row
 constexpr int kGemmThreads = 256;
+constexpr int kWN = 64;           // columns per wave
 
 enum Epilogue : int {
     EPI_F32 = 0,        // C fp32 [m][n]
@@ -70,108 +75,142 @@ __device__ __forceinline__ float gelu_grad(float z) {
     return cdf + z * pdf;
 }
 
-template <int EPI>
+// One K stage of a tile: global -> registers (chunk s of this thread is row
+// r0 + 32 s, so its address is the thread's base plus s rows of 32), and
+// registers -> LDS (the same rows at the padded pitch).
+constexpr int kRowsPerPass = kGemmThreads / kChunksPerRow;  // 32 rows per pass of the workgroup
+
+template <int C>
+__device__ __forceinline__ void stage_load(u32x4 (&r)[C], const __bf16* base, int64_t ld, int kt) {
+#pragma unroll
+    for (int s = 0; s < C; ++s)
+        r[s] = *reinterpret_cast<const u32x4*>(base + (int64_t)s * kRowsPerPass * ld + kt * kBK);
+}
+template <int C>
+__device__ __forceinline__ void stage_store(const u32x4 (&r)[C], __bf16* lds) {
+#pragma unroll
+    for (int s = 0; s < C; ++s) *reinterpret_cast<u32x4*>(lds + s * kRowsPerPass * kLdsRow) = r[s];
+}
+
+template <int EPI, int WM>
 __global__ void __launch_bounds__(kGemmThreads) gemm_nt_bf16(GemmArgs g) {
-    __shared__ __align__(16) __bf16 As[2][kBM * kLdsRow];
-    __shared__ __align__(16) __bf16 Bs[2][kBN * kLdsRow];
+    constexpr int BM = 2 * WM, BN = 2 * kWN;
+    constexpr int FM = WM / 32, FN = kWN / 32;              // MFMA blocks per wave
+    constexpr int CA = BM * kChunksPerRow / kGemmThreads;  // 16-byte chunks per thread and stage
+    constexpr int CB = BN * kChunksPerRow / kGemmThreads;
+    __shared__ __align__(16) __bf16 As[2][BM * kLdsRow];
+    __shared__ __align__(16) __bf16 Bs[2][BN * kLdsRow];
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
     const int z = blockIdx.z;
-    const int m0 = blockIdx.y * kBM, n0 = blockIdx.x * kBN;
+    const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
     const __bf16* A = g.A + z * g.strideA + (int64_t)m0 * g.lda;
     const __bf16* B = g.B + z * g.strideB + (int64_t)n0 * g.ldb;
 
-    // global -> register staging: each thread moves 2 chunks of 8 bf16 for A and B
-    // chunk c = tid + 256 s (s = 0, 1): row c / 4, columns 8 (c % 4) .. + 7
-    uint4 ra[2], rb[2];
-    auto gload = [&](int kt) {
-#pragma unroll
-        for (int s = 0; s < 2; ++s) {
-            const int c = tid + kGemmThreads * s;
-            const int row = c >> 2, col = (c & 3) * 8;
-            ra[s] = *reinterpret_cast<const uint4*>(A + (int64_t)row * g.lda + kt * kBK + col);
-            rb[s] = *reinterpret_cast<const uint4*>(B + (int64_t)row * g.ldb + kt * kBK + col);
-        }
+    // global -> register staging: chunk c = tid + 256 s is row c / 8, columns 8 (c % 8) .. + 7;
+    // the row offsets are fixed for the whole loop.  Two register sets: the loads of
+    // stage kt + 2 are issued while stage kt is multiplied, so each load has two
+    // stages of MFMA work to arrive before it is written to LDS.
+    u32x4 ra0[CA], rb0[CB], ra1[CA], rb1[CB];
+    const int r0 = tid / kChunksPerRow, c0 = (tid % kChunksPerRow) * 8;
+    const __bf16* const a0 = A + (int64_t)r0 * g.lda + c0;
+    const __bf16* const b0 = B + (int64_t)r0 * g.ldb + c0;
+    const int l0 = r0 * kLdsRow + c0;
+    auto load = [&](u32x4 (&ra)[CA], u32x4 (&rb)[CB], int kt) __attribute__((always_inline)) {
+        stage_load(ra, a0, g.lda, kt);
+        stage_load(rb, b0, g.ldb, kt);
     };
-    auto sstore = [&](int buf) {
-#pragma unroll
-        for (int s = 0; s < 2; ++s) {
-            const int c = tid + kGemmThreads * s;
-            const int row = c >> 2, col = (c & 3) * 8;
-            *reinterpret_cast<uint4*>(&As[buf][row * kLdsRow + col]) = ra[s];
-            *reinterpret_cast<uint4*>(&Bs[buf][row * kLdsRow + col]) = rb[s];
-        }
+    auto store = [&](const u32x4 (&ra)[CA], const u32x4 (&rb)[CB], int buf) __attribute__((always_inline)) {
+        stage_store(ra, &As[buf][l0]);
+        stage_store(rb, &Bs[buf][l0]);
     };
 
-    f32x16 acc[2][2];
+    f32x16 acc[FM][FN];
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < FM; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b)
+        for (int b = 0; b < FN; ++b)
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.0f;
 
-    const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+    const int wm = (wave >> 1) * WM, wn = (wave & 1) * kWN;
     const int fr = lane & 31, fk = (lane >> 5) * 8;
-    const int KT = g.K / kBK;
-    gload(0);
-    sstore(0);
-    __syncthreads();
-    for (int kt = 0; kt < KT; ++kt) {
-        const int buf = kt & 1;
-        if (kt + 1 < KT) gload(kt + 1);
+    auto compute = [&](int buf) __attribute__((always_inline)) {
 #pragma unroll
         for (int kk = 0; kk < kBK; kk += 16) {
-            bf16x8 af[2], bfr[2];
+            bf16x8 af[FM], bfr[FN];
 #pragma unroll
-            for (int a = 0; a < 2; ++a)
+            for (int a = 0; a < FM; ++a)
                 af[a] = *reinterpret_cast<const bf16x8*>(&As[buf][(wm + 32 * a + fr) * kLdsRow + kk + fk]);
 #pragma unroll
-            for (int b = 0; b < 2; ++b)
+            for (int b = 0; b < FN; ++b)
                 bfr[b] = *reinterpret_cast<const bf16x8*>(&Bs[buf][(wn + 32 * b + fr) * kLdsRow + kk + fk]);
 #pragma unroll
-            for (int a = 0; a < 2; ++a)
+            for (int a = 0; a < FM; ++a)
 #pragma unroll
-                for (int b = 0; b < 2; ++b)
+                for (int b = 0; b < FN; ++b)
                     acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[a], bfr[b], acc[a][b], 0, 0, 0);
         }
-        if (kt + 1 < KT) {
-            sstore(buf ^ 1);
-            __syncthreads();
-        }
+    };
+    // K is a multiple of 2 kBK (every dimension is a multiple of 128); stage indices
+    // past the end are clamped (those loads and stores are harmless repeats).
+    const int KT = g.K / kBK;
+    load(ra0, rb0, 0);
+    store(ra0, rb0, 0);
+    load(ra1, rb1, 1 < KT ? 1 : 0);
+    __syncthreads();
+    for (int kt = 0; kt < KT; kt += 2) {
+        // stage kt in LDS buffer 0, stage kt + 1 in set 1
+        load(ra0, rb0, kt + 2 < KT ? kt + 2 : KT - 1);
+        compute(0);
+        store(ra1, rb1, 1);  // buffer 1 was last read before the previous barrier
+        __syncthreads();
+        // stage kt + 1 in LDS buffer 1, stage kt + 2 in set 0
+        load(ra1, rb1, kt + 3 < KT ? kt + 3 : KT - 1);
+        compute(1);
+        store(ra0, rb0, 0);
+        __syncthreads();
     }
 
-    // epilogue
+    // epilogue: lane owns column n of every block and rows 8 q + 4 (lane / 32) + 0..3, q = 0..3
 #pragma unroll
-    for (int a = 0; a < 2; ++a) {
+    for (int a = 0; a < FM; ++a) {
 #pragma unroll
-        for (int b = 0; b < 2; ++b) {
+        for (int b = 0; b < FN; ++b) {
             const int n = n0 + wn + 32 * b + (lane & 31);
             float bias = 0.0f;
             if (EPI == EPI_BIAS_GELU || EPI == EPI_BIAS_F32 || EPI == EPI_BIAS_GELU_H)
                 bias = g.bias[z * g.strideBias + n];
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int m = m0 + wm + 32 * a + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-                const float v = acc[a][b][r];
-                if (EPI == EPI_F32) {
-                    g.outF[z * g.strideOutF + (int64_t)m * g.ldo + n] = v;
-                } else if (EPI == EPI_BIAS_F32) {
-                    g.outF[z * g.strideOutF + (int64_t)m * g.ldo + n] = v + bias;
-                } else if (EPI == EPI_BIAS_GELU) {
-                    const float zz = v + bias;
-                    g.outF[z * g.strideOutF + (int64_t)m * g.ldo + n] = zz;
-                    const __bf16 h = (__bf16)gelu(zz);
-                    g.outH[z * g.strideOutH + (int64_t)m * g.ldh + n] = h;
-                    g.outHt[z * g.strideOutHt + (int64_t)n * g.ldt + m] = h;
-                } else if (EPI == EPI_BIAS_GELU_H) {
-                    g.outH[z * g.strideOutH + (int64_t)m * g.ldh + n] = (__bf16)gelu(v + bias);
-                } else {  // EPI_DGELU
-                    const float zz = g.zin[z * g.strideZin + (int64_t)m * g.ldz + n];
-                    const __bf16 h = (__bf16)(v * gelu_grad(zz));
-                    g.outH[z * g.strideOutH + (int64_t)m * g.ldh + n] = h;
-                    g.outHt[z * g.strideOutHt + (int64_t)n * g.ldt + m] = h;
+            for (int q = 0; q < 4; ++q) {
+                const int mb = m0 + wm + 32 * a + 8 * q + 4 * (lane >> 5);
+                __bf16 ht[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int m = mb + i;
+                    const float v = acc[a][b][4 * q + i];
+                    if (EPI == EPI_F32) {
+                        g.outF[z * g.strideOutF + (int64_t)m * g.ldo + n] = v;
+                    } else if (EPI == EPI_BIAS_F32) {
+                        g.outF[z * g.strideOutF + (int64_t)m * g.ldo + n] = v + bias;
+                    } else if (EPI == EPI_BIAS_GELU) {
+                        const float zz = v + bias;
+                        g.outF[z * g.strideOutF + (int64_t)m * g.ldo + n] = zz;
+                        ht[i] = (__bf16)gelu(zz);
+                        g.outH[z * g.strideOutH + (int64_t)m * g.ldh + n] = ht[i];
+                    } else if (EPI == EPI_BIAS_GELU_H) {
+                        g.outH[z * g.strideOutH + (int64_t)m * g.ldh + n] = (__bf16)gelu(v + bias);
+                    } else {  // EPI_DGELU
+                        const float zz = g.zin[z * g.strideZin + (int64_t)m * g.ldz + n];
+                        ht[i] = (__bf16)(v * gelu_grad(zz));
+                        g.outH[z * g.strideOutH + (int64_t)m * g.ldh + n] = ht[i];
+                    }
+                }
+                if (EPI == EPI_BIAS_GELU || EPI == EPI_DGELU) {
+                    // rows mb .. mb + 3 of the transposed copy are consecutive: one 8-byte store
+                    __bf16 __attribute__((ext_vector_type(4))) v4 = {ht[0], ht[1], ht[2], ht[3]};
+                    *reinterpret_cast<decltype(v4)*>(&g.outHt[z * g.strideOutHt + (int64_t)n * g.ldt + mb]) = v4;
                 }
             }
         }
