@@ -304,17 +304,18 @@ unsigned grid1(int64_t n) {
     return (unsigned)g;
 }
 
-// Launch one batched NT GEMM (all members) with the given epilogue: 256 x 128
-// tiles when M allows, else 128 x 128 (every dimension is a multiple of 128).
+// Launch one batched NT GEMM (all members) with the given epilogue.  Every
+// dimension is a multiple of 128.  256 x 256 tiles where they still give at
+// least four workgroups per CU, else 256 x 128, else 128 x 128.
 template <int EPI>
 void gemm(hipStream_t s, int E, const tmm::mlp::GemmArgs& g) {
-    constexpr int BN = 2 * tmm::mlp::kWN;
-    if (g.M % 256 == 0) {
-        dim3 grid(g.N / BN, g.M / 256, E);
-        hipLaunchKernelGGL((tmm::mlp::gemm_nt_bf16<EPI, 128>), grid, dim3(tmm::mlp::kGemmThreads), 0, s, g);
+    const dim3 block(tmm::mlp::kGemmThreads);
+    if (g.M % 256 == 0 && g.N % 256 == 0 && (int64_t)(g.M / 256) * (g.N / 256) * E >= 1024) {
+        hipLaunchKernelGGL((tmm::mlp::gemm_nt_bf16<EPI, 128, 128>), dim3(g.N / 256, g.M / 256, E), block, 0, s, g);
+    } else if (g.M % 256 == 0) {
+        hipLaunchKernelGGL((tmm::mlp::gemm_nt_bf16<EPI, 128, 64>), dim3(g.N / 128, g.M / 256, E), block, 0, s, g);
     } else {
-        dim3 grid(g.N / BN, g.M / 128, E);
-        hipLaunchKernelGGL((tmm::mlp::gemm_nt_bf16<EPI, 64>), grid, dim3(tmm::mlp::kGemmThreads), 0, s, g);
+        hipLaunchKernelGGL((tmm::mlp::gemm_nt_bf16<EPI, 64, 64>), dim3(g.N / 128, g.M / 128, E), block, 0, s, g);
     }
 }
 

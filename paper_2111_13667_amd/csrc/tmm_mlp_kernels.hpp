@@ -10,8 +10,9 @@
 // backward epilogues), not by separate transposes.
 //
 // Tile: (2 WM) x (2 WN) outputs per 256-thread workgroup (WM = 128 or 64 rows,
-// WN = 64 columns per wave), 64 reduction steps per LDS stage (double-buffered,
-// rows padded by 16 bytes against bank conflicts; up to 108 KiB of LDS), four waves in a 2 x 2 grid,
+// WN = 128 or 64 columns per wave), 64 reduction steps per LDS stage
+// (double-buffered, rows padded by 16 bytes against bank conflicts; up to
+// 144 KiB of LDS), four waves in a 2 x 2 grid,
 // each owning WM/32 x WN/32 blocks of the 32x32x16 BF16 MFMA (FP32
 // accumulation).  MFMA operand layout used: lane l supplies row/column (l mod
 // 32) and 8 consecutive reduction indices starting at 8 (l / 32); accumulator
@@ -34,7 +35,6 @@ constexpr int kBK = 64;
 constexpr int kLdsRow = kBK + 8;  // padded row (bf16 elements): 144 B = 9 x 16 B, no ds_read_b128 bank conflicts
 constexpr int kChunksPerRow = kBK / 8;  // 16-byte chunks per tile row
 constexpr int kGemmThreads = 256;
-constexpr int kWN = 64;           // columns per wave
 
 enum Epilogue : int {
     EPI_F32 = 0,        // C fp32 [m][n]
@@ -92,10 +92,10 @@ __device__ __forceinline__ void stage_store(const u32x4 (&r)[C], __bf16* lds) {
     for (int s = 0; s < C; ++s) *reinterpret_cast<u32x4*>(lds + s * kRowsPerPass * kLdsRow) = r[s];
 }
 
-template <int EPI, int WM>
+template <int EPI, int WM, int WN>
 __global__ void __launch_bounds__(kGemmThreads) gemm_nt_bf16(GemmArgs g) {
-    constexpr int BM = 2 * WM, BN = 2 * kWN;
-    constexpr int FM = WM / 32, FN = kWN / 32;              // MFMA blocks per wave
+    constexpr int BM = 2 * WM, BN = 2 * WN;
+    constexpr int FM = WM / 32, FN = WN / 32;               // MFMA blocks per wave
     constexpr int CA = BM * kChunksPerRow / kGemmThreads;  // 16-byte chunks per thread and stage
     constexpr int CB = BN * kChunksPerRow / kGemmThreads;
     __shared__ __align__(16) __bf16 As[2][BM * kLdsRow];
@@ -134,8 +134,9 @@ __global__ void __launch_bounds__(kGemmThreads) gemm_nt_bf16(GemmArgs g) {
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.0f;
 
-    const int wm = (wave >> 1) * WM, wn = (wave & 1) * kWN;
+    const int wm = (wave >> 1) * WM, wn = (wave & 1) * WN;
     const int fr = lane & 31, fk = (lane >> 5) * 8;
+    // One LDS stage: four 16-deep MFMA steps.
     auto compute = [&](int buf) __attribute__((always_inline)) {
 #pragma unroll
         for (int kk = 0; kk < kBK; kk += 16) {
