@@ -2,8 +2,9 @@
 
 Near-minimax (Chebyshev) fits in 60-digit arithmetic with mpmath:
   2^f = E(f)                                     for |f| <= 1/2,
+  2^y = Es(y)                                    for |y| <= 1/64 (weak attenuation),
   sin(pi h) = h * Sh(h^2), cos(pi h) = Ch(h^2)  for |h| <= 1/128 (table residual).
-Degrees: double E 11, Sh 3, Ch 3; float E 6, Sh 1, Ch 2.
+Degrees: double E 11, Es 6, Sh 3, Ch 3; float E 6, Es 3, Sh 1, Ch 2.
 The printed fit errors are the approximation errors before rounding the
 coefficients.  The tables hold cos(pi k/64), sin(pi k/64) for k = -64..64,
 rounded to nearest from 60-digit values.
@@ -17,7 +18,9 @@ sinc_pi = lambda s: mp.sinpi(mp.sqrt(s)) / mp.sqrt(s) if s != 0 else mp.pi
 cos_pi = lambda s: mp.cospi(mp.sqrt(s))
 exp2 = lambda x: mp.power(2, x)
 H = mp.mpf(1) / (128 * 128)
+S = mp.mpf(1) / 64
 FITS = [("kExp2D", exp2, -0.5, 0.5, 11, "double"), ("kExp2F", exp2, -0.5, 0.5, 6, "float"),
+        ("kExp2SD", exp2, -S, S, 6, "double"), ("kExp2SF", exp2, -S, S, 3, "float"),
         ("kSinHD", sinc_pi, 0, H, 3, "double"), ("kCosHD", cos_pi, 0, H, 3, "double"),
         ("kSinHF", sinc_pi, 0, H, 1, "float"), ("kCosHF", cos_pi, 0, H, 2, "float")]
 

@@ -149,7 +149,9 @@ struct TabPhase<double, PIN> {
         double s, c;
         sincospi_tab<PIN>(phr, tab, s, c);
         if (lossy) {
-            const double rho = exp2_d<PIN>(phi_im * kNegPiLog2e);
+            // weak attenuation in every lane (the usual absorbing layer): short series
+            const double y = phi_im * kNegPiLog2e;
+            const double rho = __all(__builtin_fabs(y) <= 1.0 / 64) ? horner<PIN>(kExp2SD, y) : exp2_d<PIN>(y);
             s *= rho;
             c *= rho;
         }
@@ -164,7 +166,8 @@ struct TabPhase<float, true> {
         float s, c;
         sincospi_tab_f(phr, tab, s, c);
         if (lossy) {
-            const float rho = exp2_f((float)(phi_im * kNegPiLog2e));
+            const float y = (float)(phi_im * kNegPiLog2e);
+            const float rho = __all(__builtin_fabsf(y) <= 1.0f / 64) ? horner<true>(kExp2SF, y) : exp2_f(y);
             s *= rho;
             c *= rho;
         }

@@ -37,10 +37,11 @@ def _horner(c, x):
 
 def sincospi_tab(x, tab, S, C, ftype):
     x = np.asarray(x, dtype=np.float64)
-    x = x - 2.0 * np.rint(0.5 * x)
     k = np.rint(N * x)
     h = (x - k / N).astype(ftype)
-    idx = np.clip(k.astype(np.int64) + N, 0, 2 * N)
+    kk = k - 2 * N * np.rint(k * (0.5 / N))          # k modulo 128, in [-64, 64]
+    with np.errstate(invalid="ignore"):
+        idx = np.clip(np.nan_to_num(kk).astype(np.int64), -N, N) + N
     t = tab[idx]
     h2 = h * h
     sh = h * _horner(S, h2)
@@ -64,7 +65,7 @@ def test_sincospi_double_within_a_few_ulp():
     rng = np.random.default_rng(0)
     xs = np.concatenate([rng.uniform(-3.0, 3.0, 3000), rng.uniform(-2e4, 2e4, 1000),
                          np.arange(-130, 131) / 64.0, np.arange(-130, 131) / 64.0 + 1.0 / 128,
-                         [0.0, 0.5, -0.5, 1.0, 1e6 + 0.25, 7.0 / 128 - 1e-17]])
+                         [0.0, 0.5, -0.5, 1.0, 1e6 + 0.25, 7.0 / 128 - 1e-17, 2.0 ** 40 + 0.75, -(2.0 ** 52)]])
     c, s = sincospi_tab(xs, tab, S, C, np.float64)
     err = 0.0
     for x, ci, si in zip(xs, c, s):
@@ -103,3 +104,15 @@ def test_exp2_polynomial_double():
         ref = mp.power(2, mp.mpf(float(y)))
         if ref > mp.mpf(2) ** -1021:   # normal range; below it ldexp rounds to subnormals
             assert abs(vi - ref) <= 4 * 2.0 ** -53 * ref, (y, vi, ref)
+
+
+def test_exp2_weak_attenuation_series():
+    # 2^y on |y| <= 1/64 without range reduction (the kernels' path when every
+    # lane of a wave is weakly attenuated)
+    for name, dtype, bound in (("kExp2SD", np.float64, 2 * 2.0 ** -53), ("kExp2SF", np.float32, 2 * 2.0 ** -24)):
+        E = _const(name, dtype)
+        ys = np.linspace(-1.0 / 64, 1.0 / 64, 2001).astype(dtype)
+        v = _horner(E, ys)
+        err = max(abs(float(vi) - mp.power(2, mp.mpf(float(y)))) / mp.power(2, mp.mpf(float(y)))
+                  for y, vi in zip(ys, v))
+        assert err <= bound, (name, err)
