@@ -169,7 +169,9 @@ __device__ __forceinline__ void run_stack_table(const FwdParams<R>& p, const Tab
     bool bad = (uint32_t)m_sub_raw >= (uint32_t)n_mat;
     const int m_sub = bad ? 0 : m_sub_raw;
     const Layer<R> sub = tab.get(m_sub, lane);
-    Layer<R> nxt = sub;
+    // the layer below the current one is carried as its table row (a scalar) and
+    // re-read from LDS, so no medium values are copied between registers per step
+    int nxt_row = m_sub;
     Chain<R, POL, AMP> c;
     c.init();
     static_assert(kWave % RenormPeriod<R>::value == 0, "chunks must hold whole renormalisation blocks");
@@ -198,8 +200,8 @@ __device__ __forceinline__ void run_stack_table(const FwdParams<R>& p, const Tab
             const double dj = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(my_d), sl),
                                                __builtin_amdgcn_readlane(__double2loint(my_d), sl));
             const Layer<R> cur = tab.get(code & 0xffff, lane);
-            c.step(cur, nxt, dj * c4lam, (code >> 16) != 0, phase);
-            nxt = cur;
+            c.step(cur, tab.get(nxt_row, lane), dj * c4lam, (code >> 16) != 0, phase);
+            nxt_row = code & 0xffff;
         };
         // blocks of RP steps; chunks start at multiples of kWave steps, so the
         // renormalisation points are those of a running step count
@@ -215,7 +217,7 @@ __device__ __forceinline__ void run_stack_table(const FwdParams<R>& p, const Tab
     }
     c.renorm();
     PointOut out[2];
-    finish<R, POL, AMP>(c, amb, nxt, sub, nsub_r, nsub_i, L, out);
+    finish<R, POL, AMP>(c, amb, tab.get(nxt_row, lane), sub, nsub_r, nsub_i, L, out);
     if (active) {
         const bool valid = lane_ok && !bad;
         constexpr int P = (POL == 3) ? 2 : 1;

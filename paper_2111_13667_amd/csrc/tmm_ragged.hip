@@ -181,7 +181,7 @@ __global__ void __launch_bounds__(kThreads) ragged_kernel(Params<R> p) {
             const R* drow = p.d + l0;
             const int32_t* mrow = p.mat + l0;
             const Layer<R> sub = tab.get(s_row, lane);
-            Layer<R> nxt = sub;
+            int nxt_row = s_row;  // the layer below, as its table row (re-read from LDS per step)
             Chain<R, POL, false> c;
             c.init();
             constexpr int RP = RenormPeriod<R>::value;
@@ -206,9 +206,8 @@ __global__ void __launch_bounds__(kThreads) ragged_kernel(Params<R> p) {
                     const int m = __builtin_amdgcn_readlane(my_m, sl);
                     const double dj = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(my_d), sl),
                                                        __builtin_amdgcn_readlane(__double2loint(my_d), sl));
-                    const Layer<R> cur = tab.get(m, lane);
-                    c.step(cur, nxt, dj * c4lam, (lossy_mask >> m) & 1u, phase);
-                    nxt = cur;
+                    c.step(tab.get(m, lane), tab.get(nxt_row, lane), dj * c4lam, (lossy_mask >> m) & 1u, phase);
+                    nxt_row = m;
                 };
                 // renormalisation blocks at the points of a running step count
                 for (int bt = top; bt >= lo; bt -= RP) {
@@ -223,7 +222,7 @@ __global__ void __launch_bounds__(kThreads) ragged_kernel(Params<R> p) {
             }
             c.renorm();
             PointOut out[2];
-            finish<R, POL, false>(c, amb, nxt, sub, 0.0, 0.0, L, out);
+            finish<R, POL, false>(c, amb, tab.get(nxt_row, lane), sub, 0.0, 0.0, L, out);
             if (active) {
                 const bool valid = lam_ok && amb.ok && !bad;
                 const double nan = __builtin_nan("");
