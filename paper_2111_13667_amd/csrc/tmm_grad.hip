@@ -110,11 +110,14 @@ __device__ __forceinline__ AL al_from(double nr, double ni, const FL& f) {
     return a;
 }
 
-// Media from the block's LDS table (material ids, at most kGradMaxTableMat rows).
+// Media from the block's LDS table (material ids, at most kGradMaxTableMat rows);
+// thicknesses and rows by scalar loads.
 struct TabSrc {
     const double2* tab;   // this lane's entries: tab[(m * kTabFields + f) * kWave]
     ciptr mrow;  // the stack's rows [L + 2]
+    cdptr drow;  // the stack's thicknesses [L]
     int n_mat;
+    __device__ __forceinline__ double d(int j) const { return drow[j - 1]; }
     __device__ __forceinline__ int row(int j) const {
         const int m = mrow[j];
         return m < 0 ? 0 : (m >= n_mat ? n_mat - 1 : m);
@@ -131,13 +134,38 @@ struct TabSrc {
     }
 };
 
+// Same table, with the stack's thicknesses and rows held one per lane
+// (L + 2 <= 64) and broadcast by readlane: no memory access per layer.
+struct TabRegSrc {
+    const double2* tab;
+    double my_d;  // lane l: thickness of layer l + 1
+    int my_row;   // lane l: table row of medium l, clamped to the table
+    __device__ __forceinline__ double d(int j) const {
+        return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(my_d), j - 1),
+                                __builtin_amdgcn_readlane(__double2loint(my_d), j - 1));
+    }
+    __device__ __forceinline__ int row(int j) const { return __builtin_amdgcn_readlane(my_row, j); }
+    __device__ __forceinline__ FL fwd(int j) const {
+        const double2* e = tab + row(j) * kTabFields * kWave;
+        const double2 a = e[0], b = e[kWave];
+        return FL{{a.x, a.y}, {b.x, b.y}};
+    }
+    __device__ __forceinline__ AL adj(int j, const FL&) const {
+        const double2* e = tab + row(j) * kTabFields * kWave;
+        const double2 a = e[2 * kWave], b = e[3 * kWave], c = e[4 * kWave], d = e[5 * kWave];
+        return AL{{a.x, a.y}, {b.x, b.y}, {c.x, c.y}, {d.x, d.y}};
+    }
+};
+
 // Media computed in place (per-layer rows, or tables too large for LDS).
 struct InlSrc {
     const double* nk;
+    cdptr drow;  // the stack's thicknesses [L]
     ciptr mrow;  // NULL: implicit rows base + j
     int64_t base;
     int n_mat, dispersive, n_wl, i;
     double kx;
+    __device__ __forceinline__ double d(int j) const { return drow[j - 1]; }
     __device__ __forceinline__ int64_t row(int j) const {
         if (!mrow) return base + j;
         const int m = mrow[j];
@@ -242,7 +270,6 @@ __device__ void grad_stack(const GradParams& p, const Src& src, const Ambient& a
     const double lam = p.wl[i];
     const double c4lam = 4.0 / lam;           // phi = c4lam d q (half-turns of 2 delta)
     const double two_pi_lam = 2.0 * M_PI / lam;
-    const cdptr drow = (cdptr)(p.d + (int64_t)b * L);
     auto ck = [&](int c, int comp) -> double& { return ws[((size_t)c * kCkptDoubles + comp) * kWave + lane]; };
     auto save = [&](int c, const State& z) {
         ck(c, 0) = z.ss.re; ck(c, 1) = z.ss.im; ck(c, 2) = z.ts.re; ck(c, 3) = z.ts.im;
@@ -268,7 +295,7 @@ __device__ void grad_stack(const GradParams& p, const Src& src, const Ambient& a
         const int lo = top - kSeg + 1 > 1 ? top - kSeg + 1 : 1;
         for (int j = top; j >= lo; --j) {
             const FL cur = src.fwd(j);
-            const double cd = drow[j - 1] * c4lam;
+            const double cd = src.d(j) * c4lam;
             const double phi = cd * cur.q.im;
             const bool lossy = __any(phi != 0.0);
             const cx<double> E = phase(cd * cur.q.re, phi, lossy);
@@ -354,7 +381,7 @@ __device__ void grad_stack(const GradParams& p, const Src& src, const Ambient& a
         for (int t = 0; t < NST; ++t) {
             const int j = top - t;
             const FL cur = src.fwd(j);
-            const double cd = drow[j - 1] * c4lam;
+            const double cd = src.d(j) * c4lam;
             const double phi = cd * cur.q.im;
             const bool lossy = __any(phi != 0.0);
             Es[t] = phase(cd * cur.q.re, phi, lossy);
@@ -380,7 +407,7 @@ __device__ void grad_stack(const GradParams& p, const Src& src, const Ambient& a
             FL up = sub;
             if (j != L) up = src.fwd(j + 1);
             const AL ca = src.adj(j, cur);
-            const double dj = drow[j - 1];
+            const double dj = src.d(j);
             cx<double> Eb = {0.0, 0.0};
             cx<double> qb = pend_q, eb = pend_e;
             if (POL & 1) {
@@ -532,18 +559,29 @@ __global__ void __launch_bounds__(kGradBlock) __attribute__((amdgpu_waves_per_eu
                     double n0r, n0i;
                     load_n(p.nk, p.dispersive, p.n_wl, a_row, i, n0r, n0i);
                     const Ambient amb = make_ambient(n0r, n0i, st, ct);
-                    TabSrc src;
-                    src.tab = tab + lane;
-                    src.mrow = mrow;
-                    src.n_mat = p.n_mat;
-                    grad_stack<POL>(p, src, amb, b, tk.k, i, lane, active, lam_ok && amb.ok && !bad, ws, red, part,
-                                    phase);
+                    const bool ok = lam_ok && amb.ok && !bad;
+                    if (L2 <= kWave) {
+                        TabRegSrc src;
+                        src.tab = tab + lane;
+                        src.my_d = lane < p.L ? p.d[(int64_t)b * p.L + lane] : 0.0;
+                        const int m = lane < L2 ? p.mat[(int64_t)b * L2 + lane] : 0;
+                        src.my_row = m < 0 ? 0 : (m >= p.n_mat ? p.n_mat - 1 : m);
+                        grad_stack<POL>(p, src, amb, b, tk.k, i, lane, active, ok, ws, red, part, phase);
+                    } else {
+                        TabSrc src;
+                        src.tab = tab + lane;
+                        src.mrow = mrow;
+                        src.drow = (cdptr)(p.d + (int64_t)b * p.L);
+                        src.n_mat = p.n_mat;
+                        grad_stack<POL>(p, src, amb, b, tk.k, i, lane, active, ok, ws, red, part, phase);
+                    }
                     done = true;
                 }
             }
         } else if (has) {
             InlSrc src;
             src.nk = p.nk;
+            src.drow = (cdptr)(p.d + (int64_t)b * p.L);
             src.mrow = mrow;
             src.base = (int64_t)b * L2;
             src.n_mat = p.n_mat;
