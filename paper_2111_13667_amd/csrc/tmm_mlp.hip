@@ -51,43 +51,78 @@ constexpr int kTile = 64;
 // outputs, sum_o (Y - T)^2 / B (its gradient scale keeps Adam's epsilon far
 // below the gradients).  dY = 2 (Y - T) / B for rows < B (0 beyond), bf16
 // [m][n] and [n][m]; loss[e] += sum (Y - T)^2 / (B n_out), the mean squared
-// error per output (reported only).  grid (n_out/64, Bt/64, E), block 256.
-__global__ void loss_grad(const float* Y, const float* T, int B, int Bt, int n_out, int64_t strideY,
-                          __bf16* dY, __bf16* dYt, int64_t strideD, float* loss) {
-    __shared__ __bf16 tile[kTile][kTile + 2];
-    __shared__ float red[256];
-    const int e = blockIdx.z;
+// error per output (reported only: each block writes its partial sum to
+// part[e][block], sum_parts adds them in a fixed order).  grid (n_out/64, Bt/64), block 256: the
+// block's 64 x 64 target tile is read once and kept in registers while the
+// members are processed in turn.  Thread t owns rows t/16 + 16 s (s = 0..3),
+// columns 4 (t % 16) .. + 3; the transposed copy goes through LDS, each
+// thread writing 16 consecutive rows of one column (32 bytes).
+__global__ void loss_grad(const float* Y, const float* T, int B, int Bt, int n_out, int E, int64_t strideY,
+                          __bf16* dY, __bf16* dYt, int64_t strideD, float* part) {
+    typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+    typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+    __shared__ __align__(16) __bf16 tile[kTile][kTile + 8];
+    __shared__ float red[4];
     const int m0 = blockIdx.y * kTile, n0 = blockIdx.x * kTile;
+    const int64_t nblk = (int64_t)gridDim.x * gridDim.y, blk = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
+    const int c4 = (threadIdx.x & 15) * 4, r0 = threadIdx.x >> 4;
     const float inv = 1.0f / ((float)B * (float)n_out);
     const float ginv = 2.0f / (float)B;
-    float acc = 0.0f;
-    for (int t = threadIdx.x; t < kTile * kTile; t += blockDim.x) {
-        const int r = t / kTile, c = t % kTile;
-        const int m = m0 + r, n = n0 + c;
-        float g = 0.0f;
-        if (m < B) {
-            const float diff = Y[e * strideY + (int64_t)m * n_out + n] - T[(int64_t)m * n_out + n];
-            g = diff * ginv;
-            acc += diff * diff * inv;
+    float4 tv[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int m = m0 + r0 + 16 * q;
+        tv[q] = m < B ? *reinterpret_cast<const float4*>(T + (int64_t)m * n_out + n0 + c4) : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    const int tc = threadIdx.x >> 2, tr = (threadIdx.x & 3) * 16;  // transposed: column, first row
+    for (int e = 0; e < E; ++e) {
+        float acc = 0.0f;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int r = r0 + 16 * q, m = m0 + r;
+            float4 g = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (m < B) {
+                const float4 y = *reinterpret_cast<const float4*>(Y + e * strideY + (int64_t)m * n_out + n0 + c4);
+                const float4 df = make_float4(y.x - tv[q].x, y.y - tv[q].y, y.z - tv[q].z, y.w - tv[q].w);
+                acc += (df.x * df.x + df.y * df.y + df.z * df.z + df.w * df.w) * inv;
+                g = make_float4(df.x * ginv, df.y * ginv, df.z * ginv, df.w * ginv);
+            }
+            const bf16x4 h = {(__bf16)g.x, (__bf16)g.y, (__bf16)g.z, (__bf16)g.w};
+            *reinterpret_cast<bf16x4*>(dY + e * strideD + (int64_t)m * n_out + n0 + c4) = h;
+            *reinterpret_cast<bf16x4*>(&tile[r][c4]) = h;
         }
-        const __bf16 h = (__bf16)g;
-        dY[e * strideD + (int64_t)m * n_out + n] = h;
-        tile[r][c] = h;
-    }
-    __syncthreads();
-    for (int t = threadIdx.x; t < kTile * kTile; t += blockDim.x) {
-        const int c = t / kTile, r = t % kTile;
-        dYt[e * strideD + (int64_t)(n0 + c) * Bt + (m0 + r)] = tile[r][c];
-    }
-    if (loss) {
-        red[threadIdx.x] = acc;
         __syncthreads();
-        for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-            if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-            __syncthreads();
+        bf16x8 lo, hi;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            lo[i] = tile[tr + i][tc];
+            hi[i] = tile[tr + 8 + i][tc];
         }
-        if (threadIdx.x == 0) atomicAdd(loss + e, red[0]);
+        __bf16* dst = dYt + e * strideD + (int64_t)(n0 + tc) * Bt + m0 + tr;
+        *reinterpret_cast<bf16x8*>(dst) = lo;
+        *reinterpret_cast<bf16x8*>(dst + 8) = hi;
+        if (part) {
+            for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
+            if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+        }
+        __syncthreads();  // the tile (and red) are rewritten by the next member
+        if (part && threadIdx.x == 0) part[e * nblk + blk] = (red[0] + red[1]) + (red[2] + red[3]);
     }
+}
+
+// loss[e] = sum over blocks of part[e][block], in a fixed order.  grid (E), block 256.
+__global__ void sum_parts(const float* part, int64_t nblk, float* loss) {
+    __shared__ float red[256];
+    const float* p = part + (int64_t)blockIdx.x * nblk;
+    float acc = 0.0f;
+    for (int64_t i = threadIdx.x; i < nblk; i += blockDim.x) acc += p[i];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int st = blockDim.x / 2; st > 0; st >>= 1) {
+        if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) loss[blockIdx.x] = red[0];
 }
 
 // db[e][o] = sum_m dZt[e][o][m]; one wave per row.  grid (ceil(out*E/4)), block 256.
@@ -184,18 +219,26 @@ __global__ void fill_f32(float* x, int64_t n, float v) {
 // mean and spread over members: Y [E][Bt][n_out] -> mean, sigma [B][n_out]
 // (rows < B); sigma is the sample standard deviation (0 for one member).
 __global__ void ensemble_stats(const float* Y, int E, int B, int n_out, int64_t strideY, float* mean, float* sigma) {
-    const int64_t total = (int64_t)B * n_out;
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
-        float s = 0.0f;
-        for (int e = 0; e < E; ++e) s += Y[e * strideY + t];
-        const float mu = s / (float)E;
-        float q = 0.0f;
-        for (int e = 0; e < E; ++e) {
-            const float d = Y[e * strideY + t] - mu;
-            q += d * d;
+    // one pass, four consecutive outputs per thread (n_out is a multiple of 128);
+    // sums of the differences to member 0 keep the variance free of cancellation
+    const int64_t total4 = (int64_t)B * n_out / 4;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total4; t += (int64_t)gridDim.x * blockDim.x) {
+        const float4 y0 = reinterpret_cast<const float4*>(Y)[t];
+        float4 s1 = make_float4(0.f, 0.f, 0.f, 0.f), s2 = s1;
+        for (int e = 1; e < E; ++e) {
+            const float4 y = reinterpret_cast<const float4*>(Y + e * strideY)[t];
+            const float4 dl = make_float4(y.x - y0.x, y.y - y0.y, y.z - y0.z, y.w - y0.w);
+            s1.x += dl.x; s1.y += dl.y; s1.z += dl.z; s1.w += dl.w;
+            s2.x += dl.x * dl.x; s2.y += dl.y * dl.y; s2.z += dl.z * dl.z; s2.w += dl.w * dl.w;
         }
-        mean[t] = mu;
-        if (sigma) sigma[t] = E > 1 ? sqrtf(q / (float)(E - 1)) : 0.0f;
+        const float inv = 1.0f / (float)E;
+        reinterpret_cast<float4*>(mean)[t] =
+            make_float4(y0.x + s1.x * inv, y0.y + s1.y * inv, y0.z + s1.z * inv, y0.w + s1.w * inv);
+        if (sigma) {
+            const float c = E > 1 ? 1.0f / (float)(E - 1) : 0.0f;
+            auto sd = [&](float a, float b) { return sqrtf(fmaxf(b - a * a * inv, 0.0f) * c); };
+            reinterpret_cast<float4*>(sigma)[t] = make_float4(sd(s1.x, s2.x), sd(s1.y, s2.y), sd(s1.z, s2.z), sd(s1.w, s2.w));
+        }
     }
 }
 
@@ -269,6 +312,7 @@ struct tmm_surrogate {
     float* dc;
     int32_t* matc;
     float* Rc;
+    float* loss_part;  // [E][blocks of loss_grad] per-block partial losses
     int fallback_L2;
 };
 
@@ -280,7 +324,7 @@ using tmm::ok;
 void free_all(tmm_surrogate* h) {
     void* ptrs[] = {h->W, h->Wm, h->Wv, h->Wg, h->b, h->bm, h->bv, h->bg, h->Wb, h->Wt, h->Xb, h->Xt,
                     h->Y, h->dY, h->dYt, h->dZa, h->dZat, h->dZb, h->dZbt, h->mean_buf, h->sigma_buf,
-                    h->list, h->count, h->dc, h->matc, h->Rc};
+                    h->list, h->count, h->dc, h->matc, h->Rc, h->loss_part};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     for (float* p : h->Z)
@@ -475,6 +519,7 @@ tmm_status tmm_surrogate_create(const tmm_surrogate_config* c, tmm_surrogate** o
     h->dc = nullptr;
     h->matc = nullptr;
     h->Rc = nullptr;
+    h->loss_part = nullptr;
     h->fallback_L2 = 0;
     int64_t wo = 0, bo = 0;
     for (int l = 0; l < h->NL; ++l) {
@@ -497,7 +542,8 @@ tmm_status tmm_surrogate_create(const tmm_surrogate_config* c, tmm_surrogate** o
                dalloc(&h->dYt, E * Bt * No) && dalloc(&h->dZa, E * Bt * Hd) && dalloc(&h->dZat, E * Bt * Hd) &&
                dalloc(&h->dZb, E * Bt * Hd) && dalloc(&h->dZbt, E * Bt * Hd) && dalloc(&h->mean_buf, Bt * No) &&
                dalloc(&h->sigma_buf, Bt * No) && dalloc(&h->list, Bt) && dalloc(&h->count, 1) &&
-               dalloc(&h->dc, Bt * c->n_in) && dalloc(&h->Rc, Bt * No);
+               dalloc(&h->dc, Bt * c->n_in) && dalloc(&h->Rc, Bt * No) &&
+               dalloc(&h->loss_part, E * (No / tmm::mlp::kTile) * (Bt / tmm::mlp::kTile));
     for (int l = 0; okk && l < c->n_layers; ++l) {
         float* z = nullptr;
         __bf16 *a = nullptr, *at = nullptr;
@@ -597,10 +643,13 @@ static tmm_status grads_common(tmm_surrogate* h, const float* x, const float* y,
     (void)hipGetLastError();
     prep(h, x, B, s);
     forward(h, s, true);
-    if (loss) hipLaunchKernelGGL(tmm::mlp::fill_f32, dim3(1), dim3(256), 0, s, loss, (int64_t)h->E, 0.0f);
-    dim3 grid(h->cfg.n_out / tmm::mlp::kTile, h->Bt / tmm::mlp::kTile, h->E);
-    hipLaunchKernelGGL(tmm::mlp::loss_grad, grid, dim3(256), 0, s, h->Y, y, (int)B, h->Bt, h->cfg.n_out,
-                       (int64_t)h->Bt * h->cfg.n_out, h->dY, h->dYt, (int64_t)h->Bt * h->cfg.n_out, loss);
+    dim3 grid(h->cfg.n_out / tmm::mlp::kTile, h->Bt / tmm::mlp::kTile);
+    hipLaunchKernelGGL(tmm::mlp::loss_grad, grid, dim3(256), 0, s, h->Y, y, (int)B, h->Bt, h->cfg.n_out, h->E,
+                       (int64_t)h->Bt * h->cfg.n_out, h->dY, h->dYt, (int64_t)h->Bt * h->cfg.n_out,
+                       loss ? h->loss_part : nullptr);
+    if (loss)
+        hipLaunchKernelGGL(tmm::mlp::sum_parts, dim3(h->E), dim3(256), 0, s, h->loss_part,
+                           (int64_t)grid.x * grid.y, loss);
     backward(h, s);
     return tmm::check_launch(who);
 }
@@ -646,7 +695,7 @@ tmm_status tmm_surrogate_predict(tmm_surrogate* h, const float* x, int32_t B, fl
         prep(h, x + (int64_t)b0 * h->cfg.n_in, nb, s);
         forward(h, s, false);
         if (mean)
-            hipLaunchKernelGGL(tmm::mlp::ensemble_stats, dim3(grid1((int64_t)nb * No)), dim3(256), 0, s, h->Y, h->E,
+            hipLaunchKernelGGL(tmm::mlp::ensemble_stats, dim3(grid1((int64_t)nb * No / 4)), dim3(256), 0, s, h->Y, h->E,
                                nb, No, (int64_t)h->Bt * No, mean + (int64_t)b0 * No,
                                sigma ? sigma + (int64_t)b0 * No : nullptr);
         if (members)
@@ -687,7 +736,7 @@ tmm_status tmm_surrogate_predict_fallback(tmm_surrogate* h, const float* x, int3
         const float* xc = x + (int64_t)b0 * h->cfg.n_in;
         prep(h, xc, nb, s);
         forward(h, s, false);
-        hipLaunchKernelGGL(tmm::mlp::ensemble_stats, dim3(grid1((int64_t)nb * No)), dim3(256), 0, s, h->Y, h->E, nb,
+        hipLaunchKernelGGL(tmm::mlp::ensemble_stats, dim3(grid1((int64_t)nb * No / 4)), dim3(256), 0, s, h->Y, h->E, nb,
                            No, (int64_t)h->Bt * No, out + (int64_t)b0 * No, h->sigma_buf);
         hipLaunchKernelGGL(tmm::mlp::zero_int, dim3(1), dim3(64), 0, s, h->count);
         hipLaunchKernelGGL(tmm::mlp::flag_stacks, dim3((nb + 3) / 4), dim3(256), 0, s, h->sigma_buf, nb, No,
