@@ -18,6 +18,7 @@ template <> struct RenormPeriod<float> { static constexpr int value = 4; };
 // The layer recursion (see tmm_device.hpp).
 template <typename R, int POL, bool AMP>
 struct Chain {
+    static constexpr bool kRatio = false;
     cx<R> ss, ts, sp, tp;  // sigma, tau of s and p
     int es, ep;            // power-of-two exponents taken out of (ss, ts), (sp, tp)
     R pis, pip;            // prod |q_j|^2, prod |eta_j|^2 (R, T only)
@@ -82,17 +83,91 @@ struct Chain {
     }
 };
 
+// ---------------------------------------------------------------------------
+// Ratio form of the recursion.  Step j divided by q_j (s) or eta_j (p):
+//   s: a = sigma + rho_s tau,   b = sigma - rho_s tau,   rho_s = q_{j+1} / q_j
+//   p: a = rho_p sigma + tau,   b = rho_p sigma - tau,   rho_p = eta_{j+1} / eta_j
+//   sigma <- a + E_j b,  tau <- a - E_j b.
+// The state is the division-free one divided by prod q_j (s) or prod eta_j (p)
+// over the finite layers, which are exactly the products that T and t carry,
+// so they drop out of the extraction (prod = 1).  The ratios depend only on the
+// pair (material j, material j + 1) and the lane, so a workgroup tabulates
+// them once; per step that saves two complex products and the two running
+// products of the division-free form.  Per-step growth is bounded by
+// 2 (1 + |rho|); with |rho| <= kPairRatioMax (checked when the table is built)
+// 32 double steps or 8 float steps stay far from overflow.
+constexpr double kPairRatioMax = 256.0;
+template <typename R> struct PairRenormPeriod;
+template <> struct PairRenormPeriod<double> { static constexpr int value = 32; };
+template <> struct PairRenormPeriod<float> { static constexpr int value = 8; };
+
+template <typename R, int POL, bool AMP>
+struct PairChain {
+    static constexpr bool kRatio = true;
+    cx<R> ss, ts, sp, tp;
+    int es, ep;
+    double S;  // sum of y_j = -pi Im(phi_j) / ln 2: log2 of the attenuation
+    double F;  // sum 256 Re(phi_j), reduced modulo 1024 (amplitudes wanted)
+
+    __device__ __forceinline__ void init() {
+        ss = ts = sp = tp = {(R)1, (R)0};
+        es = ep = 0;
+        S = 0.0;
+        F = 0.0;
+    }
+
+    // rs, rp: the pair's ratios; (cre, cim): phi_j = d (cre / 256 + i cim / kNegPiLog2e),
+    // i.e. cre is in units of 1/256 half-turn per unit d and cim is already the
+    // base-2 exponent of the attenuation per unit d.  d cre < kScFastRange.
+    __device__ __forceinline__ void step(cx<R> rs, cx<R> rp, double cre, double cim, double d, bool lossy,
+                                         const TabPhase<R>& phase) {
+        const double g = d * cre;
+        cx<R> E = phase.cis_g(g);
+        if (lossy) {
+            const double y = d * cim;
+            S += y;
+            const R g = phase.atten(y);
+            E.re *= g;
+            E.im *= g;
+        }
+        if (AMP) F = reduce1024(F + g);
+        if (POL & 1) {
+            const cx<R> X = cmul(rs, ts);
+            const cx<R> a = cadd(ss, X), b = csub(ss, X);
+            const cx<R> Eb = cmul(E, b);
+            ss = cadd(a, Eb);
+            ts = csub(a, Eb);
+        }
+        if (POL & 2) {
+            const cx<R> X = cmul(rp, sp);
+            const cx<R> a = cadd(X, tp), b = csub(X, tp);
+            const cx<R> Eb = cmul(E, b);
+            sp = cadd(a, Eb);
+            tp = csub(a, Eb);
+        }
+    }
+
+    __device__ __forceinline__ void renorm() {
+        if (POL & 1) renorm_pair(ss, ts, es);
+        if (POL & 2) renorm_pair(sp, tp, ep);
+    }
+};
+
 struct PointOut {
     double R, T;
     cx<double> r, t;
 };
 
 // Ambient step (j = 0, no phase) and extraction of r, t, R, T (Eq. (3), (7)).
-template <typename R, int POL, bool AMP>
-__device__ __forceinline__ void finish(const Chain<R, POL, AMP>& c, const Ambient& amb,
+// C is Chain (division-free) or PairChain (ratio form: the products are 1 and S
+// is already the base-2 exponent).
+template <typename R, int POL, bool AMP, class C>
+__device__ __forceinline__ void finish(const C& c, const Ambient& amb,
                                        const Layer<R>& first, const Layer<R>& sub,
                                        double nsub_r, double nsub_i, int L, PointOut* out) {
-    const double eS = exp2(c.S * kNegPiLog2e);
+    const double ly = C::kRatio ? c.S : c.S * kNegPiLog2e;
+    const double Fh = C::kRatio ? c.F * (1.0 / kScSteps) : c.F;  // half-turns
+    const double eS = exp2(ly);
     const int two_L1 = 2 * (L + 1);
     if (POL & 1) {
         const cx<double> q0 = {amb.q0r, amb.q0i};
@@ -102,25 +177,31 @@ __device__ __forceinline__ void finish(const Chain<R, POL, AMP>& c, const Ambien
         const double na = cnorm(a);
         PointOut& o = out[0];
         o.R = cnorm(b) / na;
-        double prod;
-        int eprod;
-        if (AMP) {
-            prod = cnorm(widen(c.Pq));
-            eprod = 2 * c.ePq;
-        } else {
-            prod = (double)c.pis;
-            eprod = c.epis;
+        double prod = 1.0;
+        int eprod = 0;
+        cx<double> Pq = {1.0, 0.0};
+        int ePq = 0;
+        if constexpr (!C::kRatio) {
+            if (AMP) {
+                Pq = widen(c.Pq);
+                ePq = c.ePq;
+                prod = cnorm(Pq);
+                eprod = 2 * ePq;
+            } else {
+                prod = (double)c.pis;
+                eprod = c.epis;
+            }
         }
         o.T = ldexp(amb.Ks * prod * sub.pr * eS / na, two_L1 + eprod - 2 * c.es);
         if (AMP) {
             o.r = cdiv(b, a);
             double sn, cs;
-            sincospi(0.5 * c.F, &sn, &cs);
-            const double m = exp2(0.5 * c.S * kNegPiLog2e);
+            sincospi(0.5 * Fh, &sn, &cs);
+            const double m = exp2(0.5 * ly);
             const cx<double> ph = {m * cs, m * sn};
-            cx<double> num = cmul(cmul(q0, widen(c.Pq)), ph);
+            cx<double> num = cmul(cmul(q0, Pq), ph);
             cx<double> tt = cdiv(num, a);
-            const int e = (L + 1) + c.ePq - c.es;
+            const int e = (L + 1) + ePq - c.es;
             o.t = {ldexp(tt.re, e), ldexp(tt.im, e)};
         }
     }
@@ -132,29 +213,35 @@ __device__ __forceinline__ void finish(const Chain<R, POL, AMP>& c, const Ambien
         const double na = cnorm(a);
         PointOut& o = out[(POL & 1) ? 1 : 0];
         o.R = cnorm(b) / na;
-        double prod;
-        int eprod;
-        if (AMP) {
-            prod = cnorm(widen(c.Pe));
-            eprod = 2 * c.ePe;
-        } else {
-            prod = (double)c.pip;
-            eprod = c.epip;
+        double prod = 1.0;
+        int eprod = 0;
+        cx<double> Pe = {1.0, 0.0};
+        int ePe = 0;
+        if constexpr (!C::kRatio) {
+            if (AMP) {
+                Pe = widen(c.Pe);
+                ePe = c.ePe;
+                prod = cnorm(Pe);
+                eprod = 2 * ePe;
+            } else {
+                prod = (double)c.pip;
+                eprod = c.epip;
+            }
         }
         o.T = ldexp(amb.Kp * prod * (double)sub.e.re * eS / na, two_L1 + eprod - 2 * c.ep);
         if (AMP) {
             o.r = cdiv(b, a);
             double sn, cs;
-            sincospi(0.5 * c.F, &sn, &cs);
-            const double m = exp2(0.5 * c.S * kNegPiLog2e);
+            sincospi(0.5 * Fh, &sn, &cs);
+            const double m = exp2(0.5 * ly);
             const cx<double> ph = {m * cs, m * sn};
             // P_p = 2^{L+1} n_0 n_sub / q_sub prod eta_j
             const cx<double> n0 = {amb.n0r, amb.n0i};
             const cx<double> nsub = {nsub_r, nsub_i};
             const cx<double> qsub = {sub.pr, sub.pi};
-            const cx<double> num = cmul(cmul(cdiv(cmul(n0, nsub), qsub), widen(c.Pe)), ph);
+            const cx<double> num = cmul(cmul(cdiv(cmul(n0, nsub), qsub), Pe), ph);
             const cx<double> tt = cdiv(num, a);
-            const int e = (L + 1) + c.ePe - c.ep;
+            const int e = (L + 1) + ePe - c.ep;
             o.t = {ldexp(tt.re, e), ldexp(tt.im, e)};
         }
     }

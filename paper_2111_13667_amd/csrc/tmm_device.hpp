@@ -134,44 +134,59 @@ __device__ __forceinline__ Layer<R> to_layer(const Medium& m) {
 }
 
 // E = e^{i pi phi} for phi = phr + i phi_im (half-turns), through an LDS copy
-// of the (cos, sin) table of tmm_math.hpp.  `lossy` is wave-uniform and false
-// only when phi_im == 0 in every lane, where the modulus is exactly 1.  Every
-// workgroup fills its copy once (fill_phase_tab, then a barrier) before the
-// layer loops use it.  PIN: polynomial coefficients pinned in scalar registers
-// (see fma3).
-template <typename R, bool PIN = true>
+// of the (cos, sin) table of tmm_phase_table.hpp.  Every workgroup fills its
+// copy once (fill_phase_tab, then a barrier) before the layer loops use it.
+//   cis_g(g) e^{i pi g / 256} for real g, |g| < kScFastRange (no period reduction);
+//   atten(y) 2^y for y <= 0, through the short series when every lane of the
+//            wave has |y| <= 1/16 (the usual weakly absorbing layer);
+//   (phr, phi_im, lossy)  the whole factor for any finite phr; `lossy` is
+//            wave-uniform and false only when phi_im == 0 in every lane, where
+//            the modulus is exactly 1.
+template <typename R>
 struct TabPhase;
 
-template <bool PIN>
-struct TabPhase<double, PIN> {
+template <>
+struct TabPhase<double> {
     const double2* tab;
-    __device__ __forceinline__ cx<double> operator()(double phr, double phi_im, bool lossy) const {
+    __device__ __forceinline__ cx<double> cis_g(double g) const {
         double s, c;
-        sincospi_tab<PIN>(phr, tab, s, c);
-        if (lossy) {
-            // weak attenuation in every lane (the usual absorbing layer): short series
-            const double y = phi_im * kNegPiLog2e;
-            const double rho = __all(__builtin_fabs(y) <= 1.0 / 64) ? horner<PIN>(kExp2SD, y) : exp2_d<PIN>(y);
-            s *= rho;
-            c *= rho;
-        }
+        sincospi_g<true>(g, tab, s, c);
         return {c, s};
+    }
+    __device__ __forceinline__ double atten(double y) const {
+        return __all(__builtin_fabs(y) <= kExp2WeakRange) ? horner<true>(kExp2SD, y) : exp2_d<true>(y);
+    }
+    __device__ __forceinline__ cx<double> operator()(double phr, double phi_im, bool lossy) const {
+        cx<double> e = cis_g(sc_exact_g(phr));
+        if (lossy) {
+            const double rho = atten(phi_im * kNegPiLog2e);
+            e.re *= rho;
+            e.im *= rho;
+        }
+        return e;
     }
 };
 
 template <>
-struct TabPhase<float, true> {
+struct TabPhase<float> {
     const float2* tab;
-    __device__ __forceinline__ cx<float> operator()(double phr, double phi_im, bool lossy) const {
+    __device__ __forceinline__ cx<float> cis_g(double g) const {
         float s, c;
-        sincospi_tab_f(phr, tab, s, c);
-        if (lossy) {
-            const float y = (float)(phi_im * kNegPiLog2e);
-            const float rho = __all(__builtin_fabsf(y) <= 1.0f / 64) ? horner<true>(kExp2SF, y) : exp2_f(y);
-            s *= rho;
-            c *= rho;
-        }
+        sincospi_g_f(g, tab, s, c);
         return {c, s};
+    }
+    __device__ __forceinline__ float atten(double yd) const {
+        const float y = (float)yd;
+        return __all(__builtin_fabsf(y) <= (float)kExp2WeakRange) ? horner<true>(kExp2SF, y) : exp2_f(y);
+    }
+    __device__ __forceinline__ cx<float> operator()(double phr, double phi_im, bool lossy) const {
+        cx<float> e = cis_g(sc_exact_g(phr));
+        if (lossy) {
+            const float rho = atten(phi_im * kNegPiLog2e);
+            e.re *= rho;
+            e.im *= rho;
+        }
+        return e;
     }
 };
 
@@ -201,6 +216,8 @@ __device__ __forceinline__ TabPhase<R> phase_of(const unsigned char* lds) {
 
 // x - 4 round(x / 4): exact, keeps a running half-turn phase within [-2, 2].
 __device__ __forceinline__ double reduce4(double x) { return x - 4.0 * rint(0.25 * x); }
+// The same for a phase in units of 1/256 half-turn (period 1024).
+__device__ __forceinline__ double reduce1024(double g) { return g - 1024.0 * rint(g * (1.0 / 1024)); }
 
 // Scale a pair of complex numbers by a power of two so that the largest
 // component is in [0.5, 1); the exponent taken out is added to e.

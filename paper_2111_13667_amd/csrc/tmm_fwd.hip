@@ -8,7 +8,19 @@
 // one stack per wave at a time: the stack index, the layer loop, thicknesses
 // and material ids are wave-uniform and stay on the scalar unit.
 //
-// Two ways to obtain q_j and eta_j for the layer loop:
+// Three ways to obtain the per-layer values of the layer loop:
+//   pair   : when a material-id array is given and the table is small enough
+//            (at most 6 materials in double, 8 in float), the workgroup
+//            tabulates, for its 64 wavelengths, the ratios q_{j+1}/q_j,
+//            eta_{j+1}/eta_j of every ordered pair of materials and the phase
+//            coefficient 4 q_j / lambda in LDS, and the layer loop runs the
+//            ratio form of the recursion (tmm_chain.hpp) on them: one LDS row
+//            per step, no complex products beyond the recursion itself.  The
+//            workgroup is as large as the LDS allows (up to 16 waves on one
+//            CU).  A stack falls back to the inline source below when the
+//            ratios are out of range, its ambient differs, or a phase is beyond
+//            the range of the fast argument reduction; that path is kept out of
+//            the layer-loop registers' way (it is rare and needs no table).
 //   table  : when a material-id array is given and the table has at most
 //            kMaxTableMat rows, the workgroup computes q, eta, |q|^2, |eta|^2 of
 //            every material for its 64 wavelengths once (complex sqrt and one
@@ -19,6 +31,8 @@
 // The recursion itself is described in tmm_device.hpp.
 #include <math.h>
 #include <string.h>
+
+#include <atomic>
 
 #include "tmm_chain.hpp"
 #include "tmm_device.hpp"
@@ -311,6 +325,271 @@ __global__ void __launch_bounds__(kBlock) fwd_kernel(FwdParams<R> p) {
 }
 
 // ---------------------------------------------------------------------------
+// Pair path.  LDS: phase table | media Table<R> (finish, fallback) | one block
+// per ordered material pair (m, m') | flags.  A block holds, for the 64 lanes,
+// rho_s = q_{m'}/q_m, rho_p = eta_{m'}/eta_m and (cre, cim) with
+// phi = d (cre / 256 + i cim / kNegPiLog2e): cre = 1024 Re(q_m)/lambda (the
+// phase per unit d in units of 1/256 half-turn) and cim = kNegPiLog2e 4 Im(q_m)/lambda
+// (the base-2 attenuation exponent per unit d).
+template <typename R> struct PairTab;
+
+template <>
+struct PairTab<double> {
+    static constexpr int kBlockBytes = 3 * kWave * 16;  // rho_s[64], rho_p[64], (cre, cim)[64]
+    __device__ static void put(unsigned char* blk, int lane, cx<double> rs, cx<double> rp, double cre, double cim) {
+        double2* b = reinterpret_cast<double2*>(blk);
+        b[lane] = make_double2(rs.re, rs.im);
+        b[kWave + lane] = make_double2(rp.re, rp.im);
+        b[2 * kWave + lane] = make_double2(cre, cim);
+    }
+    // `at` is the block address plus lane * 16
+    __device__ __forceinline__ static void get(const unsigned char* at, cx<double>& rs, cx<double>& rp, double& cre,
+                                               double& cim) {
+        const double2* b = reinterpret_cast<const double2*>(at);
+        const double2 x = b[0], y = b[kWave], z = b[2 * kWave];
+        rs = {x.x, x.y};
+        rp = {y.x, y.y};
+        cre = z.x;
+        cim = z.y;
+    }
+};
+
+template <>
+struct PairTab<float> {
+    static constexpr int kBlockBytes = 2 * kWave * 16;  // (rho_s, rho_p)[64] as float4, (cre, cim)[64]
+    __device__ static void put(unsigned char* blk, int lane, cx<double> rs, cx<double> rp, double cre, double cim) {
+        reinterpret_cast<float4*>(blk)[lane] = make_float4((float)rs.re, (float)rs.im, (float)rp.re, (float)rp.im);
+        reinterpret_cast<double2*>(blk + kWave * 16)[lane] = make_double2(cre, cim);
+    }
+    __device__ __forceinline__ static void get(const unsigned char* at, cx<float>& rs, cx<float>& rp, double& cre,
+                                               double& cim) {
+        const float4 x = *reinterpret_cast<const float4*>(at);
+        const double2 z = *reinterpret_cast<const double2*>(at + kWave * 16);
+        rs = {x.x, x.y};
+        rp = {x.z, x.w};
+        cre = z.x;
+        cim = z.y;
+    }
+};
+
+// Waves per workgroup at most: 16 (4 per SIMD, at most 128 VGPRs) for every
+// variant but the double-precision two-polarisation amplitude one, which needs
+// more registers and runs 12 (3 per SIMD).
+template <typename R, int POL, bool AMP>
+__host__ __device__ constexpr int pair_max_waves() {
+    return (sizeof(R) == 8 && AMP && POL == 3) ? 12 : 16;
+}
+constexpr int kPairMaxWaves = 16;
+constexpr int kPairMaxMat = 8;
+constexpr size_t kLdsPerCU = 160 * 1024;
+constexpr size_t kPairFlagBytes = 4 * kPairMaxMat + 4 * kPairMaxWaves + 8 * kPairMaxWaves + 16;
+
+template <typename R>
+__host__ __device__ constexpr size_t pair_lds_bytes(int n_mat) {
+    return phase_tab_bytes<R>() + (size_t)n_mat * Table<R>::kBlockBytes +
+           (size_t)n_mat * n_mat * PairTab<R>::kBlockBytes + kPairFlagBytes;
+}
+
+template <typename R>
+constexpr int pair_max_mat() {
+    int n = 0;
+    while (n < kPairMaxMat && pair_lds_bytes<R>(n + 1) <= kLdsPerCU) ++n;
+    return n;
+}
+
+// One stack on the pair table.  Returns false, having stored nothing, when a
+// layer's phase could leave the range of the fast reduction (thickness above
+// dmax, or not a number); the caller then evaluates the stack on the exact path.
+template <typename R, int POL, bool AMP>
+__device__ __forceinline__ bool run_stack_pair(const FwdParams<R>& p, const unsigned char* pair_base,
+                                               const Table<R>& tab, uint32_t lossy_mask, double dmax,
+                                               const Ambient& amb, int b, int k, int i, int lane, bool active,
+                                               bool lane_ok, double nsub_r, double nsub_i,
+                                               const TabPhase<R>& phase) {
+    const int L = p.L;
+    const int n_mat = p.n_mat;
+    const R* drow = p.d + (int64_t)b * L;
+    const int32_t* mrow = p.mat + (int64_t)b * (L + 2);
+    const int m_sub_raw = mrow[L + 1];
+    bool bad = (uint32_t)m_sub_raw >= (uint32_t)n_mat;
+    const int m_sub = bad ? 0 : m_sub_raw;
+    const unsigned char* const lane_base = pair_base + lane * 16;
+    PairChain<R, POL, AMP> c;
+    c.init();
+    constexpr int RP = PairRenormPeriod<R>::value;
+    static_assert(kWave % RP == 0, "chunks must hold whole renormalisation blocks");
+    for (int top = L; top >= 1; top -= kWave) {
+        const int lo = top - kWave + 1 > 1 ? top - kWave + 1 : 1;
+        // lane l holds layer lo + l: thickness and pair block offset | lossy << 31
+        const int j = lo + lane;
+        double my_d = 0.0;
+        int my_code = 0;
+        bool lane_bad = false, lane_far = false;
+        if (j <= top) {
+            const R dj = drow[j - 1];
+            const int m = mrow[j], mn = mrow[j + 1];
+            const bool mbad = (uint32_t)m >= (uint32_t)n_mat || (uint32_t)mn >= (uint32_t)n_mat;
+            lane_bad = mbad || bad_thickness(dj);
+            lane_far = !((double)dj <= dmax);
+            const int mc = mbad ? 0 : m, mnc = mbad ? 0 : mn;
+            my_d = (double)dj;
+            my_code = (mc * n_mat + mnc) * PairTab<R>::kBlockBytes | (int)(((lossy_mask >> mc) & 1u) << 31);
+        }
+        if (__any(lane_far)) return false;
+        bad = bad || __any(lane_bad);
+        auto step = [&](int jj) {
+            const int sl = jj - lo;
+            const int code = __builtin_amdgcn_readlane(my_code, sl);
+            const double dj = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(my_d), sl),
+                                               __builtin_amdgcn_readlane(__double2loint(my_d), sl));
+            cx<R> rs, rp;
+            double cre, cim;
+            PairTab<R>::get(lane_base + (code & 0x7fffffff), rs, rp, cre, cim);
+            c.step(rs, rp, cre, cim, dj, code < 0, phase);
+        };
+        for (int bt = top; bt >= lo; bt -= RP) {
+            if (bt - lo >= RP - 1) {
+#pragma unroll 2
+                for (int u = 0; u < RP; ++u) step(bt - u);
+                c.renorm();
+            } else {
+                for (int jj = bt; jj >= lo; --jj) step(jj);
+            }
+        }
+    }
+    c.renorm();
+    const int m_first_raw = L >= 1 ? mrow[1] : m_sub;
+    const int m_first = (uint32_t)m_first_raw < (uint32_t)n_mat ? m_first_raw : 0;
+    PointOut out[2];
+    finish<R, POL, AMP>(c, amb, tab.get(m_first, lane), tab.get(m_sub, lane), nsub_r, nsub_i, L, out);
+    if (active) {
+        const bool valid = lane_ok && !bad;
+        constexpr int P = (POL == 3) ? 2 : 1;
+        store_point(p, b, k, i, 0, P, out[0], valid);
+        if (POL == 3) store_point(p, b, k, i, 1, P, out[1], valid);
+    }
+    return true;
+}
+
+template <typename R, int POL, bool AMP>
+__global__ void __launch_bounds__((pair_max_waves<R, POL, AMP>() * kWave)) fwd_pair_kernel(FwdParams<R> p) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int nthr = blockDim.x;  // a multiple of kWave, at most pair_max_waves * kWave
+    const int nwaves = nthr / kWave;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    int bid = blockIdx.x;
+    const int tile = bid % p.n_tiles;
+    bid /= p.n_tiles;
+    const int k = bid % p.n_theta;
+    bid /= p.n_theta;
+    const int b0 = bid * p.chunk;
+    const int b1 = min(b0 + p.chunk, p.B);
+    const int i_raw = tile * kWave + lane;
+    const bool active = i_raw < p.n_wl;
+    const int i = active ? i_raw : p.n_wl - 1;  // ragged tail: compute a valid point, store nothing
+    const double lam = (double)p.wl[i];
+    const bool lam_ok = lam > 0.0 && lam < __builtin_inf();
+    const double c4lam = 4.0 / lam;
+    const double st = (double)p.sin_t[k], ct = (double)p.cos_t[k];
+    const int L2 = p.L + 2;
+    const int n_mat = p.n_mat;
+    fill_phase_tab<R>(smem, threadIdx.x, nthr);
+    unsigned char* const tab_base = smem + phase_tab_bytes<R>();
+    unsigned char* const pair_base = tab_base + (size_t)n_mat * Table<R>::kBlockBytes;
+    unsigned char* const flag_base = pair_base + (size_t)n_mat * n_mat * PairTab<R>::kBlockBytes;
+    int* const lossy_f = reinterpret_cast<int*>(flag_base);
+    int* const bad_w = lossy_f + kPairMaxMat;
+    double* const cmax_w = reinterpret_cast<double*>(bad_w + kPairMaxWaves);
+    int* const next_b = reinterpret_cast<int*>(cmax_w + kPairMaxWaves);
+
+    int amb_row = p.mat[(int64_t)b0 * L2];
+    amb_row = amb_row < 0 ? 0 : (amb_row >= n_mat ? n_mat - 1 : amb_row);
+    double n0r, n0i;
+    load_n(p.nk, p.dispersive, p.n_wl, amb_row, i, n0r, n0i);
+    const Ambient amb = make_ambient(n0r, n0i, st, ct);
+    Table<R> tab(tab_base, n_mat);
+    for (int m = wave; m < n_mat; m += nwaves) {
+        double nr, ni;
+        load_n(p.nk, p.dispersive, p.n_wl, m, i, nr, ni);
+        const Medium md = make_medium(nr, ni, amb.kx);
+        tab.put(m, lane, md);
+        const bool lossy = __any(md.qi != 0.0);
+        if (lane == 0) lossy_f[m] = lossy ? 1 : 0;
+    }
+    // pair blocks; lanes whose results are stored check the ratio bound and
+    // give the largest phase coefficient
+    const bool lane_used = active && lam_ok && amb.ok;
+    bool bad_lane = false;
+    double cmax = 0.0;
+    for (int pi = wave; pi < n_mat * n_mat; pi += nwaves) {
+        const int mc = pi / n_mat, mn = pi - mc * n_mat;
+        double ar, ai, br, bi;
+        load_n(p.nk, p.dispersive, p.n_wl, mc, i, ar, ai);
+        load_n(p.nk, p.dispersive, p.n_wl, mn, i, br, bi);
+        const Medium ma = make_medium(ar, ai, amb.kx), mb = make_medium(br, bi, amb.kx);
+        const cx<double> rs = cdiv({mb.qr, mb.qi}, {ma.qr, ma.qi});
+        const cx<double> rp = cdiv({mb.er, mb.ei}, {ma.er, ma.ei});
+        const double cre = (c4lam * kScSteps) * ma.qr, cim = c4lam * ma.qi * kNegPiLog2e;
+        PairTab<R>::put(pair_base + (size_t)pi * PairTab<R>::kBlockBytes, lane, rs, rp, cre, cim);
+        if (lane_used) {
+            const double mag = fmax(fmax(fabs(rs.re), fabs(rs.im)), fmax(fabs(rp.re), fabs(rp.im)));
+            bad_lane = bad_lane || !(mag <= kPairRatioMax);
+            cmax = fmax(cmax, fabs(cre));
+        }
+    }
+    const bool wave_bad = __any(bad_lane);
+    for (int off = kWave / 2; off >= 1; off >>= 1) cmax = fmax(cmax, __shfl_xor(cmax, off));
+    if (lane == 0) {
+        bad_w[wave] = wave_bad ? 1 : 0;
+        cmax_w[wave] = cmax;
+    }
+    if (threadIdx.x == 0) *next_b = b0 + nwaves;
+    __syncthreads();
+    uint32_t mask = 0;
+    for (int m = 0; m < n_mat; ++m) mask |= (uint32_t)lossy_f[m] << m;
+    mask = __builtin_amdgcn_readfirstlane(mask);
+    int any_bad = 0;
+    double cm = 0.0;
+    for (int w = 0; w < nwaves; ++w) {
+        any_bad |= bad_w[w];
+        cm = fmax(cm, cmax_w[w]);
+    }
+    const bool pair_ok = __builtin_amdgcn_readfirstlane(any_bad) == 0;
+    // every layer of a stack with d <= dmax keeps |phi| below the fast range
+    const double dmax = (0.5 * kScFastRange) / cm;
+    const TabPhase<R> phase = phase_of<R>(smem);
+    // stacks are handed out one at a time from an LDS counter (the first one
+    // per wave statically): waves that run faster take more stacks, so the
+    // workgroup's waves finish together and the CU does not idle at its end
+    for (int b = b0 + wave; b < b1;) {
+        const int bb = b;
+        {
+            int nb = 0;
+            if (lane == 0) nb = atomicAdd(next_b, 1);
+            b = __builtin_amdgcn_readfirstlane(nb);
+        }
+        const int32_t* mrow = p.mat + (int64_t)bb * L2;
+        int sub_row = mrow[p.L + 1];
+        sub_row = sub_row < 0 ? 0 : (sub_row >= n_mat ? n_mat - 1 : sub_row);
+        double nsr = 0.0, nsi = 0.0;
+        if (AMP) load_n(p.nk, p.dispersive, p.n_wl, sub_row, i, nsr, nsi);
+        if (pair_ok && mrow[0] == amb_row &&
+            run_stack_pair<R, POL, AMP>(p, pair_base, tab, mask, dmax, amb, bb, k, i, lane, active, lam_ok && amb.ok,
+                                        nsr, nsi, phase))
+            continue;
+        // per-step media: any ambient, any ratio, any finite phase
+        int a_row = mrow[0];
+        a_row = a_row < 0 ? 0 : (a_row >= n_mat ? n_mat - 1 : a_row);
+        double ar, ai;
+        load_n(p.nk, p.dispersive, p.n_wl, a_row, i, ar, ai);
+        const Ambient amb_b = make_ambient(ar, ai, st, ct);
+        InlineSource<R> src{p.nk, mrow, 0, n_mat, p.dispersive, p.n_wl, i, amb_b.kx};
+        run_stack<R, POL, AMP>(p, src, amb_b, bb, k, i, active, lam_ok && amb_b.ok, c4lam, nsr, nsi, phase);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Host side.
 
 template <typename R, int POL, bool AMP, bool TABLE>
@@ -330,6 +609,60 @@ static hipError_t dispatch_pol(const FwdParams<R>& p, unsigned pol, bool amp, in
     if (pol == 1) return launch_fwd<R, 1, false, TABLE>(p, blocks, lds, s);
     if (pol == 2) return launch_fwd<R, 2, false, TABLE>(p, blocks, lds, s);
     return launch_fwd<R, 3, false, TABLE>(p, blocks, lds, s);
+}
+
+template <typename R, int POL, bool AMP>
+static hipError_t launch_pair(const FwdParams<R>& p, int blocks, int threads, size_t lds, hipStream_t s) {
+    // dynamic LDS above 64 KiB: raise the kernel's limit once per device
+    static std::atomic<size_t> raised[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
+    if (raised[dev].load() < lds) {
+        (void)hipFuncSetAttribute((const void*)&fwd_pair_kernel<R, POL, AMP>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        (void)hipGetLastError();
+        raised[dev].store(lds);
+    }
+    hipLaunchKernelGGL((fwd_pair_kernel<R, POL, AMP>), dim3(blocks), dim3(threads), lds, s, p);
+    return hipGetLastError();
+}
+
+// Launch shape of the pair kernel: as many workgroups per CU as the LDS holds
+// (at most 4), and waves per workgroup so that the CU holds its maximum of
+// resident waves; stacks per workgroup up to 32 per wave, fewer when the grid
+// would otherwise hold less than 64 workgroups per resident slot.
+template <typename R, int POL, bool AMP>
+static tmm_status run_pair(FwdParams<R> p, int64_t B, int64_t cols, hipStream_t s) {
+    const size_t lds = pair_lds_bytes<R>(p.n_mat);
+    const size_t granule = 2048;
+    int per_cu = (int)(kLdsPerCU / ((lds + granule - 1) / granule * granule));
+    per_cu = per_cu < 1 ? 1 : (per_cu > 4 ? 4 : per_cu);
+    const int waves = pair_max_waves<R, POL, AMP>() / per_cu;
+    const int64_t slots = 256 * (int64_t)per_cu * 64;
+    int64_t chunk = ceil_div(B * cols, slots);
+    chunk = ceil_div(chunk, waves) * waves;
+    if (chunk < waves) chunk = waves;
+    if (chunk > 32 * waves) chunk = 32 * waves;
+    p.chunk = (int)chunk;
+    const int64_t blocks = cols * ceil_div(B, (int64_t)p.chunk);
+    if (blocks > 0x7fffffff)
+        return fail(TMM_ERR_UNSUPPORTED, "tmm_rt: grid of %lld workgroups is too large", (long long)blocks);
+    const hipError_t e = launch_pair<R, POL, AMP>(p, (int)blocks, waves * kWave, lds, s);
+    if (e != hipSuccess) return fail(TMM_ERR_HIP, "tmm_rt: launch failed: %s", hipGetErrorString(e));
+    return ok();
+}
+
+template <typename R>
+static tmm_status dispatch_pair(const FwdParams<R>& p, unsigned pol, bool amp, int64_t B, int64_t cols,
+                                hipStream_t s) {
+    if (amp) {
+        if (pol == 1) return run_pair<R, 1, true>(p, B, cols, s);
+        if (pol == 2) return run_pair<R, 2, true>(p, B, cols, s);
+        return run_pair<R, 3, true>(p, B, cols, s);
+    }
+    if (pol == 1) return run_pair<R, 1, false>(p, B, cols, s);
+    if (pol == 2) return run_pair<R, 2, false>(p, B, cols, s);
+    return run_pair<R, 3, false>(p, B, cols, s);
 }
 
 // Stacks per workgroup: enough workgroups to fill 256 CUs many times over,
@@ -363,16 +696,18 @@ static tmm_status run_fwd(const tmm_rt_args* a, hipStream_t s) {
     p.r_out = static_cast<R*>(a->r);
     p.t_out = static_cast<R*>(a->t);
     p.n_tiles = (int)ceil_div(a->n_wl, kWave);
-    p.chunk = pick_chunk(a->B, (int64_t)p.n_tiles * a->n_theta);
-    const int64_t blocks = (int64_t)p.n_tiles * a->n_theta * ceil_div(a->B, p.chunk);
-    if (blocks > 0x7fffffff) return fail(TMM_ERR_UNSUPPORTED, "tmm_rt: grid of %lld workgroups is too large",
-                                         (long long)blocks);
-    const bool table = a->mat != nullptr && a->n_mat <= kMaxTableMat;
+    const int64_t cols = (int64_t)p.n_tiles * a->n_theta;
     const bool amp = a->r != nullptr || a->t != nullptr;
-    const size_t lds = table ? table_bytes<R>(a->n_mat) : phase_tab_bytes<R>();
     (void)hipGetLastError();
-    hipError_t e = table ? dispatch_pol<R, true>(p, a->pol_mask, amp, (int)blocks, lds, s)
-                         : dispatch_pol<R, false>(p, a->pol_mask, amp, (int)blocks, lds, s);
+    if (a->mat != nullptr && a->n_mat <= pair_max_mat<R>()) return dispatch_pair<R>(p, a->pol_mask, amp, a->B, cols, s);
+    p.chunk = pick_chunk(a->B, cols);
+    const int64_t blocks = cols * ceil_div(a->B, p.chunk);
+    if (blocks > 0x7fffffff)
+        return fail(TMM_ERR_UNSUPPORTED, "tmm_rt: grid of %lld workgroups is too large", (long long)blocks);
+    const bool table = a->mat != nullptr && a->n_mat <= kMaxTableMat;
+    const size_t lds = table ? table_bytes<R>(a->n_mat) : phase_tab_bytes<R>();
+    const hipError_t e = table ? dispatch_pol<R, true>(p, a->pol_mask, amp, (int)blocks, lds, s)
+                               : dispatch_pol<R, false>(p, a->pol_mask, amp, (int)blocks, lds, s);
     if (e != hipSuccess) return fail(TMM_ERR_HIP, "tmm_rt: launch failed: %s", hipGetErrorString(e));
     return ok();
 }

@@ -2,9 +2,9 @@
 //
 // The phase of every layer step needs e^{i pi phi}; the library versions carry
 // argument handling this loop does not need, so these are written directly:
-// exact reduction to a table point k/64 and a residual |h| <= 1/128 (sin,
-// cos, combined with the table by the angle-sum formulas) or to |f| <= 1/2
-// (exp2), then near-minimax polynomials (Chebyshev fits in 60-digit arithmetic; the
+// reduction to a table point k/256 and a residual |h| <= 1/512 (sin, cos,
+// combined with the table by the angle-sum formulas) or to |f| <= 1/2 (exp2),
+// then near-minimax polynomials (Chebyshev fits in 60-digit arithmetic; the
 // coefficients and fit errors come from gen_poly.py), evaluated by Horner's
 // rule with FMA.  tests/test_phase_math_cpu.py replays these steps on the CPU
 // with the constants of this file against 40-digit values (double: within 4
@@ -13,6 +13,9 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "tmm_phase_table.hpp"
 
 namespace tmm {
 
@@ -24,159 +27,33 @@ constexpr double kExp2D[12] = {1.0, 0.6931471805599453, 0.24022650695910158, 0.0
 // fit error 1.95e-09
 constexpr float kExp2F[7] = {1.000000000e+00f, 6.931471825e-01f, 2.402265072e-01f, 5.550327152e-02f,
                              9.618056938e-03f, 1.340042800e-03f, 1.546144485e-04f};
-// 2^y for weak attenuation, |y| <= 1/64 (no range reduction).
-// fit error 5.43e-20
-constexpr double kExp2SD[7] = {1.0, 0.6931471805599453, 0.24022650695910072, 0.05550410866402609, 0.009618129107559553, 0.0013333623313270518, 0.00015403586856124675};
-// fit error 7.18e-11
-constexpr float kExp2SF[4] = {1.000000000e+00f, 6.931471825e-01f, 2.402288616e-01f, 5.550443381e-02f};
+// 2^y for weak attenuation, |y| <= 1/16 (no range reduction).
+// fit error 2.42e-18
+constexpr double kExp2SD[8] = {1.0, 0.6931471805599453, 0.2402265069591204, 0.055504108664823096, 0.00961812908242099, 0.0013333558127014689, 0.00015404562882891175, 1.5253528985683798e-05};
+// fit error 8.01e-11
+constexpr float kExp2SF[5] = {1.000000000e+00f, 6.931471825e-01f, 2.402265072e-01f, 5.551061779e-02f, 9.618881159e-03f};
+constexpr double kExp2WeakRange = 1.0 / 16;
 
-// Table-driven sin/cos of pi x: (cos, sin)(pi k / 64) for k = -64..64 (index
-// k + 64), rounded to nearest, and near-minimax fits of sin(pi h) = h Sh(h^2),
-// cos(pi h) = Ch(h^2) on |h| <= 1/128, the residual after x - round(64 x)/64.
-constexpr int kScSteps = 64;                 // table points per half-turn
-constexpr int kScEntries = 2 * kScSteps + 1;
-// fit error 8.91e-21
-constexpr double kSinHD[4] = {3.141592653589793, -5.167712780049965, 2.5501640394948275, -0.5992545018222493};
-// fit error 2.55e-20
-constexpr double kCosHD[4] = {1.0, -4.934802200544666, 4.0587121253209375, -1.3352340422353792};
-// fit error 1.19e-09
-constexpr float kSinHF[2] = {3.141592741e+00f, -5.167557240e+00f};
-// fit error 9.49e-15
-constexpr float kCosHF[3] = {1.000000000e+00f, -4.934802055e+00f, 4.058589935e+00f};
-constexpr double kScTabD[kScEntries][2] = {
-    {-1.0, 0.0}, {-0.9987954562051724, -0.049067674327418015},
-    {-0.9951847266721969, -0.0980171403295606}, {-0.989176509964781, -0.14673047445536175},
-    {-0.9807852804032304, -0.19509032201612828}, {-0.970031253194544, -0.2429801799032639},
-    {-0.9569403357322088, -0.2902846772544624}, {-0.9415440651830208, -0.33688985339222005},
-    {-0.9238795325112867, -0.3826834323650898}, {-0.9039892931234433, -0.4275550934302821},
-    {-0.881921264348355, -0.47139673682599764}, {-0.8577286100002721, -0.5141027441932218},
-    {-0.8314696123025452, -0.5555702330196022}, {-0.8032075314806449, -0.5956993044924334},
-    {-0.773010453362737, -0.6343932841636455}, {-0.7409511253549591, -0.6715589548470184},
-    {-0.7071067811865476, -0.7071067811865476}, {-0.6715589548470184, -0.7409511253549591},
-    {-0.6343932841636455, -0.773010453362737}, {-0.5956993044924334, -0.8032075314806449},
-    {-0.5555702330196022, -0.8314696123025452}, {-0.5141027441932218, -0.8577286100002721},
-    {-0.47139673682599764, -0.881921264348355}, {-0.4275550934302821, -0.9039892931234433},
-    {-0.3826834323650898, -0.9238795325112867}, {-0.33688985339222005, -0.9415440651830208},
-    {-0.2902846772544624, -0.9569403357322088}, {-0.2429801799032639, -0.970031253194544},
-    {-0.19509032201612828, -0.9807852804032304}, {-0.14673047445536175, -0.989176509964781},
-    {-0.0980171403295606, -0.9951847266721969}, {-0.049067674327418015, -0.9987954562051724},
-    {0.0, -1.0}, {0.049067674327418015, -0.9987954562051724},
-    {0.0980171403295606, -0.9951847266721969}, {0.14673047445536175, -0.989176509964781},
-    {0.19509032201612828, -0.9807852804032304}, {0.2429801799032639, -0.970031253194544},
-    {0.2902846772544624, -0.9569403357322088}, {0.33688985339222005, -0.9415440651830208},
-    {0.3826834323650898, -0.9238795325112867}, {0.4275550934302821, -0.9039892931234433},
-    {0.47139673682599764, -0.881921264348355}, {0.5141027441932218, -0.8577286100002721},
-    {0.5555702330196022, -0.8314696123025452}, {0.5956993044924334, -0.8032075314806449},
-    {0.6343932841636455, -0.773010453362737}, {0.6715589548470184, -0.7409511253549591},
-    {0.7071067811865476, -0.7071067811865476}, {0.7409511253549591, -0.6715589548470184},
-    {0.773010453362737, -0.6343932841636455}, {0.8032075314806449, -0.5956993044924334},
-    {0.8314696123025452, -0.5555702330196022}, {0.8577286100002721, -0.5141027441932218},
-    {0.881921264348355, -0.47139673682599764}, {0.9039892931234433, -0.4275550934302821},
-    {0.9238795325112867, -0.3826834323650898}, {0.9415440651830208, -0.33688985339222005},
-    {0.9569403357322088, -0.2902846772544624}, {0.970031253194544, -0.2429801799032639},
-    {0.9807852804032304, -0.19509032201612828}, {0.989176509964781, -0.14673047445536175},
-    {0.9951847266721969, -0.0980171403295606}, {0.9987954562051724, -0.049067674327418015},
-    {1.0, 0.0}, {0.9987954562051724, 0.049067674327418015},
-    {0.9951847266721969, 0.0980171403295606}, {0.989176509964781, 0.14673047445536175},
-    {0.9807852804032304, 0.19509032201612828}, {0.970031253194544, 0.2429801799032639},
-    {0.9569403357322088, 0.2902846772544624}, {0.9415440651830208, 0.33688985339222005},
-    {0.9238795325112867, 0.3826834323650898}, {0.9039892931234433, 0.4275550934302821},
-    {0.881921264348355, 0.47139673682599764}, {0.8577286100002721, 0.5141027441932218},
-    {0.8314696123025452, 0.5555702330196022}, {0.8032075314806449, 0.5956993044924334},
-    {0.773010453362737, 0.6343932841636455}, {0.7409511253549591, 0.6715589548470184},
-    {0.7071067811865476, 0.7071067811865476}, {0.6715589548470184, 0.7409511253549591},
-    {0.6343932841636455, 0.773010453362737}, {0.5956993044924334, 0.8032075314806449},
-    {0.5555702330196022, 0.8314696123025452}, {0.5141027441932218, 0.8577286100002721},
-    {0.47139673682599764, 0.881921264348355}, {0.4275550934302821, 0.9039892931234433},
-    {0.3826834323650898, 0.9238795325112867}, {0.33688985339222005, 0.9415440651830208},
-    {0.2902846772544624, 0.9569403357322088}, {0.2429801799032639, 0.970031253194544},
-    {0.19509032201612828, 0.9807852804032304}, {0.14673047445536175, 0.989176509964781},
-    {0.0980171403295606, 0.9951847266721969}, {0.049067674327418015, 0.9987954562051724},
-    {0.0, 1.0}, {-0.049067674327418015, 0.9987954562051724},
-    {-0.0980171403295606, 0.9951847266721969}, {-0.14673047445536175, 0.989176509964781},
-    {-0.19509032201612828, 0.9807852804032304}, {-0.2429801799032639, 0.970031253194544},
-    {-0.2902846772544624, 0.9569403357322088}, {-0.33688985339222005, 0.9415440651830208},
-    {-0.3826834323650898, 0.9238795325112867}, {-0.4275550934302821, 0.9039892931234433},
-    {-0.47139673682599764, 0.881921264348355}, {-0.5141027441932218, 0.8577286100002721},
-    {-0.5555702330196022, 0.8314696123025452}, {-0.5956993044924334, 0.8032075314806449},
-    {-0.6343932841636455, 0.773010453362737}, {-0.6715589548470184, 0.7409511253549591},
-    {-0.7071067811865476, 0.7071067811865476}, {-0.7409511253549591, 0.6715589548470184},
-    {-0.773010453362737, 0.6343932841636455}, {-0.8032075314806449, 0.5956993044924334},
-    {-0.8314696123025452, 0.5555702330196022}, {-0.8577286100002721, 0.5141027441932218},
-    {-0.881921264348355, 0.47139673682599764}, {-0.9039892931234433, 0.4275550934302821},
-    {-0.9238795325112867, 0.3826834323650898}, {-0.9415440651830208, 0.33688985339222005},
-    {-0.9569403357322088, 0.2902846772544624}, {-0.970031253194544, 0.2429801799032639},
-    {-0.9807852804032304, 0.19509032201612828}, {-0.989176509964781, 0.14673047445536175},
-    {-0.9951847266721969, 0.0980171403295606}, {-0.9987954562051724, 0.049067674327418015},
-    {-1.0, 0.0},
-};
-constexpr float kScTabF[kScEntries][2] = {
-    {-1.000000000e+00f, 0.000000000e+00f}, {-9.987954497e-01f, -4.906767607e-02f},
-    {-9.951847196e-01f, -9.801714122e-02f}, {-9.891765118e-01f, -1.467304677e-01f},
-    {-9.807852507e-01f, -1.950903237e-01f}, {-9.700312614e-01f, -2.429801822e-01f},
-    {-9.569403529e-01f, -2.902846634e-01f}, {-9.415440559e-01f, -3.368898630e-01f},
-    {-9.238795042e-01f, -3.826834261e-01f}, {-9.039893150e-01f, -4.275550842e-01f},
-    {-8.819212914e-01f, -4.713967443e-01f}, {-8.577286005e-01f, -5.141027570e-01f},
-    {-8.314695954e-01f, -5.555702448e-01f}, {-8.032075167e-01f, -5.956993103e-01f},
-    {-7.730104327e-01f, -6.343932748e-01f}, {-7.409511209e-01f, -6.715589762e-01f},
-    {-7.071067691e-01f, -7.071067691e-01f}, {-6.715589762e-01f, -7.409511209e-01f},
-    {-6.343932748e-01f, -7.730104327e-01f}, {-5.956993103e-01f, -8.032075167e-01f},
-    {-5.555702448e-01f, -8.314695954e-01f}, {-5.141027570e-01f, -8.577286005e-01f},
-    {-4.713967443e-01f, -8.819212914e-01f}, {-4.275550842e-01f, -9.039893150e-01f},
-    {-3.826834261e-01f, -9.238795042e-01f}, {-3.368898630e-01f, -9.415440559e-01f},
-    {-2.902846634e-01f, -9.569403529e-01f}, {-2.429801822e-01f, -9.700312614e-01f},
-    {-1.950903237e-01f, -9.807852507e-01f}, {-1.467304677e-01f, -9.891765118e-01f},
-    {-9.801714122e-02f, -9.951847196e-01f}, {-4.906767607e-02f, -9.987954497e-01f},
-    {0.000000000e+00f, -1.000000000e+00f}, {4.906767607e-02f, -9.987954497e-01f},
-    {9.801714122e-02f, -9.951847196e-01f}, {1.467304677e-01f, -9.891765118e-01f},
-    {1.950903237e-01f, -9.807852507e-01f}, {2.429801822e-01f, -9.700312614e-01f},
-    {2.902846634e-01f, -9.569403529e-01f}, {3.368898630e-01f, -9.415440559e-01f},
-    {3.826834261e-01f, -9.238795042e-01f}, {4.275550842e-01f, -9.039893150e-01f},
-    {4.713967443e-01f, -8.819212914e-01f}, {5.141027570e-01f, -8.577286005e-01f},
-    {5.555702448e-01f, -8.314695954e-01f}, {5.956993103e-01f, -8.032075167e-01f},
-    {6.343932748e-01f, -7.730104327e-01f}, {6.715589762e-01f, -7.409511209e-01f},
-    {7.071067691e-01f, -7.071067691e-01f}, {7.409511209e-01f, -6.715589762e-01f},
-    {7.730104327e-01f, -6.343932748e-01f}, {8.032075167e-01f, -5.956993103e-01f},
-    {8.314695954e-01f, -5.555702448e-01f}, {8.577286005e-01f, -5.141027570e-01f},
-    {8.819212914e-01f, -4.713967443e-01f}, {9.039893150e-01f, -4.275550842e-01f},
-    {9.238795042e-01f, -3.826834261e-01f}, {9.415440559e-01f, -3.368898630e-01f},
-    {9.569403529e-01f, -2.902846634e-01f}, {9.700312614e-01f, -2.429801822e-01f},
-    {9.807852507e-01f, -1.950903237e-01f}, {9.891765118e-01f, -1.467304677e-01f},
-    {9.951847196e-01f, -9.801714122e-02f}, {9.987954497e-01f, -4.906767607e-02f},
-    {1.000000000e+00f, 0.000000000e+00f}, {9.987954497e-01f, 4.906767607e-02f},
-    {9.951847196e-01f, 9.801714122e-02f}, {9.891765118e-01f, 1.467304677e-01f},
-    {9.807852507e-01f, 1.950903237e-01f}, {9.700312614e-01f, 2.429801822e-01f},
-    {9.569403529e-01f, 2.902846634e-01f}, {9.415440559e-01f, 3.368898630e-01f},
-    {9.238795042e-01f, 3.826834261e-01f}, {9.039893150e-01f, 4.275550842e-01f},
-    {8.819212914e-01f, 4.713967443e-01f}, {8.577286005e-01f, 5.141027570e-01f},
-    {8.314695954e-01f, 5.555702448e-01f}, {8.032075167e-01f, 5.956993103e-01f},
-    {7.730104327e-01f, 6.343932748e-01f}, {7.409511209e-01f, 6.715589762e-01f},
-    {7.071067691e-01f, 7.071067691e-01f}, {6.715589762e-01f, 7.409511209e-01f},
-    {6.343932748e-01f, 7.730104327e-01f}, {5.956993103e-01f, 8.032075167e-01f},
-    {5.555702448e-01f, 8.314695954e-01f}, {5.141027570e-01f, 8.577286005e-01f},
-    {4.713967443e-01f, 8.819212914e-01f}, {4.275550842e-01f, 9.039893150e-01f},
-    {3.826834261e-01f, 9.238795042e-01f}, {3.368898630e-01f, 9.415440559e-01f},
-    {2.902846634e-01f, 9.569403529e-01f}, {2.429801822e-01f, 9.700312614e-01f},
-    {1.950903237e-01f, 9.807852507e-01f}, {1.467304677e-01f, 9.891765118e-01f},
-    {9.801714122e-02f, 9.951847196e-01f}, {4.906767607e-02f, 9.987954497e-01f},
-    {0.000000000e+00f, 1.000000000e+00f}, {-4.906767607e-02f, 9.987954497e-01f},
-    {-9.801714122e-02f, 9.951847196e-01f}, {-1.467304677e-01f, 9.891765118e-01f},
-    {-1.950903237e-01f, 9.807852507e-01f}, {-2.429801822e-01f, 9.700312614e-01f},
-    {-2.902846634e-01f, 9.569403529e-01f}, {-3.368898630e-01f, 9.415440559e-01f},
-    {-3.826834261e-01f, 9.238795042e-01f}, {-4.275550842e-01f, 9.039893150e-01f},
-    {-4.713967443e-01f, 8.819212914e-01f}, {-5.141027570e-01f, 8.577286005e-01f},
-    {-5.555702448e-01f, 8.314695954e-01f}, {-5.956993103e-01f, 8.032075167e-01f},
-    {-6.343932748e-01f, 7.730104327e-01f}, {-6.715589762e-01f, 7.409511209e-01f},
-    {-7.071067691e-01f, 7.071067691e-01f}, {-7.409511209e-01f, 6.715589762e-01f},
-    {-7.730104327e-01f, 6.343932748e-01f}, {-8.032075167e-01f, 5.956993103e-01f},
-    {-8.314695954e-01f, 5.555702448e-01f}, {-8.577286005e-01f, 5.141027570e-01f},
-    {-8.819212914e-01f, 4.713967443e-01f}, {-9.039893150e-01f, 4.275550842e-01f},
-    {-9.238795042e-01f, 3.826834261e-01f}, {-9.415440559e-01f, 3.368898630e-01f},
-    {-9.569403529e-01f, 2.902846634e-01f}, {-9.700312614e-01f, 2.429801822e-01f},
-    {-9.807852507e-01f, 1.950903237e-01f}, {-9.891765118e-01f, 1.467304677e-01f},
-    {-9.951847196e-01f, 9.801714122e-02f}, {-9.987954497e-01f, 4.906767607e-02f},
-    {-1.000000000e+00f, 0.000000000e+00f},
-};
+// Table-driven sin/cos of pi x: the table (tmm_phase_table.hpp) holds
+// (cos, sin)(pi k / 256) for k = 0..511, one period.  The argument is taken in
+// units of 1/256 half-turn, g = 256 x; Sg, Cg are near-minimax fits of
+// sin(pi g / 256) = g Sg(g^2), cos(pi g / 256) = Cg(g^2) on |g| <= 1/2, the
+// residual after g - round(g).
+constexpr int kScSteps = 256;                // table points per half-turn
+constexpr int kScEntries = 2 * kScSteps;     // one period, a power of two
+// Adding 1.5 * 2^52 rounds a double of magnitude below 2^51 to an integer, and
+// the low 32 bits of the sum's encoding are that integer modulo 2^32.
+constexpr double kRoundMagic = 6755399441055744.0;
+// Largest |g| accepted by sincospi_g (its reduction is exact below 2^51).
+constexpr double kScFastRange = 1125899906842624.0;  // 2^50
+// fit error 4.06e-21
+constexpr double kSinGD[3] = {0.01227184630308513, -3.0801968455583244e-07, 2.319357564247385e-12};
+// fit error 2.32e-18
+constexpr double kCosGD[3] = {1.0, -7.529910584310532e-05, 9.449907778733635e-10};
+// fit error 1.81e-14
+constexpr float kSinGF[2] = {1.227184664e-02f, -3.080191107e-07f};
+// fit error 7.38e-12
+constexpr float kCosGF[2] = {1.000000000e+00f, -7.529887080e-05f};
 
 // One Horner step acc * x + c as a single three-operand FMA with the
 // coefficient in scalar registers (it is the same for every lane).  Written as
@@ -240,38 +117,47 @@ __device__ __forceinline__ float exp2_f(float y) {
     return __builtin_amdgcn_ldexpf(horner<true>(kExp2F, f), (int)k);
 }
 
-// e^{i pi x} = (c, s) through the table `tab` (an LDS copy of kScTabD):
-// k = round(64 x), h = x - k/64 (exact, |h| <= 1/128), and k reduced modulo 128
-// (one period) in exact double arithmetic to kk in [-64, 64], then the
-// angle-sum formulas with the table entry kk + 64.  Exact for every finite x;
-// a non-finite x gives NaN (the index is clamped, so the read stays in range).
+// Table point and residual of g (units of 1/256 half-turn, |g| < 2^50):
+// t = g + 1.5 * 2^52 rounds g to the integer k, the low bits of t's encoding
+// give the entry k mod 512, and r = g - k is exact with |r| <= 1/2.
+// A non-finite g gives a NaN residual, and the masked index stays in the table.
+__device__ __forceinline__ double sc_reduce(double g, uint32_t& idx) {
+    const double t = g + kRoundMagic;
+    idx = (uint32_t)__double2loint(t) & (uint32_t)(kScEntries - 1);
+    return g - (t - kRoundMagic);
+}
+
+// e^{i pi g / 256} = (c, s) through the table `tab` (an LDS copy of kScTabD)
+// and the angle-sum formulas; |g| < kScFastRange.
 template <bool PIN>
-__device__ __forceinline__ void sincospi_tab(double x, const double2* tab, double& s, double& c) {
-    const double k = __builtin_rint((double)kScSteps * x);
-    const double h = __builtin_fma(-1.0 / kScSteps, k, x);
-    const double kk = __builtin_fma(-2.0 * kScSteps, __builtin_rint(k * (0.5 / kScSteps)), k);
-    const int idx = min(max((int)kk, -kScSteps), kScSteps);
-    const double2 t = tab[idx + kScSteps];
-    const double h2 = h * h;
-    const double sh = h * horner<PIN>(kSinHD, h2);
-    const double ch = horner<PIN>(kCosHD, h2);
+__device__ __forceinline__ void sincospi_g(double g, const double2* tab, double& s, double& c) {
+    uint32_t idx;
+    const double r = sc_reduce(g, idx);
+    const double2 t = tab[idx];
+    const double r2 = r * r;
+    const double sh = r * horner<PIN>(kSinGD, r2);
+    const double ch = horner<PIN>(kCosGD, r2);
     c = __builtin_fma(t.x, ch, -(t.y * sh));
     s = __builtin_fma(t.y, ch, t.x * sh);
 }
 
 // Same in float: the index and residual in exact double arithmetic, then float
 // polynomials and table (`tab` is an LDS copy of kScTabF).
-__device__ __forceinline__ void sincospi_tab_f(double x, const float2* tab, float& s, float& c) {
-    const double k = __builtin_rint((double)kScSteps * x);
-    const float h = (float)__builtin_fma(-1.0 / kScSteps, k, x);
-    const double kk = __builtin_fma(-2.0 * kScSteps, __builtin_rint(k * (0.5 / kScSteps)), k);
-    const int idx = min(max((int)kk, -kScSteps), kScSteps);
-    const float2 t = tab[idx + kScSteps];
-    const float h2 = h * h;
-    const float sh = h * horner<true>(kSinHF, h2);
-    const float ch = horner<true>(kCosHF, h2);
+__device__ __forceinline__ void sincospi_g_f(double g, const float2* tab, float& s, float& c) {
+    uint32_t idx;
+    const float r = (float)sc_reduce(g, idx);
+    const float2 t = tab[idx];
+    const float r2 = r * r;
+    const float sh = r * horner<true>(kSinGF, r2);
+    const float ch = horner<true>(kCosGF, r2);
     c = __builtin_fmaf(t.x, ch, -(t.y * sh));
     s = __builtin_fmaf(t.y, ch, t.x * sh);
+}
+
+// Any finite x (half-turns): x is first reduced modulo 2, exactly
+// (x - 2 rint(x/2)), then scaled by 256 (exact).
+__device__ __forceinline__ double sc_exact_g(double x) {
+    return __builtin_fma(-2.0, __builtin_rint(0.5 * x), x) * (double)kScSteps;
 }
 
 }  // namespace tmm

@@ -32,9 +32,12 @@
 namespace tmm {
 namespace ragged {
 
-constexpr int kThreads = 256;  // four waves, each with its own media table and layer staging
-constexpr int kWaves = kThreads / kWave;
+// Every wave works on its own units with its own media table and layer staging;
+// a workgroup is 1-12 such waves plus the shared phase table, sized at launch
+// so that the CU's resident waves fit its LDS.
+constexpr int kMaxThreads = 768;
 constexpr int kMaxMat = 8;
+constexpr size_t kLdsPerCU = 160 * 1024;
 
 template <typename R>
 struct Params {
@@ -125,11 +128,11 @@ __global__ void reset_counter(unsigned long long* c) {
 }
 
 template <typename R, int POL>
-__global__ void __launch_bounds__(kThreads) ragged_kernel(Params<R> p) {
+__global__ void __launch_bounds__(kMaxThreads) ragged_kernel(Params<R> p) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-    fill_phase_tab<R>(smem, threadIdx.x, kThreads);
+    fill_phase_tab<R>(smem, threadIdx.x, blockDim.x);
     __syncthreads();
     const TabPhase<R> phase = phase_of<R>(smem);
     unsigned char* my = smem + phase_tab_bytes<R>() + (size_t)wave * wave_lds_bytes(p.n_mat);
@@ -240,11 +243,41 @@ __global__ void __launch_bounds__(kThreads) ragged_kernel(Params<R> p) {
     }
 }
 
-// Launch shape chosen by the autotuner.
+// Launch shape chosen by the autotuner: workgroups per CU, units taken per
+// counter update, waves per workgroup.
 struct Shape {
     int blocks_per_cu;
     int grain;
+    int waves;
 };
+
+template <typename R>
+size_t shape_lds(int n_mat, int waves) {
+    return phase_tab_bytes<R>() + (size_t)waves * wave_lds_bytes(n_mat);
+}
+
+// Workgroup shapes that hold the most resident waves per CU (at most 12: 3 per
+// SIMD at the kernel's register count) within the CU's LDS; the three with the
+// largest workgroups.
+template <typename R>
+std::vector<Shape> candidate_shapes(int n_mat) {
+    const size_t granule = 2048;
+    int best = 0;
+    std::vector<Shape> out;
+    for (int waves = 12; waves >= 1; --waves) {
+        const size_t lds = (shape_lds<R>(n_mat, waves) + granule - 1) / granule * granule;
+        int per_cu = (int)(kLdsPerCU / lds);
+        if (per_cu > 12 / waves) per_cu = 12 / waves;
+        if (per_cu < 1) continue;
+        const int total = per_cu * waves;
+        if (total > best) {
+            best = total;
+            out.clear();
+        }
+        if (total == best && out.size() < 3) out.push_back({per_cu, 1, waves});
+    }
+    return out;
+}
 
 // Autotune cache: (dtype, pol, mean-layer bucket, unit-count bucket) -> shape.
 std::mutex g_tune_mutex;
@@ -305,23 +338,35 @@ tmm::ragged::Params<R> make_params(const tmm_ragged_plan* pl, const tmm_ragged_d
 template <typename R>
 hipError_t launch(const tmm_ragged_plan* pl, tmm::ragged::Params<R> p, tmm::ragged::Shape sh, hipStream_t s) {
     p.grain = sh.grain;
-    const size_t lds = tmm::phase_tab_bytes<R>() + (size_t)tmm::ragged::kWaves * tmm::ragged::wave_lds_bytes(p.n_mat);
+    const size_t lds = tmm::ragged::shape_lds<R>(p.n_mat, sh.waves);
     const int blocks = pl->n_cu * sh.blocks_per_cu;
+    const dim3 threads(sh.waves * tmm::kWave);
     hipLaunchKernelGGL(tmm::ragged::reset_counter, dim3(1), dim3(64), 0, s, pl->d_counter);
     if (pl->pol_mask == 1u)
-        hipLaunchKernelGGL((tmm::ragged::ragged_kernel<R, 1>), dim3(blocks), dim3(tmm::ragged::kThreads), lds, s, p);
+        hipLaunchKernelGGL((tmm::ragged::ragged_kernel<R, 1>), dim3(blocks), threads, lds, s, p);
     else if (pl->pol_mask == 2u)
-        hipLaunchKernelGGL((tmm::ragged::ragged_kernel<R, 2>), dim3(blocks), dim3(tmm::ragged::kThreads), lds, s, p);
+        hipLaunchKernelGGL((tmm::ragged::ragged_kernel<R, 2>), dim3(blocks), threads, lds, s, p);
     else
-        hipLaunchKernelGGL((tmm::ragged::ragged_kernel<R, 3>), dim3(blocks), dim3(tmm::ragged::kThreads), lds, s, p);
+        hipLaunchKernelGGL((tmm::ragged::ragged_kernel<R, 3>), dim3(blocks), threads, lds, s, p);
     return hipGetLastError();
 }
 
 // Times every candidate shape on the real data (each run produces the full,
 // valid output) and keeps the fastest; the result is cached per
 // (dtype, pol, layer bucket, unit bucket) for later plans.
+// Dynamic LDS above 64 KiB: raise the kernels' limit (outside any capture).
+template <typename R>
+void raise_lds_limit() {
+    const int lim = (int)tmm::ragged::kLdsPerCU;
+    (void)hipFuncSetAttribute((const void*)&tmm::ragged::ragged_kernel<R, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    (void)hipFuncSetAttribute((const void*)&tmm::ragged::ragged_kernel<R, 2>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    (void)hipFuncSetAttribute((const void*)&tmm::ragged::ragged_kernel<R, 3>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    (void)hipGetLastError();
+}
+
 template <typename R>
 tmm_status tune(tmm_ragged_plan* pl, const tmm::ragged::Params<R>& p, int di, hipStream_t s) {
+    raise_lds_limit<R>();
     const int lb = pl->mean_layers / 16;
     int ub = 0;
     for (int64_t u = pl->n_units; u > 1; u >>= 2) ++ub;
@@ -335,16 +380,16 @@ tmm_status tune(tmm_ragged_plan* pl, const tmm::ragged::Params<R>& p, int di, hi
             return ok();
         }
     }
-    const int bpc[] = {1, 2, 4};
+    const std::vector<tmm::ragged::Shape> shapes = tmm::ragged::candidate_shapes<R>(p.n_mat);
     const int grains[] = {1, 4};
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
         return fail(TMM_ERR_HIP, "tmm_ragged_run: event creation failed");
     float best = 1e30f;
-    tmm::ragged::Shape best_sh = {2, 1};
-    for (int b : bpc) {
+    tmm::ragged::Shape best_sh = shapes.front();
+    for (const tmm::ragged::Shape& base : shapes) {
         for (int g : grains) {
-            const tmm::ragged::Shape sh = {b, g};
+            const tmm::ragged::Shape sh = {base.blocks_per_cu, g, base.waves};
             hipEventRecord(e0, s);
             if (launch<R>(pl, p, sh, s) != hipSuccess) {
                 hipEventDestroy(e0);

@@ -243,3 +243,82 @@ def test_binding_rejects_arrays_smaller_than_the_batch():
     with pytest.raises(ValueError):
         tmm.tmm_rt(dev(w.d, torch.float64), dev(w.nk[:, :4], torch.complex128), dev(w.wl, torch.float64),
                    dev(w.sin_t, torch.float64), dev(w.cos_t, torch.float64), mat=dev(w.mat, torch.int32), R=R)
+
+
+# --- material-table (pair) path ---------------------------------------------
+# With material ids and a small table the forward kernel runs the ratio form of
+# the recursion on per-pair LDS blocks (up to 6 materials in float64, 8 in
+# float32); these cases cover the table sizes on both sides of those limits,
+# the workgroup shapes they select, layer counts across renormalisation blocks
+# and 64-layer chunks, and the fallbacks.
+
+def _material_workload(seed, B, L, n_wl, n_theta, n_inner, *, theta_max_deg=89.0, n_amb=1.0, n_sub=1.52,
+                       k_max=0.02):
+    from dataclasses import replace
+    rng = np.random.default_rng(seed)
+    w = workloads.random_stacks(seed, B=B, L=L, n_wl=n_wl, n_theta=n_theta, theta_max_deg=theta_max_deg)
+    k = np.where(rng.random(n_inner) < 0.5, 0.0, rng.uniform(0.0, k_max, n_inner))
+    nk = np.empty((n_inner + 2, n_wl), np.complex128)
+    nk[:n_inner] = workloads.cauchy(rng.uniform(1.3, 2.6, n_inner), rng.uniform(0.0, 0.03, n_inner), k, w.wl)
+    nk[n_inner] = n_amb
+    nk[n_inner + 1] = n_sub
+    mat = np.empty((B, L + 2), np.int32)
+    mat[:, 0] = n_inner
+    mat[:, 1:L + 1] = rng.integers(0, n_inner, (B, L))
+    mat[:, L + 1] = n_inner + 1
+    return replace(w, nk=nk, mat=mat)
+
+
+@pytest.mark.parametrize("n_inner,L", [(1, 5), (2, 33), (4, 70), (5, 40), (6, 17)])
+def test_material_table_sizes_f64(n_inner, L):
+    w = _material_workload(40 + n_inner, B=29, L=L, n_wl=97, n_theta=3, n_inner=n_inner)
+    assert_close64(run_gpu(w, amplitudes=True), run_oracle(w, amplitudes=True), ("R", "T", "r", "t"))
+    assert_close64(run_gpu(w), run_oracle(w))
+
+
+@pytest.mark.parametrize("n_inner,L", [(2, 9), (6, 66), (7, 24)])
+def test_material_table_sizes_f32(n_inner, L):
+    w = _material_workload(50 + n_inner, B=21, L=L, n_wl=70, n_theta=2, n_inner=n_inner)
+    assert_close32(run_gpu(w, dtype="f32"), run_oracle(w.rounded_f32()))
+
+
+def test_many_stacks_per_workgroup_with_ragged_chunk():
+    # 200 stacks: several stack chunks per (angle, wavelength tile), the last one partial
+    w = _material_workload(60, B=200, L=12, n_wl=64, n_theta=2, n_inner=4)
+    assert_close64(run_gpu(w, amplitudes=True), run_oracle(w, amplitudes=True), ("R", "T", "r", "t"))
+
+
+def test_near_critical_layer_takes_the_division_free_path():
+    # Dense ambient (n = 1.5) and one air layer per stack at 4e-6 (relative)
+    # from its critical angle: q of the air layer is ~2.5e-3 (real or
+    # imaginary), so the pair ratios exceed their bound and those workgroups
+    # evaluate their stacks with the division-free recursion (the angle 0.3
+    # rad stays on the pair path).  One such layer per stack keeps the problem
+    # well conditioned: k of them amplify rounding by about (1/|t|)^k.
+    from dataclasses import replace
+    w = _material_workload(61, B=6, L=8, n_wl=64, n_theta=3, n_inner=3, n_amb=1.5, k_max=0.0)
+    nk = w.nk.copy()
+    nk[0] = 1.0
+    mat = w.mat.copy()
+    inner = mat[:, 1:-1]
+    inner[inner == 0] = 1
+    inner[np.arange(w.B), np.arange(w.B) % w.L] = 0
+    th_c = np.arcsin(1.0 / 1.5)
+    theta = np.array([0.3, th_c * (1 + 4e-6), th_c * (1 - 4e-6)])
+    s, c = workloads.angles(theta)
+    w = replace(w, nk=nk, mat=mat, theta=theta, sin_t=s, cos_t=c)
+    assert_close64(run_gpu(w, amplitudes=True), run_oracle(w, amplitudes=True), ("R", "T", "r", "t"))
+
+
+@pytest.mark.parametrize("d_thick", [1e9, 1e16])
+def test_thick_lossless_layer_conserves_energy(d_thick):
+    # A 1 m layer stays on the fast phase reduction, a 1e16 nm layer takes the
+    # exact one (phase beyond 2^49 / 256 half-turns).  The phase of such layers
+    # is ill-conditioned (its rounding alone is ~1e-8 rad at 1 m), so the check
+    # is the property that holds for any phase: R + T = 1 without absorption.
+    w = _material_workload(62, B=4, L=6, n_wl=64, n_theta=3, n_inner=3, k_max=0.0)
+    w.d[:, 2] = d_thick
+    got = run_gpu(w)
+    for k in ("R", "T"):
+        assert np.isfinite(got[k]).all(), k
+    assert np.abs(got["R"] + got["T"] - 1.0).max() <= 1e-12
