@@ -164,10 +164,13 @@ struct PointOut {
 template <typename R, int POL, bool AMP, class C>
 __device__ __forceinline__ void finish(const C& c, const Ambient& amb,
                                        const Layer<R>& first, const Layer<R>& sub,
-                                       double nsub_r, double nsub_i, int L, PointOut* out) {
+                                       double nsub_r, double nsub_i, int L, PointOut* out,
+                                       const TabPhase<R>& phase) {
     const double ly = C::kRatio ? c.S : c.S * kNegPiLog2e;
     const double Fh = C::kRatio ? c.F * (1.0 / kScSteps) : c.F;  // half-turns
-    const double eS = exp2(ly);
+    // the layer loop's own 2^y and table sin/cos (their constants are already
+    // resident; library versions would add their own per stack)
+    const double eS = exp2_d<true>(ly);
     const int two_L1 = 2 * (L + 1);
     if (POL & 1) {
         const cx<double> q0 = {amb.q0r, amb.q0i};
@@ -195,9 +198,9 @@ __device__ __forceinline__ void finish(const C& c, const Ambient& amb,
         o.T = ldexp(amb.Ks * prod * sub.pr * eS / na, two_L1 + eprod - 2 * c.es);
         if (AMP) {
             o.r = cdiv(b, a);
-            double sn, cs;
-            sincospi(0.5 * Fh, &sn, &cs);
-            const double m = exp2(0.5 * ly);
+            const cx<R> rot = phase.cis_g(sc_exact_g(0.5 * Fh));
+            const double cs = (double)rot.re, sn = (double)rot.im;
+            const double m = exp2_d<true>(0.5 * ly);
             const cx<double> ph = {m * cs, m * sn};
             cx<double> num = cmul(cmul(q0, Pq), ph);
             cx<double> tt = cdiv(num, a);
@@ -231,9 +234,9 @@ __device__ __forceinline__ void finish(const C& c, const Ambient& amb,
         o.T = ldexp(amb.Kp * prod * (double)sub.e.re * eS / na, two_L1 + eprod - 2 * c.ep);
         if (AMP) {
             o.r = cdiv(b, a);
-            double sn, cs;
-            sincospi(0.5 * Fh, &sn, &cs);
-            const double m = exp2(0.5 * ly);
+            const cx<R> rot = phase.cis_g(sc_exact_g(0.5 * Fh));
+            const double cs = (double)rot.re, sn = (double)rot.im;
+            const double m = exp2_d<true>(0.5 * ly);
             const cx<double> ph = {m * cs, m * sn};
             // P_p = 2^{L+1} n_0 n_sub / q_sub prod eta_j
             const cx<double> n0 = {amb.n0r, amb.n0i};

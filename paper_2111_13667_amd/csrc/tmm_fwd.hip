@@ -158,7 +158,7 @@ __device__ __forceinline__ void run_stack(const FwdParams<R>& p, const Src& src,
     }
     c.renorm();
     PointOut out[2];
-    finish<R, POL, AMP>(c, amb, nxt, sub, nsub_r, nsub_i, L, out);
+    finish<R, POL, AMP>(c, amb, nxt, sub, nsub_r, nsub_i, L, out, phase);
     if (active) {
         const bool valid = lane_ok && !bad;
         constexpr int P = (POL == 3) ? 2 : 1;
@@ -231,7 +231,7 @@ __device__ __forceinline__ void run_stack_table(const FwdParams<R>& p, const Tab
     }
     c.renorm();
     PointOut out[2];
-    finish<R, POL, AMP>(c, amb, tab.get(nxt_row, lane), sub, nsub_r, nsub_i, L, out);
+    finish<R, POL, AMP>(c, amb, tab.get(nxt_row, lane), sub, nsub_r, nsub_i, L, out, phase);
     if (active) {
         const bool valid = lane_ok && !bad;
         constexpr int P = (POL == 3) ? 2 : 1;
@@ -461,7 +461,7 @@ __device__ __forceinline__ bool run_stack_pair(const FwdParams<R>& p, const unsi
     const int m_first_raw = L >= 1 ? mrow[1] : m_sub;
     const int m_first = (uint32_t)m_first_raw < (uint32_t)n_mat ? m_first_raw : 0;
     PointOut out[2];
-    finish<R, POL, AMP>(c, amb, tab.get(m_first, lane), tab.get(m_sub, lane), nsub_r, nsub_i, L, out);
+    finish<R, POL, AMP>(c, amb, tab.get(m_first, lane), tab.get(m_sub, lane), nsub_r, nsub_i, L, out, phase);
     if (active) {
         const bool valid = lane_ok && !bad;
         constexpr int P = (POL == 3) ? 2 : 1;

@@ -225,7 +225,7 @@ __global__ void __launch_bounds__(kMaxThreads) ragged_kernel(Params<R> p) {
             }
             c.renorm();
             PointOut out[2];
-            finish<R, POL, false>(c, amb, tab.get(nxt_row, lane), sub, 0.0, 0.0, L, out);
+            finish<R, POL, false>(c, amb, tab.get(nxt_row, lane), sub, 0.0, 0.0, L, out, phase);
             if (active) {
                 const bool valid = lam_ok && amb.ok && !bad;
                 const double nan = __builtin_nan("");
