@@ -629,8 +629,11 @@ static hipError_t launch_pair(const FwdParams<R>& p, int blocks, int threads, si
 
 // Launch shape of the pair kernel: as many workgroups per CU as the LDS holds
 // (at most 4), and waves per workgroup so that the CU holds its maximum of
-// resident waves; stacks per workgroup up to 32 per wave, fewer when the grid
-// would otherwise hold less than 64 workgroups per resident slot.
+// resident waves.  Stacks per workgroup: enough layer steps to amortise the
+// workgroup's table build (about 320 VALU instructions per material pair and
+// 150 per material, against about 60 per layer step) twenty times over, more
+// while the grid keeps at least 64 workgroups per resident slot (a short last
+// round of workgroups), at most 32 per wave.
 template <typename R, int POL, bool AMP>
 static tmm_status run_pair(FwdParams<R> p, int64_t B, int64_t cols, hipStream_t s) {
     const size_t lds = pair_lds_bytes<R>(p.n_mat);
@@ -638,11 +641,12 @@ static tmm_status run_pair(FwdParams<R> p, int64_t B, int64_t cols, hipStream_t 
     int per_cu = (int)(kLdsPerCU / ((lds + granule - 1) / granule * granule));
     per_cu = per_cu < 1 ? 1 : (per_cu > 4 ? 4 : per_cu);
     const int waves = pair_max_waves<R, POL, AMP>() / per_cu;
-    const int64_t slots = 256 * (int64_t)per_cu * 64;
-    int64_t chunk = ceil_div(B * cols, slots);
-    chunk = ceil_div(chunk, waves) * waves;
-    if (chunk < waves) chunk = waves;
+    const int64_t table_cost = 320 * (int64_t)p.n_mat * p.n_mat + 150 * (int64_t)p.n_mat;
+    const int64_t amortise = ceil_div(20 * table_cost, 60 * ((int64_t)p.L + 1));
+    const int64_t fill = ceil_div(B * cols, 256 * (int64_t)per_cu * 64);
+    int64_t chunk = amortise > fill ? amortise : fill;
     if (chunk > 32 * waves) chunk = 32 * waves;
+    chunk = ceil_div(chunk, waves) * waves;
     p.chunk = (int)chunk;
     const int64_t blocks = cols * ceil_div(B, (int64_t)p.chunk);
     if (blocks > 0x7fffffff)
