@@ -95,8 +95,8 @@ struct Chain {
 // them once; per step that saves two complex products and the two running
 // products of the division-free form.  Per-step growth is bounded by
 // 2 (1 + |rho|); with |rho| <= kPairRatioMax (checked when the table is built)
-// 32 double steps or 8 float steps stay far from overflow.
-constexpr double kPairRatioMax = 256.0;
+// 32 double steps or 8 float steps stay far from overflow (kPairRatioMax is in
+// tmm_device.hpp).
 template <typename R> struct PairRenormPeriod;
 template <> struct PairRenormPeriod<double> { static constexpr int value = 32; };
 template <> struct PairRenormPeriod<float> { static constexpr int value = 8; };
@@ -126,9 +126,9 @@ struct PairChain {
         if (lossy) {
             const double y = d * cim;
             S += y;
-            const R g = phase.atten(y);
-            E.re *= g;
-            E.im *= g;
+            const R att = phase.atten(y);
+            E.re *= att;
+            E.im *= att;
         }
         if (AMP) F = reduce1024(F + g);
         if (POL & 1) {

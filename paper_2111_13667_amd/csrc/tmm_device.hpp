@@ -41,6 +41,9 @@ namespace tmm {
 constexpr int kWave = 64;
 constexpr double kNegPiLog2e = -4.5323601418271938;  // -pi / ln 2
 constexpr double kBranchEps = 100.0 * 2.220446049250313e-16;
+// Largest modulus of a tabulated ratio q_{j+1}/q_j or eta_{j+1}/eta_j in the
+// ratio form of the recursion (a larger one falls back to the division-free form).
+constexpr double kPairRatioMax = 256.0;
 
 template <typename R>
 struct cx {

@@ -77,7 +77,8 @@ struct GradParams {
     double* partial;   // [column][stack - b_begin][L][3]
     int b_begin, b_end;
     int n_tiles, n_seg;
-    int64_t n_tasks;   // columns * ceil((b_end - b_begin) / kGradWaves)
+    int64_t n_tasks;   // columns * ceil((b_end - b_begin) / waves per block)
+    int64_t n_tasks_pair;  // the same for the ratio-form kernel's blocks
     int64_t per_block;
 };
 
@@ -597,6 +598,472 @@ __global__ void __launch_bounds__(kGradBlock) __attribute__((amdgpu_waves_per_eu
     }
 }
 
+// ---------------------------------------------------------------------------
+// Ratio form (material ids, small tables, L + 2 <= 64).  The forward steps are
+// those of the forward kernel's pair path: step j divided by q_j (s) or eta_j
+// (p), with rho_s = q_{j+1}/q_j and rho_p = eta_{j+1}/eta_j tabulated per
+// ordered material pair, and the normalisation products gone from T.
+// Adjoint of one step, X = rho tau (s) or rho sigma (p):
+//   s: a = s + X, b = s - X        p: a = X + t, b = X - t
+//   ab = sb' + tb', Y = sb' - tb', bb = conj(E) Y, Eb += conj(b) Y,
+//   s: sb = ab + bb, Xb = ab - bb, tb = conj(rho) Xb
+//   p: Xb = ab + bb, tb = ab - bb, sb = conj(rho) Xb
+//   rhob = conj(tau) Xb (s) or conj(sigma) Xb (p), and w = conj(rho) rhob = conj(X) Xb.
+// rho_j depends on q_j as -rho/q_j and on q_{j+1} as rho/q_{j+1}, so layer j
+// collects conj(1/q_j) (w_{j-1} - w_j) (w_0 = 0: the ambient step keeps the
+// division-free form), and dl/dn_j takes it through (dq/dn)/q (same for eta).
+constexpr int kGradPairWaves = 8;        // two per SIMD at the kernel's register count
+constexpr int kGradPairBlock = kGradPairWaves * kWave;
+constexpr int kGradPairMaxBlocks = kGradMaxBlocks * kGradWaves / kGradPairWaves;  // same checkpoint slots
+constexpr int kGradPairMaxMat = 5;
+constexpr int kPairFields = 6;           // q, eta, dq/dn, deta/dn, (dq/dn)/q, (deta/dn)/eta
+constexpr int kGradPairBlockBytes = 3 * kWave * 16;  // rho_s[64], rho_p[64], (cre, cim)[64]
+
+__host__ __device__ constexpr size_t grad_pair_lds_bytes(int n_mat) {
+    return phase_tab_bytes<double>() + (size_t)kGradPairWaves * kRed * kWave * sizeof(double) +
+           (size_t)n_mat * kPairFields * kWave * sizeof(double2) + (size_t)n_mat * n_mat * kGradPairBlockBytes;
+}
+
+// Layer data of the stack, one value per lane (L + 2 <= 64), broadcast by readlane.
+struct PairLayers {
+    const double2* mtab;            // material table + lane: mtab[(row * kPairFields + f) * kWave]
+    const unsigned char* pair_lane; // pair blocks + lane * 16
+    double my_d;   // lane l: thickness of layer l + 1
+    int my_code;   // lane l: pair block offset of layer l + 1 | lossy << 31
+    int my_row;    // lane l: material row of medium l
+    __device__ __forceinline__ double d(int j) const {
+        return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(my_d), j - 1),
+                                __builtin_amdgcn_readlane(__double2loint(my_d), j - 1));
+    }
+    __device__ __forceinline__ int code(int j) const { return __builtin_amdgcn_readlane(my_code, j - 1); }
+    __device__ __forceinline__ int row(int j) const { return __builtin_amdgcn_readlane(my_row, j); }
+    __device__ __forceinline__ cx<double> field(int m, int f) const {
+        const double2 v = mtab[(m * kPairFields + f) * kWave];
+        return {v.x, v.y};
+    }
+    // rho_s, rho_p and the phase coefficients of step j
+    __device__ __forceinline__ void pair(int code, cx<double>& rs, cx<double>& rp, double& cre, double& cim) const {
+        const double2* e = reinterpret_cast<const double2*>(pair_lane + (code & 0x7fffffff));
+        const double2 x = e[0], y = e[kWave], z = e[2 * kWave];
+        rs = {x.x, x.y};
+        rp = {y.x, y.y};
+        cre = z.x;
+        cim = z.y;
+    }
+};
+
+template <int POL>
+__device__ __forceinline__ void ratio_step(State& z, const cx<double>& rs, const cx<double>& rp,
+                                           const cx<double>& E) {
+    if (POL & 1) {
+        const cx<double> X = cmul(rs, z.ts);
+        const cx<double> a = cadd(z.ss, X), b = csub(z.ss, X);
+        const cx<double> Eb = cmul(E, b);
+        z.ss = cadd(a, Eb);
+        z.ts = csub(a, Eb);
+    }
+    if (POL & 2) {
+        const cx<double> X = cmul(rp, z.sp);
+        const cx<double> a = cadd(X, z.tp), b = csub(X, z.tp);
+        const cx<double> Eb = cmul(E, b);
+        z.sp = cadd(a, Eb);
+        z.tp = csub(a, Eb);
+    }
+}
+
+// E_j and the base-2 attenuation exponent of step j (|d cre| < kScFastRange).
+__device__ __forceinline__ cx<double> pair_phase(double dj, double cre, double cim, bool lossy,
+                                                 const TabPhase<double>& phase, double& y) {
+    cx<double> E = phase.cis_g(dj * cre);
+    y = 0.0;
+    if (lossy) {
+        y = dj * cim;
+        const double att = phase.atten(y);
+        E.re *= att;
+        E.im *= att;
+    }
+    return E;
+}
+
+template <int POL>
+__device__ void grad_stack_pair(const GradParams& p, const PairLayers& src, const Ambient& amb, int b, int k, int i,
+                                int lane, bool active, bool valid, double* ws, double* red, double* part,
+                                const TabPhase<double>& phase) {
+    const int L = p.L;
+    constexpr int P = (POL == 3) ? 2 : 1;
+    const double two_pi_lam = 2.0 * M_PI / p.wl[i];
+    auto ck = [&](int c, int comp) -> double& { return ws[((size_t)c * kCkptDoubles + comp) * kWave + lane]; };
+    auto save = [&](int c, const State& z) {
+        ck(c, 0) = z.ss.re; ck(c, 1) = z.ss.im; ck(c, 2) = z.ts.re; ck(c, 3) = z.ts.im;
+        ck(c, 4) = z.sp.re; ck(c, 5) = z.sp.im; ck(c, 6) = z.tp.re; ck(c, 7) = z.tp.im;
+    };
+    auto load = [&](int c) -> State {
+        State z;
+        z.ss = {ck(c, 0), ck(c, 1)}; z.ts = {ck(c, 2), ck(c, 3)};
+        z.sp = {ck(c, 4), ck(c, 5)}; z.tp = {ck(c, 6), ck(c, 7)};
+        return z;
+    };
+
+    // ---- pass A: forward with checkpoints --------------------------------
+    State z;
+    z.ss = z.ts = z.sp = z.tp = {1.0, 0.0};
+    int es = 0, ep = 0;
+    double S = 0.0;  // sum of the base-2 attenuation exponents
+    save(0, z);
+    for (int s = 0; s < p.n_seg; ++s) {
+        const int top = L - s * kSeg;
+        const int lo = top - kSeg + 1 > 1 ? top - kSeg + 1 : 1;
+        for (int j = top; j >= lo; --j) {
+            const int code = src.code(j);
+            cx<double> rs, rp;
+            double cre, cim, y;
+            src.pair(code, rs, rp, cre, cim);
+            const cx<double> E = pair_phase(src.d(j), cre, cim, code < 0, phase, y);
+            S += y;
+            ratio_step<POL>(z, rs, rp, E);
+        }
+        if (POL & 1) renorm_pair(z.ss, z.ts, es);
+        if (POL & 2) renorm_pair(z.sp, z.tp, ep);
+        save(s + 1, z);
+    }
+    const int m1 = src.row(1), msub = src.row(L + 1);
+    const cx<double> q1 = src.field(m1, 0), e1 = src.field(m1, 1);
+    const double eS = exp2_d<true>(S);
+    const int two_L1 = 2 * (L + 1);
+    const double nan = __builtin_nan("");
+    const double w_act = active ? 1.0 : 0.0;  // ragged-tail lanes contribute nothing
+
+    // ambient step (division-free: a = q0 sigma + q1 tau, a = eta1 sigma + eta0 tau) and output adjoints
+    cx<double> sb_s = {0, 0}, tb_s = {0, 0}, sb_p = {0, 0}, tb_p = {0, 0};
+    cx<double> pend_q = {0, 0}, pend_e = {0, 0};  // adjoints of q_1, eta_1 from the ambient step
+    double cT_s = 0.0, cT_p = 0.0;
+    const cx<double> q0 = {amb.q0r, amb.q0i}, e0 = {amb.e0r, amb.e0i};
+    if (POL & 1) {
+        const cx<double> A = cmul(q0, z.ss), Bv = cmul(q1, z.ts);
+        const cx<double> a = cadd(A, Bv), bb = csub(A, Bv);
+        const double na = cnorm(a);
+        const double R = cnorm(bb) / na;
+        const double T = ldexp(amb.Ks * src.field(msub, 0).re * eS / na, two_L1 - 2 * es);
+        const int64_t o = (((int64_t)b * P + 0) * p.n_theta + k) * p.n_wl + i;
+        if (active && p.R_out) p.R_out[o] = valid ? R : nan;
+        if (active && p.T_out) p.T_out[o] = valid ? T : nan;
+        const double gR = p.gR ? p.gR[o] * w_act : 0.0;
+        const double gT = p.gT ? p.gT[o] * w_act : 0.0;
+        cT_s = gT * T;
+        const cx<double> abar = cscale(-2.0 * (gR * R + gT * T) / na, a);
+        const cx<double> bbar = cscale(2.0 * gR / na, bb);
+        const cx<double> Ab = cadd(abar, bbar), Bb = csub(abar, bbar);
+        sb_s = cmulc(q0, Ab);
+        tb_s = cmulc(q1, Bb);
+        pend_q = cmulc(z.ts, Bb);
+    }
+    if (POL & 2) {
+        const cx<double> A = cmul(e1, z.sp), Bv = cmul(e0, z.tp);
+        const cx<double> a = cadd(A, Bv), bb = csub(A, Bv);
+        const double na = cnorm(a);
+        const double R = cnorm(bb) / na;
+        const double T = ldexp(amb.Kp * src.field(msub, 1).re * eS / na, two_L1 - 2 * ep);
+        const int64_t o = (((int64_t)b * P + (P - 1)) * p.n_theta + k) * p.n_wl + i;
+        if (active && p.R_out) p.R_out[o] = valid ? R : nan;
+        if (active && p.T_out) p.T_out[o] = valid ? T : nan;
+        const double gR = p.gR ? p.gR[o] * w_act : 0.0;
+        const double gT = p.gT ? p.gT[o] * w_act : 0.0;
+        cT_p = gT * T;
+        const cx<double> abar = cscale(-2.0 * (gR * R + gT * T) / na, a);
+        const cx<double> bbar = cscale(2.0 * gR / na, bb);
+        const cx<double> Ab = cadd(abar, bbar), Bb = csub(abar, bbar);
+        sb_p = cmulc(e1, Ab);
+        tb_p = cmulc(e0, Bb);
+        pend_e = cmulc(z.sp, Ab);
+    }
+    const double cT = (POL & 1 ? cT_s : 0.0) + (POL & 2 ? cT_p : 0.0);
+    if (!valid) {  // poison the gradients of this lane's stack
+        sb_s = tb_s = sb_p = tb_p = pend_q = pend_e = {nan, nan};
+    }
+    cx<double> wprev_s = {0, 0}, wprev_p = {0, 0};  // w of the step below the current layer
+
+    // ---- pass B: segments from the ambient side ----------------------------
+    const int v_red = lane >> 2 < kRed ? lane >> 2 : kRed - 1;  // share this lane sums
+    const double2* red_in = reinterpret_cast<const double2*>(red + v_red * kWave + (lane & 3) * 16);
+    auto segment = [&](auto nst_c, int s, int top) {
+        constexpr int NST = decltype(nst_c)::value;
+        State zin[NST];
+        cx<double> Es[NST];
+        State zz = load(s);
+#pragma unroll
+        for (int t = 0; t < NST; ++t) {
+            const int j = top - t;
+            const int code = src.code(j);
+            cx<double> rs, rp;
+            double cre, cim, y;
+            src.pair(code, rs, rp, cre, cim);
+            Es[t] = pair_phase(src.d(j), cre, cim, code < 0, phase, y);
+            zin[t] = zz;
+            ratio_step<POL>(zz, rs, rp, Es[t]);
+        }
+        // the forward pass renormalised the segment's end state; undo on the adjoint
+        if (POL & 1) {
+            const double f = ldexp(1.0, -pair_exp(zz.ss, zz.ts));
+            sb_s = cscale(f, sb_s);
+            tb_s = cscale(f, tb_s);
+        }
+        if (POL & 2) {
+            const double f = ldexp(1.0, -pair_exp(zz.sp, zz.tp));
+            sb_p = cscale(f, sb_p);
+            tb_p = cscale(f, tb_p);
+        }
+#pragma unroll
+        for (int t = NST - 1; t >= 0; --t) {
+            const int j = top - t;
+            cx<double> rs, rp;
+            double cre, cim;
+            src.pair(src.code(j), rs, rp, cre, cim);
+            const cx<double> E = Es[t];
+            cx<double> Eb = {0.0, 0.0};
+            cx<double> w_s = {0, 0}, w_p = {0, 0};
+            if (POL & 1) {
+                const cx<double> X = cmul(rs, zin[t].ts);
+                const cx<double> bv = csub(zin[t].ss, X);
+                const cx<double> ab = cadd(sb_s, tb_s), Y = csub(sb_s, tb_s);
+                const cx<double> bb = cmulc(E, Y);
+                Eb = cadd(Eb, cmulc(bv, Y));
+                const cx<double> Xb = csub(ab, bb);
+                sb_s = cadd(ab, bb);
+                tb_s = cmulc(rs, Xb);
+                w_s = cmulc(X, Xb);
+            }
+            if (POL & 2) {
+                const cx<double> X = cmul(rp, zin[t].sp);
+                const cx<double> bv = csub(X, zin[t].tp);
+                const cx<double> ab = cadd(sb_p, tb_p), Y = csub(sb_p, tb_p);
+                const cx<double> bb = cmulc(E, Y);
+                Eb = cadd(Eb, cmulc(bv, Y));
+                const cx<double> Xb = cadd(ab, bb);
+                tb_p = csub(ab, bb);
+                sb_p = cmulc(rp, Xb);
+                w_p = cmulc(X, Xb);
+            }
+            const int m = src.row(j);
+            const cx<double> qj = src.field(m, 0);
+            const double dj = src.d(j);
+            // deltab = -2i conj(E) Eb - 2i cT  (chain and e^{-2 Im sum delta})
+            const cx<double> cE = cmulc(E, Eb);
+            const cx<double> db = {2.0 * cE.im, -2.0 * cE.re - 2.0 * cT};
+            const double gd = two_pi_lam * (db.re * qj.re + db.im * qj.im);
+            const cx<double> qb = cadd(pend_q, cscale(two_pi_lam * dj, db));
+            cx<double> nb = cmulc(src.field(m, 2), qb);
+            if (POL & 2) nb = cadd(nb, cmulc(src.field(m, 3), pend_e));
+            if (POL & 1) nb = cadd(nb, cmulc(src.field(m, 4), csub(wprev_s, w_s)));
+            if (POL & 2) nb = cadd(nb, cmulc(src.field(m, 5), csub(wprev_p, w_p)));
+            wprev_s = w_s;
+            wprev_p = w_p;
+            pend_q = pend_e = {0.0, 0.0};
+            red[(3 * t + 0) * kWave + lane] = gd;
+            red[(3 * t + 1) * kWave + lane] = nb.re;
+            red[(3 * t + 2) * kWave + lane] = nb.im;
+        }
+    };
+    for (int s = p.n_seg - 1; s >= 0; --s) {
+        const int top = L - s * kSeg;
+        const int lo = top - kSeg + 1 > 1 ? top - kSeg + 1 : 1;
+        const int nst = top - lo + 1;
+        if (nst == kSeg) {
+            segment(std::integral_constant<int, kSeg>(), s, top);
+        } else {
+            static_assert(kSeg <= 4, "segment lengths below are spelled out");
+            if (nst == 1) segment(std::integral_constant<int, 1>(), s, top);
+            if (kSeg > 2 && nst == 2) segment(std::integral_constant<int, (kSeg > 2 ? 2 : 1)>(), s, top);
+            if (kSeg > 3 && nst == 3) segment(std::integral_constant<int, (kSeg > 3 ? 3 : 1)>(), s, top);
+        }
+        wave_sync();
+        double acc = 0.0;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const double2 x = red_in[u];
+            acc += x.x;
+            acc += x.y;
+        }
+        acc = quad_add<0xB1>(acc);
+        acc = quad_add<0x4E>(acc);
+        if ((lane & 3) == 0 && (lane >> 2) < 3 * nst) {
+            const int v = lane >> 2;
+            const int t = v / 3;
+            part[(top - t - 1) * 3 + (v - 3 * t)] = acc;
+        }
+        wave_sync();
+    }
+}
+
+// Fills the block's material table and pair blocks for one column and ambient
+// row (all waves share the work), and per wave: a ratio out of bound in a used
+// lane, the largest phase coefficient, and the lossy flag of each material.
+__device__ void build_pair_table(const GradParams& p, double2* mtab, unsigned char* pairs, int amb_row, int i,
+                                 bool lane_used, double st, double ct, int wave, int lane, int* s_bad,
+                                 double* s_cmax, int* s_lossy) {
+    double n0r, n0i;
+    load_n(p.nk, p.dispersive, p.n_wl, amb_row, i, n0r, n0i);
+    const Ambient a = make_ambient(n0r, n0i, st, ct);
+    const double lam = p.wl[i];
+    for (int m = wave; m < p.n_mat; m += kGradPairWaves) {
+        double nr, ni;
+        load_n(p.nk, p.dispersive, p.n_wl, m, i, nr, ni);
+        const Medium md = make_medium(nr, ni, a.kx);
+        const FL f = fl_from(md);
+        const AL g = al_from(nr, ni, f);
+        const cx<double> lq = cdiv(g.nq, f.q), le = cdiv(g.de, f.e);
+        double2* e = mtab + m * kPairFields * kWave + lane;
+        e[0] = make_double2(f.q.re, f.q.im);
+        e[kWave] = make_double2(f.e.re, f.e.im);
+        e[2 * kWave] = make_double2(g.nq.re, g.nq.im);
+        e[3 * kWave] = make_double2(g.de.re, g.de.im);
+        e[4 * kWave] = make_double2(lq.re, lq.im);
+        e[5 * kWave] = make_double2(le.re, le.im);
+        const bool lossy = __any(md.qi != 0.0);
+        if (lane == 0) s_lossy[m] = lossy ? 1 : 0;
+    }
+    bool bad = false;
+    double cmax = 0.0;
+    const double c4lam = 4.0 / lam;
+    for (int pi = wave; pi < p.n_mat * p.n_mat; pi += kGradPairWaves) {
+        const int mc = pi / p.n_mat, mn = pi - mc * p.n_mat;
+        double ar, ai, br, bi;
+        load_n(p.nk, p.dispersive, p.n_wl, mc, i, ar, ai);
+        load_n(p.nk, p.dispersive, p.n_wl, mn, i, br, bi);
+        const Medium ma = make_medium(ar, ai, a.kx), mb = make_medium(br, bi, a.kx);
+        const cx<double> rs = cdiv({mb.qr, mb.qi}, {ma.qr, ma.qi});
+        const cx<double> rp = cdiv({mb.er, mb.ei}, {ma.er, ma.ei});
+        const double cre = (c4lam * kScSteps) * ma.qr, cim = c4lam * ma.qi * kNegPiLog2e;
+        double2* e = reinterpret_cast<double2*>(pairs + (size_t)pi * kGradPairBlockBytes) + lane;
+        e[0] = make_double2(rs.re, rs.im);
+        e[kWave] = make_double2(rp.re, rp.im);
+        e[2 * kWave] = make_double2(cre, cim);
+        if (lane_used) {
+            const double mag = fmax(fmax(fabs(rs.re), fabs(rs.im)), fmax(fabs(rp.re), fabs(rp.im)));
+            bad = bad || !(mag <= kPairRatioMax);
+            cmax = fmax(cmax, fabs(cre));
+        }
+    }
+    const bool wbad = __any(bad);
+    for (int off = kWave / 2; off >= 1; off >>= 1) cmax = fmax(cmax, __shfl_xor(cmax, off));
+    if (lane == 0) {
+        s_bad[wave] = wbad ? 1 : 0;
+        s_cmax[wave] = cmax;
+    }
+}
+
+template <int POL>
+__global__ void __launch_bounds__(kGradPairBlock) __attribute__((amdgpu_waves_per_eu(2)))
+grad_pair_kernel(GradParams p) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int s_rows[kGradPairWaves];
+    __shared__ int s_bad[kGradPairWaves];
+    __shared__ double s_cmax[kGradPairWaves];
+    __shared__ int s_lossy[kGradPairMaxMat];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    fill_phase_tab<double>(smem, threadIdx.x, kGradPairBlock);
+    __syncthreads();
+    const TabPhase<double> phase = phase_of<double>(smem);
+    unsigned char* const lds = smem + phase_tab_bytes<double>();
+    double* red = reinterpret_cast<double*>(lds) + wave * kRed * kWave;
+    double2* mtab = reinterpret_cast<double2*>(lds + (size_t)kGradPairWaves * kRed * kWave * sizeof(double));
+    unsigned char* pairs = reinterpret_cast<unsigned char*>(mtab + (size_t)p.n_mat * kPairFields * kWave);
+    double* ws = p.ws + ((size_t)blockIdx.x * kGradPairWaves + wave) * (size_t)(p.n_seg + 1) * kCkptDoubles * kWave;
+    const int L2 = p.L + 2;
+    const int64_t nbs = p.b_end - p.b_begin;
+    const int64_t groups = (nbs + kGradPairWaves - 1) / kGradPairWaves;
+    const int64_t t0 = (int64_t)blockIdx.x * p.per_block;
+    const int64_t t1 = t0 + p.per_block < p.n_tasks ? t0 + p.per_block : p.n_tasks;
+    int64_t tab_col = -1;
+    int tab_row = -1;
+    for (int64_t t = t0; t < t1; ++t) {
+        // task = (column, group of kGradPairWaves stacks)
+        const int64_t col = t / groups;
+        const int tk_k = (int)(col / p.n_tiles);
+        const int tk_tile = (int)(col - (int64_t)tk_k * p.n_tiles);
+        const int tk_b = p.b_begin + (int)(t - col * groups) * kGradPairWaves + wave;
+        const int i_raw = tk_tile * kWave + lane;
+        const bool active = i_raw < p.n_wl;
+        const int i = active ? i_raw : p.n_wl - 1;
+        const double lam = p.wl[i];
+        const bool lam_ok = lam > 0.0 && lam < __builtin_inf();
+        const double st = p.sin_t[tk_k], ct = p.cos_t[tk_k];
+        const bool has = tk_b < p.b_end;
+        const int b = has ? tk_b : p.b_end - 1;
+        const ciptr mrow = (ciptr)(p.mat + (int64_t)b * L2);
+        double* part = p.partial + ((size_t)col * nbs + (b - p.b_begin)) * (size_t)p.L * 3;
+        const double* drow = p.d + (int64_t)b * p.L;
+        const bool bad = stack_bad(p, drow, mrow, lane);
+        int a_row = mrow[0];
+        a_row = a_row < 0 ? 0 : (a_row >= p.n_mat ? p.n_mat - 1 : a_row);
+        bool done = !has;
+        // one sub-round per distinct ambient row among the block's stacks
+        for (;;) {
+            __syncthreads();
+            if (lane == 0) s_rows[wave] = done ? INT_MAX : a_row;
+            __syncthreads();
+            int r = s_rows[0];
+            for (int w = 1; w < kGradPairWaves; ++w) r = min(r, s_rows[w]);
+            if (r == INT_MAX) break;
+            if (r != tab_row || col != tab_col) {
+                double n0r, n0i;
+                load_n(p.nk, p.dispersive, p.n_wl, r, i, n0r, n0i);
+                const bool used = active && lam_ok && make_ambient(n0r, n0i, st, ct).ok;
+                build_pair_table(p, mtab, pairs, r, i, used, st, ct, wave, lane, s_bad, s_cmax, s_lossy);
+                tab_row = r;
+                tab_col = col;
+            }
+            __syncthreads();
+            if (!done && a_row == r) {
+                int any_bad = 0;
+                double cm = 0.0;
+                for (int w = 0; w < kGradPairWaves; ++w) {
+                    any_bad |= s_bad[w];
+                    cm = fmax(cm, s_cmax[w]);
+                }
+                uint32_t mask = 0;
+                for (int m = 0; m < p.n_mat; ++m) mask |= (uint32_t)s_lossy[m] << m;
+                double n0r, n0i;
+                load_n(p.nk, p.dispersive, p.n_wl, a_row, i, n0r, n0i);
+                const Ambient amb = make_ambient(n0r, n0i, st, ct);
+                const bool ok = lam_ok && amb.ok && !bad;
+                // layer data one per lane; a layer thicker than 2^49 / (256 max cre) would
+                // leave the fast phase reduction's range
+                PairLayers src;
+                src.mtab = mtab + lane;
+                src.pair_lane = pairs + lane * 16;
+                src.my_d = lane < p.L ? drow[lane] : 0.0;
+                int m_row = lane < L2 ? mrow[lane] : 0;
+                m_row = m_row < 0 ? 0 : (m_row >= p.n_mat ? p.n_mat - 1 : m_row);
+                src.my_row = m_row;
+                int m_nx = lane + 1 < L2 ? mrow[lane + 1] : 0;
+                m_nx = m_nx < 0 ? 0 : (m_nx >= p.n_mat ? p.n_mat - 1 : m_nx);
+                // lane l holds layer l + 1: its row is medium l + 1, the next one l + 2
+                const int m_cur = __shfl_down(m_row, 1, kWave);
+                const int m_nxt = __shfl_down(m_nx, 1, kWave);
+                src.my_code = (m_cur * p.n_mat + m_nxt) * kGradPairBlockBytes | (int)(((mask >> m_cur) & 1u) << 31);
+                const bool far = __any(lane < p.L && !(src.my_d <= (0.5 * kScFastRange) / cm));
+                if (any_bad == 0 && !far) {
+                    grad_stack_pair<POL>(p, src, amb, b, tk_k, i, lane, active, ok, ws, red, part, phase);
+                } else {
+                    InlSrc isrc;
+                    isrc.nk = p.nk;
+                    isrc.drow = (cdptr)drow;
+                    isrc.mrow = mrow;
+                    isrc.base = (int64_t)b * L2;
+                    isrc.n_mat = p.n_mat;
+                    isrc.dispersive = p.dispersive;
+                    isrc.n_wl = p.n_wl;
+                    isrc.i = i;
+                    isrc.kx = amb.kx;
+                    grad_stack<POL>(p, isrc, amb, b, tk_k, i, lane, active, ok, ws, red, part, phase);
+                }
+                done = true;
+            }
+        }
+    }
+}
+
 // grad[g] = sum over the columns of partial[col][g] in column order (g runs
 // over the launch's stacks x layers x {d, Re n, Im n}).
 __global__ void grad_reduce(const double* partial, int64_t cols, int64_t n, int64_t g0, double* grad_d,
@@ -636,9 +1103,14 @@ static GradShape grad_shape(const tmm_rt_args* a) {
     g.n_seg = (int)ceil_div(a->L, kSeg);
     g.cols = (int64_t)g.n_tiles * a->n_theta;
     g.per_stack = (size_t)g.cols * a->L * 3 * sizeof(double);
+    // checkpoint slots of the persistent grid: blocks of kGradWaves (division-free
+    // kernel) or kGradPairWaves (ratio-form kernel) waves, whichever needs more
     const int64_t tasks = g.cols * ceil_div(a->B, kGradWaves);
     const int64_t blocks = tasks < kGradMaxBlocks ? tasks : kGradMaxBlocks;
-    g.ckpt_bytes = align256((size_t)blocks * kGradWaves * (size_t)(g.n_seg + 1) * kCkptDoubles * kWave * sizeof(double));
+    const int64_t tasks8 = g.cols * ceil_div(a->B, kGradPairWaves);
+    const int64_t blocks8 = tasks8 < kGradPairMaxBlocks ? tasks8 : kGradPairMaxBlocks;
+    const int64_t slots = blocks * kGradWaves > blocks8 * kGradPairWaves ? blocks * kGradWaves : blocks8 * kGradPairWaves;
+    g.ckpt_bytes = align256((size_t)slots * (size_t)(g.n_seg + 1) * kCkptDoubles * kWave * sizeof(double));
     return g;
 }
 
@@ -675,6 +1147,37 @@ static int occupancy_blocks(size_t lds) {
         n = 1;
     cache[lds] = n;
     return n;
+}
+
+template <int POL>
+static int occupancy_pair_blocks(size_t lds) {
+    static std::mutex mu;
+    static std::map<size_t, int> cache;
+    std::lock_guard<std::mutex> g(mu);
+    auto it = cache.find(lds);
+    if (it != cache.end()) return it->second;
+    // dynamic LDS above 64 KiB: raise the kernel's limit first
+    (void)hipFuncSetAttribute((const void*)&grad_pair_kernel<POL>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)lds);
+    (void)hipGetLastError();
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, grad_pair_kernel<POL>, kGradPairBlock, lds) != hipSuccess ||
+        n < 1)
+        n = 1;
+    cache[lds] = n;
+    return n;
+}
+
+template <int POL>
+static hipError_t launch_grad_pair(GradParams p, int n_cu, size_t lds, hipStream_t s) {
+    p.n_tasks = p.n_tasks_pair;
+    int64_t grid = (int64_t)n_cu * occupancy_pair_blocks<POL>(lds);
+    if (grid > kGradPairMaxBlocks) grid = kGradPairMaxBlocks;
+    if (grid > p.n_tasks) grid = p.n_tasks;
+    p.per_block = ceil_div(p.n_tasks, grid);
+    grid = ceil_div(p.n_tasks, p.per_block);
+    hipLaunchKernelGGL((grad_pair_kernel<POL>), dim3((unsigned)grid), dim3(kGradPairBlock), lds, s, p);
+    return hipGetLastError();
 }
 
 template <int POL, bool TABLE>
@@ -755,15 +1258,24 @@ tmm_status tmm_rt_grad(const tmm_rt_args* a, const void* dl_dR, const void* dl_d
     p.n_tiles = g.n_tiles;
     p.n_seg = g.n_seg;
     const bool table = a->mat != nullptr && a->n_mat <= tmm::kGradMaxTableMat;
-    const size_t lds = tmm::phase_tab_bytes<double>() + (size_t)tmm::kGradWaves * tmm::kRed * tmm::kWave * sizeof(double) +
-                       (table ? (size_t)a->n_mat * tmm::kTabFields * tmm::kWave * sizeof(double2) : 0);
+    // ratio form: material ids, a small table, and the stack's layer data one per lane
+    const bool pair = a->mat != nullptr && a->n_mat <= tmm::kGradPairMaxMat && a->L + 2 <= tmm::kWave;
+    const size_t lds = pair ? tmm::grad_pair_lds_bytes(a->n_mat)
+                            : tmm::phase_tab_bytes<double>() +
+                                  (size_t)tmm::kGradWaves * tmm::kRed * tmm::kWave * sizeof(double) +
+                                  (table ? (size_t)a->n_mat * tmm::kTabFields * tmm::kWave * sizeof(double2) : 0);
     (void)hipGetLastError();
     for (int64_t b0 = 0; b0 < a->B; b0 += chunk) {
         p.b_begin = (int)b0;
         p.b_end = (int)(b0 + chunk < a->B ? b0 + chunk : a->B);
         p.n_tasks = g.cols * tmm::ceil_div(p.b_end - p.b_begin, tmm::kGradWaves);
+        p.n_tasks_pair = g.cols * tmm::ceil_div(p.b_end - p.b_begin, tmm::kGradPairWaves);
         hipError_t e;
-        if (a->pol_mask == 1u)
+        if (pair)
+            e = a->pol_mask == 1u   ? tmm::launch_grad_pair<1>(p, n_cu, lds, s)
+                : a->pol_mask == 2u ? tmm::launch_grad_pair<2>(p, n_cu, lds, s)
+                                    : tmm::launch_grad_pair<3>(p, n_cu, lds, s);
+        else if (a->pol_mask == 1u)
             e = table ? tmm::launch_grad<1, true>(p, n_cu, lds, s) : tmm::launch_grad<1, false>(p, n_cu, lds, s);
         else if (a->pol_mask == 2u)
             e = table ? tmm::launch_grad<2, true>(p, n_cu, lds, s) : tmm::launch_grad<2, false>(p, n_cu, lds, s);

@@ -322,3 +322,29 @@ def test_thick_lossless_layer_conserves_energy(d_thick):
     for k in ("R", "T"):
         assert np.isfinite(got[k]).all(), k
     assert np.abs(got["R"] + got["T"] - 1.0).max() <= 1e-12
+
+
+@pytest.mark.parametrize("pol", ["s", "p"])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_material_table_single_polarisation_rt(pol, dtype):
+    # single-polarisation pair-path variants without amplitudes
+    w = _material_workload(70, B=11, L=37, n_wl=80, n_theta=3, n_inner=4)
+    if dtype == "f64":
+        assert_close64(run_gpu(w, pol=pol), run_oracle(w, pol=pol))
+    else:
+        assert_close32(run_gpu(w, dtype="f32", pol=pol), run_oracle(w.rounded_f32(), pol=pol))
+
+
+@pytest.mark.parametrize("pol", ["both", "s", "p"])
+def test_material_table_float_amplitudes(pol):
+    # float pair path with r, t: 2e-5 * max(1, |ref|) against the oracle fed the
+    # float32-rounded inputs (the same bar as R and T)
+    w = _material_workload(71, B=9, L=21, n_wl=70, n_theta=3, n_inner=5)
+    got = run_gpu(w, dtype="f32", amplitudes=True, pol=pol)
+    ref = run_oracle(w.rounded_f32(), amplitudes=True, pol=pol)
+    assert_close32(got, ref)
+    for k in ("r", "t"):
+        g = got[k].astype(np.complex128)
+        assert np.isfinite(g).all(), k
+        err = np.abs(g - ref[k]) / np.maximum(1.0, np.abs(ref[k]))
+        assert err.max() <= TOL32, f"{k}: max error {err.max():.3e}"

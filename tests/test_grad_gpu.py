@@ -218,3 +218,84 @@ def test_table_path_with_mixed_ambient_rows():
     od, on = oracle.rt_grad_cs(wp.d, wp.nk, wp.wl, wp.sin_t, wp.cos_t, gR=gR)
     assert (rel_err(gd, od) <= REL).all(), rel_err(gd, od)
     assert (rel_err(gn, on) <= REL).all(), rel_err(gn, on)
+
+
+# --- ratio form (material ids, at most 5 table rows, L + 2 <= 64) -------------
+
+def _material_workload(seed, B, L, n_wl, n_theta, n_inner, *, theta_max_deg=80.0, n_amb=1.0, k_max=0.02):
+    from dataclasses import replace
+    rng = np.random.default_rng(seed)
+    w = workloads.random_stacks(seed, B=B, L=L, n_wl=n_wl, n_theta=n_theta, theta_max_deg=theta_max_deg)
+    k = np.where(rng.random(n_inner) < 0.5, 0.0, rng.uniform(0.0, k_max, n_inner))
+    nk = np.empty((n_inner + 2, n_wl), np.complex128)
+    nk[:n_inner] = workloads.cauchy(rng.uniform(1.3, 2.6, n_inner), rng.uniform(0.0, 0.03, n_inner), k, w.wl)
+    nk[n_inner] = n_amb
+    nk[n_inner + 1] = 1.52
+    mat = np.empty((B, L + 2), np.int32)
+    mat[:, 0] = n_inner
+    mat[:, 1:L + 1] = rng.integers(0, n_inner, (B, L))
+    mat[:, L + 1] = n_inner + 1
+    return replace(w, nk=nk, mat=mat)
+
+
+def _check_against_oracle(w, gR, gT=None, pol="both"):
+    gd, gn = gpu_grad(w, gR, gT, pol=pol)
+    wp = w.per_layer()
+    od, on = oracle.rt_grad_cs(wp.d, wp.nk, wp.wl, wp.sin_t, wp.cos_t, gR=gR, gT=gT, pol=pol)
+    assert (rel_err(gd, od) <= REL).all(), rel_err(gd, od)
+    assert (rel_err(gn, on) <= REL).all(), rel_err(gn, on)
+
+
+@pytest.mark.parametrize("n_inner,L", [(2, 9), (3, 31), (3, 62)])
+def test_ratio_form_gradient_matches_complex_step(n_inner, L):
+    # 4-5 table rows (two or three layer materials, lossy and lossless), segment
+    # counts with a partial last segment, and L + 2 = 64 (every lane holds a medium)
+    w = _material_workload(80 + L, B=5, L=L, n_wl=70, n_theta=3, n_inner=n_inner)
+    rng = np.random.default_rng(81)
+    shape = (w.B, 2, w.theta.size, w.wl.size)
+    _check_against_oracle(w, rng.normal(size=shape), rng.normal(size=shape))
+
+
+@pytest.mark.parametrize("pol", ["s", "p"])
+def test_ratio_form_single_polarisation(pol):
+    w = _material_workload(82, B=9, L=14, n_wl=40, n_theta=2, n_inner=3)
+    rng = np.random.default_rng(83)
+    shape = (w.B, 1, w.theta.size, w.wl.size)
+    _check_against_oracle(w, rng.normal(size=shape), rng.normal(size=shape), pol=pol)
+
+
+def test_ratio_form_mixed_ambients_and_near_critical_fallback():
+    # Stacks with another ambient row in the same block (table rebuilt per row),
+    # and an angle 4e-6 from the critical angle of an air layer under a dense
+    # ambient, where the ratios exceed their bound and the block falls back to
+    # per-step media.  One air layer per stack keeps the problem well conditioned.
+    from dataclasses import replace
+    w = _material_workload(84, B=11, L=7, n_wl=64, n_theta=3, n_inner=3, n_amb=1.5, k_max=0.0)
+    nk = w.nk.copy()
+    nk[0] = 1.0
+    mat = w.mat.copy()
+    inner = mat[:, 1:-1]
+    inner[inner == 0] = 1
+    inner[np.arange(w.B), np.arange(w.B) % w.L] = 0
+    mat[[2, 7], 0] = 4        # the substrate glass as the ambient of two stacks
+    th_c = np.arcsin(1.0 / 1.5)
+    theta = np.array([0.3, th_c * (1 - 4e-6), 0.1])
+    s, c = workloads.angles(theta)
+    w = replace(w, nk=nk, mat=mat, theta=theta, sin_t=s, cos_t=c)
+    rng = np.random.default_rng(85)
+    shape = (w.B, 2, w.theta.size, w.wl.size)
+    _check_against_oracle(w, rng.normal(size=shape), rng.normal(size=shape))
+
+
+def test_ratio_form_bitwise_reproducible_and_chunking_invariant():
+    w = _material_workload(86, B=19, L=20, n_wl=150, n_theta=3, n_inner=3)
+    rng = np.random.default_rng(87)
+    gR = rng.normal(size=(w.B, 2, w.theta.size, w.wl.size))
+    gd1, gn1 = _grad_call(w, gR)
+    gd2, gn2 = _grad_call(w, gR)
+    gd3, gn3 = _grad_call(w, gR, workspace="min")
+    assert np.array_equal(gd1, gd2) and np.array_equal(gn1, gn2)
+    assert np.array_equal(gd1, gd3) and np.array_equal(gn1, gn3)
+    sp = w.take([0, 18]).per_layer()
+    od, on = oracle.rt_grad_cs(sp.d, sp.nk, sp.wl, sp.sin_t, sp.cos_t, gR=gR[[0, 18]])
+    assert (rel_err(gd1[[0, 18]], od) <= REL).all() and (rel_err(gn1[[0, 18]], on) <= REL).all()
