@@ -348,3 +348,12 @@ def test_material_table_float_amplitudes(pol):
         assert np.isfinite(g).all(), k
         err = np.abs(g - ref[k]) / np.maximum(1.0, np.abs(ref[k]))
         assert err.max() <= TOL32, f"{k}: max error {err.max():.3e}"
+
+
+@pytest.mark.parametrize("L,B", [(0, 1), (0, 3), (1, 1), (1, 5)])
+def test_material_table_degenerate_stacks(L, B):
+    # bare interface and one layer with material ids, fewer stacks than the
+    # workgroup has waves, one layer material
+    w = _material_workload(90 + L + B, B=B, L=L, n_wl=67, n_theta=3, n_inner=1)
+    assert_close64(run_gpu(w, amplitudes=True), run_oracle(w, amplitudes=True), ("R", "T", "r", "t"))
+    assert_close32(run_gpu(w, dtype="f32"), run_oracle(w.rounded_f32()))

@@ -299,3 +299,12 @@ def test_ratio_form_bitwise_reproducible_and_chunking_invariant():
     sp = w.take([0, 18]).per_layer()
     od, on = oracle.rt_grad_cs(sp.d, sp.nk, sp.wl, sp.sin_t, sp.cos_t, gR=gR[[0, 18]])
     assert (rel_err(gd1[[0, 18]], od) <= REL).all() and (rel_err(gn1[[0, 18]], on) <= REL).all()
+
+
+@pytest.mark.parametrize("B", [1, 3])
+def test_ratio_form_one_layer_few_stacks(B):
+    # one layer, fewer stacks than the eight-wave block, dl/dT only
+    w = _material_workload(88 + B, B=B, L=1, n_wl=30, n_theta=2, n_inner=2)
+    rng = np.random.default_rng(89)
+    shape = (w.B, 2, w.theta.size, w.wl.size)
+    _check_against_oracle(w, None, rng.normal(size=shape))
