@@ -179,7 +179,8 @@ __device__ __forceinline__ void finish(const C& c, const Ambient& amb,
         const cx<double> a = cadd(A, Bv), b = csub(A, Bv);
         const double na = cnorm(a);
         PointOut& o = out[0];
-        o.R = cnorm(b) / na;
+        const double ina = 1.0 / na;  // one division serves R and T
+        o.R = cnorm(b) * ina;
         double prod = 1.0;
         int eprod = 0;
         cx<double> Pq = {1.0, 0.0};
@@ -195,7 +196,7 @@ __device__ __forceinline__ void finish(const C& c, const Ambient& amb,
                 eprod = c.epis;
             }
         }
-        o.T = ldexp(amb.Ks * prod * sub.pr * eS / na, two_L1 + eprod - 2 * c.es);
+        o.T = ldexp(amb.Ks * prod * sub.pr * eS * ina, two_L1 + eprod - 2 * c.es);
         if (AMP) {
             o.r = cdiv(b, a);
             const cx<R> rot = phase.cis_g(sc_exact_g(0.5 * Fh));
@@ -215,7 +216,8 @@ __device__ __forceinline__ void finish(const C& c, const Ambient& amb,
         const cx<double> a = cadd(A, Bv), b = csub(A, Bv);
         const double na = cnorm(a);
         PointOut& o = out[(POL & 1) ? 1 : 0];
-        o.R = cnorm(b) / na;
+        const double ina = 1.0 / na;  // one division serves R and T
+        o.R = cnorm(b) * ina;
         double prod = 1.0;
         int eprod = 0;
         cx<double> Pe = {1.0, 0.0};
@@ -231,7 +233,7 @@ __device__ __forceinline__ void finish(const C& c, const Ambient& amb,
                 eprod = c.epip;
             }
         }
-        o.T = ldexp(amb.Kp * prod * (double)sub.e.re * eS / na, two_L1 + eprod - 2 * c.ep);
+        o.T = ldexp(amb.Kp * prod * (double)sub.e.re * eS * ina, two_L1 + eprod - 2 * c.ep);
         if (AMP) {
             o.r = cdiv(b, a);
             const cx<R> rot = phase.cis_g(sc_exact_g(0.5 * Fh));
