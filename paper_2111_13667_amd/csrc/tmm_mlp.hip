@@ -349,17 +349,20 @@ unsigned grid1(int64_t n) {
 }
 
 // Launch one batched NT GEMM (all members) with the given epilogue.  Every
-// dimension is a multiple of 128.  256 x 256 tiles where they still give at
-// least four workgroups per CU, else 256 x 128, else 128 x 128.
+// dimension is a multiple of 128.  256 x 256 tiles (eight waves of 128 x 64)
+// where they still give at least four workgroups per CU, else 256 x 128 (eight
+// waves of 64 x 64), else 128 x 128 (four waves of 64 x 64).
 template <int EPI>
 void gemm(hipStream_t s, int E, const tmm::mlp::GemmArgs& g) {
-    const dim3 block(tmm::mlp::kGemmThreads);
     if (g.M % 256 == 0 && g.N % 256 == 0 && (int64_t)(g.M / 256) * (g.N / 256) * E >= 1024) {
-        hipLaunchKernelGGL((tmm::mlp::gemm_nt_bf16<EPI, 128, 128>), dim3(g.N / 256, g.M / 256, E), block, 0, s, g);
+        hipLaunchKernelGGL((tmm::mlp::gemm_nt_bf16<EPI, 128, 64, 2, 4>), dim3(g.N / 256, g.M / 256, E), dim3(512), 0,
+                           s, g);
     } else if (g.M % 256 == 0) {
-        hipLaunchKernelGGL((tmm::mlp::gemm_nt_bf16<EPI, 128, 64>), dim3(g.N / 128, g.M / 256, E), block, 0, s, g);
+        hipLaunchKernelGGL((tmm::mlp::gemm_nt_bf16<EPI, 64, 64, 4, 2>), dim3(g.N / 128, g.M / 256, E), dim3(512), 0, s,
+                           g);
     } else {
-        hipLaunchKernelGGL((tmm::mlp::gemm_nt_bf16<EPI, 64, 64>), dim3(g.N / 128, g.M / 128, E), block, 0, s, g);
+        hipLaunchKernelGGL((tmm::mlp::gemm_nt_bf16<EPI, 64, 64, 2, 2>), dim3(g.N / 128, g.M / 128, E), dim3(256), 0, s,
+                           g);
     }
 }
 

@@ -9,15 +9,17 @@
 // The transposed copies are written by the producers (optimizer, forward and
 // backward epilogues), not by separate transposes.
 //
-// Tile: (2 WM) x (2 WN) outputs per 256-thread workgroup (WM = 128 or 64 rows,
-// WN = 128 or 64 columns per wave), 64 reduction steps per LDS stage
-// (double-buffered, rows padded by 16 bytes against bank conflicts; up to
-// 144 KiB of LDS), four waves in a 2 x 2 grid,
-// each owning WM/32 x WN/32 blocks of the 32x32x16 BF16 MFMA (FP32
-// accumulation).  MFMA operand layout used: lane l supplies row/column (l mod
-// 32) and 8 consecutive reduction indices starting at 8 (l / 32); accumulator
-// element r of lane l is C[8 (r/4) + 4 (l/32) + r mod 4][l mod 32].  (Any
-// consistent permutation of the 16 reduction indices gives the same sum.)
+// Tile: NWM x NWN waves, each owning WM x WN outputs (WM/32 x WN/32 blocks of
+// the 32x32x16 BF16 MFMA, FP32 accumulation), so a workgroup covers
+// (NWM WM) x (NWN WN).  64 reduction steps per LDS stage (double-buffered, rows
+// padded by 16 bytes against bank conflicts; up to 144 KiB of LDS).  The large
+// shapes use eight waves (two per SIMD, 128 x 64 or 64 x 64 per wave): while
+// one wave of a SIMD waits on LDS, global memory or its epilogue, the other
+// keeps the matrix unit busy.  MFMA operand layout used: lane l supplies
+// row/column (l mod 32) and 8 consecutive reduction indices starting at
+// 8 (l / 32); accumulator element r of lane l is
+// C[8 (r/4) + 4 (l/32) + r mod 4][l mod 32].  (Any consistent permutation of the
+// 16 reduction indices gives the same sum.)
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -34,7 +36,6 @@ typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));  // one 16-byte 
 constexpr int kBK = 64;
 constexpr int kLdsRow = kBK + 8;  // padded row (bf16 elements): 144 B = 9 x 16 B, no ds_read_b128 bank conflicts
 constexpr int kChunksPerRow = kBK / 8;  // 16-byte chunks per tile row
-constexpr int kGemmThreads = 256;
 
 enum Epilogue : int {
     EPI_F32 = 0,        // C fp32 [m][n]
@@ -66,38 +67,63 @@ struct GemmArgs {
     int64_t strideOutHt;
 };
 
+// erf without branches (gen_poly.py fits, coefficients lowest degree first;
+// max abs error 1.2e-7 in FP32):
+//   |x| < 0.875:  erf(x) = x * P(x^2)
+//   otherwise:    erf(|x|) = 1 - 2^Q(min(|x|, 4))  with Q ~ log2 erfc
+// (erfc(4) = 1.5e-8, below half an ulp of 1).  Both pieces are evaluated and one
+// is selected, so a wave never splits into two paths.
+constexpr float kErfSmall[6] = {1.128379107e+00f, -3.761255443e-01f, 1.128249690e-01f,
+                                -2.679294720e-02f, 5.034370814e-03f, -6.214585155e-04f};
+constexpr float kErfcLog2[9] = {4.546713317e-04f,  -1.630561113e+00f, -9.115559459e-01f,
+                                -1.588001102e-01f, 3.811602667e-02f,  -6.867640652e-03f,
+                                8.615075494e-04f,  -6.653598393e-05f, 2.367627530e-06f};
+__device__ __forceinline__ float erf_fit(float x) {
+    const float a = fabsf(x), s = a * a;
+    float p = kErfSmall[5];
+#pragma unroll
+    for (int i = 4; i >= 0; --i) p = fmaf(p, s, kErfSmall[i]);
+    const float t = fminf(a, 4.0f);
+    float q = kErfcLog2[8];
+#pragma unroll
+    for (int i = 7; i >= 0; --i) q = fmaf(q, t, kErfcLog2[i]);
+    const float r = a < 0.875f ? a * p : 1.0f - __builtin_amdgcn_exp2f(q);
+    return copysignf(r, x);
+}
 __device__ __forceinline__ float gelu(float z) {
-    return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f));
+    return 0.5f * z * (1.0f + erf_fit(z * 0.70710678118654752f));
 }
 __device__ __forceinline__ float gelu_grad(float z) {
-    const float cdf = 0.5f * (1.0f + erff(z * 0.70710678118654752f));
+    const float cdf = 0.5f * (1.0f + erf_fit(z * 0.70710678118654752f));
     const float pdf = 0.39894228040143268f * __expf(-0.5f * z * z);
     return cdf + z * pdf;
 }
 
 // One K stage of a tile: global -> registers (chunk s of this thread is row
-// r0 + 32 s, so its address is the thread's base plus s rows of 32), and
-// registers -> LDS (the same rows at the padded pitch).
-constexpr int kRowsPerPass = kGemmThreads / kChunksPerRow;  // 32 rows per pass of the workgroup
-
-template <int C>
+// r0 + RPP s, RPP = threads / 8 rows per pass of the workgroup, so its address is
+// the thread's base plus s passes), and registers -> LDS (the same rows at the
+// padded pitch).
+template <int C, int RPP>
 __device__ __forceinline__ void stage_load(u32x4 (&r)[C], const __bf16* base, int64_t ld, int kt) {
 #pragma unroll
     for (int s = 0; s < C; ++s)
-        r[s] = *reinterpret_cast<const u32x4*>(base + (int64_t)s * kRowsPerPass * ld + kt * kBK);
+        r[s] = *reinterpret_cast<const u32x4*>(base + (int64_t)s * RPP * ld + kt * kBK);
 }
-template <int C>
+template <int C, int RPP>
 __device__ __forceinline__ void stage_store(const u32x4 (&r)[C], __bf16* lds) {
 #pragma unroll
-    for (int s = 0; s < C; ++s) *reinterpret_cast<u32x4*>(lds + s * kRowsPerPass * kLdsRow) = r[s];
+    for (int s = 0; s < C; ++s) *reinterpret_cast<u32x4*>(lds + s * RPP * kLdsRow) = r[s];
 }
 
-template <int EPI, int WM, int WN>
-__global__ void __launch_bounds__(kGemmThreads) gemm_nt_bf16(GemmArgs g) {
-    constexpr int BM = 2 * WM, BN = 2 * WN;
-    constexpr int FM = WM / 32, FN = WN / 32;               // MFMA blocks per wave
-    constexpr int CA = BM * kChunksPerRow / kGemmThreads;  // 16-byte chunks per thread and stage
-    constexpr int CB = BN * kChunksPerRow / kGemmThreads;
+template <int EPI, int WM, int WN, int NWM, int NWN>
+__global__ void __launch_bounds__(64 * NWM * NWN) gemm_nt_bf16(GemmArgs g) {
+    constexpr int NT = 64 * NWM * NWN;                  // threads
+    constexpr int BM = NWM * WM, BN = NWN * WN;
+    constexpr int FM = WM / 32, FN = WN / 32;           // MFMA blocks per wave
+    constexpr int RPP = NT / kChunksPerRow;             // tile rows per pass of the workgroup
+    constexpr int CA = BM * kChunksPerRow / NT;         // 16-byte chunks per thread and stage
+    constexpr int CB = BN * kChunksPerRow / NT;
+    static_assert(CA * NT == BM * kChunksPerRow && CB * NT == BN * kChunksPerRow, "tile not covered");
     __shared__ __align__(16) __bf16 As[2][BM * kLdsRow];
     __shared__ __align__(16) __bf16 Bs[2][BN * kLdsRow];
     const int tid = threadIdx.x;
@@ -118,12 +144,12 @@ __global__ void __launch_bounds__(kGemmThreads) gemm_nt_bf16(GemmArgs g) {
     const __bf16* const b0 = B + (int64_t)r0 * g.ldb + c0;
     const int l0 = r0 * kLdsRow + c0;
     auto load = [&](u32x4 (&ra)[CA], u32x4 (&rb)[CB], int kt) __attribute__((always_inline)) {
-        stage_load(ra, a0, g.lda, kt);
-        stage_load(rb, b0, g.ldb, kt);
+        stage_load<CA, RPP>(ra, a0, g.lda, kt);
+        stage_load<CB, RPP>(rb, b0, g.ldb, kt);
     };
     auto store = [&](const u32x4 (&ra)[CA], const u32x4 (&rb)[CB], int buf) __attribute__((always_inline)) {
-        stage_store(ra, &As[buf][l0]);
-        stage_store(rb, &Bs[buf][l0]);
+        stage_store<CA, RPP>(ra, &As[buf][l0]);
+        stage_store<CB, RPP>(rb, &Bs[buf][l0]);
     };
 
     f32x16 acc[FM][FN];
@@ -134,7 +160,7 @@ __global__ void __launch_bounds__(kGemmThreads) gemm_nt_bf16(GemmArgs g) {
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.0f;
 
-    const int wm = (wave >> 1) * WM, wn = (wave & 1) * WN;
+    const int wm = (wave / NWN) * WM, wn = (wave % NWN) * WN;
     const int fr = lane & 31, fk = (lane >> 5) * 8;
     // One LDS stage: four 16-deep MFMA steps.
     auto compute = [&](int buf) __attribute__((always_inline)) {
@@ -152,6 +178,13 @@ __global__ void __launch_bounds__(kGemmThreads) gemm_nt_bf16(GemmArgs g) {
 #pragma unroll
                 for (int b = 0; b < FN; ++b)
                     acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[a], bfr[b], acc[a][b], 0, 0, 0);
+            // scheduling hint: alternate the fragment reads with the first MFMAs
+#pragma unroll
+            for (int i = 0; i < FM + FN; ++i) {
+                __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // one LDS read
+                __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // one MFMA
+            }
+            __builtin_amdgcn_sched_group_barrier(0x008, FM * FN - FM - FN, 0);
         }
     };
     // K is a multiple of 2 kBK (every dimension is a multiple of 128); stage indices
