@@ -152,6 +152,28 @@ def time_ragged(dtype="f64", steps=3):
             "algorithmic_TFLOPs": round(layer_steps * FLOPS_PER_POINT_STEP / (ms * 1e-3) / 1e12, 2)}
 
 
+def time_surrogate(n_train=262144, epochs=1):
+    """Surrogate + transfer-matrix fallback against plain TMM on the 30-layer
+    surrogate task (256 wavelengths x 16 angles x s,p R outputs per stack): a
+    short training run (one epoch of 262144 TMM-labelled stacks), calibration of
+    the error scale for a 1e-3 max-abs R bound, then throughput on 65536 stacks."""
+    from paper_2111_13667_amd import surrogate
+    rep = surrogate.run(n_train=n_train, n_cal=8192, n_test=65536, epochs=epochs, log=lambda *_: None)
+    tp = rep["throughput_stacks_per_s"]
+    return {"workload": "surrogate_batch: 30 layers, 256 wl x 16 angles x s,p R; ensemble of 5 MLPs "
+                        "30 -> 5 x 1024 GELU -> 8192, BF16 MFMA; %d training stacks x %d epoch(s)"
+                        % (n_train, epochs),
+            "bound": rep["config"]["bound"],
+            "surrogate_fallback_stacks_per_s": round(tp["surrogate_fallback"], 1),
+            "surrogate_only_stacks_per_s": round(tp["surrogate_only"], 1),
+            "tmm_f32_stacks_per_s": round(tp["tmm_f32"], 1),
+            "gain_vs_tmm_f32": round(rep["gain_vs_tmm_f32"], 3),
+            "fallback_fraction": rep["fallback_fraction_eval_batch"],
+            "max_abs_after_fallback_vs_f64": rep["max_abs_after_fallback_vs_f64"],
+            "test_mae": round(rep["test_mae"], 4),
+            "train_tflops": round(rep["train_tflops"], 1)}
+
+
 def roofline(w, dtype, kernel_ms, out_bytes, traffic=None):
     flops = w.n_points * (w.L + 1) * FLOPS_PER_POINT_STEP
     achieved = flops / (kernel_ms * 1e-3) / 1e12
@@ -189,10 +211,10 @@ def main():
     ap.add_argument("--dtype", choices=["f64", "f32"], default="f64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true",
-                    help="skip the other-precision, amplitude, adjoint and ragged measurements")
+                    help="skip the other-precision, amplitude, adjoint, ragged and surrogate measurements")
     ap.add_argument("--cpu-stacks", type=int, default=64)
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"))
-    ap.add_argument("--only", choices=["adjoint", "ragged_f64", "ragged_f32"], default=None,
+    ap.add_argument("--only", choices=["adjoint", "ragged_f64", "ragged_f32", "surrogate"], default=None,
                     help="run only this extra measurement and print its record (for profiling)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="first run a plain N-MiB elementwise copy kernel (profiler calibration)")
@@ -213,6 +235,8 @@ def main():
     if args.only:
         if args.only == "adjoint":
             rec = time_grad(max(1, args.steps))
+        elif args.only == "surrogate":
+            rec = time_surrogate()
         else:
             rec = time_ragged(args.only.split("_")[1], max(1, args.steps))
         print(json.dumps({"only": args.only, **rec}), flush=True)
@@ -273,6 +297,7 @@ def main():
         extra["adjoint_f64"] = time_grad()
         extra["ragged_f64"] = time_ragged("f64")
         extra["ragged_f32"] = time_ragged("f32")
+        extra["surrogate"] = time_surrogate()
         rec["extra"] = extra
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(w, args.cpu_stacks)

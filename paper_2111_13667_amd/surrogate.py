@@ -235,9 +235,13 @@ def calibrate(mean, sigma, truth, bound):
     return float(scale), first_bad / len(order)
 
 
-def train(sur: Surrogate, x, y, *, epochs, batch, lr_max=1e-3, lr_min=1e-5, seed=0, log_every=0):
+def _log(line):
+    print(line, flush=True)
+
+
+def train(sur: Surrogate, x, y, *, epochs, batch, lr_max=1e-3, lr_min=1e-5, seed=0, log_every=0, log=_log):
     """Adam over shuffled mini-batches with a cosine learning-rate schedule.
-    Returns the per-epoch mean training loss of member 0."""
+    Returns the per-epoch mean training loss of every member."""
     import torch
     N = x.shape[0]
     steps_per_epoch = N // batch
@@ -260,7 +264,7 @@ def train(sur: Surrogate, x, y, *, epochs, batch, lr_max=1e-3, lr_min=1e-5, seed
             step += 1
         hist.append((acc / steps_per_epoch).cpu().numpy().tolist())
         if log_every and (ep + 1) % log_every == 0:
-            print(json.dumps({"epoch": ep + 1, "loss": hist[-1]}), flush=True)
+            log(json.dumps({"epoch": ep + 1, "loss": hist[-1]}))
     return hist
 
 
@@ -281,7 +285,7 @@ def _timeit(fn, reps=3):
 
 
 def run(n_train=2_000_000, n_cal=50_000, n_test=50_000, epochs=10, batch=4096, hidden=1024, layers=5,
-        members=5, lr_max=1e-3, lr_min=1e-5, eval_batch=65536, bound=1e-3, seed=0, log=print):
+        members=5, lr_max=1e-3, lr_min=1e-5, eval_batch=65536, bound=1e-3, seed=0, log=_log):
     """Train the surrogate on tmm_rt data and report accuracy and throughput."""
     import torch
     dev = "cuda"
@@ -305,7 +309,7 @@ def run(n_train=2_000_000, n_cal=50_000, n_test=50_000, epochs=10, batch=4096, h
                     max_batch=max(batch, 4096), seed=seed + 1, in_shift=135.0, in_scale=1.0 / 66.4)
     t0 = time.perf_counter()
     hist = train(sur, xtr, ytr, epochs=epochs, batch=batch, lr_max=lr_max, lr_min=lr_min, seed=seed,
-                 log_every=1)
+                 log_every=1, log=log)
     torch.cuda.synchronize()
     report["train_s"] = time.perf_counter() - t0
     report["loss_per_epoch"] = [h[0] for h in hist]
