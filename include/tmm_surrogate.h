@@ -47,6 +47,9 @@ typedef struct tmm_surrogate_config {
     uint64_t seed;      /* weight initialisation                                                      */
     float in_shift, in_scale;                  /* input normalisation                                 */
     float lr, beta1, beta2, eps, weight_decay; /* Adam (lr here is informative; train_step takes lr) */
+    int32_t gemm_tile;  /* GEMM workgroup tile: 0 automatic; 1 = 256 x 256 (eight waves), 2 = 256 x 128
+                           (eight waves), 3 = 128 x 128 (four waves).  A forced tile that does not
+                           divide a product's M and N falls back to the automatic choice for it.   */
 } tmm_surrogate_config;
 
 /* Allocate and initialise (weights U(-a, a), a = sqrt(6/fan_in) for hidden layers

@@ -349,15 +349,19 @@ unsigned grid1(int64_t n) {
 }
 
 // Launch one batched NT GEMM (all members) with the given epilogue.  Every
-// dimension is a multiple of 128.  256 x 256 tiles (eight waves of 128 x 64)
-// where they still give at least four workgroups per CU, else 256 x 128 (eight
-// waves of 64 x 64), else 128 x 128 (four waves of 64 x 64).
+// dimension is a multiple of 128.  Automatic tile (tile = 0): 256 x 256 (eight
+// waves of 128 x 64) where it still gives at least four workgroups per CU, else
+// 256 x 128 (eight waves of 64 x 64), else 128 x 128 (four waves of 64 x 64).
+// tile = 1, 2, 3 forces one of the three where it divides M and N.
 template <int EPI>
-void gemm(hipStream_t s, int E, const tmm::mlp::GemmArgs& g) {
-    if (g.M % 256 == 0 && g.N % 256 == 0 && (int64_t)(g.M / 256) * (g.N / 256) * E >= 1024) {
+void gemm(hipStream_t s, int E, const tmm::mlp::GemmArgs& g, int tile) {
+    const bool fit256 = g.M % 256 == 0 && g.N % 256 == 0, fit128 = g.M % 256 == 0;
+    if ((tile == 1 && !fit256) || (tile == 2 && !fit128)) tile = 0;
+    if (tile == 0) tile = fit256 && (int64_t)(g.M / 256) * (g.N / 256) * E >= 1024 ? 1 : fit128 ? 2 : 3;
+    if (tile == 1) {
         hipLaunchKernelGGL((tmm::mlp::gemm_nt_bf16<EPI, 128, 64, 2, 4>), dim3(g.N / 256, g.M / 256, E), dim3(512), 0,
                            s, g);
-    } else if (g.M % 256 == 0) {
+    } else if (tile == 2) {
         hipLaunchKernelGGL((tmm::mlp::gemm_nt_bf16<EPI, 64, 64, 4, 2>), dim3(g.N / 128, g.M / 256, E), dim3(512), 0, s,
                            g);
     } else {
@@ -405,9 +409,9 @@ void forward(tmm_surrogate* h, hipStream_t s, bool train) {
                 g.outHt = h->Ht[l];
                 g.ldt = Bt;
                 g.strideOutHt = sH;
-                gemm<tmm::mlp::EPI_BIAS_GELU>(s, E, g);
+                gemm<tmm::mlp::EPI_BIAS_GELU>(s, E, g, h->cfg.gemm_tile);
             } else {
-                gemm<tmm::mlp::EPI_BIAS_GELU_H>(s, E, g);
+                gemm<tmm::mlp::EPI_BIAS_GELU_H>(s, E, g, h->cfg.gemm_tile);
             }
             in = h->H[l];
             in_dim = Hd;
@@ -416,7 +420,7 @@ void forward(tmm_surrogate* h, hipStream_t s, bool train) {
             g.outF = h->Y;
             g.ldo = out;
             g.strideOutF = (int64_t)Bt * out;
-            gemm<tmm::mlp::EPI_BIAS_F32>(s, E, g);
+            gemm<tmm::mlp::EPI_BIAS_F32>(s, E, g, h->cfg.gemm_tile);
         }
     }
 }
@@ -437,7 +441,7 @@ void backward(tmm_surrogate* h, hipStream_t s) {
         g.outF = h->Wg + h->woff[l];
         g.ldo = in;
         g.strideOutF = h->wsz;
-        gemm<tmm::mlp::EPI_F32>(s, E, g);
+        gemm<tmm::mlp::EPI_F32>(s, E, g, h->cfg.gemm_tile);
         hipLaunchKernelGGL(tmm::mlp::bias_grad, dim3((out * E + 3) / 4), dim3(256), 0, s, dZt, out, Bt, E, sdz,
                            h->bg + h->boff[l], h->bsz);
         if (l > 0) {
@@ -454,7 +458,7 @@ void backward(tmm_surrogate* h, hipStream_t s) {
             g2.outHt = nzt;
             g2.ldt = Bt;
             g2.strideOutHt = (int64_t)Bt * Hd;
-            gemm<tmm::mlp::EPI_DGELU>(s, E, g2);
+            gemm<tmm::mlp::EPI_DGELU>(s, E, g2, h->cfg.gemm_tile);
             dZ = nz;
             dZt = nzt;
             sdz = (int64_t)Bt * Hd;
@@ -502,6 +506,8 @@ tmm_status tmm_surrogate_create(const tmm_surrogate_config* c, tmm_surrogate** o
         return fail(TMM_ERR_INVALID_ARG,
                     "tmm_surrogate_create: need n_in >= 1, n_hidden and n_out multiples of 128, n_layers >= 1, "
                     "n_members >= 1, max_batch a multiple of 128");
+    if (c->gemm_tile < 0 || c->gemm_tile > 3)
+        return fail(TMM_ERR_INVALID_ARG, "tmm_surrogate_create: gemm_tile must be 0 (automatic), 1, 2 or 3");
     if (!(c->in_scale == c->in_scale) || !(c->lr >= 0.0f) || !(c->beta1 >= 0.0f && c->beta1 < 1.0f) ||
         !(c->beta2 >= 0.0f && c->beta2 < 1.0f) || !(c->eps > 0.0f))
         return fail(TMM_ERR_INVALID_ARG, "tmm_surrogate_create: bad optimiser or input scaling parameters");

@@ -24,6 +24,7 @@ class SurrogateConfig(ctypes.Structure):
         ("in_shift", ctypes.c_float), ("in_scale", ctypes.c_float),
         ("lr", ctypes.c_float), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float),
         ("eps", ctypes.c_float), ("weight_decay", ctypes.c_float),
+        ("gemm_tile", ctypes.c_int32),
     ]
 
 
@@ -67,9 +68,9 @@ class Surrogate:
     """Ensemble MLP surrogate living in device memory (one handle)."""
 
     def __init__(self, n_in, n_out, *, n_hidden=1024, n_layers=5, n_members=5, max_batch=4096, seed=0,
-                 in_shift=0.0, in_scale=1.0, beta1=0.9, beta2=0.999, eps=1e-8, weight_decay=0.0):
+                 in_shift=0.0, in_scale=1.0, beta1=0.9, beta2=0.999, eps=1e-8, weight_decay=0.0, gemm_tile=0):
         self.cfg = SurrogateConfig(n_in, n_hidden, n_layers, n_out, n_members, max_batch, seed,
-                                   in_shift, in_scale, 0.0, beta1, beta2, eps, weight_decay)
+                                   in_shift, in_scale, 0.0, beta1, beta2, eps, weight_decay, gemm_tile)
         h = ctypes.c_void_p()
         tmm._check(_lib().tmm_surrogate_create(ctypes.byref(self.cfg), ctypes.byref(h)))
         self.h = h

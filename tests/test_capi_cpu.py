@@ -105,3 +105,18 @@ def test_ragged_plan_rejects_bad_offsets_on_host():
         with pytest.raises(tmm.TmmError) as e:
             ragged.RaggedPlan(lo, wo, to)
         assert e.value.status == tmm.TMM_ERR_INVALID_ARG
+
+
+def test_surrogate_config_rejected_on_host():
+    # every check runs before the first device call, so a CPU-only host sees them
+    from paper_2111_13667_amd import surrogate as S
+    lib = S._lib()
+    good = dict(n_in=30, n_hidden=256, n_layers=2, n_out=256, n_members=2, max_batch=256, seed=1,
+                in_shift=0.0, in_scale=1.0, lr=0.0, beta1=0.9, beta2=0.999, eps=1e-8, weight_decay=0.0,
+                gemm_tile=0)
+    for bad in (dict(gemm_tile=4), dict(gemm_tile=-1), dict(n_hidden=200), dict(max_batch=100),
+                dict(n_members=0), dict(eps=0.0), dict(beta1=1.0)):
+        cfg = S.SurrogateConfig(**{**good, **bad})
+        h = ctypes.c_void_p()
+        assert lib.tmm_surrogate_create(ctypes.byref(cfg), ctypes.byref(h)) == tmm.TMM_ERR_INVALID_ARG, bad
+        assert not h.value

@@ -13,14 +13,20 @@ pytestmark = pytest.mark.gpu
 SHIFT, SCALE = 135.0, 1.0 / 66.4   # U[20, 250] -> roughly zero mean, unit variance
 
 
-def small(n_hidden=256, n_layers=2, n_out=256, E=2, max_batch=256, seed=3):
+def small(n_hidden=256, n_layers=2, n_out=256, E=2, max_batch=256, seed=3, gemm_tile=0):
     from paper_2111_13667_amd.surrogate import Surrogate
     return Surrogate(30, n_out, n_hidden=n_hidden, n_layers=n_layers, n_members=E, max_batch=max_batch,
-                     seed=seed, in_shift=SHIFT, in_scale=SCALE)
+                     seed=seed, in_shift=SHIFT, in_scale=SCALE, gemm_tile=gemm_tile)
 
 
-def test_forward_matches_reference_every_member():
-    sur = small()
+# gemm_tile: 0 automatic (256 x 128 at these sizes), 1 = 256 x 256 eight waves,
+# 2 = 256 x 128 eight waves, 3 = 128 x 128 four waves.
+TILES = [0, 1, 2, 3]
+
+
+@pytest.mark.parametrize("tile", TILES)
+def test_forward_matches_reference_every_member(tile):
+    sur = small(gemm_tile=tile)
     rng = np.random.default_rng(0)
     x = rng.uniform(20, 250, (200, 30)).astype(np.float32)   # ragged: 200 of 256 rows
     params = sur.export()
@@ -39,8 +45,9 @@ def test_forward_matches_reference_every_member():
     sur.close()
 
 
-def test_gradients_match_reference():
-    sur = small(E=2)
+@pytest.mark.parametrize("tile", TILES)
+def test_gradients_match_reference(tile):
+    sur = small(E=2, gemm_tile=tile)
     rng = np.random.default_rng(1)
     x = rng.uniform(20, 250, (256, 30)).astype(np.float32)
     t = rng.uniform(0, 1, (256, 256)).astype(np.float32)
