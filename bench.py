@@ -152,6 +152,20 @@ def time_ragged(dtype="f64", steps=3):
             "algorithmic_TFLOPs": round(layer_steps * FLOPS_PER_POINT_STEP / (ms * 1e-3) / 1e12, 2)}
 
 
+# The paper's own timings (section "Core functionality speedup and dataset
+# generation"): CPU only, hardware model not stated, polarisations not stated.
+# Points counted as stack x wavelength x angle (one polarisation).  Other
+# workloads and machines: context for the reader, not a baseline.
+PAPER_CONTEXT = {
+    "source": "arXiv 2111.13667, section 'Core functionality speedup and dataset generation' (CPU)",
+    "tmm_fast_numpy": {"seconds": 0.168, "workload": "10 stacks x 21 layers, 100 wl (400-700 nm) x 20 angles",
+                       "points_per_s": round(10 * 100 * 20 / 0.168, -2)},
+    "original_tmm_per_point": {"seconds": 17.5, "workload": "same", "points_per_s": round(10 * 100 * 20 / 17.5, 0)},
+    "dask_dataset": {"seconds": 2400, "workload": "1e6 stacks x 9 layers, 100 wl x 10 angles, eight-core machine",
+                     "points_per_s": round(1e6 * 100 * 10 / 2400, -3)},
+}
+
+
 def time_surrogate(n_train=262144, epochs=1):
     """Surrogate + transfer-matrix fallback against plain TMM on the 30-layer
     surrogate task (256 wavelengths x 16 angles x s,p R outputs per stack): a
@@ -301,6 +315,7 @@ def main():
         rec["extra"] = extra
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(w, args.cpu_stacks)
+    rec["paper_context"] = PAPER_CONTEXT
     rec["gpu"] = torch.cuda.get_device_name(0)
     print(json.dumps(rec), flush=True)
 
