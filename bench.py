@@ -149,7 +149,9 @@ def time_ragged(dtype="f64", steps=3):
     return {"workload": f"ragged_batch: 8192 stacks, 2-100 layers, 256-2048 wl, 1-64 angles, s+p, {dtype}",
             "points": rw.n_points, "ms": round(ms, 3), "graph_ms": round(gms, 3),
             "points_per_s": round(rw.n_points / (ms * 1e-3), 1),
-            "algorithmic_TFLOPs": round(layer_steps * FLOPS_PER_POINT_STEP / (ms * 1e-3) / 1e12, 2)}
+            "algorithmic_TFLOPs": round(layer_steps * FLOPS_PER_POINT_STEP / (ms * 1e-3) / 1e12, 2),
+            "frac_of_valu_peak": round(layer_steps * FLOPS_PER_POINT_STEP / (ms * 1e-3) / 1e12
+                                       / PEAK_TFLOPS[dtype], 4)}
 
 
 # The paper's own timings (section "Core functionality speedup and dataset
