@@ -286,12 +286,16 @@ def _timeit(fn, reps=3):
 
 
 def run(n_train=2_000_000, n_cal=50_000, n_test=50_000, epochs=10, batch=4096, hidden=1024, layers=5,
-        members=5, lr_max=1e-3, lr_min=1e-5, eval_batch=65536, bound=1e-3, seed=0, log=_log):
-    """Train the surrogate on tmm_rt data and report accuracy and throughput."""
+        members=5, lr_max=1e-3, lr_min=1e-5, eval_batch=65536, bound=1e-3, seed=0, infer_batch=16384,
+        log=_log):
+    """Train the surrogate on tmm_rt data and report accuracy and throughput.
+    Inference runs on a second handle whose internal batch is infer_batch rows
+    (larger GEMMs than the training batch), loaded with the trained weights."""
     import torch
     dev = "cuda"
     report = {"config": dict(n_train=n_train, n_cal=n_cal, n_test=n_test, epochs=epochs, batch=batch,
-                             hidden=hidden, layers=layers, members=members, bound=bound)}
+                             hidden=hidden, layers=layers, members=members, bound=bound,
+                             infer_batch=infer_batch)}
     task = make_task("f32")
     task64 = make_task("f64")
     g = torch.Generator(device=dev)
@@ -320,6 +324,11 @@ def run(n_train=2_000_000, n_cal=50_000, n_test=50_000, epochs=10, batch=4096, h
     report["train_tflops"] = flop_step * steps / report["train_s"] / 1e12
     log(json.dumps({"stage": "train", "seconds": round(report["train_s"], 2),
                     "TFLOP/s": round(report["train_tflops"], 1)}))
+    params = sur.export()
+    sur.close()
+    sur = Surrogate(task.n_layers, task.n_out, n_hidden=hidden, n_layers=layers, n_members=members,
+                    max_batch=infer_batch, seed=seed + 1, in_shift=135.0, in_scale=1.0 / 66.4)
+    sur.load(params)
     # accuracy on held-out stacks
     mean, sigma, _ = sur.predict(xte)
     err = (mean - yte).abs()
@@ -376,10 +385,11 @@ if __name__ == "__main__":
     ap.add_argument("--members", type=int, default=5)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--bound", type=float, default=1e-3)
+    ap.add_argument("--infer-batch", type=int, default=16384, help="internal batch of the inference handle")
     ap.add_argument("--out", default=None)
     a = ap.parse_args()
     rep = run(n_train=a.n_train, n_cal=a.n_cal, n_test=a.n_test, epochs=a.epochs, batch=a.batch, hidden=a.hidden,
-              layers=a.layers, members=a.members, lr_max=a.lr, bound=a.bound)
+              layers=a.layers, members=a.members, lr_max=a.lr, bound=a.bound, infer_batch=a.infer_batch)
     print(json.dumps(rep), flush=True)
     if a.out:
         with open(a.out, "w") as f:
