@@ -382,36 +382,37 @@ tmm_status tune(tmm_ragged_plan* pl, const tmm::ragged::Params<R>& p, int di, hi
     }
     const std::vector<tmm::ragged::Shape> shapes = tmm::ragged::candidate_shapes<R>(p.n_mat);
     const int grains[] = {1, 4};
-    hipEvent_t e0, e1;
-    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    auto release = [&]() {
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+    };
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        release();
         return fail(TMM_ERR_HIP, "tmm_ragged_run: event creation failed");
+    }
     float best = 1e30f;
     tmm::ragged::Shape best_sh = shapes.front();
     for (const tmm::ragged::Shape& base : shapes) {
         for (int g : grains) {
             const tmm::ragged::Shape sh = {base.blocks_per_cu, g, base.waves};
-            hipEventRecord(e0, s);
-            if (launch<R>(pl, p, sh, s) != hipSuccess) {
-                hipEventDestroy(e0);
-                hipEventDestroy(e1);
+            if (hipEventRecord(e0, s) != hipSuccess || launch<R>(pl, p, sh, s) != hipSuccess ||
+                hipEventRecord(e1, s) != hipSuccess) {
+                release();
                 return fail(TMM_ERR_HIP, "tmm_ragged_run: launch failed while tuning");
             }
-            hipEventRecord(e1, s);
-            if (hipEventSynchronize(e1) != hipSuccess) {
-                hipEventDestroy(e0);
-                hipEventDestroy(e1);
+            float ms = 0.0f;
+            if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                release();
                 return fail(TMM_ERR_HIP, "tmm_ragged_run: kernel failed while tuning");
             }
-            float ms = 0.0f;
-            hipEventElapsedTime(&ms, e0, e1);
             if (ms < best) {
                 best = ms;
                 best_sh = sh;
             }
         }
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    release();
     pl->shape[di] = best_sh;
     pl->tuned[di] = true;
     std::lock_guard<std::mutex> g(tmm::ragged::g_tune_mutex);
