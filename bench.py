@@ -228,7 +228,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the other-precision, amplitude, adjoint, ragged and surrogate measurements")
-    ap.add_argument("--cpu-stacks", type=int, default=64)
+    ap.add_argument("--cpu-stacks", type=int, default=384,
+                    help="stacks of the CPU oracle sample (about 10 s on 16 cores)")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"))
     ap.add_argument("--only", choices=["adjoint", "ragged_f64", "ragged_f32", "surrogate"], default=None,
                     help="run only this extra measurement and print its record (for profiling)")

@@ -98,7 +98,9 @@ tmm_status tmm_surrogate_predict(tmm_surrogate *h, const float *x, int32_t B, fl
  * out [B][n_out] has the layout of tmm_rt's R; its d and output fields are
  * ignored.  n_fallback (host, may be NULL) receives the number of recomputed
  * stacks.  Synchronises the stream once per max_batch chunk (to size the
- * fallback launch). */
+ * fallback launch).  The first call, and a call with more layers than any
+ * before it, allocates the handle's material-id staging buffer (max_batch rows
+ * of L + 2 ids); the handle frees it. */
 tmm_status tmm_surrogate_predict_fallback(tmm_surrogate *h, const float *x, int32_t B, const tmm_rt_args *tmpl,
                                           float err_scale, float bound, float *out, int32_t *n_fallback,
                                           void *stream);
