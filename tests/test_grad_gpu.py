@@ -308,3 +308,21 @@ def test_ratio_form_one_layer_few_stacks(B):
     rng = np.random.default_rng(89)
     shape = (w.B, 2, w.theta.size, w.wl.size)
     _check_against_oracle(w, None, rng.normal(size=shape))
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_seeded_sweep_gradients(seed):
+    # Four seeded configurations drawn at random: 1-8 inner materials (ratio form
+    # up to 3, i.e. 5 table rows, division-free above), 1-24 layers, 1-60
+    # wavelengths, 1-3 angles, one or both polarisations, dl/dT present or not.
+    rng = np.random.default_rng(3000 + seed)
+    n_inner = int(rng.integers(1, 9))
+    L = int(rng.integers(1, 25))
+    n_wl = int(rng.integers(1, 61))
+    n_theta = int(rng.integers(1, 4))
+    B = int(rng.integers(1, 7))
+    pol = ["s", "p", "both"][int(rng.integers(0, 3))]
+    w = _material_workload(3100 + seed, B=B, L=L, n_wl=n_wl, n_theta=n_theta, n_inner=n_inner)
+    shape = (w.B, 2 if pol == "both" else 1, w.theta.size, w.wl.size)
+    gT = rng.normal(size=shape) if rng.integers(0, 2) else None
+    _check_against_oracle(w, rng.normal(size=shape), gT, pol=pol)

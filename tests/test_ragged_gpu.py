@@ -105,3 +105,19 @@ def test_invalid_material_row_is_nan_for_that_stack_only():
     for b in range(rw.B):
         seg = Rh[off[b]:off[b + 1]]
         assert np.isnan(seg).all() if b in (2, 4) else np.isfinite(seg).all(), b
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_seeded_sweep_ragged(seed):
+    # Three seeded batches drawn at random: 5-40 stacks, layer counts up to 100,
+    # 1-300 wavelengths and 1-9 angles per stack, one or both polarisations,
+    # both precisions; every stack against the oracle.
+    rng = np.random.default_rng(4000 + seed)
+    B = int(rng.integers(5, 41))
+    lo = int(rng.integers(0, 20))
+    hi = lo + int(rng.integers(0, 81))
+    pol = ["s", "p", "both"][int(rng.integers(0, 3))]
+    dtype = ["f64", "f32"][seed % 2]
+    rw = workloads.ragged_batch(seed=4100 + seed, B=B, L_range=(lo, hi), wl_range=(1, 300), th_range=(1, 9))
+    plan, _, R, T = run(rw, dtype, pol)
+    check_stacks(rw, plan, R, T, range(rw.B), dtype, pol)
