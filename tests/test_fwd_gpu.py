@@ -384,3 +384,32 @@ def test_seeded_sweep_material_ids(seed):
         got = run_gpu(w, dtype="f32", pol=pol)
         ref = run_oracle(w.rounded_f32(), pol=pol)
         assert_close32(got, ref)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_strongly_absorbing_metal_layers(dtype):
+    # Metal-like media (n' in [0.1, 1], k in [1, 6]) between dielectrics: the
+    # attenuation leaves the weak-absorption series for the full 2^y evaluation,
+    # and thin metal films (5-40 nm) keep T measurable.  Material ids (pair path)
+    # and per-layer indices (inline path).
+    from dataclasses import replace
+    rng = np.random.default_rng(77)
+    B, L, n_wl, n_theta = 13, 9, 83, 4
+    w = workloads.random_stacks(77, B=B, L=L, n_wl=n_wl, n_theta=n_theta, theta_max_deg=80.0)
+    nk = np.empty((6, n_wl), np.complex128)
+    nk[0] = workloads.cauchy(np.array([0.15]), np.array([0.0]), np.array([3.5]), w.wl)[0]
+    nk[1] = workloads.cauchy(np.array([0.9]), np.array([0.0]), np.array([5.8]), w.wl)[0]
+    nk[2] = workloads.cauchy(np.array([2.3]), np.array([0.02]), np.array([0.0]), w.wl)[0]
+    nk[3] = workloads.cauchy(np.array([1.46]), np.array([0.004]), np.array([1.2]), w.wl)[0]
+    nk[4] = 1.0
+    nk[5] = 1.52
+    mat = np.empty((B, L + 2), np.int32)
+    mat[:, 0], mat[:, L + 1] = 4, 5
+    mat[:, 1:L + 1] = rng.integers(0, 4, (B, L))
+    d = np.where(mat[:, 1:L + 1] < 2, rng.uniform(5.0, 40.0, (B, L)), rng.uniform(20.0, 250.0, (B, L)))
+    w = replace(w, d=d, nk=nk, mat=mat)
+    for ww in (w, w.per_layer()):
+        if dtype == "f64":
+            assert_close64(run_gpu(ww, amplitudes=True), run_oracle(ww, amplitudes=True), ("R", "T", "r", "t"))
+        else:
+            assert_close32(run_gpu(ww, dtype="f32"), run_oracle(ww.rounded_f32()))
