@@ -326,3 +326,27 @@ def test_seeded_sweep_gradients(seed):
     shape = (w.B, 2 if pol == "both" else 1, w.theta.size, w.wl.size)
     gT = rng.normal(size=shape) if rng.integers(0, 2) else None
     _check_against_oracle(w, rng.normal(size=shape), gT, pol=pol)
+
+
+def test_metal_layers_gradient_both_forms():
+    # A metal-like medium (0.2 + 3.8i) between two dielectrics, 5-40 nm metal
+    # films: strong attenuation in the adjoint of the phase factor.  Material ids
+    # (three inner materials: ratio form) and per-layer rows (division-free form).
+    from dataclasses import replace
+    rng = np.random.default_rng(91)
+    B, L, n_wl, n_theta = 4, 11, 30, 2
+    w = workloads.random_stacks(91, B=B, L=L, n_wl=n_wl, n_theta=n_theta, theta_max_deg=60.0)
+    nk = np.empty((5, n_wl), np.complex128)
+    nk[0] = workloads.cauchy(np.array([0.2]), np.array([0.0]), np.array([3.8]), w.wl)[0]
+    nk[1] = workloads.cauchy(np.array([2.3]), np.array([0.02]), np.array([0.0]), w.wl)[0]
+    nk[2] = workloads.cauchy(np.array([1.46]), np.array([0.004]), np.array([0.01]), w.wl)[0]
+    nk[3], nk[4] = 1.0, 1.52
+    mat = np.empty((B, L + 2), np.int32)
+    mat[:, 0], mat[:, L + 1] = 3, 4
+    mat[:, 1:L + 1] = rng.integers(0, 3, (B, L))
+    d = np.where(mat[:, 1:L + 1] == 0, rng.uniform(5.0, 40.0, (B, L)), rng.uniform(30.0, 200.0, (B, L)))
+    w = replace(w, d=d, nk=nk, mat=mat)
+    shape = (B, 2, n_theta, n_wl)
+    gR, gT = rng.normal(size=shape), rng.normal(size=shape)
+    _check_against_oracle(w, gR, gT)
+    _check_against_oracle(w.per_layer(), gR, gT)
