@@ -118,7 +118,7 @@ __global__ void sum_parts(const float* part, int64_t nblk, float* loss) {
     for (int64_t i = threadIdx.x; i < nblk; i += blockDim.x) acc += p[i];
     red[threadIdx.x] = acc;
     __syncthreads();
-    for (int st = blockDim.x / 2; st > 0; st >>= 1) {
+    for (unsigned st = blockDim.x / 2; st > 0; st >>= 1) {
         if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
         __syncthreads();
     }
