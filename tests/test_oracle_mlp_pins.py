@@ -1,5 +1,4 @@
 """Pins of the float64 MLP reference (CPU only)."""
-import math
 
 import numpy as np
 

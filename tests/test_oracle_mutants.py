@@ -5,7 +5,6 @@ Every mutant is a one-token edit of ``oracle/tmm_oracle.c`` compiled into a
 temporary library; the pins of ``test_oracle_pins.py`` are then run against it.
 """
 import os
-import tempfile
 
 import pytest
 

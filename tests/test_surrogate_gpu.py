@@ -5,7 +5,6 @@ import numpy as np
 import pytest
 
 from oracle import mlp
-from paper_2111_13667_amd import workloads
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
