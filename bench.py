@@ -272,12 +272,15 @@ def main():
         torch.cuda.synchronize()
         del x, y
 
-    traffic = None
+    # HBM bytes per launch from the profiler's FETCH_SIZE + WRITE_SIZE (scaled by a
+    # copy kernel), per dtype; null for a dtype that has not been measured.
+    traffic_all = {}
     if os.path.exists(args.traffic_json):
         try:
-            traffic = json.load(open(args.traffic_json)).get(args.dtype)
+            traffic_all = json.load(open(args.traffic_json))
         except (OSError, ValueError):
-            traffic = None
+            traffic_all = {}
+    traffic = traffic_all.get(args.dtype)
 
     kernel_ms, wall, out_bytes = time_gpu(w, args.dtype, args.steps, args.warmup)
     value = w.n_points / (kernel_ms * 1e-3)
@@ -306,7 +309,7 @@ def main():
         other = "f32" if args.dtype == "f64" else "f64"
         ms, _, ob = time_gpu(w, other, max(3, args.steps // 2), 1)
         extra[other] = {"value": round(w.n_points / (ms * 1e-3), 1), "ms_per_step": round(ms, 4),
-                        "roofline": roofline(w, other, ms, ob)}
+                        "roofline": roofline(w, other, ms, ob, traffic_all.get(other))}
         ms, _, ob = time_gpu(w, args.dtype, max(3, args.steps // 2), 1, amplitudes=True)
         extra[args.dtype + "_with_r_t"] = {"value": round(w.n_points / (ms * 1e-3), 1),
                                            "ms_per_step": round(ms, 4),
