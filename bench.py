@@ -6,6 +6,13 @@ s and p, R and T written to HBM.  Inputs and outputs are resident in device
 memory before the timed region starts.  Prints one JSON line.
 
     python bench.py [--steps K] [--warmup W] [--dtype f64|f32] [--no-cpu-baseline]
+
+The record carries the roofline of the forward kernel (algorithmic FP64 flops
+against the VALU peak, HBM traffic from the profiler's counters), the CPU
+oracle on a bounded sample of the same batch, the other precision, the
+amplitude variant, the adjoint, ragged batches, the surrogate with its
+transfer-matrix fallback against plain TMM (extra records), and the paper's own
+CPU timings as labelled context.
 """
 from __future__ import annotations
 
