@@ -10,7 +10,8 @@
  *
  *   an ensemble of E multilayer perceptrons, each
  *     x (n_in thicknesses, normalised as (x - in_shift) * in_scale)
- *     -> n_layers x [Linear(n_hidden) + GELU (exact erf form)] -> Linear(n_out),
+ *     -> n_layers x [Linear(n_hidden) + GELU in its erf form, x Phi(x)
+ *        (erf evaluated to 1.2e-7 absolute)] -> Linear(n_out),
  *   trained with Adam on the squared error summed over the outputs and averaged
  *   over the batch (the reported loss is the mean squared error per output);
  *   BF16 weights and activations
