@@ -413,3 +413,16 @@ def test_strongly_absorbing_metal_layers(dtype):
             assert_close64(run_gpu(ww, amplitudes=True), run_oracle(ww, amplitudes=True), ("R", "T", "r", "t"))
         else:
             assert_close32(run_gpu(ww, dtype="f32"), run_oracle(ww.rounded_f32()))
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_long_stacks_many_renormalisation_blocks(dtype):
+    # 400 layers: thirteen 32-step renormalisation blocks in double (fifty of 8
+    # in float) and seven 64-layer chunks of the per-wave layer broadcast, on the
+    # pair path (material ids) and the inline path (per-layer rows).
+    w = _material_workload(95, B=3, L=400, n_wl=70, n_theta=3, n_inner=4, theta_max_deg=70.0, k_max=0.002)
+    for ww in (w, w.per_layer()):
+        if dtype == "f64":
+            assert_close64(run_gpu(ww, amplitudes=True), run_oracle(ww, amplitudes=True), ("R", "T", "r", "t"))
+        else:
+            assert_close32(run_gpu(ww, dtype="f32"), run_oracle(ww.rounded_f32()))
