@@ -52,7 +52,8 @@ namespace tmm {
 
 constexpr int kGradBlock = 256;
 constexpr int kGradWaves = kGradBlock / kWave;
-constexpr int kSeg = 3;                  // layers per checkpoint segment
+constexpr int kSeg = 3;                  // layers per checkpoint segment (the ratio-form kernel
+                                         // takes its own SEG: 4 for tables of at most four rows)
 constexpr int kRed = 3 * kSeg;           // shares per segment: dl/dd, dl/dRe n, dl/dIm n per layer
 constexpr int kGradMaxTableMat = 16;
 constexpr int kTabFields = 6;            // q, eta, n/q, (n/q)(2 - eta/q), 2q/|q|^2, 2 eta/|eta|^2
@@ -616,11 +617,12 @@ constexpr int kGradPairWaves = 8;        // two per SIMD at the kernel's registe
 constexpr int kGradPairBlock = kGradPairWaves * kWave;
 constexpr int kGradPairMaxBlocks = kGradMaxBlocks * kGradWaves / kGradPairWaves;  // same checkpoint slots
 constexpr int kGradPairMaxMat = 5;
+constexpr int kGradPairSeg4MaxMat = 4;  // four-layer segments: 48 KiB of shares, 128 KiB in all at 4 rows
 constexpr int kPairFields = 6;           // q, eta, dq/dn, deta/dn, (dq/dn)/q, (deta/dn)/eta
 constexpr int kGradPairBlockBytes = 3 * kWave * 16;  // rho_s[64], rho_p[64], (cre, cim)[64]
 
-__host__ __device__ constexpr size_t grad_pair_lds_bytes(int n_mat) {
-    return phase_tab_bytes<double>() + (size_t)kGradPairWaves * kRed * kWave * sizeof(double) +
+__host__ __device__ constexpr size_t grad_pair_lds_bytes(int n_mat, int seg) {
+    return phase_tab_bytes<double>() + (size_t)kGradPairWaves * 3 * seg * kWave * sizeof(double) +
            (size_t)n_mat * kPairFields * kWave * sizeof(double2) + (size_t)n_mat * n_mat * kGradPairBlockBytes;
 }
 
@@ -685,7 +687,7 @@ __device__ __forceinline__ cx<double> pair_phase(double dj, double cre, double c
     return E;
 }
 
-template <int POL>
+template <int POL, int SEG>
 __device__ void grad_stack_pair(const GradParams& p, const PairLayers& src, const Ambient& amb, int b, int k, int i,
                                 int lane, bool active, bool valid, double* ws, double* red, double* part,
                                 const TabPhase<double>& phase) {
@@ -711,8 +713,8 @@ __device__ void grad_stack_pair(const GradParams& p, const PairLayers& src, cons
     double S = 0.0;  // sum of the base-2 attenuation exponents
     save(0, z);
     for (int s = 0; s < p.n_seg; ++s) {
-        const int top = L - s * kSeg;
-        const int lo = top - kSeg + 1 > 1 ? top - kSeg + 1 : 1;
+        const int top = L - s * SEG;
+        const int lo = top - SEG + 1 > 1 ? top - SEG + 1 : 1;
         for (int j = top; j >= lo; --j) {
             const int code = src.code(j);
             cx<double> rs, rp;
@@ -783,7 +785,7 @@ __device__ void grad_stack_pair(const GradParams& p, const PairLayers& src, cons
     cx<double> wprev_s = {0, 0}, wprev_p = {0, 0};  // w of the step below the current layer
 
     // ---- pass B: segments from the ambient side ----------------------------
-    const int v_red = lane >> 2 < kRed ? lane >> 2 : kRed - 1;  // share this lane sums
+    const int v_red = lane >> 2 < (3 * SEG) ? lane >> 2 : (3 * SEG) - 1;  // share this lane sums
     const double2* red_in = reinterpret_cast<const double2*>(red + v_red * kWave + (lane & 3) * 16);
     auto segment = [&](auto nst_c, int s, int top) {
         constexpr int NST = decltype(nst_c)::value;
@@ -864,16 +866,16 @@ __device__ void grad_stack_pair(const GradParams& p, const PairLayers& src, cons
         }
     };
     for (int s = p.n_seg - 1; s >= 0; --s) {
-        const int top = L - s * kSeg;
-        const int lo = top - kSeg + 1 > 1 ? top - kSeg + 1 : 1;
+        const int top = L - s * SEG;
+        const int lo = top - SEG + 1 > 1 ? top - SEG + 1 : 1;
         const int nst = top - lo + 1;
-        if (nst == kSeg) {
-            segment(std::integral_constant<int, kSeg>(), s, top);
+        if (nst == SEG) {
+            segment(std::integral_constant<int, SEG>(), s, top);
         } else {
-            static_assert(kSeg <= 4, "segment lengths below are spelled out");
+            static_assert(SEG <= 4, "segment lengths below are spelled out");
             if (nst == 1) segment(std::integral_constant<int, 1>(), s, top);
-            if (kSeg > 2 && nst == 2) segment(std::integral_constant<int, (kSeg > 2 ? 2 : 1)>(), s, top);
-            if (kSeg > 3 && nst == 3) segment(std::integral_constant<int, (kSeg > 3 ? 3 : 1)>(), s, top);
+            if (SEG > 2 && nst == 2) segment(std::integral_constant<int, (SEG > 2 ? 2 : 1)>(), s, top);
+            if (SEG > 3 && nst == 3) segment(std::integral_constant<int, (SEG > 3 ? 3 : 1)>(), s, top);
         }
         wave_sync();
         double acc = 0.0;
@@ -951,7 +953,7 @@ __device__ void build_pair_table(const GradParams& p, double2* mtab, unsigned ch
     }
 }
 
-template <int POL>
+template <int POL, int SEG>
 __global__ void __launch_bounds__(kGradPairBlock) __attribute__((amdgpu_waves_per_eu(2)))
 grad_pair_kernel(GradParams p) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -965,8 +967,8 @@ grad_pair_kernel(GradParams p) {
     __syncthreads();
     const TabPhase<double> phase = phase_of<double>(smem);
     unsigned char* const lds = smem + phase_tab_bytes<double>();
-    double* red = reinterpret_cast<double*>(lds) + wave * kRed * kWave;
-    double2* mtab = reinterpret_cast<double2*>(lds + (size_t)kGradPairWaves * kRed * kWave * sizeof(double));
+    double* red = reinterpret_cast<double*>(lds) + wave * (3 * SEG) * kWave;
+    double2* mtab = reinterpret_cast<double2*>(lds + (size_t)kGradPairWaves * (3 * SEG) * kWave * sizeof(double));
     unsigned char* pairs = reinterpret_cast<unsigned char*>(mtab + (size_t)p.n_mat * kPairFields * kWave);
     double* ws = p.ws + ((size_t)blockIdx.x * kGradPairWaves + wave) * (size_t)(p.n_seg + 1) * kCkptDoubles * kWave;
     const int L2 = p.L + 2;
@@ -1044,7 +1046,7 @@ grad_pair_kernel(GradParams p) {
                 src.my_code = (m_cur * p.n_mat + m_nxt) * kGradPairBlockBytes | (int)(((mask >> m_cur) & 1u) << 31);
                 const bool far = __any(lane < p.L && !(src.my_d <= (0.5 * kScFastRange) / cm));
                 if (any_bad == 0 && !far) {
-                    grad_stack_pair<POL>(p, src, amb, b, tk_k, i, lane, active, ok, ws, red, part, phase);
+                    grad_stack_pair<POL, SEG>(p, src, amb, b, tk_k, i, lane, active, ok, ws, red, part, phase);
                 } else {
                     InlSrc isrc;
                     isrc.nk = p.nk;
@@ -1149,7 +1151,7 @@ static int occupancy_blocks(size_t lds) {
     return n;
 }
 
-template <int POL>
+template <int POL, int SEG>
 static int occupancy_pair_blocks(size_t lds) {
     static std::mutex mu;
     static std::map<size_t, int> cache;
@@ -1157,26 +1159,27 @@ static int occupancy_pair_blocks(size_t lds) {
     auto it = cache.find(lds);
     if (it != cache.end()) return it->second;
     // dynamic LDS above 64 KiB: raise the kernel's limit first
-    (void)hipFuncSetAttribute((const void*)&grad_pair_kernel<POL>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    (void)hipFuncSetAttribute((const void*)&grad_pair_kernel<POL, SEG>, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)lds);
     (void)hipGetLastError();
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, grad_pair_kernel<POL>, kGradPairBlock, lds) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, grad_pair_kernel<POL, SEG>, kGradPairBlock, lds) != hipSuccess ||
         n < 1)
         n = 1;
     cache[lds] = n;
     return n;
 }
 
-template <int POL>
+template <int POL, int SEG>
 static hipError_t launch_grad_pair(GradParams p, int n_cu, size_t lds, hipStream_t s) {
     p.n_tasks = p.n_tasks_pair;
-    int64_t grid = (int64_t)n_cu * occupancy_pair_blocks<POL>(lds);
+    p.n_seg = (int)ceil_div(p.L, SEG);  // at most the checkpoint slots sized for kSeg
+    int64_t grid = (int64_t)n_cu * occupancy_pair_blocks<POL, SEG>(lds);
     if (grid > kGradPairMaxBlocks) grid = kGradPairMaxBlocks;
     if (grid > p.n_tasks) grid = p.n_tasks;
     p.per_block = ceil_div(p.n_tasks, grid);
     grid = ceil_div(p.n_tasks, p.per_block);
-    hipLaunchKernelGGL((grad_pair_kernel<POL>), dim3((unsigned)grid), dim3(kGradPairBlock), lds, s, p);
+    hipLaunchKernelGGL((grad_pair_kernel<POL, SEG>), dim3((unsigned)grid), dim3(kGradPairBlock), lds, s, p);
     return hipGetLastError();
 }
 
@@ -1260,7 +1263,10 @@ tmm_status tmm_rt_grad(const tmm_rt_args* a, const void* dl_dR, const void* dl_d
     const bool table = a->mat != nullptr && a->n_mat <= tmm::kGradMaxTableMat;
     // ratio form: material ids, a small table, and the stack's layer data one per lane
     const bool pair = a->mat != nullptr && a->n_mat <= tmm::kGradPairMaxMat && a->L + 2 <= tmm::kWave;
-    const size_t lds = pair ? tmm::grad_pair_lds_bytes(a->n_mat)
+    // segments of four layers where their larger share buffer still fits the LDS
+    // beside the table (at most four rows), else of three
+    const bool seg4 = pair && a->n_mat <= tmm::kGradPairSeg4MaxMat;
+    const size_t lds = pair ? tmm::grad_pair_lds_bytes(a->n_mat, seg4 ? 4 : tmm::kSeg)
                             : tmm::phase_tab_bytes<double>() +
                                   (size_t)tmm::kGradWaves * tmm::kRed * tmm::kWave * sizeof(double) +
                                   (table ? (size_t)a->n_mat * tmm::kTabFields * tmm::kWave * sizeof(double2) : 0);
@@ -1271,10 +1277,14 @@ tmm_status tmm_rt_grad(const tmm_rt_args* a, const void* dl_dR, const void* dl_d
         p.n_tasks = g.cols * tmm::ceil_div(p.b_end - p.b_begin, tmm::kGradWaves);
         p.n_tasks_pair = g.cols * tmm::ceil_div(p.b_end - p.b_begin, tmm::kGradPairWaves);
         hipError_t e;
-        if (pair)
-            e = a->pol_mask == 1u   ? tmm::launch_grad_pair<1>(p, n_cu, lds, s)
-                : a->pol_mask == 2u ? tmm::launch_grad_pair<2>(p, n_cu, lds, s)
-                                    : tmm::launch_grad_pair<3>(p, n_cu, lds, s);
+        if (pair && seg4)
+            e = a->pol_mask == 1u   ? tmm::launch_grad_pair<1, 4>(p, n_cu, lds, s)
+                : a->pol_mask == 2u ? tmm::launch_grad_pair<2, 4>(p, n_cu, lds, s)
+                                    : tmm::launch_grad_pair<3, 4>(p, n_cu, lds, s);
+        else if (pair)
+            e = a->pol_mask == 1u   ? tmm::launch_grad_pair<1, tmm::kSeg>(p, n_cu, lds, s)
+                : a->pol_mask == 2u ? tmm::launch_grad_pair<2, tmm::kSeg>(p, n_cu, lds, s)
+                                    : tmm::launch_grad_pair<3, tmm::kSeg>(p, n_cu, lds, s);
         else if (a->pol_mask == 1u)
             e = table ? tmm::launch_grad<1, true>(p, n_cu, lds, s) : tmm::launch_grad<1, false>(p, n_cu, lds, s);
         else if (a->pol_mask == 2u)
