@@ -53,7 +53,7 @@ namespace tmm {
 constexpr int kGradBlock = 256;
 constexpr int kGradWaves = kGradBlock / kWave;
 constexpr int kSeg = 3;                  // layers per checkpoint segment (the ratio-form kernel
-                                         // takes its own SEG: 4 for tables of at most four rows)
+                                         // takes its own SEG: 5 for tables of at most four rows)
 constexpr int kRed = 3 * kSeg;           // shares per segment: dl/dd, dl/dRe n, dl/dIm n per layer
 constexpr int kGradMaxTableMat = 16;
 constexpr int kTabFields = 6;            // q, eta, n/q, (n/q)(2 - eta/q), 2q/|q|^2, 2 eta/|eta|^2
@@ -617,7 +617,7 @@ constexpr int kGradPairWaves = 8;        // two per SIMD at the kernel's registe
 constexpr int kGradPairBlock = kGradPairWaves * kWave;
 constexpr int kGradPairMaxBlocks = kGradMaxBlocks * kGradWaves / kGradPairWaves;  // same checkpoint slots
 constexpr int kGradPairMaxMat = 5;
-constexpr int kGradPairSeg4MaxMat = 4;  // four-layer segments: 48 KiB of shares, 128 KiB in all at 4 rows
+constexpr int kGradPairLongSegMaxMat = 4;  // five-layer segments: 60 KiB of shares, 140 KiB in all at 4 rows
 constexpr int kPairFields = 6;           // q, eta, dq/dn, deta/dn, (dq/dn)/q, (deta/dn)/eta
 constexpr int kGradPairBlockBytes = 3 * kWave * 16;  // rho_s[64], rho_p[64], (cre, cim)[64]
 
@@ -872,10 +872,11 @@ __device__ void grad_stack_pair(const GradParams& p, const PairLayers& src, cons
         if (nst == SEG) {
             segment(std::integral_constant<int, SEG>(), s, top);
         } else {
-            static_assert(SEG <= 4, "segment lengths below are spelled out");
+            static_assert(SEG <= 5, "segment lengths below are spelled out");
             if (nst == 1) segment(std::integral_constant<int, 1>(), s, top);
             if (SEG > 2 && nst == 2) segment(std::integral_constant<int, (SEG > 2 ? 2 : 1)>(), s, top);
             if (SEG > 3 && nst == 3) segment(std::integral_constant<int, (SEG > 3 ? 3 : 1)>(), s, top);
+            if (SEG > 4 && nst == 4) segment(std::integral_constant<int, (SEG > 4 ? 4 : 1)>(), s, top);
         }
         wave_sync();
         double acc = 0.0;
@@ -1263,10 +1264,10 @@ tmm_status tmm_rt_grad(const tmm_rt_args* a, const void* dl_dR, const void* dl_d
     const bool table = a->mat != nullptr && a->n_mat <= tmm::kGradMaxTableMat;
     // ratio form: material ids, a small table, and the stack's layer data one per lane
     const bool pair = a->mat != nullptr && a->n_mat <= tmm::kGradPairMaxMat && a->L + 2 <= tmm::kWave;
-    // segments of four layers where their larger share buffer still fits the LDS
-    // beside the table (at most four rows), else of three
-    const bool seg4 = pair && a->n_mat <= tmm::kGradPairSeg4MaxMat;
-    const size_t lds = pair ? tmm::grad_pair_lds_bytes(a->n_mat, seg4 ? 4 : tmm::kSeg)
+    // segments of five layers where their larger share buffer still fits the LDS
+    // beside the table (at most four rows; 15 shares fill 60 reduction lanes), else of three
+    const bool seg5 = pair && a->n_mat <= tmm::kGradPairLongSegMaxMat;
+    const size_t lds = pair ? tmm::grad_pair_lds_bytes(a->n_mat, seg5 ? 5 : tmm::kSeg)
                             : tmm::phase_tab_bytes<double>() +
                                   (size_t)tmm::kGradWaves * tmm::kRed * tmm::kWave * sizeof(double) +
                                   (table ? (size_t)a->n_mat * tmm::kTabFields * tmm::kWave * sizeof(double2) : 0);
@@ -1277,10 +1278,10 @@ tmm_status tmm_rt_grad(const tmm_rt_args* a, const void* dl_dR, const void* dl_d
         p.n_tasks = g.cols * tmm::ceil_div(p.b_end - p.b_begin, tmm::kGradWaves);
         p.n_tasks_pair = g.cols * tmm::ceil_div(p.b_end - p.b_begin, tmm::kGradPairWaves);
         hipError_t e;
-        if (pair && seg4)
-            e = a->pol_mask == 1u   ? tmm::launch_grad_pair<1, 4>(p, n_cu, lds, s)
-                : a->pol_mask == 2u ? tmm::launch_grad_pair<2, 4>(p, n_cu, lds, s)
-                                    : tmm::launch_grad_pair<3, 4>(p, n_cu, lds, s);
+        if (pair && seg5)
+            e = a->pol_mask == 1u   ? tmm::launch_grad_pair<1, 5>(p, n_cu, lds, s)
+                : a->pol_mask == 2u ? tmm::launch_grad_pair<2, 5>(p, n_cu, lds, s)
+                                    : tmm::launch_grad_pair<3, 5>(p, n_cu, lds, s);
         else if (pair)
             e = a->pol_mask == 1u   ? tmm::launch_grad_pair<1, tmm::kSeg>(p, n_cu, lds, s)
                 : a->pol_mask == 2u ? tmm::launch_grad_pair<2, tmm::kSeg>(p, n_cu, lds, s)

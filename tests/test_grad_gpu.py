@@ -246,10 +246,10 @@ def _check_against_oracle(w, gR, gT=None, pol="both"):
     assert (rel_err(gn, on) <= REL).all(), rel_err(gn, on)
 
 
-@pytest.mark.parametrize("n_inner,L", [(2, 9), (2, 10), (2, 11), (1, 62), (3, 31), (3, 62)])
+@pytest.mark.parametrize("n_inner,L", [(2, 9), (2, 11), (2, 12), (2, 13), (1, 62), (3, 31), (3, 62)])
 def test_ratio_form_gradient_matches_complex_step(n_inner, L):
-    # 3-5 table rows (one to three layer materials, lossy and lossless): four-layer
-    # segments up to four rows (last segment of 1, 2 and 3 layers), three-layer
+    # 3-5 table rows (one to three layer materials, lossy and lossless): five-layer
+    # segments up to four rows (last segment of 4, 1, 2 and 3 layers), three-layer
     # segments at five; L + 2 = 64 (every lane holds a medium)
     w = _material_workload(80 + L, B=5, L=L, n_wl=70, n_theta=3, n_inner=n_inner)
     rng = np.random.default_rng(81)
