@@ -45,6 +45,7 @@
 #include <mutex>
 #include <type_traits>
 
+#include "tmm_check.hpp"
 #include "tmm_device.hpp"
 #include "tmm_host.hpp"
 
@@ -77,7 +78,9 @@ struct GradParams {
     double* ws;        // checkpoints: [block][wave][n_seg + 1][kCkptDoubles][kWave]
     double* partial;   // [column][stack - b_begin][L][3]
     int b_begin, b_end;
-    int n_tiles, n_seg;
+    int n_tiles, n_seg;  // n_seg: segments of kSeg layers (division-free adjoint, and the
+                         // checkpoint stride of every kernel)
+    int n_seg_pair;      // segments of the ratio-form kernel's own length SEG
     int64_t n_tasks;   // columns * ceil((b_end - b_begin) / waves per block)
     int64_t n_tasks_pair;  // the same for the ratio-form kernel's blocks
     int64_t per_block;
@@ -712,7 +715,7 @@ __device__ void grad_stack_pair(const GradParams& p, const PairLayers& src, cons
     int es = 0, ep = 0;
     double S = 0.0;  // sum of the base-2 attenuation exponents
     save(0, z);
-    for (int s = 0; s < p.n_seg; ++s) {
+    for (int s = 0; s < p.n_seg_pair; ++s) {
         const int top = L - s * SEG;
         const int lo = top - SEG + 1 > 1 ? top - SEG + 1 : 1;
         for (int j = top; j >= lo; --j) {
@@ -865,7 +868,7 @@ __device__ void grad_stack_pair(const GradParams& p, const PairLayers& src, cons
             red[(3 * t + 2) * kWave + lane] = nb.im;
         }
     };
-    for (int s = p.n_seg - 1; s >= 0; --s) {
+    for (int s = p.n_seg_pair - 1; s >= 0; --s) {
         const int top = L - s * SEG;
         const int lo = top - SEG + 1 > 1 ? top - SEG + 1 : 1;
         const int nst = top - lo + 1;
@@ -1174,7 +1177,11 @@ static int occupancy_pair_blocks(size_t lds) {
 template <int POL, int SEG>
 static hipError_t launch_grad_pair(GradParams p, int n_cu, size_t lds, hipStream_t s) {
     p.n_tasks = p.n_tasks_pair;
-    p.n_seg = (int)ceil_div(p.L, SEG);  // at most the checkpoint slots sized for kSeg
+    // The ratio-form stacks walk segments of SEG layers; stacks that fall back to
+    // the division-free adjoint inside the same kernel keep p.n_seg segments of
+    // kSeg, and p.n_seg + 1 stays the per-wave checkpoint stride (SEG >= kSeg).
+    static_assert(SEG >= kSeg, "checkpoint slots are sized for segments of kSeg layers");
+    p.n_seg_pair = (int)ceil_div(p.L, SEG);
     int64_t grid = (int64_t)n_cu * occupancy_pair_blocks<POL, SEG>(lds);
     if (grid > kGradPairMaxBlocks) grid = kGradPairMaxBlocks;
     if (grid > p.n_tasks) grid = p.n_tasks;
@@ -1222,6 +1229,13 @@ tmm_status tmm_rt_grad(const tmm_rt_args* a, const void* dl_dR, const void* dl_d
     if (!grad_d && !grad_n) return fail(TMM_ERR_INVALID_ARG, "tmm_rt_grad: grad_d and grad_n are both NULL");
     if (a->B == 0 || a->L == 0) return tmm::ok();
     hipStream_t s = static_cast<hipStream_t>(stream);
+    if (a->flags & TMM_CHECK_FINITE) {
+        const int P = a->pol_mask == 3u ? 2 : 1;
+        const int64_t n_pts = (int64_t)a->B * P * a->n_theta * a->n_wl;
+        st = tmm::check_rt_inputs<double>(a, static_cast<const double*>(dl_dR), n_pts,
+                                          static_cast<const double*>(dl_dT), n_pts, "tmm_rt_grad", s);
+        if (st != TMM_OK) return st;
+    }
     const int64_t n_grad = (int64_t)a->B * a->L;
     if (a->n_wl == 0 || a->n_theta == 0) {
         // no points: the gradients are zero
@@ -1261,6 +1275,7 @@ tmm_status tmm_rt_grad(const tmm_rt_args* a, const void* dl_dR, const void* dl_d
     p.partial = reinterpret_cast<double*>(static_cast<unsigned char*>(workspace) + g.ckpt_bytes);
     p.n_tiles = g.n_tiles;
     p.n_seg = g.n_seg;
+    p.n_seg_pair = g.n_seg;
     const bool table = a->mat != nullptr && a->n_mat <= tmm::kGradMaxTableMat;
     // ratio form: material ids, a small table, and the stack's layer data one per lane
     const bool pair = a->mat != nullptr && a->n_mat <= tmm::kGradPairMaxMat && a->L + 2 <= tmm::kWave;
