@@ -39,9 +39,11 @@
  * stack closed form, R + T = 1, zero-thickness and split-layer invariance,
  * reciprocity of T, the half-wave absentee layer, the inner-branch flip,
  * normal-incidence s/p relations, passivity, and a 50-digit evaluation of the
- * independent Abeles characteristic-matrix formulation.
- * Parity unpinned: T_p when the exit medium is absorbing or evanescent (only
- * the passivity inequality applies there).
+ * independent Abeles characteristic-matrix formulation, whose exit media
+ * include lossless glass, an evanescent exit (air behind a dense ambient
+ * beyond the critical angle) and absorbing exits (lossy glass, a metal-like
+ * medium): there T = 4 eta_0 Re(eta_sub) / |eta_0 B + C|^2 with the tilted
+ * admittances fixes the flux form of T_s and T_p, conj(cos) included.
  *
  * oracle_rt_dir_cs (bottom of this file) repeats the same steps in bicomplex
  * arithmetic to give complex-step directional derivatives of R and T; it is
@@ -230,6 +232,56 @@ int oracle_rt(int B, int L, int n_wl, int n_theta,
                     }
                 }
             }
+        }
+        free(nbuf);
+        free(cbuf);
+    }
+    return threads;
+}
+
+/*
+ * The same point definition at an explicit list of n_pts points (sampled
+ * checks of large batches): point m is stack b[m], wavelength index i[m],
+ * angle index k[m], polarisation pol[m] (0 = s, 1 = p), with the grids and
+ * tables laid out as for oracle_rt.  R, T [n_pts] (either may be NULL).
+ * Returns the number of OpenMP threads used, or -1 on a bad argument.
+ */
+int oracle_rt_points(int B, int L, int n_wl, int n_theta,
+                     const double *d, const double *nk, int n_mat, int dispersive,
+                     const int32_t *mat, const double *wl,
+                     const double *sin_t, const double *cos_t, int64_t n_pts,
+                     const int32_t *pb, const int32_t *pi_wl, const int32_t *pk, const int32_t *ppol,
+                     double *R, double *T) {
+    if (B < 0 || L < 0 || n_wl < 0 || n_theta < 0 || n_pts < 0) return -1;
+    for (int64_t m = 0; m < n_pts; ++m)
+        if (pb[m] < 0 || pb[m] >= B || pi_wl[m] < 0 || pi_wl[m] >= n_wl || pk[m] < 0 ||
+            pk[m] >= n_theta || ppol[m] < 0 || ppol[m] > 1)
+            return -1;
+    int threads = 1;
+#pragma omp parallel
+    {
+#ifdef _OPENMP
+#pragma omp single
+        threads = omp_get_num_threads();
+#endif
+        cplx *nbuf = (cplx *)malloc(sizeof(cplx) * (size_t)(L + 2));
+        cplx *cbuf = (cplx *)malloc(sizeof(cplx) * (size_t)(L + 2));
+#pragma omp for schedule(dynamic, 64)
+        for (int64_t m = 0; m < n_pts; ++m) {
+            const int b = pb[m], i = pi_wl[m], k = pk[m];
+            int bad_row = 0;
+            for (int j = 0; j < L + 2; ++j) {
+                int row = material_row(b, j, L, mat);
+                if (row < 0 || row >= n_mat) bad_row = 1;
+                else nbuf[j] = nk_at(nk, dispersive, n_wl, row, i);
+            }
+            cplx rr, tt;
+            double RR = NAN, TT = NAN;
+            if (!bad_row)
+                oracle_point(L, nbuf, d + (int64_t)b * L, wl[i], sin_t[k], cos_t[k], ppol[m],
+                             NULL, cbuf, &rr, &tt, &RR, &TT);
+            if (R) R[m] = RR;
+            if (T) T[m] = TT;
         }
         free(nbuf);
         free(cbuf);

@@ -30,6 +30,8 @@ MUTANTS = {
                              "T = tt;"),
     "no branch fix-up": ("if (!is_forward(n[j] * c)) c = -c;", ";"),
     "Snell without n_0": ("cplx kx = n[0] * sin_t;", "cplx kx = sin_t;"),
+    "T_p flux without conj": ("T = tt * creal(n[L + 1] * conj(cos_buf[L + 1])) / creal(n[0] * conj(cos_buf[0]));",
+                              "T = tt * creal(n[L + 1] * cos_buf[L + 1]) / creal(n[0] * conj(cos_buf[0]));"),
     "matrix off-diagonal": ("cplx Mj[4] = {em / t, em * r / t, ep * r / t, ep / t};",
                             "cplx Mj[4] = {em / t, ep * r / t, em * r / t, ep / t};"),
 }
@@ -50,6 +52,7 @@ PIN_TESTS = [
     (pins.test_normal_incidence_polarisation_relations, {}),
     (pins.test_against_50_digit_abeles_matrices, {"seed": 0}),
     (pins.test_against_50_digit_abeles_matrices, {"seed": 4}),
+    (pins.test_against_50_digit_abeles_matrices, {"seed": 8}),
 ]
 
 

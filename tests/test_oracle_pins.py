@@ -285,17 +285,25 @@ def _abeles_mp(n, d, lam, th0, pol):
     return complex(r), float(abs(r) ** 2), float(T), complex(t_s)
 
 
-@pytest.mark.parametrize("seed", range(6))
+# Exit media per seed: 0-3 lossless glass; 4-5 air behind a dense ambient beyond
+# the critical angle (evanescent exit: the phase of r depends on its branch);
+# 6-7 weakly absorbing glass and 8-9 a metal-like medium (absorbing exit: the
+# flux form of T_p, with conj(cos) in Eq. (3)'s Poynting reading, is what the
+# admittance formula Re(eta_sub) fixes here).
+_ABELES_MEDIA = {0: (1.0, 1.52), 1: (1.0, 1.52), 2: (1.0, 1.52), 3: (1.0, 1.52),
+                 4: (1.52, 1.0), 5: (1.52, 1.0), 6: (1.0, 1.52 + 0.05j), 7: (1.33, 1.52 + 0.05j),
+                 8: (1.0, 0.2 + 3.5j), 9: (1.0, 0.2 + 3.5j)}
+
+
+@pytest.mark.parametrize("seed", range(10))
 def test_against_50_digit_abeles_matrices(seed):
-    # Seeds 4 and 5 enter from a dense medium into air beyond the critical angle,
-    # so the exit medium is evanescent and the phase of r depends on its branch.
     rng = np.random.default_rng(100 + seed)
     L = int(rng.integers(1, 14))
-    n_in, n_out = (1.0, 1.52) if seed < 4 else (1.52, 1.0)
+    n_in, n_out = _ABELES_MEDIA[seed]
     n = [n_in] + list(rng.uniform(1.3, 2.6, L) + 1j * rng.uniform(0, 0.05, L)) + [n_out]
     d = rng.uniform(10, 300, L)
     wl = rng.uniform(350, 1100, 3)
-    th = np.deg2rad(rng.uniform(0, 88, 3) if seed < 4 else rng.uniform(45, 88, 3))
+    th = np.deg2rad(rng.uniform(45, 88, 3) if seed in (4, 5) else rng.uniform(0, 88, 3))
     o = one_stack(n, d, wl, th)
     for k in range(3):
         for i in range(3):
