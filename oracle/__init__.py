@@ -65,6 +65,10 @@ def _bind(lib):
     lib.oracle_rt.argtypes = [ctypes.c_int] * 4 + [P, P, ctypes.c_int, ctypes.c_int,
                                                     P, P, P, P, ctypes.c_uint,
                                                     P, P, P, P, P]
+    lib.oracle_rt_points.restype = ctypes.c_int
+    lib.oracle_rt_points.argtypes = [ctypes.c_int] * 4 + [P, P, ctypes.c_int, ctypes.c_int,
+                                                           P, P, P, P, ctypes.c_int64,
+                                                           P, P, P, P, P, P]
     lib.oracle_max_threads.restype = ctypes.c_int
     lib.oracle_rt_dir_cs.restype = ctypes.c_int
     lib.oracle_rt_dir_cs.argtypes = [ctypes.c_int] * 4 + [P, P, ctypes.c_int, P, P, P, ctypes.c_uint,
@@ -140,6 +144,39 @@ def rt(d, nk, wl, sin_t, cos_t, *, mat=None, dispersive=None, pol="both",
         out["r"] = r
         out["t"] = t
     return out
+
+
+def rt_points(d, nk, wl, sin_t, cos_t, b, i, k, pol, *, mat=None, dispersive=None):
+    """R, T at an explicit list of points: stack b[m], wavelength index i[m],
+    angle index k[m], polarisation pol[m] (0 = s, 1 = p); same inputs as ``rt``.
+    Returns (R [n], T [n])."""
+    lib = _load()
+    d = np.ascontiguousarray(d, dtype=np.float64)
+    B, L = d.shape
+    nk = np.ascontiguousarray(nk, dtype=np.complex128)
+    wl = np.ascontiguousarray(wl, dtype=np.float64).ravel()
+    sin_t = np.ascontiguousarray(sin_t, dtype=np.float64).ravel()
+    cos_t = np.ascontiguousarray(cos_t, dtype=np.float64).ravel()
+    if dispersive is None:
+        dispersive = nk.ndim == 2
+    if dispersive and (nk.ndim != 2 or nk.shape[1] != wl.size):
+        raise ValueError("dispersive nk must be [n_mat, n_wl]")
+    if mat is not None:
+        mat = np.ascontiguousarray(mat, dtype=np.int32)
+        if mat.shape != (B, L + 2):
+            raise ValueError("mat must be [B, L+2]")
+    idx = [np.ascontiguousarray(x, dtype=np.int32).ravel() for x in (b, i, k, pol)]
+    n = idx[0].size
+    if any(x.size != n for x in idx):
+        raise ValueError("b, i, k, pol differ in length")
+    R = np.empty(n)
+    T = np.empty(n)
+    th = lib.oracle_rt_points(B, L, wl.size, sin_t.size, _ptr(d), _ptr(nk), nk.shape[0],
+                              int(bool(dispersive)), _ptr(mat), _ptr(wl), _ptr(sin_t), _ptr(cos_t),
+                              n, *[_ptr(x) for x in idx], _ptr(R), _ptr(T))
+    if th < 0:
+        raise ValueError("oracle_rt_points rejected its arguments")
+    return R, T
 
 
 def rt_dir_cs(d, nk, wl, sin_t, cos_t, *, gR=None, gT=None, vd=None, vn=None, pol="both",
