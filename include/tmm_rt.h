@@ -48,6 +48,7 @@ typedef enum tmm_status {
     TMM_OK = 0,
     TMM_ERR_INVALID_ARG = 1, /* a size, pointer or flag is out of its documented range */
     TMM_ERR_UNSUPPORTED = 2, /* a valid request this build does not handle           */
+    TMM_ERR_NONFINITE = 3,   /* TMM_CHECK_FINITE found a NaN or infinity in an input   */
     TMM_ERR_HIP = 4,         /* the HIP runtime reported an error on launch            */
     TMM_ERR_WORKSPACE = 5    /* a caller-provided workspace is missing or too small    */
 } tmm_status;
@@ -58,6 +59,21 @@ typedef enum tmm_dtype {
 } tmm_dtype;
 
 enum { TMM_POL_S = 1u, TMM_POL_P = 2u, TMM_POL_BOTH = 3u };
+
+/* Bits of tmm_rt_args.flags. */
+enum {
+    /* Validate the device-resident inputs before launching: one scan kernel and
+     * one read-back (the call then synchronises the stream once).  A NaN or
+     * infinity in d, nk, wl, sin_theta, cos_theta (or, for tmm_rt_grad, in
+     * dl_dR / dl_dT) returns TMM_ERR_NONFINITE; a finite value outside its
+     * range (d < 0, wl <= 0, a material id outside [0, n_mat), sin or cos of
+     * the angle outside [0, 1], an absorbing ambient row when some angle is
+     * oblique) returns TMM_ERR_INVALID_ARG.  Nothing is launched after a failed
+     * check and the outputs are untouched.  Off by default: without it such
+     * values give NaN in the affected outputs (see above).  The check keeps its
+     * status word in a small static device array (no allocation). */
+    TMM_CHECK_FINITE = 1u
+};
 
 /*
  * One batch of B stacks with the same number L of finite layers.
@@ -83,6 +99,7 @@ enum { TMM_POL_S = 1u, TMM_POL_P = 2u, TMM_POL_BOTH = 3u };
  *             the substrate side of the last one.  The p coefficients follow
  *             the sign convention of Eq. (2), so r_p = -r_s at normal incidence.
  *             At least one of R, T, r, t must be non-NULL.
+ *  flags      0 or TMM_CHECK_FINITE (any other bit: TMM_ERR_INVALID_ARG).
  */
 typedef struct tmm_rt_args {
     int32_t B, L, n_wl, n_theta;
@@ -96,6 +113,7 @@ typedef struct tmm_rt_args {
     const void *cos_theta;
     uint32_t pol_mask;
     void *R, *T, *r, *t;
+    uint32_t flags;
 } tmm_rt_args;
 
 /*
@@ -108,7 +126,8 @@ typedef struct tmm_rt_args {
  *  stream  hipStream_t as void*, NULL = default stream.
  * Sizes: B, n_wl, n_theta >= 0 (zero: nothing to do, TMM_OK); 0 <= L <= 1<<20;
  * n_mat >= 1; the output element count B*P*n_theta*n_wl must fit in int64.
- * Returns TMM_OK or a tmm_status error.
+ * Returns TMM_OK or a tmm_status error (TMM_ERR_NONFINITE only with
+ * TMM_CHECK_FINITE in a->flags).
  */
 tmm_status tmm_rt(const tmm_rt_args *a, tmm_dtype dtype, void *stream);
 
@@ -150,8 +169,10 @@ size_t tmm_rt_grad_workspace_min_size(const tmm_rt_args *a);
  * (wavelength, angle) points taken in a fixed order, so repeated calls give the
  * same bits (also with a smaller workspace).  Points that are invalid
  * (see the NaN rules above) make their stack's gradients NaN.
- * Returns TMM_OK, TMM_ERR_INVALID_ARG, TMM_ERR_UNSUPPORTED, TMM_ERR_WORKSPACE
- * or TMM_ERR_HIP.
+ * With TMM_CHECK_FINITE in a->flags, dl_dR and dl_dT are checked for
+ * finiteness along with the forward inputs.
+ * Returns TMM_OK, TMM_ERR_INVALID_ARG, TMM_ERR_UNSUPPORTED, TMM_ERR_WORKSPACE,
+ * TMM_ERR_NONFINITE or TMM_ERR_HIP.
  */
 tmm_status tmm_rt_grad(const tmm_rt_args *a, const void *dl_dR, const void *dl_dT, void *grad_d,
                        void *grad_n, void *workspace, size_t workspace_bytes, tmm_dtype dtype,

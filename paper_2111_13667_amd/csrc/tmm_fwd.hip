@@ -35,6 +35,7 @@
 #include <atomic>
 
 #include "tmm_chain.hpp"
+#include "tmm_check.hpp"
 #include "tmm_device.hpp"
 #include "tmm_host.hpp"
 
@@ -726,6 +727,8 @@ tmm_status check_rt_args(const tmm_rt_args* a, const char* who, bool need_output
         return fail(TMM_ERR_INVALID_ARG, "%s: pol_mask must be 1 (s), 2 (p) or 3 (both), got %u", who, a->pol_mask);
     if (a->dispersive != 0 && a->dispersive != 1)
         return fail(TMM_ERR_INVALID_ARG, "%s: dispersive must be 0 or 1", who);
+    if (a->flags & ~(uint32_t)TMM_CHECK_FINITE)
+        return fail(TMM_ERR_INVALID_ARG, "%s: unknown flag bits 0x%x", who, a->flags & ~(uint32_t)TMM_CHECK_FINITE);
     if (a->B == 0 || a->n_wl == 0 || a->n_theta == 0) return ok();  // nothing to compute
     if (a->n_mat < 1) return fail(TMM_ERR_INVALID_ARG, "%s: n_mat must be >= 1", who);
     if (!a->nk || !a->wl || !a->sin_theta || !a->cos_theta)
@@ -756,6 +759,7 @@ const char* tmm_status_string(tmm_status s) {
         case TMM_OK: return "ok";
         case TMM_ERR_INVALID_ARG: return "invalid argument";
         case TMM_ERR_UNSUPPORTED: return "unsupported request";
+        case TMM_ERR_NONFINITE: return "non-finite input value";
         case TMM_ERR_HIP: return "HIP runtime error";
         case TMM_ERR_WORKSPACE: return "workspace missing or too small";
     }
@@ -773,6 +777,11 @@ tmm_status tmm_rt(const tmm_rt_args* a, tmm_dtype dtype, void* stream) {
     if (dtype != TMM_F64 && dtype != TMM_F32) return fail(TMM_ERR_INVALID_ARG, "tmm_rt: unknown dtype %d", (int)dtype);
     if (a->B == 0 || a->n_wl == 0 || a->n_theta == 0) return tmm::ok();  // nothing to compute
     hipStream_t s = static_cast<hipStream_t>(stream);
+    if (a->flags & TMM_CHECK_FINITE) {
+        st = dtype == TMM_F64 ? tmm::check_rt_inputs<double>(a, nullptr, 0, nullptr, 0, "tmm_rt", s)
+                              : tmm::check_rt_inputs<float>(a, nullptr, 0, nullptr, 0, "tmm_rt", s);
+        if (st != TMM_OK) return st;
+    }
     return dtype == TMM_F64 ? tmm::run_fwd<double>(a, s) : tmm::run_fwd<float>(a, s);
 }
 

@@ -84,6 +84,7 @@ struct GradParams {
     int64_t n_tasks;   // columns * ceil((b_end - b_begin) / waves per block)
     int64_t n_tasks_pair;  // the same for the ratio-form kernel's blocks
     int64_t per_block;
+    int64_t slots;     // checkpoint slots in the workspace (waves of the persistent grid)
 };
 
 // Per-stack layer data is read-only during the launch and read at
@@ -1098,12 +1099,15 @@ __global__ void zero_fill(double* x, int64_t n) {
 struct GradShape {
     int n_tiles, n_seg;
     int64_t cols;
-    size_t per_stack, ckpt_bytes;
+    int64_t slots;  // checkpoint slots (one per wave of the persistent grid)
+    size_t per_stack, slot_bytes, ckpt_bytes;
 };
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-static GradShape grad_shape(const tmm_rt_args* a) {
+// max_slots caps the checkpoint slots, and with them the persistent grid (the
+// launches then use fewer blocks); it must allow one block of either kernel.
+static GradShape grad_shape(const tmm_rt_args* a, int64_t max_slots = INT64_MAX) {
     GradShape g;
     g.n_tiles = (int)ceil_div(a->n_wl, kWave);
     g.n_seg = (int)ceil_div(a->L, kSeg);
@@ -1116,7 +1120,9 @@ static GradShape grad_shape(const tmm_rt_args* a) {
     const int64_t tasks8 = g.cols * ceil_div(a->B, kGradPairWaves);
     const int64_t blocks8 = tasks8 < kGradPairMaxBlocks ? tasks8 : kGradPairMaxBlocks;
     const int64_t slots = blocks * kGradWaves > blocks8 * kGradPairWaves ? blocks * kGradWaves : blocks8 * kGradPairWaves;
-    g.ckpt_bytes = align256((size_t)slots * (size_t)(g.n_seg + 1) * kCkptDoubles * kWave * sizeof(double));
+    g.slots = slots < max_slots ? slots : max_slots;
+    g.slot_bytes = (size_t)(g.n_seg + 1) * kCkptDoubles * kWave * sizeof(double);
+    g.ckpt_bytes = align256((size_t)g.slots * g.slot_bytes);
     return g;
 }
 
@@ -1184,6 +1190,7 @@ static hipError_t launch_grad_pair(GradParams p, int n_cu, size_t lds, hipStream
     p.n_seg_pair = (int)ceil_div(p.L, SEG);
     int64_t grid = (int64_t)n_cu * occupancy_pair_blocks<POL, SEG>(lds);
     if (grid > kGradPairMaxBlocks) grid = kGradPairMaxBlocks;
+    if (grid > p.slots / kGradPairWaves) grid = p.slots / kGradPairWaves;
     if (grid > p.n_tasks) grid = p.n_tasks;
     p.per_block = ceil_div(p.n_tasks, grid);
     grid = ceil_div(p.n_tasks, p.per_block);
@@ -1195,6 +1202,7 @@ template <int POL, bool TABLE>
 static hipError_t launch_grad(GradParams p, int n_cu, size_t lds, hipStream_t s) {
     int64_t grid = (int64_t)n_cu * occupancy_blocks<POL, TABLE>(lds);
     if (grid > kGradMaxBlocks) grid = kGradMaxBlocks;
+    if (grid > p.slots / kGradWaves) grid = p.slots / kGradWaves;
     if (grid > p.n_tasks) grid = p.n_tasks;
     p.per_block = ceil_div(p.n_tasks, grid);
     grid = ceil_div(p.n_tasks, p.per_block);
@@ -1202,59 +1210,47 @@ static hipError_t launch_grad(GradParams p, int n_cu, size_t lds, hipStream_t s)
     return hipGetLastError();
 }
 
-}  // namespace tmm
-
-extern "C" {
-
-size_t tmm_rt_grad_workspace_size(const tmm_rt_args* a) {
-    if (!a || a->B <= 0 || a->L <= 0 || a->n_wl <= 0 || a->n_theta <= 0) return 0;
-    const tmm::GradShape g = tmm::grad_shape(a);
-    return tmm::ws_bytes(g, tmm::preferred_stacks(g, a->B));
-}
-
-size_t tmm_rt_grad_workspace_min_size(const tmm_rt_args* a) {
-    if (!a || a->B <= 0 || a->L <= 0 || a->n_wl <= 0 || a->n_theta <= 0) return 0;
-    const tmm::GradShape g = tmm::grad_shape(a);
-    return tmm::ws_bytes(g, a->B < tmm::kGradWaves ? a->B : tmm::kGradWaves);
-}
-
-tmm_status tmm_rt_grad(const tmm_rt_args* a, const void* dl_dR, const void* dl_dT, void* grad_d, void* grad_n,
-                       void* workspace, size_t workspace_bytes, tmm_dtype dtype, void* stream) {
-    using tmm::fail;
-    tmm_status st = tmm::check_rt_args(a, "tmm_rt_grad", false);
+// Checks and the cases without gradient kernels, shared by the entry points.
+// *done = true: nothing (more) to launch, the returned status is final.
+static tmm_status grad_prologue(const tmm_rt_args* a, const void* dl_dR, const void* dl_dT, void* grad_d,
+                                void* grad_n, tmm_dtype dtype, hipStream_t s, const char* who, bool* done) {
+    *done = true;
+    tmm_status st = check_rt_args(a, who, false);
     if (st != TMM_OK) return st;
-    if (dtype != TMM_F64) return fail(TMM_ERR_UNSUPPORTED, "tmm_rt_grad: only TMM_F64 is implemented");
-    if (a->r || a->t) return fail(TMM_ERR_INVALID_ARG, "tmm_rt_grad: r and t outputs are not produced here");
-    if (!dl_dR && !dl_dT) return fail(TMM_ERR_INVALID_ARG, "tmm_rt_grad: dl_dR and dl_dT are both NULL");
-    if (!grad_d && !grad_n) return fail(TMM_ERR_INVALID_ARG, "tmm_rt_grad: grad_d and grad_n are both NULL");
-    if (a->B == 0 || a->L == 0) return tmm::ok();
-    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (dtype != TMM_F64) return fail(TMM_ERR_UNSUPPORTED, "%s: only TMM_F64 is implemented", who);
+    if (a->r || a->t) return fail(TMM_ERR_INVALID_ARG, "%s: r and t outputs are not produced here", who);
+    if (!dl_dR && !dl_dT) return fail(TMM_ERR_INVALID_ARG, "%s: dl_dR and dl_dT are both NULL", who);
+    if (!grad_d && !grad_n) return fail(TMM_ERR_INVALID_ARG, "%s: grad_d and grad_n are both NULL", who);
+    if (a->B == 0 || a->L == 0) return ok();
     if (a->flags & TMM_CHECK_FINITE) {
         const int P = a->pol_mask == 3u ? 2 : 1;
         const int64_t n_pts = (int64_t)a->B * P * a->n_theta * a->n_wl;
-        st = tmm::check_rt_inputs<double>(a, static_cast<const double*>(dl_dR), n_pts,
-                                          static_cast<const double*>(dl_dT), n_pts, "tmm_rt_grad", s);
+        st = check_rt_inputs<double>(a, static_cast<const double*>(dl_dR), n_pts, static_cast<const double*>(dl_dT),
+                                     n_pts, who, s);
         if (st != TMM_OK) return st;
     }
-    const int64_t n_grad = (int64_t)a->B * a->L;
     if (a->n_wl == 0 || a->n_theta == 0) {
         // no points: the gradients are zero
+        const int64_t n_grad = (int64_t)a->B * a->L;
         (void)hipGetLastError();
-        if (grad_d) hipLaunchKernelGGL(tmm::zero_fill, dim3(256), dim3(256), 0, s, (double*)grad_d, n_grad);
-        if (grad_n) hipLaunchKernelGGL(tmm::zero_fill, dim3(256), dim3(256), 0, s, (double*)grad_n, 2 * n_grad);
-        return tmm::check_launch("tmm_rt_grad");
+        if (grad_d) hipLaunchKernelGGL(zero_fill, dim3(256), dim3(256), 0, s, (double*)grad_d, n_grad);
+        if (grad_n) hipLaunchKernelGGL(zero_fill, dim3(256), dim3(256), 0, s, (double*)grad_n, 2 * n_grad);
+        return check_launch(who);
     }
-    const tmm::GradShape g = tmm::grad_shape(a);
-    const int64_t chunk = workspace ? tmm::stacks_per_launch(g, a->B, workspace_bytes) : 0;
-    if (chunk == 0)
-        return fail(TMM_ERR_WORKSPACE, "tmm_rt_grad: workspace of at least %zu bytes needed (%zu preferred), %zu given",
-                    tmm::ws_bytes(g, a->B < tmm::kGradWaves ? a->B : tmm::kGradWaves),
-                    tmm::ws_bytes(g, tmm::preferred_stacks(g, a->B)), workspace ? workspace_bytes : (size_t)0);
+    *done = false;
+    return ok();
+}
+
+// The gradient launches over `chunk` stacks at a time with the workspace
+// laid out as g describes (checkpoints of g.slots waves, then partial sums).
+static tmm_status grad_launch(const tmm_rt_args* a, const void* dl_dR, const void* dl_dT, void* grad_d,
+                              void* grad_n, void* workspace, const GradShape& g, int64_t chunk, hipStream_t s,
+                              const char* who) {
     int dev = 0, n_cu = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n_cu < 1)
-        return fail(TMM_ERR_HIP, "tmm_rt_grad: no device");
-    tmm::GradParams p;
+        return fail(TMM_ERR_HIP, "%s: no device", who);
+    GradParams p;
     p.B = a->B;
     p.L = a->L;
     p.n_wl = a->n_wl;
@@ -1276,45 +1272,76 @@ tmm_status tmm_rt_grad(const tmm_rt_args* a, const void* dl_dR, const void* dl_d
     p.n_tiles = g.n_tiles;
     p.n_seg = g.n_seg;
     p.n_seg_pair = g.n_seg;
-    const bool table = a->mat != nullptr && a->n_mat <= tmm::kGradMaxTableMat;
+    p.slots = g.slots;
+    const bool table = a->mat != nullptr && a->n_mat <= kGradMaxTableMat;
     // ratio form: material ids, a small table, and the stack's layer data one per lane
-    const bool pair = a->mat != nullptr && a->n_mat <= tmm::kGradPairMaxMat && a->L + 2 <= tmm::kWave;
+    const bool pair = a->mat != nullptr && a->n_mat <= kGradPairMaxMat && a->L + 2 <= kWave;
     // segments of five layers where their larger share buffer still fits the LDS
     // beside the table (at most four rows; 15 shares fill 60 reduction lanes), else of three
-    const bool seg5 = pair && a->n_mat <= tmm::kGradPairLongSegMaxMat;
-    const size_t lds = pair ? tmm::grad_pair_lds_bytes(a->n_mat, seg5 ? 5 : tmm::kSeg)
-                            : tmm::phase_tab_bytes<double>() +
-                                  (size_t)tmm::kGradWaves * tmm::kRed * tmm::kWave * sizeof(double) +
-                                  (table ? (size_t)a->n_mat * tmm::kTabFields * tmm::kWave * sizeof(double2) : 0);
+    const bool seg5 = pair && a->n_mat <= kGradPairLongSegMaxMat;
+    const size_t lds = pair ? grad_pair_lds_bytes(a->n_mat, seg5 ? 5 : kSeg)
+                            : phase_tab_bytes<double>() + (size_t)kGradWaves * kRed * kWave * sizeof(double) +
+                                  (table ? (size_t)a->n_mat * kTabFields * kWave * sizeof(double2) : 0);
     (void)hipGetLastError();
     for (int64_t b0 = 0; b0 < a->B; b0 += chunk) {
         p.b_begin = (int)b0;
         p.b_end = (int)(b0 + chunk < a->B ? b0 + chunk : a->B);
-        p.n_tasks = g.cols * tmm::ceil_div(p.b_end - p.b_begin, tmm::kGradWaves);
-        p.n_tasks_pair = g.cols * tmm::ceil_div(p.b_end - p.b_begin, tmm::kGradPairWaves);
+        p.n_tasks = g.cols * ceil_div(p.b_end - p.b_begin, kGradWaves);
+        p.n_tasks_pair = g.cols * ceil_div(p.b_end - p.b_begin, kGradPairWaves);
         hipError_t e;
         if (pair && seg5)
-            e = a->pol_mask == 1u   ? tmm::launch_grad_pair<1, 5>(p, n_cu, lds, s)
-                : a->pol_mask == 2u ? tmm::launch_grad_pair<2, 5>(p, n_cu, lds, s)
-                                    : tmm::launch_grad_pair<3, 5>(p, n_cu, lds, s);
+            e = a->pol_mask == 1u   ? launch_grad_pair<1, 5>(p, n_cu, lds, s)
+                : a->pol_mask == 2u ? launch_grad_pair<2, 5>(p, n_cu, lds, s)
+                                    : launch_grad_pair<3, 5>(p, n_cu, lds, s);
         else if (pair)
-            e = a->pol_mask == 1u   ? tmm::launch_grad_pair<1, tmm::kSeg>(p, n_cu, lds, s)
-                : a->pol_mask == 2u ? tmm::launch_grad_pair<2, tmm::kSeg>(p, n_cu, lds, s)
-                                    : tmm::launch_grad_pair<3, tmm::kSeg>(p, n_cu, lds, s);
+            e = a->pol_mask == 1u   ? launch_grad_pair<1, kSeg>(p, n_cu, lds, s)
+                : a->pol_mask == 2u ? launch_grad_pair<2, kSeg>(p, n_cu, lds, s)
+                                    : launch_grad_pair<3, kSeg>(p, n_cu, lds, s);
         else if (a->pol_mask == 1u)
-            e = table ? tmm::launch_grad<1, true>(p, n_cu, lds, s) : tmm::launch_grad<1, false>(p, n_cu, lds, s);
+            e = table ? launch_grad<1, true>(p, n_cu, lds, s) : launch_grad<1, false>(p, n_cu, lds, s);
         else if (a->pol_mask == 2u)
-            e = table ? tmm::launch_grad<2, true>(p, n_cu, lds, s) : tmm::launch_grad<2, false>(p, n_cu, lds, s);
+            e = table ? launch_grad<2, true>(p, n_cu, lds, s) : launch_grad<2, false>(p, n_cu, lds, s);
         else
-            e = table ? tmm::launch_grad<3, true>(p, n_cu, lds, s) : tmm::launch_grad<3, false>(p, n_cu, lds, s);
-        if (e != hipSuccess) return tmm::check_launch("tmm_rt_grad");
+            e = table ? launch_grad<3, true>(p, n_cu, lds, s) : launch_grad<3, false>(p, n_cu, lds, s);
+        if (e != hipSuccess) return check_launch(who);
         const int64_t n = (int64_t)(p.b_end - p.b_begin) * a->L * 3;
-        const int64_t blocks = tmm::ceil_div(n, 256) < 2048 ? tmm::ceil_div(n, 256) : 2048;
-        hipLaunchKernelGGL(tmm::grad_reduce, dim3((unsigned)blocks), dim3(256), 0, s, p.partial, g.cols, n,
-                           (int64_t)p.b_begin * a->L, static_cast<double*>(grad_d),
-                           static_cast<double*>(grad_n));
+        const int64_t blocks = ceil_div(n, 256) < 2048 ? ceil_div(n, 256) : 2048;
+        hipLaunchKernelGGL(grad_reduce, dim3((unsigned)blocks), dim3(256), 0, s, p.partial, g.cols, n,
+                           (int64_t)p.b_begin * a->L, static_cast<double*>(grad_d), static_cast<double*>(grad_n));
     }
-    return tmm::check_launch("tmm_rt_grad");
+    return check_launch(who);
+}
+
+}  // namespace tmm
+
+extern "C" {
+
+size_t tmm_rt_grad_workspace_size(const tmm_rt_args* a) {
+    if (!a || a->B <= 0 || a->L <= 0 || a->n_wl <= 0 || a->n_theta <= 0) return 0;
+    const tmm::GradShape g = tmm::grad_shape(a);
+    return tmm::ws_bytes(g, tmm::preferred_stacks(g, a->B));
+}
+
+size_t tmm_rt_grad_workspace_min_size(const tmm_rt_args* a) {
+    if (!a || a->B <= 0 || a->L <= 0 || a->n_wl <= 0 || a->n_theta <= 0) return 0;
+    const tmm::GradShape g = tmm::grad_shape(a);
+    return tmm::ws_bytes(g, a->B < tmm::kGradWaves ? a->B : tmm::kGradWaves);
+}
+
+tmm_status tmm_rt_grad(const tmm_rt_args* a, const void* dl_dR, const void* dl_dT, void* grad_d, void* grad_n,
+                       void* workspace, size_t workspace_bytes, tmm_dtype dtype, void* stream) {
+    using tmm::fail;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    bool done = true;
+    tmm_status st = tmm::grad_prologue(a, dl_dR, dl_dT, grad_d, grad_n, dtype, s, "tmm_rt_grad", &done);
+    if (st != TMM_OK || done) return st;
+    const tmm::GradShape g = tmm::grad_shape(a);
+    const int64_t chunk = workspace ? tmm::stacks_per_launch(g, a->B, workspace_bytes) : 0;
+    if (chunk == 0)
+        return fail(TMM_ERR_WORKSPACE, "tmm_rt_grad: workspace of at least %zu bytes needed (%zu preferred), %zu given",
+                    tmm::ws_bytes(g, a->B < tmm::kGradWaves ? a->B : tmm::kGradWaves),
+                    tmm::ws_bytes(g, tmm::preferred_stacks(g, a->B)), workspace ? workspace_bytes : (size_t)0);
+    return tmm::grad_launch(a, dl_dR, dl_dT, grad_d, grad_n, workspace, g, chunk, s, "tmm_rt_grad");
 }
 
 }  // extern "C"

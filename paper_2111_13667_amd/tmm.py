@@ -19,11 +19,13 @@ LIB_PATH = os.path.join(_HERE, "libtmm_rt.so")
 TMM_OK = 0
 TMM_ERR_INVALID_ARG = 1
 TMM_ERR_UNSUPPORTED = 2
+TMM_ERR_NONFINITE = 3
 TMM_ERR_HIP = 4
 TMM_ERR_WORKSPACE = 5
 TMM_F64 = 0
 TMM_F32 = 1
 POL = {"s": 1, "p": 2, "both": 3}
+TMM_CHECK_FINITE = 1
 
 
 class TmmError(RuntimeError):
@@ -43,6 +45,7 @@ class TmmRtArgs(ctypes.Structure):
         ("pol_mask", ctypes.c_uint32),
         ("R", ctypes.c_void_p), ("T", ctypes.c_void_p),
         ("r", ctypes.c_void_p), ("t", ctypes.c_void_p),
+        ("flags", ctypes.c_uint32),
     ]
 
 
@@ -91,13 +94,14 @@ def _ptr(x) -> Optional[int]:
 
 
 def tmm_rt(d, nk, wl, sin_theta, cos_theta, *, mat=None, n_mat=None, dispersive=None,
-           pol_mask: int = 3, R=None, T=None, r=None, t=None, stream=None) -> None:
+           pol_mask: int = 3, R=None, T=None, r=None, t=None, flags: int = 0, stream=None) -> None:
     """Launch tmm_rt on device tensors (see include/tmm_rt.h for the layout).
 
     d [B, L] real; nk complex [n_mat, n_wl] or [n_mat]; mat [B, L+2] int32 or None;
     wl [n_wl], sin_theta / cos_theta [n_theta]; R, T real and r, t complex
     [B, P, n_theta, n_wl] outputs (any may be None).  All real tensors share one
     dtype (float64 or float32); complex ones are the matching complex dtype.
+    flags: 0 or TMM_CHECK_FINITE (validate the device inputs first).
     """
     import torch
     real = d.dtype
@@ -130,7 +134,7 @@ def tmm_rt(d, nk, wl, sin_theta, cos_theta, *, mat=None, n_mat=None, dispersive=
             raise ValueError(f"{name} must have shape {shape}")
     a = TmmRtArgs(B, L, wl.numel(), sin_theta.numel(), _ptr(d), _ptr(nk), n_mat, int(dispersive),
                   _ptr(mat), _ptr(wl), _ptr(sin_theta), _ptr(cos_theta), pol_mask,
-                  _ptr(R), _ptr(T), _ptr(r), _ptr(t))
+                  _ptr(R), _ptr(T), _ptr(r), _ptr(t), flags)
     _check(library().tmm_rt(ctypes.byref(a), dt, _stream_handle(stream)))
 
 
@@ -165,7 +169,7 @@ def _check_shapes(d, nk, wl, sin_theta, cos_theta, mat, n_mat, dispersive) -> in
 
 
 def _rt_args(d, nk, wl, sin_theta, cos_theta, mat, n_mat, dispersive, pol_mask, R=None, T=None,
-             r=None, t=None):
+             r=None, t=None, flags=0):
     B, L = d.shape
     if dispersive is None:
         dispersive = nk.dim() == 2
@@ -173,7 +177,7 @@ def _rt_args(d, nk, wl, sin_theta, cos_theta, mat, n_mat, dispersive, pol_mask, 
         n_mat = nk.shape[0]
     return TmmRtArgs(B, L, wl.numel(), sin_theta.numel(), _ptr(d), _ptr(nk), n_mat, int(dispersive),
                      _ptr(mat), _ptr(wl), _ptr(sin_theta), _ptr(cos_theta), pol_mask,
-                     _ptr(R), _ptr(T), _ptr(r), _ptr(t))
+                     _ptr(R), _ptr(T), _ptr(r), _ptr(t), flags)
 
 
 def grad_workspace_size(d, nk, wl, sin_theta, cos_theta, *, mat=None, pol_mask=3, minimum=False) -> int:
@@ -187,7 +191,7 @@ def grad_workspace_size(d, nk, wl, sin_theta, cos_theta, *, mat=None, pol_mask=3
 
 def tmm_rt_grad(d, nk, wl, sin_theta, cos_theta, *, mat=None, n_mat=None, dispersive=None,
                 pol_mask: int = 3, dl_dR=None, dl_dT=None, grad_d=None, grad_n=None,
-                workspace=None, R=None, T=None, stream=None) -> None:
+                workspace=None, R=None, T=None, flags: int = 0, stream=None) -> None:
     """Launch tmm_rt_grad (float64): gradients of sum(dl_dR * R + dl_dT * T) w.r.t.
     d [B, L] into grad_d [B, L] and w.r.t. the finite layers' indices into
     grad_n [B, L] complex128.  workspace: a uint8 device tensor of at least
@@ -214,7 +218,7 @@ def tmm_rt_grad(d, nk, wl, sin_theta, cos_theta, *, mat=None, n_mat=None, disper
     if nk.dtype != torch.complex128:
         raise TypeError("nk must be complex128")
     n_mat = _check_shapes(d, nk, wl, sin_theta, cos_theta, mat, n_mat, dispersive)
-    a = _rt_args(d, nk, wl, sin_theta, cos_theta, mat, n_mat, dispersive, pol_mask, R, T)
+    a = _rt_args(d, nk, wl, sin_theta, cos_theta, mat, n_mat, dispersive, pol_mask, R, T, flags=flags)
     lib = library()
     need = int(lib.tmm_rt_grad_workspace_size(ctypes.byref(a)))
     if workspace is None:

@@ -37,8 +37,9 @@ def test_library_exports_declared_symbol(name):
 def test_version_and_status_strings():
     lib = tmm.library()
     assert re.match(rb"^\d+\.\d+\.\d+$", lib.tmm_version())
-    for s in (0, 1, 2, 4, 5):
+    for s in (0, 1, 2, 3, 4, 5):
         assert lib.tmm_status_string(s)
+    assert lib.tmm_status_string(3) == b"non-finite input value"
 
 
 FAKE = 0x1000  # never dereferenced: validation fails before any device access
@@ -58,6 +59,8 @@ BAD = [
     ("L too large", dict(L=(1 << 20) + 1)),
     ("pol_mask 0", dict(pol_mask=0)),
     ("pol_mask 4", dict(pol_mask=4)),
+    ("unknown flag bit", dict(flags=2)),
+    ("unknown flag bits with the check", dict(flags=0x81)),
     ("no outputs", dict(R=None)),
     ("n_mat 0", dict(n_mat=0)),
     ("dispersive 2", dict(dispersive=2)),
