@@ -50,89 +50,114 @@ def cpu_model() -> str:
     return platform.processor() or "unknown"
 
 
-def time_gpu(w, dtype: str, steps: int, warmup: int, amplitudes: bool = False):
+def launch_times(fn, steps: int, warmup: int, stream=None):
+    """Run fn warmup times, then steps times with a HIP event pair around every
+    launch on the stream the work goes to.  Returns (per-launch ms list, wall
+    seconds of the bracketed region)."""
     import torch
-    from paper_2111_13667_amd import tmm
-
-    real = torch.float64 if dtype == "f64" else torch.float32
-    cplx = torch.complex128 if dtype == "f64" else torch.complex64
-    dev = "cuda"
-    d = torch.as_tensor(w.d, dtype=real, device=dev)
-    nk = torch.as_tensor(w.nk, dtype=cplx, device=dev)
-    mat = torch.as_tensor(w.mat, dtype=torch.int32, device=dev)
-    wl = torch.as_tensor(w.wl, dtype=real, device=dev)
-    s = torch.as_tensor(w.sin_t, dtype=real, device=dev)
-    c = torch.as_tensor(w.cos_t, dtype=real, device=dev)
-    shape = (w.B, 2, w.theta.size, w.wl.size)
-    R = torch.empty(shape, dtype=real, device=dev)
-    T = torch.empty(shape, dtype=real, device=dev)
-    r = torch.empty(shape, dtype=cplx, device=dev) if amplitudes else None
-    t = torch.empty(shape, dtype=cplx, device=dev) if amplitudes else None
-
-    def step():
-        tmm.tmm_rt(d, nk, wl, s, c, mat=mat, pol_mask=3, R=R, T=T, r=r, t=t)
-
+    stream = stream or torch.cuda.current_stream()
     for _ in range(warmup):
-        step()
+        fn()
     torch.cuda.synchronize()
-    stream = torch.cuda.current_stream()  # tmm_rt launches on this stream
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
     t0 = time.perf_counter()
-    ev0.record(stream)
-    for _ in range(steps):
-        step()
-    ev1.record(stream)
+    for e0, e1 in evs:
+        e0.record(stream)
+        fn()
+        e1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    kernel_ms = ev0.elapsed_time(ev1) / steps
+    return [e0.elapsed_time(e1) for e0, e1 in evs], wall
+
+
+def summary(ms):
+    ms = np.asarray(ms, dtype=np.float64)
+    return {"median_ms": round(float(np.median(ms)), 4), "mean_ms": round(float(ms.mean()), 4),
+            "min_ms": round(float(ms.min()), 4), "max_ms": round(float(ms.max()), 4), "launches": int(ms.size)}
+
+
+def device_inputs(w, dtype):
+    import torch
+    real = torch.float64 if dtype == "f64" else torch.float32
+    cplx = torch.complex128 if dtype == "f64" else torch.complex64
+    dev = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device="cuda")
+    mat = None if w.mat is None else dev(w.mat, torch.int32)
+    return (dev(w.d, real), dev(w.nk, cplx), dev(w.wl, real), dev(w.sin_t, real), dev(w.cos_t, real)), mat, real, cplx
+
+
+def time_gpu(w, dtype: str, steps: int, warmup: int, amplitudes: bool = False):
+    """tmm_rt over the whole batch (one kernel launch), outputs preallocated in
+    device memory.  Returns (per-launch ms, wall s, output bytes per launch)."""
+    import torch
+    from paper_2111_13667_amd import tmm
+    args, mat, real, cplx = device_inputs(w, dtype)
+    shape = (w.B, 2, w.theta.size, w.wl.size)
+    R = torch.empty(shape, dtype=real, device="cuda")
+    T = torch.empty(shape, dtype=real, device="cuda")
+    r = torch.empty(shape, dtype=cplx, device="cuda") if amplitudes else None
+    t = torch.empty(shape, dtype=cplx, device="cuda") if amplitudes else None
+
+    def step():
+        tmm.tmm_rt(*args, mat=mat, pol_mask=3, R=R, T=T, r=r, t=t)
+
+    ms, wall = launch_times(step, steps, warmup)  # tmm_rt launches on the current stream
     out_bytes = sum(x.numel() * x.element_size() for x in (R, T, r, t) if x is not None)
     del R, T, r, t
     torch.cuda.empty_cache()
-    return kernel_ms, wall, out_bytes
+    return ms, wall, out_bytes
 
 
 def _event_time(fn, steps, warmup, stream=None):
-    import torch
-    for _ in range(warmup):
-        fn()
-    torch.cuda.synchronize()
-    stream = stream or torch.cuda.current_stream()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(steps):
-        fn()
-    e1.record(stream)
-    torch.cuda.synchronize()
-    return e0.elapsed_time(e1) / steps
+    """Median per-launch milliseconds of fn (event pair around every launch)."""
+    ms, _ = launch_times(fn, steps, warmup, stream)
+    return float(np.median(ms))
 
 
-def time_grad(steps=3):
+# Algorithmic arithmetic of the adjoint per (point, interface): the forward step
+# (64 flops, as above) plus its adjoint.  Chain adjoint per polarisation and
+# layer step: two complex sums, two complex differences (8 flops), five complex
+# products (30) and one complex multiply-add (8) = 46; per layer step shared by
+# both polarisations: the phase-factor adjoint (8), dl/dd (4), the thickness
+# term of dl/dq (4), the interface terms of dl/dq (s, 4) and dl/deta (p, 4),
+# dl/dn through dq/dn and deta/dn (14) = 38.  (2 x 46 + 38) / 2 = 65 per
+# (point, interface); 64 + 65 = 129.  Checkpoint recomputation is not counted.
+GRAD_FLOPS_PER_POINT_STEP = 129.0
+
+
+def time_grad(steps=10):
     """Adjoint gradients on the 1024 x 60-layer batch (512 wl x 31 angles, s+p):
     dl/dd and dl/dn of an MSE against a long-pass target, float64."""
     import torch
     from paper_2111_13667_amd import tmm, workloads
     w = workloads.adjoint_batch()
-    dev = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device="cuda")
-    d, nk, mat = dev(w.d, torch.float64), dev(w.nk, torch.complex128), dev(w.mat, torch.int32)
-    wl, s, c = dev(w.wl, torch.float64), dev(w.sin_t, torch.float64), dev(w.cos_t, torch.float64)
+    (d, nk, wl, s, c), mat, _, _ = device_inputs(w, "f64")
     shape = (w.B, 2, w.theta.size, w.wl.size)
     R = torch.empty(shape, dtype=torch.float64, device="cuda")
     tmm.tmm_rt(d, nk, wl, s, c, mat=mat, R=R)
-    gR = 2.0 * (R - dev(workloads.longpass_target(w.wl), torch.float64)) / R.numel()
+    target = torch.as_tensor(workloads.longpass_target(w.wl), dtype=torch.float64, device="cuda")
+    gR = 2.0 * (R - target) / R.numel()
     gd = torch.empty((w.B, w.L), dtype=torch.float64, device="cuda")
     gn = torch.empty((w.B, w.L), dtype=torch.complex128, device="cuda")
     ws = torch.empty(tmm.grad_workspace_size(d, nk, wl, s, c, mat=mat), dtype=torch.uint8, device="cuda")
-    ms = _event_time(lambda: tmm.tmm_rt_grad(d, nk, wl, s, c, mat=mat, dl_dR=gR, grad_d=gd, grad_n=gn,
-                                             workspace=ws), steps, 1)
-    fwd_ms = _event_time(lambda: tmm.tmm_rt(d, nk, wl, s, c, mat=mat, R=R), steps, 1)
+    gms, _ = launch_times(lambda: tmm.tmm_rt_grad(d, nk, wl, s, c, mat=mat, dl_dR=gR, grad_d=gd, grad_n=gn,
+                                                  workspace=ws), steps, 1)
+    fms, _ = launch_times(lambda: tmm.tmm_rt(d, nk, wl, s, c, mat=mat, R=R), steps, 1)
+    g_med, f_med = float(np.median(gms)), float(np.median(fms))
+    units = w.n_points * (w.L + 1)
+    flops = units * GRAD_FLOPS_PER_POINT_STEP
+    achieved = flops / (float(np.mean(gms)) * 1e-3) / 1e12
     return {"workload": "adjoint_batch: 1024 stacks x 60 layers, 512 wl x 31 angles, s+p, float64",
-            "points": w.n_points, "grad_ms": round(ms, 3), "forward_ms": round(fwd_ms, 3),
-            "grad_points_per_s": round(w.n_points / (ms * 1e-3), 1), "grad_over_forward": round(ms / fwd_ms, 2),
+            "points": w.n_points, "grad_ms": round(g_med, 3), "forward_ms": round(f_med, 3),
+            "grad_timing": summary(gms),
+            "grad_points_per_s": round(w.n_points / (g_med * 1e-3), 1), "grad_over_forward": round(g_med / f_med, 2),
+            "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_TFLOPS["f64"],
+                         "unit": "TFLOP/s", "frac": round(achieved / PEAK_TFLOPS["f64"], 4),
+                         "algorithmic_flops_per_launch": flops,
+                         "flops_per_point_interface": GRAD_FLOPS_PER_POINT_STEP},
             "workspace_MB": round(ws.numel() / 1e6, 1)}
 
 
-def time_ragged(dtype="f64", steps=3):
+def time_ragged(dtype="f64", steps=10):
     """Ragged batch: 8192 stacks, 2-100 layers, 256-2048 wl, 1-64 angles, s+p, R and T,
     one persistent launch (autotuned on the first run) and its HIP-graph replay."""
     import torch
@@ -198,6 +223,7 @@ def time_surrogate(n_train=262144, epochs=1):
 
 
 def roofline(w, dtype, kernel_ms, out_bytes, traffic=None):
+    """kernel_ms: the average launch duration of the forward kernel."""
     flops = w.n_points * (w.L + 1) * FLOPS_PER_POINT_STEP
     achieved = flops / (kernel_ms * 1e-3) / 1e12
     peak = PEAK_TFLOPS[dtype]
@@ -208,38 +234,82 @@ def roofline(w, dtype, kernel_ms, out_bytes, traffic=None):
             "output_frac_of_hbm": round(out_bytes / (kernel_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)}
 
 
-def cpu_baseline(w, n_stacks: int):
-    """The CPU oracle (complex128, OpenMP over stacks) on the first n_stacks
-    stacks of the same workload, all wavelengths, angles and polarisations."""
+def time_oracle(w, runs=3, amplitudes=False):
+    """The CPU oracle (complex128, OpenMP over stacks) on workload w: one
+    warm-up run, then the median wall time of `runs` runs.  Returns
+    (median seconds, all timed seconds, threads)."""
     import oracle
+    oracle.rt(w.d, w.nk, w.wl, w.sin_t, w.cos_t, mat=w.mat, want_amplitudes=amplitudes)
+    times, threads = [], 0
+    for _ in range(runs):
+        t0 = time.perf_counter()
+        out = oracle.rt(w.d, w.nk, w.wl, w.sin_t, w.cos_t, mat=w.mat, want_amplitudes=amplitudes)
+        times.append(time.perf_counter() - t0)
+        threads = int(out["threads"])
+    return float(np.median(times)), [round(t, 4) for t in times], threads
+
+
+def cpu_baseline(w, n_stacks: int):
+    """The CPU oracle on the first n_stacks stacks of the same workload, all
+    wavelengths, angles and polarisations (median of 3 after a warm-up)."""
     sub = w.take(slice(0, n_stacks))
-    oracle.rt(sub.d[:1], sub.nk[:, :8], sub.wl[:8], sub.sin_t[:2], sub.cos_t[:2], mat=sub.mat[:1],
-              want_amplitudes=False)  # load + warm
-    t0 = time.perf_counter()
-    out = oracle.rt(sub.d, sub.nk, sub.wl, sub.sin_t, sub.cos_t, mat=sub.mat, want_amplitudes=False)
-    dt = time.perf_counter() - t0
+    dt, times, threads = time_oracle(sub)
     pts = sub.n_points
-    return {"value": round(pts / dt, 1), "unit": "points/s", "cores": int(out["threads"]),
+    return {"value": round(pts / dt, 1), "unit": "points/s", "cores": threads,
             "kind": "oracle",
             "sample": f"first {n_stacks} of {w.B} stacks, all {w.wl.size} wavelengths x "
-                      f"{w.theta.size} angles x 2 pol ({pts} points) in {dt:.2f} s",
+                      f"{w.theta.size} angles x 2 pol ({pts} points); median of 3 runs after a warm-up "
+                      f"({dt:.2f} s; runs {times})",
+            "full_batch_s_extrapolated": round(dt * w.B / n_stacks, 1),
             "cpu_model": cpu_model()}
+
+
+def gpu_and_oracle(w, label, steps=20, amplitudes=False, paper_s=None):
+    """A small workload timed in full on both sides: tmm_rt in float64 (median
+    of per-launch events) and the oracle (median of 3 after a warm-up)."""
+    ms, _, _ = time_gpu(w, "f64", steps, 3, amplitudes=amplitudes)
+    cpu_s, times, threads = time_oracle(w, amplitudes=amplitudes)
+    g_s = float(np.median(ms)) * 1e-3
+    rec = {"workload": label, "points": w.n_points, "outputs": "R,T,r,t" if amplitudes else "R,T",
+           "gpu_f64": {**summary(ms), "points_per_s": round(w.n_points / g_s, 1)},
+           "oracle": {"median_s": round(cpu_s, 6), "runs_s": times, "cores": threads,
+                      "points_per_s": round(w.n_points / cpu_s, 1)},
+           "gpu_over_oracle": round(cpu_s / g_s, 1)}
+    if paper_s is not None:
+        rec["paper_numpy_s"] = paper_s
+        rec["note"] = ("the paper's time is its NumPy code on an unstated CPU; different hardware, "
+                       "not a like-for-like comparison")
+    return rec
+
+
+def material_variant(n_pool, steps=5):
+    """The large batch with a larger material pool (n_pool + ambient + substrate
+    table rows), FP64 and FP32: the forward kernel's per-material table path."""
+    from paper_2111_13667_amd import workloads
+    w = workloads.large_batch(n_pool=n_pool)
+    rec = {"workload": f"large_batch with a {n_pool}-material pool ({n_pool + 2} table rows)"}
+    for dt in ("f64", "f32"):
+        ms, _, ob = time_gpu(w, dt, steps, 1)
+        rf = roofline(w, dt, float(np.mean(ms)), ob)
+        rec[dt] = {**summary(ms), "points_per_s": round(w.n_points / (np.median(ms) * 1e-3), 1),
+                   "frac": rf["frac"]}
+    return rec
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--dtype", choices=["f64", "f32"], default="f64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true",
-                    help="skip the other-precision, amplitude, adjoint, ragged and surrogate measurements")
-    ap.add_argument("--cpu-stacks", type=int, default=384,
-                    help="stacks of the CPU oracle sample (about 10 s on 16 cores)")
+                    help="skip the other-precision, amplitude, adjoint, ragged, material-pool and surrogate records")
+    ap.add_argument("--cpu-stacks", type=int, default=128,
+                    help="stacks of the CPU oracle sample (median of 3 runs after a warm-up)")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"))
-    ap.add_argument("--only", choices=["adjoint", "ragged_f64", "ragged_f32", "surrogate"], default=None,
-                    help="run only this extra measurement and print its record (for profiling)")
+    ap.add_argument("--only", choices=["adjoint", "ragged_f64", "ragged_f32", "surrogate", "materials"],
+                    default=None, help="run only this extra measurement and print its record (for profiling)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="first run a plain N-MiB elementwise copy kernel (profiler calibration)")
     args = ap.parse_args()
@@ -261,6 +331,8 @@ def main():
             rec = time_grad(max(1, args.steps))
         elif args.only == "surrogate":
             rec = time_surrogate()
+        elif args.only == "materials":
+            rec = {"7": material_variant(7, max(1, args.steps)), "12": material_variant(12, max(1, args.steps))}
         else:
             rec = time_ragged(args.only.split("_")[1], max(1, args.steps))
         print(json.dumps({"only": args.only, **rec}), flush=True)
@@ -289,8 +361,9 @@ def main():
             traffic_all = {}
     traffic = traffic_all.get(args.dtype)
 
-    kernel_ms, wall, out_bytes = time_gpu(w, args.dtype, args.steps, args.warmup)
-    value = w.n_points / (kernel_ms * 1e-3)
+    ms, wall, out_bytes = time_gpu(w, args.dtype, args.steps, args.warmup)
+    med, mean = float(np.median(ms)), float(np.mean(ms))
+    value = w.n_points / (med * 1e-3)
     rec = {
         "metric": METRIC,
         "value": round(value, 1),
@@ -298,8 +371,10 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(kernel_ms, 4),
-        "wall_ms_per_step": round(wall * 1e3 / args.steps, 4),
+        "ms_per_step": round(med, 4),
+        "timing": {**summary(ms), "wall_ms_per_step": round(wall * 1e3 / args.steps, 4),
+                   "note": "value and ms_per_step use the median of the per-launch HIP-event times; "
+                           "roofline.achieved uses their mean"},
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -309,21 +384,28 @@ def main():
                                "1024 wavelengths 300-1200 nm x 91 angles 0-90 deg, s+p, R and T",
                    "stacks": w.B, "layers": w.L, "n_wl": int(w.wl.size), "n_theta": int(w.theta.size),
                    "points": w.n_points, "outputs": "R,T"},
-        "roofline": roofline(w, args.dtype, kernel_ms, out_bytes, traffic),
+        "roofline": roofline(w, args.dtype, mean, out_bytes, traffic),
     }
     if not args.no_extra:
         extra = {}
         other = "f32" if args.dtype == "f64" else "f64"
-        ms, _, ob = time_gpu(w, other, max(3, args.steps // 2), 1)
-        extra[other] = {"value": round(w.n_points / (ms * 1e-3), 1), "ms_per_step": round(ms, 4),
-                        "roofline": roofline(w, other, ms, ob, traffic_all.get(other))}
-        ms, _, ob = time_gpu(w, args.dtype, max(3, args.steps // 2), 1, amplitudes=True)
-        extra[args.dtype + "_with_r_t"] = {"value": round(w.n_points / (ms * 1e-3), 1),
-                                           "ms_per_step": round(ms, 4),
-                                           "roofline": roofline(w, args.dtype, ms, ob)}
+        oms, _, ob = time_gpu(w, other, max(10, args.steps // 2), 1)
+        extra[other] = {"value": round(w.n_points / (np.median(oms) * 1e-3), 1), **summary(oms),
+                        "roofline": roofline(w, other, float(np.mean(oms)), ob, traffic_all.get(other))}
+        ams, _, ob = time_gpu(w, args.dtype, max(10, args.steps // 2), 1, amplitudes=True)
+        extra[args.dtype + "_with_r_t"] = {"value": round(w.n_points / (np.median(ams) * 1e-3), 1), **summary(ams),
+                                           "roofline": roofline(w, args.dtype, float(np.mean(ams)), ob)}
+        extra["small_batch"] = gpu_and_oracle(
+            workloads.small_batch(), "small_batch: 16 stacks x 10 layers, 128 wl x 8 angles, s+p, R,T,r,t "
+            "(timed in full on both sides)", amplitudes=True)
+        extra["speedup_example"] = gpu_and_oracle(
+            workloads.speedup_example(), "speedup_example: the paper's speed-up shape, 10 stacks x 21 media, "
+            "100 wl 400-700 nm x 20 angles 0-90 deg (points counted with both polarisations)", paper_s=0.168)
         extra["adjoint_f64"] = time_grad()
         extra["ragged_f64"] = time_ragged("f64")
         extra["ragged_f32"] = time_ragged("f32")
+        extra["material_pool_7"] = material_variant(7)
+        extra["material_pool_12"] = material_variant(12)
         extra["surrogate"] = time_surrogate()
         rec["extra"] = extra
     if not args.no_cpu_baseline:

@@ -127,30 +127,33 @@ def small_batch(seed: int = 0, B: int = 16, L: int = 10, n_wl: int = 128,
 
 
 def large_batch(seed: int = 0, B: int = 4096, L: int = 40, n_wl: int = 1024,
-                n_theta: int = 91) -> Workload:
+                n_theta: int = 91, n_pool: int = 4) -> Workload:
     """Large batch: 4096 stacks x 40 layers from a 4-material Cauchy pool
     (A ~ U[1.4,2.4], B ~ U[0.003,0.03] um^2, k = 0, 1e-3, 0, 1e-3), d ~ U[20,250] nm,
     1024 wavelengths 300-1200 nm, 91 angles 0-90 deg in 1 deg steps (grazing
-    incidence included), ambient 1.0, substrate 1.52.  Table rows 0-3 are the
-    pool, row 4 the ambient, row 5 the substrate."""
+    incidence included), ambient 1.0, substrate 1.52.  Table rows 0..n_pool-1 are
+    the pool, row n_pool the ambient, row n_pool+1 the substrate.  n_pool other
+    than 4 draws a larger (or smaller) pool the same way, k alternating 0 / 1e-3
+    (the material-count variants of the benchmark)."""
     rng = np.random.default_rng(seed)
-    A = rng.uniform(1.4, 2.4, 4)
-    Bc = rng.uniform(0.003, 0.03, 4)
-    k = np.array([0.0, 1e-3, 0.0, 1e-3])
-    mat_inner = rng.integers(0, 4, (B, L))
+    A = rng.uniform(1.4, 2.4, n_pool)
+    Bc = rng.uniform(0.003, 0.03, n_pool)
+    k = np.where(np.arange(n_pool) % 2 == 1, 1e-3, 0.0)
+    mat_inner = rng.integers(0, n_pool, (B, L))
     d = rng.uniform(20.0, 250.0, (B, L))
     wl = np.linspace(300.0, 1200.0, n_wl)
-    nk = np.empty((6, n_wl), dtype=np.complex128)
-    nk[:4] = cauchy(A, Bc, k, wl)
-    nk[4] = 1.0
-    nk[5] = 1.52
+    nk = np.empty((n_pool + 2, n_wl), dtype=np.complex128)
+    nk[:n_pool] = cauchy(A, Bc, k, wl)
+    nk[n_pool] = 1.0
+    nk[n_pool + 1] = 1.52
     mat = np.empty((B, L + 2), dtype=np.int32)
-    mat[:, 0] = 4
+    mat[:, 0] = n_pool
     mat[:, 1:L + 1] = mat_inner
-    mat[:, L + 1] = 5
+    mat[:, L + 1] = n_pool + 1
     theta = np.deg2rad(np.arange(0, n_theta, dtype=np.float64))
     s, c = angles(theta)
-    return Workload("large_batch_4096x40", d, nk, mat, wl, theta, s, c)
+    name = "large_batch_4096x40" if n_pool == 4 else f"large_batch_4096x40_{n_pool}mat"
+    return Workload(name, d, nk, mat, wl, theta, s, c)
 
 
 def adjoint_batch(seed: int = 0, B: int = 1024, L: int = 60, n_wl: int = 512,
@@ -296,6 +299,27 @@ def appendix_example(seed: int = 0, B: int = 1, n_media: int = 12, n_wl: int = 3
     theta = np.deg2rad(np.linspace(0.0, 90.0, n_theta))
     s, c = angles(theta)
     return Workload("appendix_example_12media", d, nk, None, wl, theta, s, c)
+
+
+def speedup_example(seed: int = 0, B: int = 10, n_media: int = 21, n_wl: int = 100,
+                    n_theta: int = 20) -> Workload:
+    """Shape of the paper's speed-up timing (section "Core functionality speedup
+    and dataset generation"): ten stacks of 21 media (read as 19 finite layers
+    plus the two semi-infinite ones, as the paper's listings count them), 100
+    wavelengths 400-700 nm x 20 angles 0-90 deg.  The paper states no indices or
+    thicknesses for it; the appendix example's recipe stands in: d ~ U[20,150]
+    nm, constant n ~ U[1.2,5] (the first draw is the injection medium), exit
+    medium n = 1."""
+    rng = np.random.default_rng(seed)
+    L = n_media - 2
+    d = rng.uniform(20.0, 150.0, (B, L))
+    n = rng.uniform(1.2, 5.0, (B, n_media))
+    n[:, -1] = 1.0
+    nk = n.astype(np.complex128).ravel()
+    wl = np.linspace(400.0, 700.0, n_wl)
+    theta = np.deg2rad(np.linspace(0.0, 90.0, n_theta))
+    s, c = angles(theta)
+    return Workload("speedup_example_10x21", d, nk, None, wl, theta, s, c)
 
 
 def random_stacks(seed: int, B: int, L: int, n_wl: int, n_theta: int, *,
