@@ -178,6 +178,27 @@ tmm_status tmm_rt_grad(const tmm_rt_args *a, const void *dl_dR, const void *dl_d
                        void *grad_n, void *workspace, size_t workspace_bytes, tmm_dtype dtype,
                        void *stream);
 
+/*
+ * tmm_rt_grad without a workspace argument and without any allocation, for
+ * callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc).  Same arguments,
+ * results and errors as tmm_rt_grad (the gradients are the same bits); the
+ * workspace is a static device array of tmm_rt_grad_noalloc_scratch_bytes()
+ * (192 MiB) that every GPU the library runs on holds until the process ends.
+ * A batch whose checkpoints of one persistent block plus the partial sums of
+ * four stacks do not fit in it returns TMM_ERR_WORKSPACE; larger batches run
+ * with a capped persistent grid and several launches.  Every call on one GPU
+ * shares that GPU's array: calls that overlap on one GPU (several streams or
+ * threads) race and give wrong gradients -- serialise them.  Nothing in the
+ * array needs clearing between calls (every value is written before it is
+ * read).  The first call on a device looks up the array's address there.
+ */
+tmm_status tmm_rt_grad_noalloc(const tmm_rt_args *a, const void *dl_dR, const void *dl_dT, void *grad_d,
+                               void *grad_n, tmm_dtype dtype, void *stream);
+
+/* Size in bytes of tmm_rt_grad_noalloc's static scratch array. */
+size_t tmm_rt_grad_noalloc_scratch_bytes(void);
+
 /* Static description of a status code (never NULL). */
 const char *tmm_status_string(tmm_status s);
 

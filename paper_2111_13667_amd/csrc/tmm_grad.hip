@@ -1312,6 +1312,50 @@ static tmm_status grad_launch(const tmm_rt_args* a, const void* dl_dR, const voi
     return check_launch(who);
 }
 
+// ---------------------------------------------------------------------------
+// Workspace without allocation: a static device array per GPU, for callers
+// that cannot allocate (graph capture, serving loops).  Host code reaches it
+// only through the address hipGetSymbolAddress returns for the current device.
+constexpr size_t kGradScratchBytes = (size_t)192 << 20;
+static __device__ __align__(256) unsigned char scratch[kGradScratchBytes];
+constexpr int kScratchMaxDevices = 64;
+
+static unsigned char* scratch_on(int dev, hipError_t* err) {
+    static std::mutex mu;
+    static unsigned char* addr[kScratchMaxDevices] = {};
+    std::lock_guard<std::mutex> g(mu);
+    *err = hipSuccess;
+    if (dev < 0 || dev >= kScratchMaxDevices) {
+        *err = hipErrorInvalidDevice;
+        return nullptr;
+    }
+    if (!addr[dev]) {
+        void* ptr = nullptr;
+        *err = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (*err != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        addr[dev] = static_cast<unsigned char*>(ptr);
+    }
+    return addr[dev];
+}
+
+// Workspace shape inside the static scratch: the full persistent grid if its
+// checkpoints fit in three quarters of it, else a grid capped to that share;
+// the rest holds the partial sums of as many stacks as fit (several launches).
+static bool scratch_shape(const tmm_rt_args* a, GradShape* g, int64_t* chunk) {
+    *g = grad_shape(a);
+    const size_t ckpt_cap = kGradScratchBytes / 4 * 3;
+    if (g->ckpt_bytes > ckpt_cap) {
+        const int64_t max_slots = (int64_t)(ckpt_cap / g->slot_bytes);
+        if (max_slots < kGradPairWaves) return false;
+        *g = grad_shape(a, max_slots);
+    }
+    *chunk = stacks_per_launch(*g, a->B, kGradScratchBytes);
+    return *chunk > 0;
+}
+
 }  // namespace tmm
 
 extern "C" {
@@ -1342,6 +1386,32 @@ tmm_status tmm_rt_grad(const tmm_rt_args* a, const void* dl_dR, const void* dl_d
                     tmm::ws_bytes(g, a->B < tmm::kGradWaves ? a->B : tmm::kGradWaves),
                     tmm::ws_bytes(g, tmm::preferred_stacks(g, a->B)), workspace ? workspace_bytes : (size_t)0);
     return tmm::grad_launch(a, dl_dR, dl_dT, grad_d, grad_n, workspace, g, chunk, s, "tmm_rt_grad");
+}
+
+size_t tmm_rt_grad_noalloc_scratch_bytes(void) { return tmm::kGradScratchBytes; }
+
+tmm_status tmm_rt_grad_noalloc(const tmm_rt_args* a, const void* dl_dR, const void* dl_dT, void* grad_d,
+                               void* grad_n, tmm_dtype dtype, void* stream) {
+    using tmm::fail;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    bool done = true;
+    tmm_status st = tmm::grad_prologue(a, dl_dR, dl_dT, grad_d, grad_n, dtype, s, "tmm_rt_grad_noalloc", &done);
+    if (st != TMM_OK || done) return st;
+    tmm::GradShape g;
+    int64_t chunk = 0;
+    if (!tmm::scratch_shape(a, &g, &chunk))
+        return fail(TMM_ERR_WORKSPACE,
+                    "tmm_rt_grad_noalloc: B=%d L=%d n_wl=%d n_theta=%d needs more than the %zu-byte static scratch "
+                    "(use tmm_rt_grad with a workspace)",
+                    a->B, a->L, a->n_wl, a->n_theta, tmm::kGradScratchBytes);
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(TMM_ERR_HIP, "tmm_rt_grad_noalloc: no device");
+    hipError_t e = hipSuccess;
+    unsigned char* ws = tmm::scratch_on(dev, &e);
+    if (!ws)
+        return fail(TMM_ERR_HIP, "tmm_rt_grad_noalloc: static scratch not found on device %d: %s", dev,
+                    hipGetErrorString(e));
+    return tmm::grad_launch(a, dl_dR, dl_dT, grad_d, grad_n, ws, g, chunk, s, "tmm_rt_grad_noalloc");
 }
 
 }  // extern "C"

@@ -72,6 +72,11 @@ def library() -> ctypes.CDLL:
         lib.tmm_rt_grad.restype = ctypes.c_int
         lib.tmm_rt_grad.argtypes = [ctypes.POINTER(TmmRtArgs)] + [ctypes.c_void_p] * 5 + \
             [ctypes.c_size_t, ctypes.c_int, ctypes.c_void_p]
+        lib.tmm_rt_grad_noalloc.restype = ctypes.c_int
+        lib.tmm_rt_grad_noalloc.argtypes = [ctypes.POINTER(TmmRtArgs)] + [ctypes.c_void_p] * 4 + \
+            [ctypes.c_int, ctypes.c_void_p]
+        lib.tmm_rt_grad_noalloc_scratch_bytes.restype = ctypes.c_size_t
+        lib.tmm_rt_grad_noalloc_scratch_bytes.argtypes = []
         _lib = lib
     return _lib
 
@@ -226,6 +231,37 @@ def tmm_rt_grad(d, nk, wl, sin_theta, cos_theta, *, mat=None, n_mat=None, disper
     _check(lib.tmm_rt_grad(ctypes.byref(a), _ptr(dl_dR), _ptr(dl_dT), _ptr(grad_d), _ptr(grad_n),
                            _ptr(workspace), workspace.numel() * workspace.element_size(), TMM_F64,
                            _stream_handle(stream)))
+
+
+def tmm_rt_grad_noalloc(d, nk, wl, sin_theta, cos_theta, *, mat=None, n_mat=None, dispersive=None,
+                        pol_mask: int = 3, dl_dR=None, dl_dT=None, grad_d=None, grad_n=None, R=None, T=None,
+                        flags: int = 0, stream=None) -> None:
+    """tmm_rt_grad on the library's static scratch: no workspace argument and no
+    device allocation anywhere in the call (same arguments and results)."""
+    import torch
+    if d.dtype != torch.float64:
+        raise TypeError("tmm_rt_grad_noalloc is float64 only")
+    for x in (d, nk, wl, sin_theta, cos_theta, mat, dl_dR, dl_dT, grad_d, grad_n, R, T):
+        if x is not None and (not x.is_cuda or not x.is_contiguous()):
+            raise ValueError("every tensor must be a contiguous device tensor")
+    B, L = d.shape
+    P = 2 if pol_mask == 3 else 1
+    shape = (B, P, sin_theta.numel(), wl.numel())
+    for name, x in (("dl_dR", dl_dR), ("dl_dT", dl_dT), ("R", R), ("T", T)):
+        if x is not None and (tuple(x.shape) != shape or x.dtype != torch.float64):
+            raise ValueError(f"{name} must be float64 {shape}")
+    if grad_d is not None and (tuple(grad_d.shape) != (B, L) or grad_d.dtype != torch.float64):
+        raise ValueError("grad_d must be float64 [B, L]")
+    if grad_n is not None and (tuple(grad_n.shape) != (B, L) or grad_n.dtype != torch.complex128):
+        raise ValueError("grad_n must be complex128 [B, L]")
+    if mat is not None and mat.dtype != torch.int32:
+        raise TypeError("mat must be int32")
+    if nk.dtype != torch.complex128:
+        raise TypeError("nk must be complex128")
+    n_mat = _check_shapes(d, nk, wl, sin_theta, cos_theta, mat, n_mat, dispersive)
+    a = _rt_args(d, nk, wl, sin_theta, cos_theta, mat, n_mat, dispersive, pol_mask, R, T, flags=flags)
+    _check(library().tmm_rt_grad_noalloc(ctypes.byref(a), _ptr(dl_dR), _ptr(dl_dT), _ptr(grad_d), _ptr(grad_n),
+                                         TMM_F64, _stream_handle(stream)))
 
 
 # ---------------------------------------------------------------------------
