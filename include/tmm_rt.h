@@ -179,6 +179,26 @@ tmm_status tmm_rt_grad(const tmm_rt_args *a, const void *dl_dR, const void *dl_d
                        void *stream);
 
 /*
+ * tmm_rt at an explicit list of points: R and T (for the polarisations of
+ * a->pol_mask) of the listed (stack, angle, wavelength) points of the batch a
+ * describes -- the same quantities as tmm_rt (Eq. (1)-(7)), for callers that
+ * need only scattered points, such as a surrogate model's fallback, which
+ * recomputes exactly the outputs it does not trust (paper: App. A.2, datasets
+ * of reflectance spectra for machine learning).
+ *  a        as for tmm_rt; a->R and a->T (either may be NULL, not both) are laid
+ *           out as tmm_rt's outputs, [B][P][n_theta][n_wl], and only the
+ *           elements of the listed points are written; r and t must be NULL
+ *           (TMM_ERR_UNSUPPORTED otherwise).
+ *  points   [n_points] int64 device array of flat indices
+ *           (b * n_theta + k) * n_wl + i.  An index outside [0, B*n_theta*n_wl)
+ *           is skipped (nothing written); a repeated index is evaluated twice.
+ * Asynchronous, allocates nothing.  Returns TMM_OK or a tmm_status error
+ * (TMM_CHECK_FINITE in a->flags validates the batch's inputs first).
+ */
+tmm_status tmm_rt_points(const tmm_rt_args *a, const int64_t *points, int64_t n_points, tmm_dtype dtype,
+                         void *stream);
+
+/*
  * tmm_rt_grad without a workspace argument and without any allocation, for
  * callers that cannot allocate device memory (code under HIP graph capture,
  * tight serving loops, harnesses that forbid hipMalloc).  Same arguments,

@@ -13,7 +13,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtmm_rt.so")
 
-SOURCES = ["tmm_fwd.hip", "tmm_grad.hip", "tmm_mlp.hip", "tmm_ragged.hip", "tmm_check.hip"]
+SOURCES = ["tmm_fwd.hip", "tmm_grad.hip", "tmm_mlp.hip", "tmm_ragged.hip", "tmm_check.hip", "tmm_points.hip"]
 
 # Packed FP32 instructions are disabled on purpose: the kernels rely on scalar
 # FP32/FP64 VALU code only.

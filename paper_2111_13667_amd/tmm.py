@@ -72,6 +72,9 @@ def library() -> ctypes.CDLL:
         lib.tmm_rt_grad.restype = ctypes.c_int
         lib.tmm_rt_grad.argtypes = [ctypes.POINTER(TmmRtArgs)] + [ctypes.c_void_p] * 5 + \
             [ctypes.c_size_t, ctypes.c_int, ctypes.c_void_p]
+        lib.tmm_rt_points.restype = ctypes.c_int
+        lib.tmm_rt_points.argtypes = [ctypes.POINTER(TmmRtArgs), ctypes.c_void_p, ctypes.c_int64, ctypes.c_int,
+                                      ctypes.c_void_p]
         lib.tmm_rt_grad_noalloc.restype = ctypes.c_int
         lib.tmm_rt_grad_noalloc.argtypes = [ctypes.POINTER(TmmRtArgs)] + [ctypes.c_void_p] * 4 + \
             [ctypes.c_int, ctypes.c_void_p]
@@ -141,6 +144,42 @@ def tmm_rt(d, nk, wl, sin_theta, cos_theta, *, mat=None, n_mat=None, dispersive=
                   _ptr(mat), _ptr(wl), _ptr(sin_theta), _ptr(cos_theta), pol_mask,
                   _ptr(R), _ptr(T), _ptr(r), _ptr(t), flags)
     _check(library().tmm_rt(ctypes.byref(a), dt, _stream_handle(stream)))
+
+
+def tmm_rt_points(d, nk, wl, sin_theta, cos_theta, points, *, mat=None, n_mat=None, dispersive=None,
+                  pol_mask: int = 3, R=None, T=None, flags: int = 0, stream=None) -> None:
+    """Launch tmm_rt_points: R and T at the listed points (int64 device tensor of
+    flat indices (b * n_theta + k) * n_wl + i), written into R, T laid out as
+    tmm_rt's outputs [B, P, n_theta, n_wl]; other elements are left as they are."""
+    import torch
+    real = d.dtype
+    if real == torch.float64:
+        dt, cdt = TMM_F64, torch.complex128
+    elif real == torch.float32:
+        dt, cdt = TMM_F32, torch.complex64
+    else:
+        raise TypeError("d must be float64 or float32")
+    for name, x in (("wl", wl), ("sin_theta", sin_theta), ("cos_theta", cos_theta), ("R", R), ("T", T)):
+        if x is not None and x.dtype != real:
+            raise TypeError(f"{name} must be {real}")
+    if nk.dtype != cdt:
+        raise TypeError(f"nk must be {cdt}")
+    if points.dtype != torch.int64 or points.dim() != 1:
+        raise TypeError("points must be a 1-D int64 tensor")
+    for x in (d, nk, wl, sin_theta, cos_theta, mat, R, T, points):
+        if x is not None and (not x.is_cuda or not x.is_contiguous()):
+            raise ValueError("every tensor must be a contiguous device tensor")
+    if mat is not None and mat.dtype != torch.int32:
+        raise TypeError("mat must be int32")
+    B, L = d.shape
+    n_mat = _check_shapes(d, nk, wl, sin_theta, cos_theta, mat, n_mat, dispersive)
+    P = 2 if pol_mask == 3 else 1
+    shape = (B, P, sin_theta.numel(), wl.numel())
+    for name, x in (("R", R), ("T", T)):
+        if x is not None and tuple(x.shape) != shape:
+            raise ValueError(f"{name} must have shape {shape}")
+    a = _rt_args(d, nk, wl, sin_theta, cos_theta, mat, n_mat, dispersive, pol_mask, R, T, flags=flags)
+    _check(library().tmm_rt_points(ctypes.byref(a), _ptr(points), points.numel(), dt, _stream_handle(stream)))
 
 
 def _check_shapes(d, nk, wl, sin_theta, cos_theta, mat, n_mat, dispersive) -> int:
