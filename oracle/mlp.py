@@ -78,22 +78,32 @@ def forward(vec, x, dims, shift, scale, round=True):
     return z, cache
 
 
-def backward(vec, x, t, dims, shift, scale, round=True):
-    """Gradient of the objective w.r.t. the parameter vector (export layout)."""
+def backward(vec, x, t, dims, shift, scale, round=True, intermediates=False):
+    """Gradient of the objective w.r.t. the parameter vector (export layout).
+    With intermediates=True also returns y, the forward cache and, per layer l,
+    (dz_l, dh_l): the layer's output gradient and (l > 0) its input gradient
+    before the GELU derivative."""
     r = bf16 if round else (lambda a: np.asarray(a, dtype=np.float64))
     Ws, _ = unpack(np.asarray(vec, dtype=np.float64), dims)
     y, cache = forward(vec, x, dims, shift, scale, round)
     B, n_out = y.shape
     dz = r(2.0 * (y - t) / B)
     gW, gb = [None] * len(Ws), [None] * len(Ws)
+    back = [None] * len(Ws)
     for l in range(len(Ws) - 1, -1, -1):
         h, z = cache[l]
         gW[l] = dz.T @ h
         gb[l] = dz.sum(axis=0)
+        dh = None
+        dz_l = dz
         if l > 0:
             dh = dz @ r(Ws[l])
             dz = r(dh * gelu_grad(cache[l - 1][1]))
-    return np.concatenate([g.ravel() for g in gW] + [g for g in gb])
+        back[l] = (dz_l, dh)
+    g = np.concatenate([g.ravel() for g in gW] + [g for g in gb])
+    if intermediates:
+        return g, y, cache, back
+    return g
 
 
 def objective(vec, x, t, dims, shift, scale, round=True):
