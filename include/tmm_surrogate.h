@@ -91,19 +91,23 @@ tmm_status tmm_surrogate_gradients(tmm_surrogate *h, const float *x, const float
 tmm_status tmm_surrogate_predict(tmm_surrogate *h, const float *x, int32_t B, float *mean, float *sigma,
                                  float *members, void *stream);
 
-/* Surrogate with transfer-matrix fallback: predict as above, then every stack b
- * with err_scale * max_o sigma[b][o] > bound is recomputed by tmm_rt (float32)
- * and its row of out replaced.  tmpl describes the same B stacks for tmm_rt:
- * L = n_in layers whose thicknesses are x, material ids (mat, required), the
- * index table, the grids and pol_mask, with P * n_theta * n_wl = n_out so that
- * out [B][n_out] has the layout of tmm_rt's R; its d and output fields are
- * ignored.  n_fallback (host, may be NULL) receives the number of recomputed
- * stacks.  Synchronises the stream once per max_batch chunk (to size the
- * fallback launch).  The first call, and a call with more layers than any
- * before it, allocates the handle's material-id staging buffer (max_batch rows
- * of L + 2 ids); the handle frees it. */
+/* Surrogate with transfer-matrix fallback at point granularity: predict as
+ * above, then every output whose error estimate err_scale * sigma exceeds bound
+ * (or whose sigma is NaN) is recomputed by the transfer-matrix kernels
+ * (float32) and replaced in out.  A unit is one (stack, angle, wavelength) with
+ * its P polarisation outputs; a unit is recomputed when any of its outputs is
+ * flagged.  A stack whose units are all flagged goes through tmm_rt on the
+ * gathered stacks; the flagged units of the other stacks go through the
+ * point-list kernel of tmm_rt_points, which writes into out in place.
+ * tmpl describes the same B stacks for tmm_rt: L = n_in layers whose
+ * thicknesses are x, material ids (mat, required), the index table, the grids
+ * and pol_mask, with P * n_theta * n_wl = n_out so that out [B][n_out] has the
+ * layout of tmm_rt's R; its d and output fields are ignored.  n_fallback (host,
+ * may be NULL) receives the number of outputs replaced.  Synchronises the
+ * stream once per max_batch chunk (to size the fallback launches).  Allocates
+ * nothing: the lists and staging buffers belong to the handle (created with it). */
 tmm_status tmm_surrogate_predict_fallback(tmm_surrogate *h, const float *x, int32_t B, const tmm_rt_args *tmpl,
-                                          float err_scale, float bound, float *out, int32_t *n_fallback,
+                                          float err_scale, float bound, float *out, int64_t *n_fallback,
                                           void *stream);
 
 #ifdef __cplusplus

@@ -20,6 +20,7 @@
 
 #include "tmm_host.hpp"
 #include "tmm_mlp_kernels.hpp"
+#include "tmm_points.hpp"
 
 #include "tmm_surrogate.h"
 
@@ -242,16 +243,51 @@ __global__ void ensemble_stats(const float* Y, int E, int B, int n_out, int64_t 
     }
 }
 
-// Stacks whose estimated error scale * max_o sigma exceeds the bound are
-// appended to list (order unspecified).  One wave per stack.
-__global__ void flag_stacks(const float* sigma, int B, int n_out, float scale, float bound, int* list, int* count) {
-    const int b = blockIdx.x * 4 + (threadIdx.x >> 6);
+// Fallback selection, one workgroup of 256 threads per stack row b.  A unit is
+// one (angle k, wavelength i) of the row, u = k * n_wl + i, with its P outputs
+// at sigma[b][q * units + u]; it is flagged when some output has
+// scale * sigma > bound (or a NaN sigma).  A row whose units are all flagged is
+// appended to stacks (recomputed by the dense kernel); otherwise its flagged
+// units are appended to points as b * units + u (recomputed one by one).  Order
+// within the lists is unspecified.  counts[0] = stacks, counts[1] = points.
+__global__ void flag_units(const float* sigma, int units, int P, float scale, float bound, int* stacks,
+                           uint32_t* points, int* counts) {
+    __shared__ int s_cnt;
+    const int b = blockIdx.x;
     const int lane = threadIdx.x & 63;
-    if (b >= B) return;
-    float mx = 0.0f;
-    for (int o = lane; o < n_out; o += 64) mx = fmaxf(mx, sigma[(int64_t)b * n_out + o]);
-    for (int off = 32; off >= 1; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off, 64));
-    if (lane == 0 && !(scale * mx <= bound)) list[atomicAdd(count, 1)] = b;
+    const float* sg = sigma + (int64_t)b * units * P;
+    auto flagged = [&](int u) {
+        bool f = false;
+        for (int q = 0; q < P; ++q) f = f || !(scale * sg[(int64_t)q * units + u] <= bound);
+        return f;
+    };
+    if (threadIdx.x == 0) s_cnt = 0;
+    __syncthreads();
+    int cnt = 0;
+    for (int u = threadIdx.x; u < units; u += blockDim.x) cnt += flagged(u) ? 1 : 0;
+    for (int off = 32; off >= 1; off >>= 1) cnt += __shfl_xor(cnt, off, 64);
+    if (lane == 0 && cnt) atomicAdd(&s_cnt, cnt);
+    __syncthreads();
+    const int total = s_cnt;
+    if (total == 0) return;
+    if (total == units) {
+        if (threadIdx.x == 0) stacks[atomicAdd(&counts[0], 1)] = b;
+        return;
+    }
+    // wave-level compaction: one counter update per wave and 64 units
+    for (int u0 = threadIdx.x - lane; u0 < units; u0 += blockDim.x) {
+        const int u = u0 + lane;
+        const bool f = u < units && flagged(u);
+        const unsigned long long m = __ballot(f);
+        if (!m) continue;
+        int base = 0;
+        if (lane == 0) base = atomicAdd(&counts[1], __popcll(m));
+        base = __shfl(base, 0, 64);
+        if (f) {
+            const int below = __popcll(m & ((1ull << lane) - 1ull));
+            points[base + below] = (uint32_t)((int64_t)b * units + u);
+        }
+    }
 }
 
 __global__ void gather_stacks(const float* x, const int32_t* mat, const int* list, int n, int n_in, int L2,
@@ -274,8 +310,8 @@ __global__ void scatter_outputs(const float* Rc, const int* list, int n, int n_o
     }
 }
 
-__global__ void zero_int(int* x) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) *x = 0;
+__global__ void zero_int(int* x, int n) {
+    if (blockIdx.x == 0 && (int)threadIdx.x < n) x[threadIdx.x] = 0;
 }
 
 __global__ void copy_rows(const float* src, float* dst, int64_t n) {
@@ -307,13 +343,13 @@ struct tmm_surrogate {
     __bf16 *dY, *dYt;               // [E][Bt][n_out], [E][n_out][Bt]
     __bf16 *dZa, *dZat, *dZb, *dZbt;  // ping-pong hidden gradients
     float *mean_buf, *sigma_buf;    // [Bt][n_out]
-    int* list;
-    int* count;
-    float* dc;
-    int32_t* matc;
-    float* Rc;
+    int* list;         // [Bt] stacks recomputed whole by the fallback
+    uint32_t* plist;   // [Bt * n_out] units recomputed one by one
+    int* count;        // [2]: stacks, units
+    float* dc;         // [Bt][n_in] gathered thicknesses
+    int32_t* matc;     // [Bt][n_in + 2] gathered material ids
+    float* Rc;         // [Bt][n_out] dense fallback output
     float* loss_part;  // [E][blocks of loss_grad] per-block partial losses
-    int fallback_L2;
 };
 
 namespace {
@@ -324,7 +360,7 @@ using tmm::ok;
 void free_all(tmm_surrogate* h) {
     void* ptrs[] = {h->W, h->Wm, h->Wv, h->Wg, h->b, h->bm, h->bv, h->bg, h->Wb, h->Wt, h->Xb, h->Xt,
                     h->Y, h->dY, h->dYt, h->dZa, h->dZat, h->dZb, h->dZbt, h->mean_buf, h->sigma_buf,
-                    h->list, h->count, h->dc, h->matc, h->Rc, h->loss_part};
+                    h->list, h->plist, h->count, h->dc, h->matc, h->Rc, h->loss_part};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     for (float* p : h->Z)
@@ -506,6 +542,8 @@ tmm_status tmm_surrogate_create(const tmm_surrogate_config* c, tmm_surrogate** o
         return fail(TMM_ERR_INVALID_ARG,
                     "tmm_surrogate_create: need n_in >= 1, n_hidden and n_out multiples of 128, n_layers >= 1, "
                     "n_members >= 1, max_batch a multiple of 128");
+    if ((int64_t)c->max_batch * c->n_out >= ((int64_t)1 << 32))
+        return fail(TMM_ERR_INVALID_ARG, "tmm_surrogate_create: max_batch * n_out must stay below 2^32");
     if (c->gemm_tile < 0 || c->gemm_tile > 3)
         return fail(TMM_ERR_INVALID_ARG, "tmm_surrogate_create: gemm_tile must be 0 (automatic), 1, 2 or 3");
     if (!(c->in_scale == c->in_scale) || !(c->lr >= 0.0f) || !(c->beta1 >= 0.0f && c->beta1 < 1.0f) ||
@@ -525,11 +563,11 @@ tmm_status tmm_surrogate_create(const tmm_surrogate_config* c, tmm_surrogate** o
     h->dY = h->dYt = h->dZa = h->dZat = h->dZb = h->dZbt = nullptr;
     h->mean_buf = h->sigma_buf = nullptr;
     h->list = h->count = nullptr;
+    h->plist = nullptr;
     h->dc = nullptr;
     h->matc = nullptr;
     h->Rc = nullptr;
     h->loss_part = nullptr;
-    h->fallback_L2 = 0;
     int64_t wo = 0, bo = 0;
     for (int l = 0; l < h->NL; ++l) {
         const int in = l == 0 ? h->in_pad : c->n_hidden;
@@ -550,8 +588,9 @@ tmm_status tmm_surrogate_create(const tmm_surrogate_config* c, tmm_surrogate** o
                dalloc(&h->Xt, Bt * h->in_pad) && dalloc(&h->Y, E * Bt * No) && dalloc(&h->dY, E * Bt * No) &&
                dalloc(&h->dYt, E * Bt * No) && dalloc(&h->dZa, E * Bt * Hd) && dalloc(&h->dZat, E * Bt * Hd) &&
                dalloc(&h->dZb, E * Bt * Hd) && dalloc(&h->dZbt, E * Bt * Hd) && dalloc(&h->mean_buf, Bt * No) &&
-               dalloc(&h->sigma_buf, Bt * No) && dalloc(&h->list, Bt) && dalloc(&h->count, 1) &&
-               dalloc(&h->dc, Bt * c->n_in) && dalloc(&h->Rc, Bt * No) &&
+               dalloc(&h->sigma_buf, Bt * No) && dalloc(&h->list, Bt) && dalloc(&h->count, 2) &&
+               dalloc(&h->plist, Bt * No) && dalloc(&h->dc, Bt * c->n_in) &&
+               dalloc(&h->matc, Bt * (c->n_in + 2)) && dalloc(&h->Rc, Bt * No) &&
                dalloc(&h->loss_part, E * (No / tmm::mlp::kTile) * (Bt / tmm::mlp::kTile));
     for (int l = 0; okk && l < c->n_layers; ++l) {
         float* z = nullptr;
@@ -717,7 +756,7 @@ tmm_status tmm_surrogate_predict(tmm_surrogate* h, const float* x, int32_t B, fl
 }
 
 tmm_status tmm_surrogate_predict_fallback(tmm_surrogate* h, const float* x, int32_t B, const tmm_rt_args* tmpl,
-                                          float err_scale, float bound, float* out, int32_t* n_fallback,
+                                          float err_scale, float bound, float* out, int64_t* n_fallback,
                                           void* stream) {
     tmm_status st = check_handle(h, "tmm_surrogate_predict_fallback");
     if (st != TMM_OK) return st;
@@ -730,48 +769,82 @@ tmm_status tmm_surrogate_predict_fallback(tmm_surrogate* h, const float* x, int3
                     "L = n_in layers, material ids, and P * n_theta * n_wl = n_out");
     if (!(err_scale >= 0.0f) || !(bound >= 0.0f))
         return fail(TMM_ERR_INVALID_ARG, "tmm_surrogate_predict_fallback: err_scale and bound must be >= 0");
+    {
+        tmm_rt_args tc = *tmpl;  // the template's own d and outputs are ignored
+        tc.d = x;
+        tc.R = out;
+        tc.T = tc.r = tc.t = nullptr;
+        tc.flags = 0;
+        st = tmm::check_rt_args(&tc, "tmm_surrogate_predict_fallback", true);
+        if (st != TMM_OK) return st;
+    }
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int L2 = tmpl->L + 2;
-    if (h->fallback_L2 < L2) {
-        if (h->matc) (void)hipFree(h->matc);
-        h->matc = nullptr;
-        if (!dalloc(&h->matc, (size_t)h->Bt * L2)) return fail(TMM_ERR_HIP, "tmm_surrogate_predict_fallback: alloc");
-        h->fallback_L2 = L2;
-    }
-    int total = 0;
+    const int units = tmpl->n_theta * tmpl->n_wl;
+    int64_t replaced = 0;
     (void)hipGetLastError();
     for (int b0 = 0; b0 < B; b0 += h->Bt) {
         const int nb = B - b0 < h->Bt ? B - b0 : h->Bt;
         const float* xc = x + (int64_t)b0 * h->cfg.n_in;
+        float* oc = out + (int64_t)b0 * No;
+        const int32_t* mc = tmpl->mat + (int64_t)b0 * L2;
         prep(h, xc, nb, s);
         forward(h, s, false);
         hipLaunchKernelGGL(tmm::mlp::ensemble_stats, dim3(grid1((int64_t)nb * No / 4)), dim3(256), 0, s, h->Y, h->E, nb,
-                           No, (int64_t)h->Bt * No, out + (int64_t)b0 * No, h->sigma_buf);
-        hipLaunchKernelGGL(tmm::mlp::zero_int, dim3(1), dim3(64), 0, s, h->count);
-        hipLaunchKernelGGL(tmm::mlp::flag_stacks, dim3((nb + 3) / 4), dim3(256), 0, s, h->sigma_buf, nb, No,
-                           err_scale, bound, h->list, h->count);
-        int nf = 0;
-        if (hipMemcpyAsync(&nf, h->count, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+                           No, (int64_t)h->Bt * No, oc, h->sigma_buf);
+        hipLaunchKernelGGL(tmm::mlp::zero_int, dim3(1), dim3(64), 0, s, h->count, 2);
+        hipLaunchKernelGGL(tmm::mlp::flag_units, dim3(nb), dim3(256), 0, s, h->sigma_buf, units, P, err_scale, bound,
+                           h->list, h->plist, h->count);
+        int cnt[2] = {0, 0};
+        if (hipMemcpyAsync(cnt, h->count, sizeof(cnt), hipMemcpyDeviceToHost, s) != hipSuccess ||
             hipStreamSynchronize(s) != hipSuccess)
             return fail(TMM_ERR_HIP, "tmm_surrogate_predict_fallback: count readback failed");
-        total += nf;
-        if (nf == 0) continue;
-        hipLaunchKernelGGL(tmm::mlp::gather_stacks, dim3(grid1((int64_t)nf * (h->cfg.n_in + L2))), dim3(256), 0, s,
-                           xc, tmpl->mat + (int64_t)b0 * L2, h->list, nf, h->cfg.n_in, L2, h->dc, h->matc);
-        tmm_rt_args a = *tmpl;
-        a.B = nf;
-        a.d = h->dc;
-        a.mat = h->matc;
-        a.R = h->Rc;
-        a.T = nullptr;
-        a.r = nullptr;
-        a.t = nullptr;
-        st = tmm_rt(&a, TMM_F32, stream);
-        if (st != TMM_OK) return st;
-        hipLaunchKernelGGL(tmm::mlp::scatter_outputs, dim3(grid1((int64_t)nf * No)), dim3(256), 0, s, h->Rc, h->list,
-                           nf, No, out + (int64_t)b0 * No);
+        const int nf = cnt[0], npt = cnt[1];
+        replaced += (int64_t)nf * No + (int64_t)npt * P;
+        if (nf > 0) {
+            // stacks flagged everywhere: the dense kernel on the gathered stacks
+            hipLaunchKernelGGL(tmm::mlp::gather_stacks, dim3(grid1((int64_t)nf * (h->cfg.n_in + L2))), dim3(256), 0, s,
+                               xc, mc, h->list, nf, h->cfg.n_in, L2, h->dc, h->matc);
+            tmm_rt_args a = *tmpl;
+            a.B = nf;
+            a.d = h->dc;
+            a.mat = h->matc;
+            a.R = h->Rc;
+            a.T = nullptr;
+            a.r = nullptr;
+            a.t = nullptr;
+            a.flags = 0;
+            st = tmm_rt(&a, TMM_F32, stream);
+            if (st != TMM_OK) return st;
+            hipLaunchKernelGGL(tmm::mlp::scatter_outputs, dim3(grid1((int64_t)nf * No)), dim3(256), 0, s, h->Rc,
+                               h->list, nf, No, oc);
+        }
+        if (npt > 0) {
+            // the flagged points of the other stacks, written in place into out
+            tmm::pts::PtParams<float> p;
+            p.B = nb;
+            p.L = tmpl->L;
+            p.n_wl = tmpl->n_wl;
+            p.n_theta = tmpl->n_theta;
+            p.d = xc;
+            p.nk = static_cast<const float*>(tmpl->nk);
+            p.n_mat = tmpl->n_mat;
+            p.dispersive = tmpl->dispersive;
+            p.mat = mc;
+            p.wl = static_cast<const float*>(tmpl->wl);
+            p.sin_t = static_cast<const float*>(tmpl->sin_theta);
+            p.cos_t = static_cast<const float*>(tmpl->cos_theta);
+            p.R_out = oc;
+            p.T_out = nullptr;
+            p.pts64 = nullptr;
+            p.pts32 = h->plist;
+            p.n_pts = npt;
+            p.n_dev = nullptr;
+            if (tmm::pts::launch_points<float>(p, tmpl->pol_mask, npt, s) != hipSuccess)
+                return tmm::check_launch("tmm_surrogate_predict_fallback");
+        }
     }
-    if (n_fallback) *n_fallback = total;
+    if (n_fallback) *n_fallback = replaced;
     return tmm::check_launch("tmm_surrogate_predict_fallback");
 }
 

@@ -5,6 +5,7 @@ import numpy as np
 import pytest
 
 from oracle import mlp
+from tests import mlp_envelope as env
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -32,14 +33,17 @@ def test_forward_matches_reference_every_member(tile):
     mean, sig, mem = sur.predict(torch.as_tensor(x, device="cuda"), members=True)
     mem = mem.cpu().numpy()
     dims = mlp.layer_dims(30, 256, 2, 256)
-    ys = []
+    ys, s2 = [], 0.0
     for e in range(sur.E):
-        y, _ = mlp.forward(params[e].astype(np.float64), x.astype(np.float64), dims, SHIFT, SCALE)
+        vec = params[e].astype(np.float64)
+        y, cache = mlp.forward(vec, x.astype(np.float64), dims, SHIFT, SCALE)
+        sy = env.output_sigma([mlp.bf16(W) for W in mlp.unpack(vec, dims)[0]], cache)
         ys.append(y)
-        scale = np.abs(y).max()
-        assert np.abs(mem[e] - y).max() <= 2e-3 * scale, (e, np.abs(mem[e] - y).max(), scale)
+        s2 = s2 + sy ** 2
+        # element by element, within the rounding model's spread
+        assert (np.abs(mem[e] - y) <= env.LAMBDA * sy).all(), (e, (np.abs(mem[e] - y) / sy).max())
     ys = np.array(ys)
-    assert np.abs(mean.cpu().numpy() - ys.mean(0)).max() <= 2e-3 * np.abs(ys).max()
+    assert (np.abs(mean.cpu().numpy() - ys.mean(0)) <= env.LAMBDA * np.sqrt(s2) / sur.E).all()
     assert np.abs(sig.cpu().numpy() - ys.std(0, ddof=1)).max() <= 4e-3 * np.abs(ys).max()
     sur.close()
 
@@ -49,11 +53,10 @@ def test_full_size_forward_sampled_rows():
     # 16384-row internal batch, the inference configuration: the hidden layers and
     # the output layer take the 256 x 256 eight-wave tile.  Rows are independent,
     # so 48 sampled rows of every member are checked against the reference.
-    # Tolerance: with the same bf16 rounding points, FP32 accumulation alone sends
-    # a few activations per layer to the neighbouring bf16 value; through five
-    # hidden layers of 1024 that moves the output by 1.5e-3 to 2.2e-3 of its scale
-    # (float32 against float64 accumulation of the reference on the CPU, five
-    # seeds), so the bound is 5e-3 of the scale (2e-3 for the two-layer nets above).
+    # Tolerance: element by element, LAMBDA standard deviations of the rounding
+    # model of tests/mlp_envelope.py (about 0.4 % of the output scale here); a
+    # float32-accumulating emulation of the kernels on the CPU stays within half
+    # a standard deviation.
     from paper_2111_13667_amd.surrogate import Surrogate
     sur = Surrogate(30, 8192, n_hidden=1024, n_layers=5, n_members=5, max_batch=16384, seed=11,
                     in_shift=SHIFT, in_scale=SCALE)
@@ -65,9 +68,10 @@ def test_full_size_forward_sampled_rows():
     params = sur.export()
     dims = mlp.layer_dims(30, 1024, 5, 8192)
     for e in range(sur.E):
-        y, _ = mlp.forward(params[e].astype(np.float64), x[rows].astype(np.float64), dims, SHIFT, SCALE)
-        scale = np.abs(y).max()
-        assert np.abs(mem[e] - y).max() <= 5e-3 * scale, (e, np.abs(mem[e] - y).max(), scale)
+        vec = params[e].astype(np.float64)
+        y, cache = mlp.forward(vec, x[rows].astype(np.float64), dims, SHIFT, SCALE)
+        sy = env.output_sigma([mlp.bf16(W) for W in mlp.unpack(vec, dims)[0]], cache)
+        assert (np.abs(mem[e] - y) <= env.LAMBDA * sy).all(), (e, (np.abs(mem[e] - y) / sy).max())
     sur.close()
 
 
@@ -81,16 +85,16 @@ def test_gradients_match_reference(tile):
     params = sur.export()
     dims = mlp.layer_dims(30, 256, 2, 256)
     for e in range(sur.E):
-        ref = mlp.backward(params[e].astype(np.float64), x.astype(np.float64), t.astype(np.float64), dims,
-                           SHIFT, SCALE)
-        # compare layer by layer (weights and biases)
-        o = 0
-        for i, out in zip(*dims):
-            a, b = g[e][o:o + i * out], ref[o:o + i * out]
-            assert np.linalg.norm(a - b) <= 1e-2 * np.linalg.norm(b), (e, i, out)
-            o += i * out
-        a, b = g[e][o:], ref[o:]
-        assert np.linalg.norm(a - b) <= 1e-2 * np.linalg.norm(b)
+        vec = params[e].astype(np.float64)
+        ref, y, cache, back = mlp.backward(vec, x.astype(np.float64), t.astype(np.float64), dims, SHIFT, SCALE,
+                                           intermediates=True)
+        Ws, bs = mlp.unpack(vec, dims)
+        sg, _ = env.sigmas([mlp.bf16(W) for W in Ws], bs, y, cache, back)
+        # every weight and bias gradient, element by element (padded input columns: exactly 0)
+        err = np.abs(g[e] - ref)
+        assert (err <= env.LAMBDA * sg).all(), (e, int(np.argmax(err / np.maximum(sg, 1e-300))),
+                                                (err / np.maximum(sg, 1e-300)).max())
+        assert np.median(sg / np.maximum(np.abs(ref), 1e-300)) < 0.05   # the tolerance is tight
     sur.close()
 
 
@@ -131,10 +135,22 @@ def test_training_gains_over_the_mean_spectrum():
     sur.close()
 
 
+def _units_flagged(sigma, scale, bound, task):
+    # a unit = (stack, angle, wavelength) with both polarisations
+    P = 2
+    flag = ~(sigma * scale <= bound)
+    return flag.view(-1, P, task.n_theta * task.n_wl).any(dim=1)
+
+
 def test_fallback_keeps_the_bound():
-    # 30-layer task, untrained ensemble: calibration on a set, then on the same
-    # set max |out - tmm| <= bound; err_scale = inf recomputes every stack
-    # (exactly the float32 TMM values), err_scale = 0 none (exactly the mean).
+    # 30-layer task, untrained ensemble.  (a) The point-level scale calibrated
+    # on a set keeps max |out - tmm| <= bound on that set.  (b) The mechanism at
+    # a scale that flags all but 1e-4 of the outputs: about half the stacks are
+    # flagged everywhere (dense kernel on the gathered stacks), the others in
+    # part (point kernel, in place); unflagged units keep exactly the ensemble
+    # mean, flagged units get the float32 transfer-matrix values, and P outputs
+    # are replaced per flagged unit.  (c) err_scale = inf recomputes
+    # everything, err_scale = 0 nothing.
     from paper_2111_13667_amd import surrogate as S
     task = S.make_task()
     rng = np.random.default_rng(3)
@@ -144,13 +160,58 @@ def test_fallback_keeps_the_bound():
     sur = S.Surrogate(30, task.n_out, n_hidden=256, n_layers=2, n_members=3, max_batch=512, seed=2,
                       in_shift=SHIFT, in_scale=SCALE)
     mean, sigma, _ = sur.predict(x)
-    bound = 1e-3
+    bound = 0.2
     scale, frac = S.calibrate(mean, sigma, y, bound)
     out, nf = sur.predict_fallback(x, task, scale, bound)
-    assert nf == n - int(round(frac * n))
     assert (out - y).abs().max().item() <= bound
+    umax = sigma.view(n, 2, -1).amax(dim=1)   # a unit is kept only if both polarisations are
+    scale = bound / torch.quantile(umax.flatten(), 1e-4).item()
+    out, nf = sur.predict_fallback(x, task, scale, bound)
+    units = _units_flagged(sigma, scale, bound, task)
+    whole = units.all(dim=1)
+    assert 0 < int(whole.sum()) < n and int(units.sum()) < units.numel()
+    assert nf == 2 * int(units.sum().item())
+    uf = units[:, None, :].expand(n, 2, units.shape[1]).reshape(n, -1)
+    assert torch.equal(out[~uf], mean[~uf])
+    assert (out[uf] - y[uf]).abs().max().item() <= 4e-5
     out_all, nf_all = sur.predict_fallback(x, task, float("inf"), bound)
-    assert nf_all == n and torch.equal(out_all, y)
+    assert nf_all == n * task.n_out and torch.equal(out_all, y)
     out_none, nf_none = sur.predict_fallback(x, task, 0.0, bound)
     assert nf_none == 0 and torch.equal(out_none, mean)
+    sur.close()
+
+
+def test_trained_fallback_keeps_the_bound_on_held_out_data():
+    # A one-layer instance of the surrogate task (64 wavelengths x 4 angles x
+    # 2 pol) trained by the project's kernels to a held-out mean error of a few
+    # 1e-4: the point-level error scale fitted on a calibration split (margin
+    # 0.5), applied to held-out stacks, leaves every output within 1e-3 of the
+    # float64 transfer-matrix value after the fallback.  (The ensemble spread is
+    # a weak certificate: even here, where most outputs are within 1e-3, the
+    # smallest spread among the calibration outputs that miss the bound is so
+    # small that almost nothing is accepted -- the measured fraction is printed.)
+    from paper_2111_13667_amd import surrogate as S
+    task = S.make_task(L=1, n_wl=64, n_theta=4)
+    task64 = S.make_task("f64", L=1, n_wl=64, n_theta=4)
+    rng = np.random.default_rng(0)
+    n_train, n_cal, n_test = 65536, 8192, 8192
+    d = torch.as_tensor(rng.uniform(20, 250, (n_train + n_cal + n_test, 1)), dtype=torch.float32, device="cuda")
+    y = S.generate(task, d)
+    sur = S.Surrogate(1, task.n_out, n_hidden=256, n_layers=3, n_members=4, max_batch=1024, seed=1,
+                      in_shift=SHIFT, in_scale=SCALE)
+    S.train(sur, d[:n_train], y[:n_train], epochs=200, batch=1024, lr_max=2e-3)
+    xc, yc = d[n_train:n_train + n_cal], y[n_train:n_train + n_cal]
+    xt, yt = d[n_train + n_cal:], y[n_train + n_cal:]
+    mt, _, _ = sur.predict(xt)
+    mae = (mt - yt).abs().mean().item()
+    mc, sc, _ = sur.predict(xc)
+    bound = 1e-3
+    scale, frac_cal = S.calibrate(mc, sc, yc, bound, margin=0.5)
+    out, nf = sur.predict_fallback(xt, task, scale, bound)
+    y64 = S.generate(task64, xt.double())
+    err = (out.double() - y64).abs().max().item()
+    print("held-out MAE", mae, "calibration accepted", frac_cal, "held-out accepted", 1.0 - nf / out.numel(),
+          "max error after fallback", err)
+    assert mae < 2e-3
+    assert err <= bound
     sur.close()
