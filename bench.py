@@ -168,9 +168,13 @@ def time_ragged(dtype="f64", steps=10):
     real = dev[3].dtype
     R = torch.empty(plan.output_size, dtype=real, device="cuda")
     T = torch.empty(plan.output_size, dtype=real, device="cuda")
+    t0 = time.perf_counter()
     plan.run(*dev, R=R, T=T)  # tunes
     torch.cuda.synchronize()
-    ms = _event_time(lambda: plan.run(*dev, R=R, T=T), steps, 1)
+    tune_s = time.perf_counter() - t0
+    shape = plan.shape(dtype)
+    rms, _ = launch_times(lambda: plan.run(*dev, R=R, T=T), steps, 1)
+    ms = float(np.median(rms))
     st = torch.cuda.Stream()
     with torch.cuda.stream(st):
         plan.capture(*dev, R=R, T=T, stream=st)
@@ -179,7 +183,8 @@ def time_ragged(dtype="f64", steps=10):
     layer_steps = int(((np.diff(rw.layer_off) + 1) * np.diff(rw.wl_off) * np.diff(rw.th_off)).sum()) * 2
     plan.close()
     return {"workload": f"ragged_batch: 8192 stacks, 2-100 layers, 256-2048 wl, 1-64 angles, s+p, {dtype}",
-            "points": rw.n_points, "ms": round(ms, 3), "graph_ms": round(gms, 3),
+            "points": rw.n_points, "ms": round(ms, 3), "timing": summary(rms), "graph_ms": round(gms, 3),
+            "autotuned_shape": shape, "first_run_with_tuning_s": round(tune_s, 3),
             "points_per_s": round(rw.n_points / (ms * 1e-3), 1),
             "algorithmic_TFLOPs": round(layer_steps * FLOPS_PER_POINT_STEP / (ms * 1e-3) / 1e12, 2),
             "frac_of_valu_peak": round(layer_steps * FLOPS_PER_POINT_STEP / (ms * 1e-3) / 1e12

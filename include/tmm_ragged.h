@@ -11,10 +11,14 @@
  * is what a ragged batch serves.
  *
  * A plan is made once per batch shape from host copies of three offset
- * arrays; it owns device copies of them, the work list (units of one stack x
- * one angle x 64 wavelengths, longest stacks first) and the launch shape an
- * autotuner picks on the first run (timing a few shapes on the real data and
- * caching the winner per (dtype, polarisation, mean layer count, size)).
+ * arrays; it owns device copies of them, the work lists and the launch shape
+ * an autotuner picks on the first run (timing a few shapes on the real data
+ * and caching the winner per (dtype, polarisation, mean layer count, size)).
+ * A work unit is a tile of consecutive (angle, wavelength) points of one
+ * stack, longest stacks first.  The autotuner chooses the workgroup shape, the
+ * units taken per counter update, and the lanes per point: 1 (64-point
+ * tiles), or 2 / 4 (32- / 16-point tiles, the stack's layers split across the
+ * lanes of a point and their 2x2 transfer operators composed across lanes).
  */
 #ifndef TMM_RAGGED_H
 #define TMM_RAGGED_H
@@ -78,8 +82,25 @@ tmm_status tmm_ragged_plan_output_offsets(const tmm_ragged_plan *plan, int64_t *
 
 /* Evaluate every stack: asynchronous on the stream, except that the first run
  * of a plan for a dtype (when the shape is not cached yet) times several launch
- * shapes and synchronises; every one of those launches writes the full output. */
+ * shapes and synchronises; every one of those launches writes the full output,
+ * and the output left is that of the chosen shape (the same bits as later runs). */
 tmm_status tmm_ragged_run(tmm_ragged_plan *plan, const tmm_ragged_data *data, tmm_dtype dtype, void *stream);
+
+/* The same call under the name of the paper-style entry points (tmm_rt,
+ * tmm_rt_grad, tmm_rt_points): ragged batches of the section "Environment"
+ * (stacks of varying length). */
+tmm_status tmm_rt_ragged(tmm_ragged_plan *plan, const tmm_ragged_data *data, tmm_dtype dtype, void *stream);
+
+/* The launch shape the autotuner chose for dtype (after the first run):
+ * host_shape[4] = {workgroups per CU, units per counter update, waves per
+ * workgroup, lanes per point}.  TMM_ERR_INVALID_ARG before tuning. */
+tmm_status tmm_ragged_plan_shape(const tmm_ragged_plan *plan, tmm_dtype dtype, int32_t *host_shape);
+
+/* Set the launch shape for dtype instead of tuning (same layout as above).
+ * The LDS of a workgroup must fit the CU (8 KiB phase table plus 2 KiB per
+ * index-table row and wave); an oversized shape fails at launch with
+ * TMM_ERR_HIP. */
+tmm_status tmm_ragged_plan_set_shape(tmm_ragged_plan *plan, tmm_dtype dtype, const int32_t *host_shape);
 
 /* Capture the run (counter reset + persistent kernel) into a HIP graph owned by
  * the plan, replacing any earlier capture; tunes first if needed.  stream must

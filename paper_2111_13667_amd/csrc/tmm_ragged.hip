@@ -1,16 +1,25 @@
 // Ragged batches: stacks with different layer counts, wavelength grids and
 // angle grids in one persistent launch (gfx950), behind a plan object that
-// owns the work list, the autotuned launch shape and an optional HIP graph.
+// owns the work lists, the autotuned launch shape and an optional HIP graph.
 //
-// Work unit = (stack, angle, tile of 64 wavelengths); one wave evaluates one
-// unit (both polarisations, one lane per wavelength) with the same recursion
-// as the dense kernel (tmm_chain.hpp).  Units are ordered by decreasing layer
-// count (longest chains first) and handed out through an atomic counter, so
-// the wave that finishes early takes the next unit: load balance does not
-// depend on how the stacks are mixed.  For every unit the wave computes
-// q, eta of each index-table row at its 64 wavelengths into its own LDS slice
-// (a handful of complex square roots per lane), then runs the layer loop on
-// table lookups.
+// A stack's points (angle k, wavelength i) are numbered f = k * n_wl + i, the
+// order of its output block.  A work unit is one tile of consecutive points of
+// one stack: 64 points at one lane per point, or 32 / 16 points when two or
+// four lanes share a point (layer split, below).  Units are ordered by
+// decreasing layer count (longest chains first) and handed out through an
+// atomic counter, so a wave that finishes early takes the next unit.  For
+// every unit each lane computes q, eta of each index-table row at its own
+// (wavelength, angle) into the wave's LDS slice, then runs the layer loop of
+// the dense kernels (tmm_chain.hpp) on table lookups; the stack's layer data
+// are wave-uniform.
+//
+// Layer split (LPP = 2 or 4 lanes per point): the stack's layers are cut into
+// LPP contiguous segments; lane s of a point's group runs segment s as a 2x2
+// operator (the recursion applied to the two unit states, one renormalisation
+// exponent for both columns), and the group then composes the operators
+// bottom-up across its lanes (substrate side first) and the top lane finishes
+// the point.  Twice the arithmetic per layer, a fraction of the latency: for
+// batches with few points per stack.
 //
 // The plan keeps its own device copies of the offsets it was created with,
 // so the kernel never reads a caller's offset array.
@@ -32,12 +41,13 @@
 namespace tmm {
 namespace ragged {
 
-// Every wave works on its own units with its own media table and layer staging;
-// a workgroup is 1-12 such waves plus the shared phase table, sized at launch
-// so that the CU's resident waves fit its LDS.
+// Every wave works on its own units with its own media table; a workgroup is
+// 1-12 such waves plus the shared phase table, sized at launch so that the
+// CU's resident waves fit its LDS.
 constexpr int kMaxThreads = 768;
 constexpr int kMaxMat = 8;
 constexpr size_t kLdsPerCU = 160 * 1024;
+constexpr int kLppChoices[3] = {1, 2, 4};
 
 template <typename R>
 struct Params {
@@ -57,15 +67,16 @@ struct Params {
     int64_t nk_stride;  // wl_off[B]
     R* R_out;
     R* T_out;
-    const int2* units;
+    const int32_t* unit_stack;   // stack of each unit (units of a stack are consecutive)
+    const int64_t* stack_first;  // [B] first unit of each stack
     int64_t n_units;
     unsigned long long* counter;
     int grain;
 };
 
-// Per-wave media table: q and eta of every index-table row at the wave's 64
-// wavelengths (|q|^2 and |eta|^2 are recomputed in the loop, which keeps the
-// slice at 32 bytes per (row, lane) and the occupancy up).  One block per row:
+// Per-wave media table: q and eta of every index-table row at each lane's own
+// point (|q|^2 and |eta|^2 are recomputed in the loop, which keeps the slice at
+// 32 bytes per (row, lane) and the occupancy up).  One block per row:
 // FP64 [q (double2)][eta (double2)]; FP32 [q in double (double2)][q (float2)][eta (float2)].
 template <typename R> struct WaveTable;
 
@@ -127,7 +138,70 @@ __global__ void reset_counter(unsigned long long* c) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *c = 0ull;
 }
 
+// The recursion applied to two states at once (the columns of a segment's
+// operator in the (sigma, tau) basis), with one exponent per polarisation for
+// both columns.
 template <typename R, int POL>
+struct Operator {
+    Chain<R, POL, false> c0, c1;  // column 0 from (1, 0), column 1 from (0, 1); c0 holds es, ep, pis, pip, S
+    __device__ __forceinline__ void init() {
+        c0.init();
+        c1.init();
+        c0.ts = c0.tp = {(R)0, (R)0};
+        c1.ss = c1.sp = {(R)0, (R)0};
+    }
+    __device__ __forceinline__ void step(const Layer<R>& cur, const Layer<R>& nxt, double cd, bool lossy,
+                                         const TabPhase<R>& phase) {
+        const double phr = cd * cur.pr;
+        const double phi = cd * cur.pi;
+        const cx<R> E = phase(phr, phi, lossy);
+        col(c0, cur, nxt, E);
+        col(c1, cur, nxt, E);
+        if (POL & 1) c0.pis *= cur.q2;
+        if (POL & 2) c0.pip *= cur.e2;
+        c0.S += phi;
+    }
+    __device__ __forceinline__ static void col(Chain<R, POL, false>& c, const Layer<R>& cur, const Layer<R>& nxt,
+                                               const cx<R>& E) {
+        if (POL & 1) {
+            const cx<R> A = cmul(cur.q, c.ss), Bv = cmul(nxt.q, c.ts);
+            const cx<R> a = cadd(A, Bv), b = csub(A, Bv);
+            const cx<R> Eb = cmul(E, b);
+            c.ss = cadd(a, Eb);
+            c.ts = csub(a, Eb);
+        }
+        if (POL & 2) {
+            const cx<R> A = cmul(nxt.e, c.sp), Bv = cmul(cur.e, c.tp);
+            const cx<R> a = cadd(A, Bv), b = csub(A, Bv);
+            const cx<R> Eb = cmul(E, b);
+            c.sp = cadd(a, Eb);
+            c.tp = csub(a, Eb);
+        }
+    }
+    __device__ __forceinline__ void renorm() {
+        if (POL & 1) renorm_joint(c0.ss, c0.ts, c1.ss, c1.ts, c0.es);
+        if (POL & 2) renorm_joint(c0.sp, c0.tp, c1.sp, c1.tp, c0.ep);
+        if (POL & 1) renorm_one(c0.pis, c0.epis);
+        if (POL & 2) renorm_one(c0.pip, c0.epip);
+    }
+    __device__ __forceinline__ static void renorm_joint(cx<R>& a, cx<R>& b, cx<R>& c, cx<R>& d, int& e) {
+        const R m = fmax(fmax(fmax(fabs(a.re), fabs(a.im)), fmax(fabs(b.re), fabs(b.im))),
+                         fmax(fmax(fabs(c.re), fabs(c.im)), fmax(fabs(d.re), fabs(d.im))));
+        const int k = frexp_exp(m);
+        a.re = ldexp_(a.re, -k); a.im = ldexp_(a.im, -k);
+        b.re = ldexp_(b.re, -k); b.im = ldexp_(b.im, -k);
+        c.re = ldexp_(c.re, -k); c.im = ldexp_(c.im, -k);
+        d.re = ldexp_(d.re, -k); d.im = ldexp_(d.im, -k);
+        e += k;
+    }
+};
+
+template <typename R>
+__device__ __forceinline__ cx<R> shfl_down_cx(cx<R> v, int d) {
+    return {__shfl_down(v.re, d, kWave), __shfl_down(v.im, d, kWave)};
+}
+
+template <typename R, int POL, int LPP>
 __global__ void __launch_bounds__(kMaxThreads) ragged_kernel(Params<R> p) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int lane = threadIdx.x & (kWave - 1);
@@ -138,6 +212,9 @@ __global__ void __launch_bounds__(kMaxThreads) ragged_kernel(Params<R> p) {
     unsigned char* my = smem + phase_tab_bytes<R>() + (size_t)wave * wave_lds_bytes(p.n_mat);
     WaveTable<R> tab(my);
     constexpr int P = (POL == 3) ? 2 : 1;
+    constexpr int PPW = kWave / LPP;  // points per unit (the tile)
+    const int pt = lane / LPP;        // this lane's point within the unit
+    const int seg = lane % LPP;       // and its layer segment (0 = ambient side)
     for (;;) {
         unsigned long long base = 0;
         if (lane == 0) base = atomicAdd(p.counter, (unsigned long long)p.grain);
@@ -146,19 +223,20 @@ __global__ void __launch_bounds__(kMaxThreads) ragged_kernel(Params<R> p) {
         for (int g = 0; g < p.grain; ++g) {
             const int64_t u = (int64_t)base + g;
             if (u >= p.n_units) break;
-            const int2 ud = p.units[u];
-            const int b = __builtin_amdgcn_readfirstlane(ud.x);
-            const int k = __builtin_amdgcn_readfirstlane(ud.y >> 16);
-            const int tile = __builtin_amdgcn_readfirstlane(ud.y & 0xffff);
+            const int b = __builtin_amdgcn_readfirstlane(p.unit_stack[u]);
+            const int64_t tile = u - p.stack_first[b];
             const int64_t l0 = p.layer_off[b];
             const int L = (int)(p.layer_off[b + 1] - l0);
             const int64_t w0 = p.wl_off[b];
             const int nwl = (int)(p.wl_off[b + 1] - w0);
             const int64_t t0 = p.th_off[b];
             const int nth = (int)(p.th_off[b + 1] - t0);
-            const int i_raw = tile * kWave + lane;
-            const bool active = i_raw < nwl;
-            const int i = active ? i_raw : nwl - 1;
+            const int64_t npts = (int64_t)nth * nwl;
+            const int64_t f_raw = tile * PPW + pt;
+            const bool active = f_raw < npts;
+            const int64_t f = active ? f_raw : npts - 1;
+            const int k = (int)(f / nwl);
+            const int i = (int)(f - (int64_t)k * nwl);
             const int64_t col = w0 + i;  // column of this lane's wavelength in nk
             const double lam = (double)p.wl[col];
             const bool lam_ok = lam > 0.0 && lam < __builtin_inf();
@@ -170,7 +248,7 @@ __global__ void __launch_bounds__(kMaxThreads) ragged_kernel(Params<R> p) {
             s_row = min(max(s_row, 0), p.n_mat - 1);
             const Ambient amb = make_ambient((double)p.nk[2 * ((int64_t)a_row * p.nk_stride + col)],
                                              (double)p.nk[2 * ((int64_t)a_row * p.nk_stride + col) + 1], st, ct);
-            // this unit's media table: every row at this lane's wavelength
+            // this unit's media table: every row at this lane's point
             uint32_t lossy_mask = 0;
             for (int m = 0; m < p.n_mat; ++m) {
                 const int64_t e = (int64_t)m * p.nk_stride + col;
@@ -184,53 +262,141 @@ __global__ void __launch_bounds__(kMaxThreads) ragged_kernel(Params<R> p) {
             const R* drow = p.d + l0;
             const int32_t* mrow = p.mat + l0;
             const Layer<R> sub = tab.get(s_row, lane);
-            int nxt_row = s_row;  // the layer below, as its table row (re-read from LDS per step)
             Chain<R, POL, false> c;
-            c.init();
+            int first_row = s_row;  // table row of layer 1 (the substrate for L = 0)
             constexpr int RP = RenormPeriod<R>::value;
-            static_assert(kWave % RP == 0, "chunks must hold whole renormalisation blocks");
-            for (int top = L; top >= 1; top -= kWave) {
-                const int lo = top - kWave + 1 > 1 ? top - kWave + 1 : 1;
-                // lane l holds layer lo + l (thickness, table row); the loop broadcasts them
-                const int j = lo + lane;
-                double my_d = 0.0;
-                int my_m = 0;
-                bool lane_bad = false;
-                if (j <= top) {
-                    const R dj = drow[j - 1];
-                    const int m = mrow[j - 1];
-                    lane_bad = bad_thickness(dj) || (uint32_t)m >= (uint32_t)p.n_mat;
-                    my_d = (double)dj;
-                    my_m = min(max(m, 0), p.n_mat - 1);
-                }
-                bad = bad || __any(lane_bad);
-                auto step = [&](int jj) {
-                    const int sl = jj - lo;
-                    const int m = __builtin_amdgcn_readlane(my_m, sl);
-                    const double dj = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(my_d), sl),
-                                                       __builtin_amdgcn_readlane(__double2loint(my_d), sl));
-                    c.step(tab.get(m, lane), tab.get(nxt_row, lane), dj * c4lam, (lossy_mask >> m) & 1u, phase);
-                    nxt_row = m;
-                };
-                // renormalisation blocks at the points of a running step count
-                for (int bt = top; bt >= lo; bt -= RP) {
-                    if (bt - lo >= RP - 1) {
+            if constexpr (LPP == 1) {
+                int nxt_row = s_row;  // the layer below, as its table row (re-read from LDS per step)
+                c.init();
+                static_assert(kWave % RP == 0, "chunks must hold whole renormalisation blocks");
+                for (int top = L; top >= 1; top -= kWave) {
+                    const int lo = top - kWave + 1 > 1 ? top - kWave + 1 : 1;
+                    // lane l holds layer lo + l (thickness, table row); the loop broadcasts them
+                    const int j = lo + lane;
+                    double my_d = 0.0;
+                    int my_m = 0;
+                    bool lane_bad = false;
+                    if (j <= top) {
+                        const R dj = drow[j - 1];
+                        const int m = mrow[j - 1];
+                        lane_bad = bad_thickness(dj) || (uint32_t)m >= (uint32_t)p.n_mat;
+                        my_d = (double)dj;
+                        my_m = min(max(m, 0), p.n_mat - 1);
+                    }
+                    bad = bad || __any(lane_bad);
+                    auto step = [&](int jj) {
+                        const int sl = jj - lo;
+                        const int m = __builtin_amdgcn_readlane(my_m, sl);
+                        const double dj = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(my_d), sl),
+                                                           __builtin_amdgcn_readlane(__double2loint(my_d), sl));
+                        c.step(tab.get(m, lane), tab.get(nxt_row, lane), dj * c4lam, (lossy_mask >> m) & 1u, phase);
+                        nxt_row = m;
+                    };
+                    // renormalisation blocks at the points of a running step count
+                    for (int bt = top; bt >= lo; bt -= RP) {
+                        if (bt - lo >= RP - 1) {
 #pragma unroll 2
-                        for (int u = 0; u < RP; ++u) step(bt - u);
-                        c.renorm();
-                    } else {
-                        for (int jj = bt; jj >= lo; --jj) step(jj);
+                            for (int uu = 0; uu < RP; ++uu) step(bt - uu);
+                            c.renorm();
+                        } else {
+                            for (int jj = bt; jj >= lo; --jj) step(jj);
+                        }
                     }
                 }
+                c.renorm();
+                first_row = nxt_row;
+            } else {
+                // segment seg of the layers: [lo_s, hi_s], equal lengths from the top
+                const int ns = (L + LPP - 1) / LPP;
+                const int lo_s = 1 + seg * ns;
+                const int hi_s = min(L, lo_s + ns - 1);
+                Operator<R, POL> op;
+                op.init();
+                int nxt_row = s_row;
+                if (hi_s < L) {
+                    const int m = mrow[hi_s];  // layer hi_s + 1
+                    bad = bad || (uint32_t)m >= (uint32_t)p.n_mat;
+                    nxt_row = min(max(m, 0), p.n_mat - 1);
+                }
+                int cnt = 0;
+                for (int uu = 0; uu < ns; ++uu) {
+                    const int j = hi_s - uu;
+                    if (j >= lo_s) {
+                        const R dj = drow[j - 1];
+                        const int m_raw = mrow[j - 1];
+                        bad = bad || bad_thickness(dj) || (uint32_t)m_raw >= (uint32_t)p.n_mat;
+                        const int m = min(max(m_raw, 0), p.n_mat - 1);
+                        op.step(tab.get(m, lane), tab.get(nxt_row, lane), (double)dj * c4lam,
+                                (lossy_mask >> m) & 1u, phase);
+                        nxt_row = m;
+                        if (++cnt == RP) {
+                            op.renorm();
+                            cnt = 0;
+                        }
+                    }
+                }
+                op.renorm();
+                bad = __any(bad);
+                // state at the top of this segment for the substrate-side input (1, 1)
+                // of the bottom segment: compose bottom-up across the group
+                c = op.c0;  // exponents, products and phase sums of this segment
+                if (POL & 1) {
+                    c.ss = cadd(op.c0.ss, op.c1.ss);
+                    c.ts = cadd(op.c0.ts, op.c1.ts);
+                }
+                if (POL & 2) {
+                    c.sp = cadd(op.c0.sp, op.c1.sp);
+                    c.tp = cadd(op.c0.tp, op.c1.tp);
+                }
+                for (int r = LPP - 2; r >= 0; --r) {
+                    // lane seg = r takes the state reached below it (lane seg + 1) through its operator
+                    Chain<R, POL, false> v = c;
+                    if (POL & 1) {
+                        v.ss = shfl_down_cx(c.ss, 1);
+                        v.ts = shfl_down_cx(c.ts, 1);
+                        v.es = __shfl_down(c.es, 1, kWave);
+                        v.pis = __shfl_down(c.pis, 1, kWave);
+                        v.epis = __shfl_down(c.epis, 1, kWave);
+                    }
+                    if (POL & 2) {
+                        v.sp = shfl_down_cx(c.sp, 1);
+                        v.tp = shfl_down_cx(c.tp, 1);
+                        v.ep = __shfl_down(c.ep, 1, kWave);
+                        v.pip = __shfl_down(c.pip, 1, kWave);
+                        v.epip = __shfl_down(c.epip, 1, kWave);
+                    }
+                    v.S = __shfl_down(c.S, 1, kWave);
+                    if (seg == r) {
+                        if (POL & 1) {
+                            c.ss = cadd(cmul(op.c0.ss, v.ss), cmul(op.c1.ss, v.ts));
+                            c.ts = cadd(cmul(op.c0.ts, v.ss), cmul(op.c1.ts, v.ts));
+                            c.es = op.c0.es + v.es;
+                            c.pis = op.c0.pis * v.pis;
+                            c.epis = op.c0.epis + v.epis;
+                        }
+                        if (POL & 2) {
+                            c.sp = cadd(cmul(op.c0.sp, v.sp), cmul(op.c1.sp, v.tp));
+                            c.tp = cadd(cmul(op.c0.tp, v.sp), cmul(op.c1.tp, v.tp));
+                            c.ep = op.c0.ep + v.ep;
+                            c.pip = op.c0.pip * v.pip;
+                            c.epip = op.c0.epip + v.epip;
+                        }
+                        c.S = op.c0.S + v.S;
+                        c.renorm();
+                    }
+                }
+                if (L >= 1) {
+                    const int m = mrow[0];
+                    first_row = min(max(m, 0), p.n_mat - 1);
+                }
             }
-            c.renorm();
             PointOut out[2];
-            finish<R, POL, false>(c, amb, tab.get(nxt_row, lane), sub, 0.0, 0.0, L, out, phase);
-            if (active) {
+            finish<R, POL, false>(c, amb, tab.get(first_row, lane), sub, 0.0, 0.0, L, out, phase);
+            if (active && seg == 0) {
                 const bool valid = lam_ok && amb.ok && !bad;
                 const double nan = __builtin_nan("");
                 for (int q = 0; q < P; ++q) {
-                    const int64_t o = p.out_off[b] + ((int64_t)q * nth + k) * nwl + i;
+                    const int64_t o = p.out_off[b] + (int64_t)q * npts + f;
                     if (p.R_out) p.R_out[o] = (R)(valid ? out[q].R : nan);
                     if (p.T_out) p.T_out[o] = (R)(valid ? out[q].T : nan);
                 }
@@ -244,12 +410,16 @@ __global__ void __launch_bounds__(kMaxThreads) ragged_kernel(Params<R> p) {
 }
 
 // Launch shape chosen by the autotuner: workgroups per CU, units taken per
-// counter update, waves per workgroup.
+// counter update, waves per workgroup, lanes per point (1, 2 or 4; the unit
+// then covers 64, 32 or 16 points).
 struct Shape {
     int blocks_per_cu;
     int grain;
     int waves;
+    int lpp;
 };
+
+inline int lpp_index(int lpp) { return lpp == 1 ? 0 : (lpp == 2 ? 1 : 2); }
 
 template <typename R>
 size_t shape_lds(int n_mat, int waves) {
@@ -274,7 +444,7 @@ std::vector<Shape> candidate_shapes(int n_mat) {
             best = total;
             out.clear();
         }
-        if (total == best && out.size() < 3) out.push_back({per_cu, 1, waves});
+        if (total == best && out.size() < 3) out.push_back({per_cu, 1, waves, 1});
     }
     return out;
 }
@@ -291,10 +461,11 @@ struct tmm_ragged_plan {
     uint32_t pol_mask;
     int P;
     std::vector<int64_t> layer_off, wl_off, th_off, out_off;
-    int64_t n_units;
+    int64_t n_units[3];     // per lanes-per-point choice (1, 2, 4)
     int64_t out_size;
     int64_t*d_layer_off, *d_wl_off, *d_th_off, *d_out_off;
-    int2* d_units;
+    int32_t* d_unit_stack[3];
+    int64_t* d_stack_first[3];
     unsigned long long* d_counter;
     int n_cu;
     bool tuned[2];
@@ -328,26 +499,43 @@ tmm::ragged::Params<R> make_params(const tmm_ragged_plan* pl, const tmm_ragged_d
     p.nk_stride = pl->wl_off[pl->B];
     p.R_out = static_cast<R*>(a->R);
     p.T_out = static_cast<R*>(a->T);
-    p.units = pl->d_units;
-    p.n_units = pl->n_units;
+    p.unit_stack = pl->d_unit_stack[0];
+    p.stack_first = pl->d_stack_first[0];
+    p.n_units = pl->n_units[0];
     p.counter = pl->d_counter;
     p.grain = 1;
     return p;
 }
 
+template <typename R, int POL, int LPP>
+void launch_one(const tmm::ragged::Params<R>& p, int blocks, dim3 threads, size_t lds, hipStream_t s) {
+    hipLaunchKernelGGL((tmm::ragged::ragged_kernel<R, POL, LPP>), dim3(blocks), threads, lds, s, p);
+}
+
+template <typename R, int POL>
+void launch_pol(const tmm::ragged::Params<R>& p, int lpp, int blocks, dim3 threads, size_t lds, hipStream_t s) {
+    if (lpp == 1) launch_one<R, POL, 1>(p, blocks, threads, lds, s);
+    else if (lpp == 2) launch_one<R, POL, 2>(p, blocks, threads, lds, s);
+    else launch_one<R, POL, 4>(p, blocks, threads, lds, s);
+}
+
 template <typename R>
 hipError_t launch(const tmm_ragged_plan* pl, tmm::ragged::Params<R> p, tmm::ragged::Shape sh, hipStream_t s) {
+    const int li = tmm::ragged::lpp_index(sh.lpp);
     p.grain = sh.grain;
+    p.unit_stack = pl->d_unit_stack[li];
+    p.stack_first = pl->d_stack_first[li];
+    p.n_units = pl->n_units[li];
     const size_t lds = tmm::ragged::shape_lds<R>(p.n_mat, sh.waves);
     const int blocks = pl->n_cu * sh.blocks_per_cu;
     const dim3 threads(sh.waves * tmm::kWave);
     hipLaunchKernelGGL(tmm::ragged::reset_counter, dim3(1), dim3(64), 0, s, pl->d_counter);
     if (pl->pol_mask == 1u)
-        hipLaunchKernelGGL((tmm::ragged::ragged_kernel<R, 1>), dim3(blocks), threads, lds, s, p);
+        launch_pol<R, 1>(p, sh.lpp, blocks, threads, lds, s);
     else if (pl->pol_mask == 2u)
-        hipLaunchKernelGGL((tmm::ragged::ragged_kernel<R, 2>), dim3(blocks), threads, lds, s, p);
+        launch_pol<R, 2>(p, sh.lpp, blocks, threads, lds, s);
     else
-        hipLaunchKernelGGL((tmm::ragged::ragged_kernel<R, 3>), dim3(blocks), threads, lds, s, p);
+        launch_pol<R, 3>(p, sh.lpp, blocks, threads, lds, s);
     return hipGetLastError();
 }
 
@@ -355,12 +543,17 @@ hipError_t launch(const tmm_ragged_plan* pl, tmm::ragged::Params<R> p, tmm::ragg
 // valid output) and keeps the fastest; the result is cached per
 // (dtype, pol, layer bucket, unit bucket) for later plans.
 // Dynamic LDS above 64 KiB: raise the kernels' limit (outside any capture).
+template <typename R, int POL, int LPP>
+void raise_one() {
+    (void)hipFuncSetAttribute((const void*)&tmm::ragged::ragged_kernel<R, POL, LPP>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)tmm::ragged::kLdsPerCU);
+}
+
 template <typename R>
 void raise_lds_limit() {
-    const int lim = (int)tmm::ragged::kLdsPerCU;
-    (void)hipFuncSetAttribute((const void*)&tmm::ragged::ragged_kernel<R, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-    (void)hipFuncSetAttribute((const void*)&tmm::ragged::ragged_kernel<R, 2>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-    (void)hipFuncSetAttribute((const void*)&tmm::ragged::ragged_kernel<R, 3>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    raise_one<R, 1, 1>(); raise_one<R, 2, 1>(); raise_one<R, 3, 1>();
+    raise_one<R, 1, 2>(); raise_one<R, 2, 2>(); raise_one<R, 3, 2>();
+    raise_one<R, 1, 4>(); raise_one<R, 2, 4>(); raise_one<R, 3, 4>();
     (void)hipGetLastError();
 }
 
@@ -369,14 +562,18 @@ tmm_status tune(tmm_ragged_plan* pl, const tmm::ragged::Params<R>& p, int di, hi
     raise_lds_limit<R>();
     const int lb = pl->mean_layers / 16;
     int ub = 0;
-    for (int64_t u = pl->n_units; u > 1; u >>= 2) ++ub;
+    for (int64_t u = pl->n_units[0]; u > 1; u >>= 2) ++ub;
     const auto key = std::make_tuple(di, (int)pl->pol_mask, lb, ub);
     {
         std::lock_guard<std::mutex> g(tmm::ragged::g_tune_mutex);
         auto it = tmm::ragged::g_tune_cache.find(key);
         if (it != tmm::ragged::g_tune_cache.end()) {
+            // shape known from an earlier plan of the same kind: this run's output
+            // still has to be computed
             pl->shape[di] = it->second;
             pl->tuned[di] = true;
+            if (launch<R>(pl, p, pl->shape[di], s) != hipSuccess)
+                return fail(TMM_ERR_HIP, "tmm_ragged_run: launch failed");
             return ok();
         }
     }
@@ -393,9 +590,14 @@ tmm_status tune(tmm_ragged_plan* pl, const tmm::ragged::Params<R>& p, int di, hi
     }
     float best = 1e30f;
     tmm::ragged::Shape best_sh = shapes.front();
-    for (const tmm::ragged::Shape& base : shapes) {
-        for (int g : grains) {
-            const tmm::ragged::Shape sh = {base.blocks_per_cu, g, base.waves};
+    std::vector<tmm::ragged::Shape> trials;
+    for (const tmm::ragged::Shape& base : shapes)
+        for (int g : grains) trials.push_back({base.blocks_per_cu, g, base.waves, 1});
+    // lanes per point 2 and 4 (16- and 32-point tiles) at the largest workgroup shape
+    for (int lpp : {2, 4})
+        for (int g : grains) trials.push_back({shapes.front().blocks_per_cu, g, shapes.front().waves, lpp});
+    {
+        for (const tmm::ragged::Shape& sh : trials) {
             if (hipEventRecord(e0, s) != hipSuccess || launch<R>(pl, p, sh, s) != hipSuccess ||
                 hipEventRecord(e1, s) != hipSuccess) {
                 release();
@@ -415,6 +617,13 @@ tmm_status tune(tmm_ragged_plan* pl, const tmm::ragged::Params<R>& p, int di, hi
     release();
     pl->shape[di] = best_sh;
     pl->tuned[di] = true;
+    // the shapes differ in arithmetic order (lanes per point), so the run's
+    // output comes from the chosen one: launch it once more unless it ran last
+    const tmm::ragged::Shape& last = trials.back();
+    if (last.blocks_per_cu != best_sh.blocks_per_cu || last.grain != best_sh.grain || last.waves != best_sh.waves ||
+        last.lpp != best_sh.lpp) {
+        if (launch<R>(pl, p, best_sh, s) != hipSuccess) return fail(TMM_ERR_HIP, "tmm_ragged_run: launch failed");
+    }
     std::lock_guard<std::mutex> g(tmm::ragged::g_tune_mutex);
     tmm::ragged::g_tune_cache[key] = best_sh;
     return ok();
@@ -450,7 +659,6 @@ tmm_status tmm_ragged_plan_create(int32_t B, const int64_t* layer_off, const int
     const int P = pol_mask == 3u ? 2 : 1;
     std::vector<int64_t> oo(B + 1, 0);
     std::vector<int> order(B);
-    int64_t n_units = 0;
     for (int b = 0; b < B; ++b) {
         const int64_t L = layer_off[b + 1] - layer_off[b];
         const int64_t nw = wl_off[b + 1] - wl_off[b];
@@ -460,7 +668,6 @@ tmm_status tmm_ragged_plan_create(int32_t B, const int64_t* layer_off, const int
                         "tmm_ragged_plan_create: stack %d has L=%lld, n_wl=%lld, n_theta=%lld (need 0 <= L <= 2^20, "
                         "1 <= n_wl <= 4194240, 1 <= n_theta <= 32767)", b, (long long)L, (long long)nw, (long long)nt);
         oo[b + 1] = oo[b] + P * nt * nw;
-        n_units += nt * ((nw + 63) / 64);
         order[b] = b;
     }
     if (wl_off[B] > ((int64_t)1 << 40)) return fail(TMM_ERR_INVALID_ARG, "tmm_ragged_plan_create: too many wavelengths");
@@ -468,14 +675,25 @@ tmm_status tmm_ragged_plan_create(int32_t B, const int64_t* layer_off, const int
     std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
         return layer_off[x + 1] - layer_off[x] > layer_off[y + 1] - layer_off[y];
     });
-    std::vector<int2> units;
-    units.reserve((size_t)n_units);
-    for (int b : order) {
-        const int nw = (int)(wl_off[b + 1] - wl_off[b]);
-        const int nt = (int)(th_off[b + 1] - th_off[b]);
-        const int tiles = (nw + 63) / 64;
-        for (int k = 0; k < nt; ++k)
-            for (int t = 0; t < tiles; ++t) units.push_back(make_int2(b, (k << 16) | t));
+    // work lists per lanes-per-point choice: the tiles of consecutive points of
+    // each stack, stacks in the sorted order; unit -> stack, stack -> first unit
+    std::vector<int32_t> unit_stack[3];
+    std::vector<int64_t> stack_first[3];
+    int64_t n_units[3];
+    for (int li = 0; li < 3; ++li) {
+        const int64_t ppw = tmm::kWave / tmm::ragged::kLppChoices[li];
+        stack_first[li].assign((size_t)B, 0);
+        int64_t n = 0;
+        for (int b : order) n += ((wl_off[b + 1] - wl_off[b]) * (th_off[b + 1] - th_off[b]) + ppw - 1) / ppw;
+        if (n > ((int64_t)1 << 31) - 1)
+            return fail(TMM_ERR_INVALID_ARG, "tmm_ragged_plan_create: more than 2^31 work units");
+        unit_stack[li].reserve((size_t)n);
+        for (int b : order) {
+            const int64_t tiles = ((wl_off[b + 1] - wl_off[b]) * (th_off[b + 1] - th_off[b]) + ppw - 1) / ppw;
+            stack_first[li][b] = (int64_t)unit_stack[li].size();
+            unit_stack[li].insert(unit_stack[li].end(), (size_t)tiles, b);
+        }
+        n_units[li] = n;
     }
     tmm_ragged_plan* pl = new tmm_ragged_plan();
     pl->B = B;
@@ -485,13 +703,16 @@ tmm_status tmm_ragged_plan_create(int32_t B, const int64_t* layer_off, const int
     pl->wl_off.assign(wl_off, wl_off + B + 1);
     pl->th_off.assign(th_off, th_off + B + 1);
     pl->out_off = oo;
-    pl->n_units = n_units;
+    for (int li = 0; li < 3; ++li) {
+        pl->n_units[li] = n_units[li];
+        pl->d_unit_stack[li] = nullptr;
+        pl->d_stack_first[li] = nullptr;
+    }
     pl->out_size = oo[B];
     pl->tuned[0] = pl->tuned[1] = false;
     pl->graph = nullptr;
     pl->graph_exec = nullptr;
     pl->d_layer_off = pl->d_wl_off = pl->d_th_off = pl->d_out_off = nullptr;
-    pl->d_units = nullptr;
     pl->d_counter = nullptr;
     pl->mean_layers = B > 0 ? (int)(layer_off[B] / B) : 0;
     int dev = 0;
@@ -504,14 +725,22 @@ tmm_status tmm_ragged_plan_create(int32_t B, const int64_t* layer_off, const int
     const size_t nb = (size_t)(B + 1) * sizeof(int64_t);
     bool okk = hipMalloc((void**)&pl->d_layer_off, nb) == hipSuccess && hipMalloc((void**)&pl->d_wl_off, nb) == hipSuccess &&
                hipMalloc((void**)&pl->d_th_off, nb) == hipSuccess && hipMalloc((void**)&pl->d_out_off, nb) == hipSuccess &&
-               hipMalloc((void**)&pl->d_units, std::max<size_t>(1, units.size()) * sizeof(int2)) == hipSuccess &&
                hipMalloc((void**)&pl->d_counter, sizeof(unsigned long long)) == hipSuccess;
     okk = okk && hipMemcpy(pl->d_layer_off, layer_off, nb, hipMemcpyHostToDevice) == hipSuccess &&
           hipMemcpy(pl->d_wl_off, wl_off, nb, hipMemcpyHostToDevice) == hipSuccess &&
           hipMemcpy(pl->d_th_off, th_off, nb, hipMemcpyHostToDevice) == hipSuccess &&
-          hipMemcpy(pl->d_out_off, oo.data(), nb, hipMemcpyHostToDevice) == hipSuccess &&
-          (units.empty() ||
-           hipMemcpy(pl->d_units, units.data(), units.size() * sizeof(int2), hipMemcpyHostToDevice) == hipSuccess);
+          hipMemcpy(pl->d_out_off, oo.data(), nb, hipMemcpyHostToDevice) == hipSuccess;
+    for (int li = 0; okk && li < 3; ++li) {
+        const size_t nu = std::max<size_t>(1, unit_stack[li].size()) * sizeof(int32_t);
+        const size_t ns = std::max<size_t>(1, (size_t)B) * sizeof(int64_t);
+        okk = hipMalloc((void**)&pl->d_unit_stack[li], nu) == hipSuccess &&
+              hipMalloc((void**)&pl->d_stack_first[li], ns) == hipSuccess &&
+              (unit_stack[li].empty() || hipMemcpy(pl->d_unit_stack[li], unit_stack[li].data(),
+                                                   unit_stack[li].size() * sizeof(int32_t),
+                                                   hipMemcpyHostToDevice) == hipSuccess) &&
+              (B == 0 || hipMemcpy(pl->d_stack_first[li], stack_first[li].data(), (size_t)B * sizeof(int64_t),
+                                   hipMemcpyHostToDevice) == hipSuccess);
+    }
     if (!okk) {
         tmm_ragged_plan_destroy(pl);
         return fail(TMM_ERR_HIP, "tmm_ragged_plan_create: device allocation or copy failed");
@@ -525,7 +754,9 @@ tmm_status tmm_ragged_plan_destroy(tmm_ragged_plan* pl) {
     (void)hipDeviceSynchronize();
     if (pl->graph_exec) (void)hipGraphExecDestroy(pl->graph_exec);
     if (pl->graph) (void)hipGraphDestroy(pl->graph);
-    void* ptrs[] = {pl->d_layer_off, pl->d_wl_off, pl->d_th_off, pl->d_out_off, pl->d_units, pl->d_counter};
+    void* ptrs[] = {pl->d_layer_off,      pl->d_wl_off,         pl->d_th_off,         pl->d_out_off,
+                    pl->d_counter,        pl->d_unit_stack[0],  pl->d_unit_stack[1],  pl->d_unit_stack[2],
+                    pl->d_stack_first[0], pl->d_stack_first[1], pl->d_stack_first[2]};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     delete pl;
@@ -543,7 +774,7 @@ tmm_status tmm_ragged_plan_output_offsets(const tmm_ragged_plan* pl, int64_t* ho
 tmm_status tmm_ragged_run(tmm_ragged_plan* pl, const tmm_ragged_data* a, tmm_dtype dtype, void* stream) {
     tmm_status st = check_data(pl, a, dtype, "tmm_ragged_run");
     if (st != TMM_OK) return st;
-    if (pl->n_units == 0) return ok();
+    if (pl->n_units[0] == 0) return ok();
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int di = dtype == TMM_F64 ? 0 : 1;
     (void)hipGetLastError();
@@ -557,6 +788,39 @@ tmm_status tmm_ragged_run(tmm_ragged_plan* pl, const tmm_ragged_data* a, tmm_dty
         if (launch<float>(pl, p, pl->shape[di], s) != hipSuccess) return tmm::check_launch("tmm_ragged_run");
     }
     return tmm::check_launch("tmm_ragged_run");
+}
+
+tmm_status tmm_rt_ragged(tmm_ragged_plan* pl, const tmm_ragged_data* a, tmm_dtype dtype, void* stream) {
+    return tmm_ragged_run(pl, a, dtype, stream);
+}
+
+tmm_status tmm_ragged_plan_shape(const tmm_ragged_plan* pl, tmm_dtype dtype, int32_t* host_shape) {
+    if (!pl || !host_shape) return fail(TMM_ERR_INVALID_ARG, "tmm_ragged_plan_shape: NULL argument");
+    if (dtype != TMM_F64 && dtype != TMM_F32) return fail(TMM_ERR_INVALID_ARG, "tmm_ragged_plan_shape: unknown dtype");
+    const int di = dtype == TMM_F64 ? 0 : 1;
+    if (!pl->tuned[di]) return fail(TMM_ERR_INVALID_ARG, "tmm_ragged_plan_shape: not tuned for this dtype yet");
+    const tmm::ragged::Shape& sh = pl->shape[di];
+    host_shape[0] = sh.blocks_per_cu;
+    host_shape[1] = sh.grain;
+    host_shape[2] = sh.waves;
+    host_shape[3] = sh.lpp;
+    return ok();
+}
+
+tmm_status tmm_ragged_plan_set_shape(tmm_ragged_plan* pl, tmm_dtype dtype, const int32_t* host_shape) {
+    if (!pl || !host_shape) return fail(TMM_ERR_INVALID_ARG, "tmm_ragged_plan_set_shape: NULL argument");
+    if (dtype != TMM_F64 && dtype != TMM_F32)
+        return fail(TMM_ERR_INVALID_ARG, "tmm_ragged_plan_set_shape: unknown dtype");
+    const int bpc = host_shape[0], grain = host_shape[1], waves = host_shape[2], lpp = host_shape[3];
+    if (bpc < 1 || grain < 1 || grain > 64 || waves < 1 || waves > tmm::ragged::kMaxThreads / tmm::kWave ||
+        (lpp != 1 && lpp != 2 && lpp != 4) || bpc * waves > 32)
+        return fail(TMM_ERR_INVALID_ARG,
+                    "tmm_ragged_plan_set_shape: need workgroups per CU >= 1, 1 <= grain <= 64, 1 <= waves <= 12, "
+                    "lanes per point 1, 2 or 4, and at most 32 waves per CU");
+    const int di = dtype == TMM_F64 ? 0 : 1;
+    pl->shape[di] = {bpc, grain, waves, lpp};
+    pl->tuned[di] = true;
+    return ok();
 }
 
 tmm_status tmm_ragged_capture(tmm_ragged_plan* pl, const tmm_ragged_data* a, tmm_dtype dtype, void* stream) {
@@ -578,7 +842,7 @@ tmm_status tmm_ragged_capture(tmm_ragged_plan* pl, const tmm_ragged_data* a, tmm
         (void)hipGraphDestroy(pl->graph);
         pl->graph = nullptr;
     }
-    if (pl->n_units == 0) return ok();
+    if (pl->n_units[0] == 0) return ok();
     (void)hipGetLastError();
     if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess)
         return fail(TMM_ERR_HIP, "tmm_ragged_capture: begin capture failed");
@@ -603,7 +867,7 @@ tmm_status tmm_ragged_capture(tmm_ragged_plan* pl, const tmm_ragged_data* a, tmm
 
 tmm_status tmm_ragged_replay(tmm_ragged_plan* pl, void* stream) {
     if (!pl) return fail(TMM_ERR_INVALID_ARG, "tmm_ragged_replay: plan is NULL");
-    if (pl->n_units == 0) return ok();
+    if (pl->n_units[0] == 0) return ok();
     if (!pl->graph_exec) return fail(TMM_ERR_INVALID_ARG, "tmm_ragged_replay: nothing captured");
     if (hipGraphLaunch(pl->graph_exec, static_cast<hipStream_t>(stream)) != hipSuccess)
         return fail(TMM_ERR_HIP, "tmm_ragged_replay: graph launch failed");

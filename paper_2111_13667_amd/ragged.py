@@ -34,7 +34,11 @@ def _lib():
         lib.tmm_ragged_plan_output_size.argtypes = [P]
         lib.tmm_ragged_plan_output_offsets.restype = ctypes.c_int
         lib.tmm_ragged_plan_output_offsets.argtypes = [P, P]
-        for name in ("tmm_ragged_run", "tmm_ragged_capture"):
+        lib.tmm_ragged_plan_shape.restype = ctypes.c_int
+        lib.tmm_ragged_plan_shape.argtypes = [P, ctypes.c_int, P]
+        lib.tmm_ragged_plan_set_shape.restype = ctypes.c_int
+        lib.tmm_ragged_plan_set_shape.argtypes = [P, ctypes.c_int, P]
+        for name in ("tmm_ragged_run", "tmm_rt_ragged", "tmm_ragged_capture"):
             f = getattr(lib, name)
             f.restype = ctypes.c_int
             f.argtypes = [P, ctypes.POINTER(RaggedData), ctypes.c_int, P]
@@ -110,7 +114,21 @@ class RaggedPlan:
 
     def run(self, d, mat, ends, wl, sin_t, cos_t, nk, R=None, T=None, stream=None):
         data, dt = self._pack(d, mat, ends, wl, sin_t, cos_t, nk, R, T)
-        tmm._check(_lib().tmm_ragged_run(self.h, ctypes.byref(data), dt, tmm._stream_handle(stream)))
+        tmm._check(_lib().tmm_rt_ragged(self.h, ctypes.byref(data), dt, tmm._stream_handle(stream)))
+
+    def shape(self, dtype="f64") -> dict:
+        """The autotuned launch shape for dtype (after the first run)."""
+        out = np.zeros(4, dtype=np.int32)
+        tmm._check(_lib().tmm_ragged_plan_shape(self.h, tmm.TMM_F64 if dtype == "f64" else tmm.TMM_F32,
+                                                out.ctypes.data))
+        return {"workgroups_per_cu": int(out[0]), "grain": int(out[1]), "waves_per_workgroup": int(out[2]),
+                "lanes_per_point": int(out[3]), "points_per_unit": 64 // int(out[3])}
+
+    def set_shape(self, dtype="f64", *, workgroups_per_cu=1, grain=1, waves_per_workgroup=12, lanes_per_point=1):
+        """Fix the launch shape for dtype instead of tuning it on the first run."""
+        sh = np.array([workgroups_per_cu, grain, waves_per_workgroup, lanes_per_point], dtype=np.int32)
+        tmm._check(_lib().tmm_ragged_plan_set_shape(self.h, tmm.TMM_F64 if dtype == "f64" else tmm.TMM_F32,
+                                                    sh.ctypes.data))
 
     def capture(self, d, mat, ends, wl, sin_t, cos_t, nk, R=None, T=None, stream=None):
         """Capture a run into the plan's HIP graph (stream: a non-default torch stream)."""

@@ -10,9 +10,12 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 
-def run(rw, dtype="f64", pol="both"):
+def run(rw, dtype="f64", pol="both", lpp=None):
     from paper_2111_13667_amd import ragged
     plan = ragged.RaggedPlan(rw.layer_off, rw.wl_off, rw.th_off, pol=pol)
+    if lpp is not None:
+        # 2 workgroups of 6 waves per CU: fits the LDS of any table up to 8 rows
+        plan.set_shape(dtype, workgroups_per_cu=2, grain=2, waves_per_workgroup=6, lanes_per_point=lpp)
     dev = ragged.to_device(rw, dtype)
     real = dev[3].dtype
     R = torch.empty(plan.output_size, dtype=real, device="cuda")
@@ -121,3 +124,42 @@ def test_seeded_sweep_ragged(seed):
     rw = workloads.ragged_batch(seed=4100 + seed, B=B, L_range=(lo, hi), wl_range=(1, 300), th_range=(1, 9))
     plan, _, R, T = run(rw, dtype, pol)
     check_stacks(rw, plan, R, T, range(rw.B), dtype, pol)
+
+
+@pytest.mark.parametrize("lpp", [1, 2, 4])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_lanes_per_point(lpp, dtype):
+    # Every launch shape of the autotuner's space by hand: one lane per point,
+    # or the stack's layers split across two or four lanes of a point (32- and
+    # 16-point tiles) with the segments' 2x2 operators composed across lanes.
+    # Layer counts 0-70 cover empty segments (L < lanes per point) and segments
+    # longer than a renormalisation block; every stack against the oracle.
+    rw = workloads.ragged_batch(seed=50 + lpp, B=23, L_range=(0, 70), wl_range=(1, 90), th_range=(1, 5))
+    plan, _, R, T = run(rw, dtype, lpp=lpp)
+    assert plan.shape(dtype)["lanes_per_point"] == lpp
+    check_stacks(rw, plan, R, T, range(rw.B), dtype)
+
+
+@pytest.mark.parametrize("pol", ["s", "p"])
+def test_lanes_per_point_single_polarisation(pol):
+    rw = workloads.ragged_batch(seed=60, B=11, L_range=(1, 40), wl_range=(5, 70), th_range=(1, 3))
+    plan, _, R, T = run(rw, "f64", pol, lpp=4)
+    check_stacks(rw, plan, R, T, range(rw.B), "f64", pol)
+
+
+def test_autotuned_shape_is_reported():
+    rw = workloads.ragged_batch(seed=61, B=40, L_range=(2, 30), wl_range=(64, 200), th_range=(1, 4))
+    plan, _, R, T = run(rw)
+    sh = plan.shape("f64")
+    assert sh["lanes_per_point"] in (1, 2, 4) and sh["points_per_unit"] * sh["lanes_per_point"] == 64
+    check_stacks(rw, plan, R, T, [0, rw.B - 1])
+
+
+def test_first_run_of_a_plan_with_a_cached_shape_computes_its_output():
+    # A second plan of the same kind (dtype, polarisation, layer and size
+    # buckets) takes the tuned shape from the process-wide cache without timing
+    # anything; its first run must still write the whole output.
+    rw = workloads.ragged_batch(seed=62, B=40, L_range=(2, 30), wl_range=(64, 200), th_range=(1, 4))
+    run(rw)                                   # tunes and caches the shape
+    plan, _, R, T = run(rw)                   # new plan, cached shape
+    check_stacks(rw, plan, R, T, range(rw.B))
