@@ -85,6 +85,8 @@ struct GradParams {
     int64_t n_tasks_pair;  // the same for the ratio-form kernel's blocks
     int64_t per_block;
     int64_t slots;     // checkpoint slots in the workspace (waves of the persistent grid)
+    unsigned char* redo;  // [column][stack - b_begin]: 1 = left to the checkpointing kernels by
+                          // the inverse-walk kernel (NULL: every stack is processed)
 };
 
 // Per-stack layer data is read-only during the launch and read at
@@ -906,12 +908,12 @@ __device__ void grad_stack_pair(const GradParams& p, const PairLayers& src, cons
 // lane, the largest phase coefficient, and the lossy flag of each material.
 __device__ void build_pair_table(const GradParams& p, double2* mtab, unsigned char* pairs, int amb_row, int i,
                                  bool lane_used, double st, double ct, int wave, int lane, int* s_bad,
-                                 double* s_cmax, int* s_lossy) {
+                                 double* s_cmax, int* s_lossy, int nwaves = kGradPairWaves) {
     double n0r, n0i;
     load_n(p.nk, p.dispersive, p.n_wl, amb_row, i, n0r, n0i);
     const Ambient a = make_ambient(n0r, n0i, st, ct);
     const double lam = p.wl[i];
-    for (int m = wave; m < p.n_mat; m += kGradPairWaves) {
+    for (int m = wave; m < p.n_mat; m += nwaves) {
         double nr, ni;
         load_n(p.nk, p.dispersive, p.n_wl, m, i, nr, ni);
         const Medium md = make_medium(nr, ni, a.kx);
@@ -931,7 +933,7 @@ __device__ void build_pair_table(const GradParams& p, double2* mtab, unsigned ch
     bool bad = false;
     double cmax = 0.0;
     const double c4lam = 4.0 / lam;
-    for (int pi = wave; pi < p.n_mat * p.n_mat; pi += kGradPairWaves) {
+    for (int pi = wave; pi < p.n_mat * p.n_mat; pi += nwaves) {
         const int mc = pi / p.n_mat, mn = pi - mc * p.n_mat;
         double ar, ai, br, bi;
         load_n(p.nk, p.dispersive, p.n_wl, mc, i, ar, ai);
@@ -1000,10 +1002,13 @@ grad_pair_kernel(GradParams p) {
         const ciptr mrow = (ciptr)(p.mat + (int64_t)b * L2);
         double* part = p.partial + ((size_t)col * nbs + (b - p.b_begin)) * (size_t)p.L * 3;
         const double* drow = p.d + (int64_t)b * p.L;
-        const bool bad = stack_bad(p, drow, mrow, lane);
+        // after the inverse-walk kernel: only the stacks it left
+        const bool mine = has && (!p.redo || p.redo[(size_t)col * nbs + (b - p.b_begin)] != 0);
+        if (p.redo && __syncthreads_or(mine ? 1 : 0) == 0) continue;
+        const bool bad = mine && stack_bad(p, drow, mrow, lane);
         int a_row = mrow[0];
         a_row = a_row < 0 ? 0 : (a_row >= p.n_mat ? p.n_mat - 1 : a_row);
-        bool done = !has;
+        bool done = !mine;
         // one sub-round per distinct ambient row among the block's stacks
         for (;;) {
             __syncthreads();
@@ -1071,6 +1076,310 @@ grad_pair_kernel(GradParams p) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// Inverse walk (ratio form, lossless media).  When every table row is lossless
+// and propagating at the block's column (Im q = 0 in every lane), every layer
+// factor E_j = e^{2 i delta_j} has modulus 1 and the ratio step is inverted
+// exactly and stably:
+//   s: u = s' + t', v = conj(E)(s' - t'), s = (u + v)/4, X = (u - v)/4, t = X / rho_s
+//   p: u = s' + t', v = conj(E)(s' - t'), X = (u + v)/4, t = (u - v)/4, s = X / rho_p
+// where 1 / rho is the ratio of the reversed material pair (tabulated too).
+// Pass B then walks from the ambient to the substrate recovering each step's
+// input from its output, with no checkpoints and no per-segment register
+// arrays; the adjoint of each step is that of grad_stack_pair.  The state and
+// its adjoint are rescaled together by powers of two (their products, which
+// make the gradients, are unchanged).  Shares are reduced per SEG layers as in
+// grad_stack_pair.
+template <int POL, int SEG>
+__device__ void grad_stack_inv(const GradParams& p, const PairLayers& src, const Ambient& amb, int b, int k, int i,
+                               int lane, bool active, bool valid, int n_mat, double* red, double* part,
+                               const TabPhase<double>& phase) {
+    const int L = p.L;
+    constexpr int P = (POL == 3) ? 2 : 1;
+    const double two_pi_lam = 2.0 * M_PI / p.wl[i];
+
+    // ---- pass A: forward (ratio form), renormalised every block ------------
+    State z;
+    z.ss = z.ts = z.sp = z.tp = {1.0, 0.0};
+    int es = 0, ep = 0;
+    constexpr int RPA = 32;  // steps between renormalisations: growth <= 2 (1 + 256) per step
+    for (int top = L; top >= 1; top -= RPA) {
+        const int lo = top - RPA + 1 > 1 ? top - RPA + 1 : 1;
+        for (int j = top; j >= lo; --j) {
+            cx<double> rs, rp;
+            double cre, cim;
+            src.pair(src.code(j), rs, rp, cre, cim);
+            ratio_step<POL>(z, rs, rp, phase.cis_g(src.d(j) * cre));
+        }
+        if (POL & 1) renorm_pair(z.ss, z.ts, es);
+        if (POL & 2) renorm_pair(z.sp, z.tp, ep);
+    }
+    const int m1 = src.row(1), msub = src.row(L + 1);
+    const cx<double> q1 = src.field(m1, 0), e1 = src.field(m1, 1);
+    const int two_L1 = 2 * (L + 1);
+    const double nan = __builtin_nan("");
+    const double w_act = active ? 1.0 : 0.0;  // ragged-tail lanes contribute nothing
+
+    // ambient step (division-free) and output adjoints, as in grad_stack_pair (no attenuation)
+    cx<double> sb_s = {0, 0}, tb_s = {0, 0}, sb_p = {0, 0}, tb_p = {0, 0};
+    cx<double> pend_q = {0, 0}, pend_e = {0, 0};
+    double cT = 0.0;  // sum of gT T: T's dependence on Im delta (through Im n) survives at Im n = 0
+    const cx<double> q0 = {amb.q0r, amb.q0i}, e0 = {amb.e0r, amb.e0i};
+    if (POL & 1) {
+        const cx<double> A = cmul(q0, z.ss), Bv = cmul(q1, z.ts);
+        const cx<double> a = cadd(A, Bv), bb = csub(A, Bv);
+        const double na = cnorm(a);
+        const double R = cnorm(bb) / na;
+        const double T = ldexp(amb.Ks * src.field(msub, 0).re / na, two_L1 - 2 * es);
+        const int64_t o = (((int64_t)b * P + 0) * p.n_theta + k) * p.n_wl + i;
+        if (active && p.R_out) p.R_out[o] = valid ? R : nan;
+        if (active && p.T_out) p.T_out[o] = valid ? T : nan;
+        const double gR = p.gR ? p.gR[o] * w_act : 0.0;
+        const double gT = p.gT ? p.gT[o] * w_act : 0.0;
+        cT += gT * T;
+        const cx<double> abar = cscale(-2.0 * (gR * R + gT * T) / na, a);
+        const cx<double> bbar = cscale(2.0 * gR / na, bb);
+        const cx<double> Ab = cadd(abar, bbar), Bb = csub(abar, bbar);
+        sb_s = cmulc(q0, Ab);
+        tb_s = cmulc(q1, Bb);
+        pend_q = cmulc(z.ts, Bb);
+    }
+    if (POL & 2) {
+        const cx<double> A = cmul(e1, z.sp), Bv = cmul(e0, z.tp);
+        const cx<double> a = cadd(A, Bv), bb = csub(A, Bv);
+        const double na = cnorm(a);
+        const double R = cnorm(bb) / na;
+        const double T = ldexp(amb.Kp * src.field(msub, 1).re / na, two_L1 - 2 * ep);
+        const int64_t o = (((int64_t)b * P + (P - 1)) * p.n_theta + k) * p.n_wl + i;
+        if (active && p.R_out) p.R_out[o] = valid ? R : nan;
+        if (active && p.T_out) p.T_out[o] = valid ? T : nan;
+        const double gR = p.gR ? p.gR[o] * w_act : 0.0;
+        const double gT = p.gT ? p.gT[o] * w_act : 0.0;
+        cT += gT * T;
+        const cx<double> abar = cscale(-2.0 * (gR * R + gT * T) / na, a);
+        const cx<double> bbar = cscale(2.0 * gR / na, bb);
+        const cx<double> Ab = cadd(abar, bbar), Bb = csub(abar, bbar);
+        sb_p = cmulc(e1, Ab);
+        tb_p = cmulc(e0, Bb);
+        pend_e = cmulc(z.sp, Ab);
+    }
+    if (!valid) sb_s = tb_s = sb_p = tb_p = pend_q = pend_e = {nan, nan};
+    cx<double> wprev_s = {0, 0}, wprev_p = {0, 0};
+
+    // ---- pass B: from the ambient to the substrate -------------------------
+    const int n_seg = (L + SEG - 1) / SEG;
+    const int v_red = lane >> 2 < (3 * SEG) ? lane >> 2 : (3 * SEG) - 1;  // share this lane sums
+    const double2* red_in = reinterpret_cast<const double2*>(red + v_red * kWave + (lane & 3) * 16);
+    for (int s = n_seg - 1; s >= 0; --s) {
+        const int top = L - s * SEG;
+        const int lo = top - SEG + 1 > 1 ? top - SEG + 1 : 1;
+        const int nst = top - lo + 1;
+        for (int j = lo; j <= top; ++j) {
+            const int t = top - j;  // share slot, as in grad_stack_pair
+            const int code = src.code(j);
+            const int m = src.row(j);
+            cx<double> rs, rp, rs_rev, rp_rev;
+            double cre, cim, cre_r, cim_r;
+            src.pair(code, rs, rp, cre, cim);
+            src.pair((src.row(j + 1) * n_mat + m) * kGradPairBlockBytes, rs_rev, rp_rev, cre_r, cim_r);
+            const double dj = src.d(j);
+            const cx<double> E = phase.cis_g(dj * cre);
+            const cx<double> Eq = {0.25 * E.re, -0.25 * E.im};  // conj(E) / 4
+            // the step's input from its output z
+            State zin = z;
+            if (POL & 1) {
+                const cx<double> u = cadd(z.ss, z.ts), v = cmul(Eq, csub(z.ss, z.ts));
+                const cx<double> u4 = cscale(0.25, u);
+                zin.ss = cadd(u4, v);
+                zin.ts = cmul(rs_rev, csub(u4, v));
+            }
+            if (POL & 2) {
+                const cx<double> u = cadd(z.sp, z.tp), v = cmul(Eq, csub(z.sp, z.tp));
+                const cx<double> u4 = cscale(0.25, u);
+                zin.tp = csub(u4, v);
+                zin.sp = cmul(rp_rev, cadd(u4, v));
+            }
+            cx<double> Eb = {0.0, 0.0};
+            cx<double> w_s = {0, 0}, w_p = {0, 0};
+            if (POL & 1) {
+                const cx<double> X = cmul(rs, zin.ts);
+                const cx<double> bv = csub(zin.ss, X);
+                const cx<double> ab = cadd(sb_s, tb_s), Y = csub(sb_s, tb_s);
+                const cx<double> bb = cmulc(E, Y);
+                Eb = cadd(Eb, cmulc(bv, Y));
+                const cx<double> Xb = csub(ab, bb);
+                sb_s = cadd(ab, bb);
+                tb_s = cmulc(rs, Xb);
+                w_s = cmulc(X, Xb);
+            }
+            if (POL & 2) {
+                const cx<double> X = cmul(rp, zin.sp);
+                const cx<double> bv = csub(X, zin.tp);
+                const cx<double> ab = cadd(sb_p, tb_p), Y = csub(sb_p, tb_p);
+                const cx<double> bb = cmulc(E, Y);
+                Eb = cadd(Eb, cmulc(bv, Y));
+                const cx<double> Xb = cadd(ab, bb);
+                tb_p = csub(ab, bb);
+                sb_p = cmulc(rp, Xb);
+                w_p = cmulc(X, Xb);
+            }
+            const cx<double> qj = src.field(m, 0);
+            // deltab = -2i conj(E) Eb - 2i cT  (chain and e^{-2 Im sum delta})
+            const cx<double> cE = cmulc(E, Eb);
+            const cx<double> db = {2.0 * cE.im, -2.0 * cE.re - 2.0 * cT};
+            const double gd = two_pi_lam * (db.re * qj.re + db.im * qj.im);
+            const cx<double> qb = cadd(pend_q, cscale(two_pi_lam * dj, db));
+            cx<double> nb = cmulc(src.field(m, 2), qb);
+            if (POL & 2) nb = cadd(nb, cmulc(src.field(m, 3), pend_e));
+            if (POL & 1) nb = cadd(nb, cmulc(src.field(m, 4), csub(wprev_s, w_s)));
+            if (POL & 2) nb = cadd(nb, cmulc(src.field(m, 5), csub(wprev_p, w_p)));
+            wprev_s = w_s;
+            wprev_p = w_p;
+            pend_q = pend_e = {0.0, 0.0};
+            red[(3 * t + 0) * kWave + lane] = gd;
+            red[(3 * t + 1) * kWave + lane] = nb.re;
+            red[(3 * t + 2) * kWave + lane] = nb.im;
+            z = zin;
+        }
+        // keep the walked state near 1: scale it and its adjoint inversely
+        if (POL & 1) {
+            const int e = pair_exp(z.ss, z.ts);
+            const double f = ldexp(1.0, -e), g = ldexp(1.0, e);
+            z.ss = cscale(f, z.ss);
+            z.ts = cscale(f, z.ts);
+            sb_s = cscale(g, sb_s);
+            tb_s = cscale(g, tb_s);
+        }
+        if (POL & 2) {
+            const int e = pair_exp(z.sp, z.tp);
+            const double f = ldexp(1.0, -e), g = ldexp(1.0, e);
+            z.sp = cscale(f, z.sp);
+            z.tp = cscale(f, z.tp);
+            sb_p = cscale(g, sb_p);
+            tb_p = cscale(g, tb_p);
+        }
+        wave_sync();
+        double acc = 0.0;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const double2 x = red_in[u];
+            acc += x.x;
+            acc += x.y;
+        }
+        acc = quad_add<0xB1>(acc);
+        acc = quad_add<0x4E>(acc);
+        if ((lane & 3) == 0 && (lane >> 2) < 3 * nst) {
+            const int v = lane >> 2;
+            const int t = v / 3;
+            part[(top - t - 1) * 3 + (v - 3 * t)] = acc;
+        }
+        wave_sync();
+    }
+}
+
+__host__ __device__ constexpr size_t grad_inv_lds_bytes(int n_mat, int seg, int waves) {
+    return phase_tab_bytes<double>() + (size_t)waves * 3 * seg * kWave * sizeof(double) +
+           (size_t)n_mat * kPairFields * kWave * sizeof(double2) + (size_t)n_mat * n_mat * kGradPairBlockBytes;
+}
+
+// Persistent blocks of WAVES waves over tasks (column, group of WAVES stacks),
+// the block's pair table as in grad_pair_kernel.  Stacks whose column is not
+// lossless, whose ratios leave their bound or whose phases leave the fast
+// range are marked in p.redo and left to grad_pair_kernel.
+template <int POL, int SEG, int WAVES>
+__global__ void __launch_bounds__(WAVES * kWave) grad_inv_kernel(GradParams p) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int s_rows[WAVES];
+    __shared__ int s_bad[WAVES];
+    __shared__ double s_cmax[WAVES];
+    __shared__ int s_lossy[kGradPairMaxMat];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    fill_phase_tab<double>(smem, threadIdx.x, WAVES * kWave);
+    __syncthreads();
+    const TabPhase<double> phase = phase_of<double>(smem);
+    unsigned char* const lds = smem + phase_tab_bytes<double>();
+    double* red = reinterpret_cast<double*>(lds) + wave * (3 * SEG) * kWave;
+    double2* mtab = reinterpret_cast<double2*>(lds + (size_t)WAVES * (3 * SEG) * kWave * sizeof(double));
+    unsigned char* pairs = reinterpret_cast<unsigned char*>(mtab + (size_t)p.n_mat * kPairFields * kWave);
+    const int L2 = p.L + 2;
+    const int64_t nbs = p.b_end - p.b_begin;
+    const int64_t groups = (nbs + WAVES - 1) / WAVES;
+    const int64_t t0 = (int64_t)blockIdx.x * p.per_block;
+    const int64_t t1 = t0 + p.per_block < p.n_tasks ? t0 + p.per_block : p.n_tasks;
+    int64_t tab_col = -1;
+    int tab_row = -1;
+    for (int64_t t = t0; t < t1; ++t) {
+        const int64_t col = t / groups;
+        const int tk_k = (int)(col / p.n_tiles);
+        const int tk_tile = (int)(col - (int64_t)tk_k * p.n_tiles);
+        const int tk_b = p.b_begin + (int)(t - col * groups) * WAVES + wave;
+        const int i_raw = tk_tile * kWave + lane;
+        const bool active = i_raw < p.n_wl;
+        const int i = active ? i_raw : p.n_wl - 1;
+        const double lam = p.wl[i];
+        const bool lam_ok = lam > 0.0 && lam < __builtin_inf();
+        const double st = p.sin_t[tk_k], ct = p.cos_t[tk_k];
+        const bool has = tk_b < p.b_end;
+        const int b = has ? tk_b : p.b_end - 1;
+        const ciptr mrow = (ciptr)(p.mat + (int64_t)b * L2);
+        double* part = p.partial + ((size_t)col * nbs + (b - p.b_begin)) * (size_t)p.L * 3;
+        const double* drow = p.d + (int64_t)b * p.L;
+        const bool bad = stack_bad(p, drow, mrow, lane);
+        int a_row = mrow[0];
+        a_row = a_row < 0 ? 0 : (a_row >= p.n_mat ? p.n_mat - 1 : a_row);
+        bool done = !has;
+        for (;;) {
+            __syncthreads();
+            if (lane == 0) s_rows[wave] = done ? INT_MAX : a_row;
+            __syncthreads();
+            int r = s_rows[0];
+            for (int w = 1; w < WAVES; ++w) r = min(r, s_rows[w]);
+            if (r == INT_MAX) break;
+            if (r != tab_row || col != tab_col) {
+                double n0r, n0i;
+                load_n(p.nk, p.dispersive, p.n_wl, r, i, n0r, n0i);
+                const bool used = active && lam_ok && make_ambient(n0r, n0i, st, ct).ok;
+                build_pair_table(p, mtab, pairs, r, i, used, st, ct, wave, lane, s_bad, s_cmax, s_lossy, WAVES);
+                tab_row = r;
+                tab_col = col;
+            }
+            __syncthreads();
+            if (!done && a_row == r) {
+                int any_bad = 0, any_lossy = 0;
+                double cm = 0.0;
+                for (int w = 0; w < WAVES; ++w) {
+                    any_bad |= s_bad[w];
+                    cm = fmax(cm, s_cmax[w]);
+                }
+                for (int m2 = 0; m2 < p.n_mat; ++m2) any_lossy |= s_lossy[m2];
+                double n0r, n0i;
+                load_n(p.nk, p.dispersive, p.n_wl, a_row, i, n0r, n0i);
+                const Ambient amb = make_ambient(n0r, n0i, st, ct);
+                const bool ok = lam_ok && amb.ok && !bad;
+                PairLayers src;
+                src.mtab = mtab + lane;
+                src.pair_lane = pairs + lane * 16;
+                src.my_d = lane < p.L ? drow[lane] : 0.0;
+                int m_row = lane < L2 ? mrow[lane] : 0;
+                m_row = m_row < 0 ? 0 : (m_row >= p.n_mat ? p.n_mat - 1 : m_row);
+                src.my_row = m_row;
+                int m_nx = lane + 1 < L2 ? mrow[lane + 1] : 0;
+                m_nx = m_nx < 0 ? 0 : (m_nx >= p.n_mat ? p.n_mat - 1 : m_nx);
+                const int m_cur = __shfl_down(m_row, 1, kWave);
+                const int m_nxt = __shfl_down(m_nx, 1, kWave);
+                src.my_code = (m_cur * p.n_mat + m_nxt) * kGradPairBlockBytes;
+                const bool far = __any(lane < p.L && !(src.my_d <= (0.5 * kScFastRange) / cm));
+                const bool mine = any_bad == 0 && any_lossy == 0 && !far;
+                if (mine)
+                    grad_stack_inv<POL, SEG>(p, src, amb, b, tk_k, i, lane, active, ok, p.n_mat, red, part, phase);
+                if (lane == 0) p.redo[(size_t)col * nbs + (b - p.b_begin)] = mine ? 0 : 1;
+                done = true;
+            }
+        }
+    }
+}
+
 // grad[g] = sum over the columns of partial[col][g] in column order (g runs
 // over the launch's stacks x layers x {d, Re n, Im n}).
 __global__ void grad_reduce(const double* partial, int64_t cols, int64_t n, int64_t g0, double* grad_d,
@@ -1100,7 +1409,9 @@ struct GradShape {
     int n_tiles, n_seg;
     int64_t cols;
     int64_t slots;  // checkpoint slots (one per wave of the persistent grid)
-    size_t per_stack, slot_bytes, ckpt_bytes;
+    size_t per_stack;          // partial sums and inverse-walk flags of one stack
+    size_t per_stack_partial;  // the partial sums alone
+    size_t slot_bytes, ckpt_bytes;
 };
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -1112,7 +1423,8 @@ static GradShape grad_shape(const tmm_rt_args* a, int64_t max_slots = INT64_MAX)
     g.n_tiles = (int)ceil_div(a->n_wl, kWave);
     g.n_seg = (int)ceil_div(a->L, kSeg);
     g.cols = (int64_t)g.n_tiles * a->n_theta;
-    g.per_stack = (size_t)g.cols * a->L * 3 * sizeof(double);
+    g.per_stack_partial = (size_t)g.cols * a->L * 3 * sizeof(double);
+    g.per_stack = g.per_stack_partial + (size_t)g.cols;
     // checkpoint slots of the persistent grid: blocks of kGradWaves (division-free
     // kernel) or kGradPairWaves (ratio-form kernel) waves, whichever needs more
     const int64_t tasks = g.cols * ceil_div(a->B, kGradWaves);
@@ -1210,6 +1522,51 @@ static hipError_t launch_grad(GradParams p, int n_cu, size_t lds, hipStream_t s)
     return hipGetLastError();
 }
 
+template <int POL, int SEG, int WAVES>
+static hipError_t launch_grad_inv_t(GradParams p, int n_cu, hipStream_t s) {
+    const size_t lds = grad_inv_lds_bytes(p.n_mat, SEG, WAVES);
+    static std::mutex mu;
+    static std::map<size_t, int> cache;
+    int occ = 1;
+    {
+        std::lock_guard<std::mutex> g(mu);
+        auto it = cache.find(lds);
+        if (it != cache.end()) {
+            occ = it->second;
+        } else {
+            (void)hipFuncSetAttribute((const void*)&grad_inv_kernel<POL, SEG, WAVES>,
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            (void)hipGetLastError();
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, grad_inv_kernel<POL, SEG, WAVES>, WAVES * kWave,
+                                                             lds) != hipSuccess ||
+                occ < 1)
+                occ = 1;
+            cache[lds] = occ;
+        }
+    }
+    p.n_tasks = p.n_tasks_pair = 0;
+    const int64_t n_tasks = ((int64_t)p.n_tiles * p.n_theta) * ceil_div(p.b_end - p.b_begin, WAVES);
+    p.n_tasks = n_tasks;
+    int64_t grid = (int64_t)n_cu * occ;
+    if (grid > n_tasks) grid = n_tasks;
+    p.per_block = ceil_div(n_tasks, grid);
+    grid = ceil_div(n_tasks, p.per_block);
+    hipLaunchKernelGGL((grad_inv_kernel<POL, SEG, WAVES>), dim3((unsigned)grid), dim3(WAVES * kWave), lds, s, p);
+    return hipGetLastError();
+}
+
+// Sixteen-wave blocks while the table leaves room (at most four rows), else eight.
+static hipError_t launch_grad_inv(const GradParams& p, uint32_t pol, int n_cu, hipStream_t s) {
+    if (p.n_mat <= kGradPairLongSegMaxMat) {
+        if (pol == 1u) return launch_grad_inv_t<1, 3, 16>(p, n_cu, s);
+        if (pol == 2u) return launch_grad_inv_t<2, 3, 16>(p, n_cu, s);
+        return launch_grad_inv_t<3, 3, 16>(p, n_cu, s);
+    }
+    if (pol == 1u) return launch_grad_inv_t<1, 3, 8>(p, n_cu, s);
+    if (pol == 2u) return launch_grad_inv_t<2, 3, 8>(p, n_cu, s);
+    return launch_grad_inv_t<3, 3, 8>(p, n_cu, s);
+}
+
 // Checks and the cases without gradient kernels, shared by the entry points.
 // *done = true: nothing (more) to launch, the returned status is final.
 static tmm_status grad_prologue(const tmm_rt_args* a, const void* dl_dR, const void* dl_dT, void* grad_d,
@@ -1269,6 +1626,8 @@ static tmm_status grad_launch(const tmm_rt_args* a, const void* dl_dR, const voi
     p.T_out = static_cast<double*>(a->T);
     p.ws = static_cast<double*>(workspace);
     p.partial = reinterpret_cast<double*>(static_cast<unsigned char*>(workspace) + g.ckpt_bytes);
+    p.redo = nullptr;
+    unsigned char* const redo = reinterpret_cast<unsigned char*>(p.partial) + (size_t)chunk * g.per_stack_partial;
     p.n_tiles = g.n_tiles;
     p.n_seg = g.n_seg;
     p.n_seg_pair = g.n_seg;
@@ -1288,7 +1647,14 @@ static tmm_status grad_launch(const tmm_rt_args* a, const void* dl_dR, const voi
         p.b_end = (int)(b0 + chunk < a->B ? b0 + chunk : a->B);
         p.n_tasks = g.cols * ceil_div(p.b_end - p.b_begin, kGradWaves);
         p.n_tasks_pair = g.cols * ceil_div(p.b_end - p.b_begin, kGradPairWaves);
-        hipError_t e;
+        hipError_t e = hipSuccess;
+        p.redo = nullptr;
+        if (pair) {
+            // lossless columns by the inverse walk; the rest marked for the kernels below
+            p.redo = redo;
+            e = launch_grad_inv(p, a->pol_mask, n_cu, s);
+            if (e != hipSuccess) return check_launch(who);
+        }
         if (pair && seg5)
             e = a->pol_mask == 1u   ? launch_grad_pair<1, 5>(p, n_cu, lds, s)
                 : a->pol_mask == 2u ? launch_grad_pair<2, 5>(p, n_cu, lds, s)
