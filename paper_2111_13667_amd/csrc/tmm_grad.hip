@@ -1078,25 +1078,105 @@ grad_pair_kernel(GradParams p) {
 
 // ---------------------------------------------------------------------------
 // Inverse walk (ratio form, lossless media).  When every table row is lossless
-// and propagating at the block's column (Im q = 0 in every lane), every layer
-// factor E_j = e^{2 i delta_j} has modulus 1 and the ratio step is inverted
-// exactly and stably:
-//   s: u = s' + t', v = conj(E)(s' - t'), s = (u + v)/4, X = (u - v)/4, t = X / rho_s
-//   p: u = s' + t', v = conj(E)(s' - t'), X = (u + v)/4, t = (u - v)/4, s = X / rho_p
+// and propagating at the block's column (Im q = 0 in every lane), every q and
+// eta is real, so are the ratios rho_s = q_{j+1}/q_j and rho_p = eta_{j+1}/eta_j
+// and the derivative factors of the adjoint, and every layer factor
+// E_j = e^{2 i delta_j} has modulus 1.  The ratio step is then inverted exactly
+// and stably: with u = s' + t', D = s' - t' of the step's output and
+// v = conj(E) D / 4,
+//   s: s = u/4 + v, X = rho t = u/4 - v, t = X / rho_s
+//   p: X = rho s = u/4 + v, t = u/4 - v, s = X / rho_p
 // where 1 / rho is the ratio of the reversed material pair (tabulated too).
-// Pass B then walks from the ambient to the substrate recovering each step's
-// input from its output, with no checkpoints and no per-segment register
-// arrays; the adjoint of each step is that of grad_stack_pair.  The state and
-// its adjoint are rescaled together by powers of two (their products, which
-// make the gradients, are unchanged).  Shares are reduced per SEG layers as in
-// grad_stack_pair.
+// Pass B walks from the ambient to the substrate recovering each step's input
+// from its output, with no checkpoints and no per-segment register arrays.
+// The adjoint of each step is that of grad_stack_pair with real rho; its
+// difference term b (s - X or X - t) equals 2 v, so conj(E) Eb reduces to
+// sum_pol conj(D) Y / 2.  The state and its adjoint are rescaled together by
+// powers of two (their products, which make the gradients, are unchanged).
+// Shares are reduced per SEG layers as in grad_stack_pair.
+//
+// Real tables (per lane): material row m holds kInvRows double2 entries
+//   0 {cre, dq/dn}  1 {(dq/dn)/q, (deta/dn)/eta}  2 {q, eta}  3 {deta/dn, 0}
+// with cre = 4 kScSteps q / lambda (the phase of layer thickness d is d cre in
+// units of 1/kScSteps half-turn); the ordered pair (m, m') holds {rho_s, rho_p}.
+constexpr int kInvRows = 4;
+constexpr int kInvRenormSegs = 2;  // segments between rescalings: growth <= 2^9 per step either way
+
+struct InvLayers {
+    const double2* mt;  // material rows + lane: mt[(m * kInvRows + f) * kWave]
+    const double2* pr;  // pair ratios + lane: pr[pair * kWave]
+    double my_d;        // lane l: thickness of layer l + 1
+    int my_code;        // lane l: layer l + 1: pair | reversed pair << 5 | material << 10
+    int my_row;         // lane l: material row of medium l
+    __device__ __forceinline__ double d(int j) const {
+        return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(my_d), j - 1),
+                                __builtin_amdgcn_readlane(__double2loint(my_d), j - 1));
+    }
+    __device__ __forceinline__ int code(int j) const { return __builtin_amdgcn_readlane(my_code, j - 1); }
+    __device__ __forceinline__ int row(int j) const { return __builtin_amdgcn_readlane(my_row, j); }
+    __device__ __forceinline__ double2 ratio(int pair) const { return pr[pair * kWave]; }
+    __device__ __forceinline__ double2 mat(int m, int f) const { return mt[(m * kInvRows + f) * kWave]; }
+};
+
+__host__ __device__ constexpr size_t grad_inv_lds_bytes(int n_mat, int seg, int waves) {
+    return phase_tab_bytes<double>() + (size_t)waves * 3 * seg * kWave * sizeof(double) +
+           (size_t)n_mat * kInvRows * kWave * sizeof(double2) + (size_t)n_mat * n_mat * kWave * sizeof(double2);
+}
+
+// Fill the real tables for the column of wavelength i (this lane) and the
+// ambient row amb_row; flag rows that are lossy or evanescent in some lane
+// (s_lossy), ratios beyond kPairRatioMax (s_bad) and the largest |cre| (s_cmax).
+__device__ void build_inv_table(const GradParams& p, double2* mt, double2* pr, int amb_row, int i, bool lane_used,
+                                double st, double ct, int wave, int lane, int* s_bad, double* s_cmax, int* s_lossy,
+                                int nwaves) {
+    double n0r, n0i;
+    load_n(p.nk, p.dispersive, p.n_wl, amb_row, i, n0r, n0i);
+    const Ambient a = make_ambient(n0r, n0i, st, ct);
+    const double c4s = (4.0 / p.wl[i]) * kScSteps;
+    double cmax = 0.0;
+    for (int m = wave; m < p.n_mat; m += nwaves) {
+        double nr, ni;
+        load_n(p.nk, p.dispersive, p.n_wl, m, i, nr, ni);
+        const Medium md = make_medium(nr, ni, a.kx);
+        const FL f = fl_from(md);
+        const AL g = al_from(nr, ni, f);
+        double2* e = mt + m * kInvRows * kWave + lane;
+        const double cre = c4s * md.qr;
+        e[0] = make_double2(cre, g.nq.re);
+        e[kWave] = make_double2(g.nq.re / md.qr, g.de.re / md.er);
+        e[2 * kWave] = make_double2(md.qr, md.er);
+        e[3 * kWave] = make_double2(g.de.re, 0.0);
+        const bool lossy = __any(md.qi != 0.0);
+        if (lane == 0) s_lossy[m] = lossy ? 1 : 0;
+        if (lane_used) cmax = fmax(cmax, fabs(cre));
+    }
+    bool bad = false;
+    for (int pi = wave; pi < p.n_mat * p.n_mat; pi += nwaves) {
+        const int mc = pi / p.n_mat, mn = pi - mc * p.n_mat;
+        double ar, ai, br, bi;
+        load_n(p.nk, p.dispersive, p.n_wl, mc, i, ar, ai);
+        load_n(p.nk, p.dispersive, p.n_wl, mn, i, br, bi);
+        const Medium ma = make_medium(ar, ai, a.kx), mb = make_medium(br, bi, a.kx);
+        const double rs = mb.qr / ma.qr, rp = mb.er / ma.er;
+        pr[pi * kWave + lane] = make_double2(rs, rp);
+        if (lane_used) bad = bad || !(fmax(fabs(rs), fabs(rp)) <= kPairRatioMax);
+    }
+    const bool wbad = __any(bad);
+    for (int off = kWave / 2; off >= 1; off >>= 1) cmax = fmax(cmax, __shfl_xor(cmax, off));
+    if (lane == 0) {
+        s_bad[wave] = wbad ? 1 : 0;
+        s_cmax[wave] = cmax;
+    }
+}
+
 template <int POL, int SEG>
-__device__ void grad_stack_inv(const GradParams& p, const PairLayers& src, const Ambient& amb, int b, int k, int i,
-                               int lane, bool active, bool valid, int n_mat, double* red, double* part,
+__device__ void grad_stack_inv(const GradParams& p, const InvLayers& src, const Ambient& amb, int b, int k, int i,
+                               int lane, bool active, bool valid, double* red, double* part,
                                const TabPhase<double>& phase) {
     const int L = p.L;
     constexpr int P = (POL == 3) ? 2 : 1;
     const double two_pi_lam = 2.0 * M_PI / p.wl[i];
+    constexpr double kG = M_PI / (2.0 * kScSteps);  // 2 pi q / lambda = kG cre
 
     // ---- pass A: forward (ratio form), renormalised every block ------------
     State z;
@@ -1106,16 +1186,31 @@ __device__ void grad_stack_inv(const GradParams& p, const PairLayers& src, const
     for (int top = L; top >= 1; top -= RPA) {
         const int lo = top - RPA + 1 > 1 ? top - RPA + 1 : 1;
         for (int j = top; j >= lo; --j) {
-            cx<double> rs, rp;
-            double cre, cim;
-            src.pair(src.code(j), rs, rp, cre, cim);
-            ratio_step<POL>(z, rs, rp, phase.cis_g(src.d(j) * cre));
+            const int c = src.code(j);
+            const double2 r = src.ratio(c & 31);
+            const cx<double> E = phase.cis_g(src.d(j) * src.mat(c >> 10, 0).x);
+            if (POL & 1) {
+                const cx<double> X = cscale(r.x, z.ts);
+                const cx<double> a = cadd(z.ss, X), bd = csub(z.ss, X);
+                const cx<double> Eb = cmul(E, bd);
+                z.ss = cadd(a, Eb);
+                z.ts = csub(a, Eb);
+            }
+            if (POL & 2) {
+                const cx<double> X = cscale(r.y, z.sp);
+                const cx<double> a = cadd(X, z.tp), bd = csub(X, z.tp);
+                const cx<double> Eb = cmul(E, bd);
+                z.sp = cadd(a, Eb);
+                z.tp = csub(a, Eb);
+            }
         }
         if (POL & 1) renorm_pair(z.ss, z.ts, es);
         if (POL & 2) renorm_pair(z.sp, z.tp, ep);
     }
     const int m1 = src.row(1), msub = src.row(L + 1);
-    const cx<double> q1 = src.field(m1, 0), e1 = src.field(m1, 1);
+    const double2 qe1 = src.mat(m1, 2);
+    const cx<double> q1 = {qe1.x, 0.0}, e1 = {qe1.y, 0.0};
+    const double2 qesub = src.mat(msub, 2);
     const int two_L1 = 2 * (L + 1);
     const double nan = __builtin_nan("");
     const double w_act = active ? 1.0 : 0.0;  // ragged-tail lanes contribute nothing
@@ -1130,7 +1225,7 @@ __device__ void grad_stack_inv(const GradParams& p, const PairLayers& src, const
         const cx<double> a = cadd(A, Bv), bb = csub(A, Bv);
         const double na = cnorm(a);
         const double R = cnorm(bb) / na;
-        const double T = ldexp(amb.Ks * src.field(msub, 0).re / na, two_L1 - 2 * es);
+        const double T = ldexp(amb.Ks * qesub.x / na, two_L1 - 2 * es);
         const int64_t o = (((int64_t)b * P + 0) * p.n_theta + k) * p.n_wl + i;
         if (active && p.R_out) p.R_out[o] = valid ? R : nan;
         if (active && p.T_out) p.T_out[o] = valid ? T : nan;
@@ -1149,7 +1244,7 @@ __device__ void grad_stack_inv(const GradParams& p, const PairLayers& src, const
         const cx<double> a = cadd(A, Bv), bb = csub(A, Bv);
         const double na = cnorm(a);
         const double R = cnorm(bb) / na;
-        const double T = ldexp(amb.Kp * src.field(msub, 1).re / na, two_L1 - 2 * ep);
+        const double T = ldexp(amb.Kp * qesub.y / na, two_L1 - 2 * ep);
         const int64_t o = (((int64_t)b * P + (P - 1)) * p.n_theta + k) * p.n_wl + i;
         if (active && p.R_out) p.R_out[o] = valid ? R : nan;
         if (active && p.T_out) p.T_out[o] = valid ? T : nan;
@@ -1165,6 +1260,10 @@ __device__ void grad_stack_inv(const GradParams& p, const PairLayers& src, const
     }
     if (!valid) sb_s = tb_s = sb_p = tb_p = pend_q = pend_e = {nan, nan};
     cx<double> wprev_s = {0, 0}, wprev_p = {0, 0};
+    // the ambient step's share of layer 1's index adjoint (through q_1 and eta_1)
+    cx<double> pend_nb = {0.0, 0.0};
+    if (POL & 1) pend_nb = cscale(src.mat(m1, 0).y, pend_q);
+    if (POL & 2) pend_nb = cadd(pend_nb, cscale(src.mat(m1, 3).x, pend_e));
 
     // ---- pass B: from the ambient to the substrate -------------------------
     const int n_seg = (L + SEG - 1) / SEG;
@@ -1176,87 +1275,73 @@ __device__ void grad_stack_inv(const GradParams& p, const PairLayers& src, const
         const int nst = top - lo + 1;
         for (int j = lo; j <= top; ++j) {
             const int t = top - j;  // share slot, as in grad_stack_pair
-            const int code = src.code(j);
-            const int m = src.row(j);
-            cx<double> rs, rp, rs_rev, rp_rev;
-            double cre, cim, cre_r, cim_r;
-            src.pair(code, rs, rp, cre, cim);
-            src.pair((src.row(j + 1) * n_mat + m) * kGradPairBlockBytes, rs_rev, rp_rev, cre_r, cim_r);
+            const int c = src.code(j);
+            const double2 r = src.ratio(c & 31), rr = src.ratio((c >> 5) & 31);
+            const double2 f0 = src.mat(c >> 10, 0), f1 = src.mat(c >> 10, 1);  // {cre, dq/dn}, {dlog q, dlog eta}
             const double dj = src.d(j);
-            const cx<double> E = phase.cis_g(dj * cre);
+            const cx<double> E = phase.cis_g(dj * f0.x);
             const cx<double> Eq = {0.25 * E.re, -0.25 * E.im};  // conj(E) / 4
-            // the step's input from its output z
-            State zin = z;
-            if (POL & 1) {
-                const cx<double> u = cadd(z.ss, z.ts), v = cmul(Eq, csub(z.ss, z.ts));
-                const cx<double> u4 = cscale(0.25, u);
-                zin.ss = cadd(u4, v);
-                zin.ts = cmul(rs_rev, csub(u4, v));
-            }
-            if (POL & 2) {
-                const cx<double> u = cadd(z.sp, z.tp), v = cmul(Eq, csub(z.sp, z.tp));
-                const cx<double> u4 = cscale(0.25, u);
-                zin.tp = csub(u4, v);
-                zin.sp = cmul(rp_rev, cadd(u4, v));
-            }
-            cx<double> Eb = {0.0, 0.0};
+            cx<double> cD;  // sum over the polarisations of conj(D) Y
             cx<double> w_s = {0, 0}, w_p = {0, 0};
             if (POL & 1) {
-                const cx<double> X = cmul(rs, zin.ts);
-                const cx<double> bv = csub(zin.ss, X);
+                const cx<double> D = csub(z.ss, z.ts), u4 = cscale(0.25, cadd(z.ss, z.ts));
+                const cx<double> v = cmul(Eq, D);
+                const cx<double> X = csub(u4, v);
+                z.ss = cadd(u4, v);
+                z.ts = cscale(rr.x, X);
                 const cx<double> ab = cadd(sb_s, tb_s), Y = csub(sb_s, tb_s);
                 const cx<double> bb = cmulc(E, Y);
-                Eb = cadd(Eb, cmulc(bv, Y));
+                cD = cmulc(D, Y);
                 const cx<double> Xb = csub(ab, bb);
                 sb_s = cadd(ab, bb);
-                tb_s = cmulc(rs, Xb);
+                tb_s = cscale(r.x, Xb);
                 w_s = cmulc(X, Xb);
             }
             if (POL & 2) {
-                const cx<double> X = cmul(rp, zin.sp);
-                const cx<double> bv = csub(X, zin.tp);
+                const cx<double> D = csub(z.sp, z.tp), u4 = cscale(0.25, cadd(z.sp, z.tp));
+                const cx<double> v = cmul(Eq, D);
+                const cx<double> X = cadd(u4, v);
+                z.tp = csub(u4, v);
+                z.sp = cscale(rr.y, X);
                 const cx<double> ab = cadd(sb_p, tb_p), Y = csub(sb_p, tb_p);
                 const cx<double> bb = cmulc(E, Y);
-                Eb = cadd(Eb, cmulc(bv, Y));
+                cD = (POL & 1) ? cadd(cD, cmulc(D, Y)) : cmulc(D, Y);
                 const cx<double> Xb = cadd(ab, bb);
                 tb_p = csub(ab, bb);
-                sb_p = cmulc(rp, Xb);
+                sb_p = cscale(r.y, Xb);
                 w_p = cmulc(X, Xb);
             }
-            const cx<double> qj = src.field(m, 0);
-            // deltab = -2i conj(E) Eb - 2i cT  (chain and e^{-2 Im sum delta})
-            const cx<double> cE = cmulc(E, Eb);
-            const cx<double> db = {2.0 * cE.im, -2.0 * cE.re - 2.0 * cT};
-            const double gd = two_pi_lam * (db.re * qj.re + db.im * qj.im);
-            const cx<double> qb = cadd(pend_q, cscale(two_pi_lam * dj, db));
-            cx<double> nb = cmulc(src.field(m, 2), qb);
-            if (POL & 2) nb = cadd(nb, cmulc(src.field(m, 3), pend_e));
-            if (POL & 1) nb = cadd(nb, cmulc(src.field(m, 4), csub(wprev_s, w_s)));
-            if (POL & 2) nb = cadd(nb, cmulc(src.field(m, 5), csub(wprev_p, w_p)));
+            // deltab = -2i conj(E) Eb - 2i cT = -i cD - 2i cT (chain and e^{-2 Im sum delta})
+            const cx<double> db = {two_pi_lam * cD.im, -two_pi_lam * (cD.re + 2.0 * cT)};
+            const double gd = kG * cD.im * f0.x;
+            cx<double> nb = cadd(pend_nb, cscale(f0.y * dj, db));
+            if (POL & 1) nb = cadd(nb, cscale(f1.x, csub(wprev_s, w_s)));
+            if (POL & 2) nb = cadd(nb, cscale(f1.y, csub(wprev_p, w_p)));
             wprev_s = w_s;
             wprev_p = w_p;
-            pend_q = pend_e = {0.0, 0.0};
+            pend_nb = {0.0, 0.0};
             red[(3 * t + 0) * kWave + lane] = gd;
             red[(3 * t + 1) * kWave + lane] = nb.re;
             red[(3 * t + 2) * kWave + lane] = nb.im;
-            z = zin;
         }
         // keep the walked state near 1: scale it and its adjoint inversely
-        if (POL & 1) {
-            const int e = pair_exp(z.ss, z.ts);
-            const double f = ldexp(1.0, -e), g = ldexp(1.0, e);
-            z.ss = cscale(f, z.ss);
-            z.ts = cscale(f, z.ts);
-            sb_s = cscale(g, sb_s);
-            tb_s = cscale(g, tb_s);
-        }
-        if (POL & 2) {
-            const int e = pair_exp(z.sp, z.tp);
-            const double f = ldexp(1.0, -e), g = ldexp(1.0, e);
-            z.sp = cscale(f, z.sp);
-            z.tp = cscale(f, z.tp);
-            sb_p = cscale(g, sb_p);
-            tb_p = cscale(g, tb_p);
+        if (s % kInvRenormSegs == 0) {
+            if (POL & 1) {
+                const int e = pair_exp(z.ss, z.ts);
+                const double f = ldexp(1.0, -e), g = ldexp(1.0, e);
+                z.ss = cscale(f, z.ss);
+                z.ts = cscale(f, z.ts);
+                sb_s = cscale(g, sb_s);
+                tb_s = cscale(g, tb_s);
+            }
+            if (POL & 2) {
+                const int e = pair_exp(z.sp, z.tp);
+                const double f = ldexp(1.0, -e), g = ldexp(1.0, e);
+                z.sp = cscale(f, z.sp);
+                z.tp = cscale(f, z.tp);
+                sb_p = cscale(g, sb_p);
+                tb_p = cscale(g, tb_p);
+            }
         }
         wave_sync();
         double acc = 0.0;
@@ -1277,15 +1362,10 @@ __device__ void grad_stack_inv(const GradParams& p, const PairLayers& src, const
     }
 }
 
-__host__ __device__ constexpr size_t grad_inv_lds_bytes(int n_mat, int seg, int waves) {
-    return phase_tab_bytes<double>() + (size_t)waves * 3 * seg * kWave * sizeof(double) +
-           (size_t)n_mat * kPairFields * kWave * sizeof(double2) + (size_t)n_mat * n_mat * kGradPairBlockBytes;
-}
-
 // Persistent blocks of WAVES waves over tasks (column, group of WAVES stacks),
-// the block's pair table as in grad_pair_kernel.  Stacks whose column is not
-// lossless, whose ratios leave their bound or whose phases leave the fast
-// range are marked in p.redo and left to grad_pair_kernel.
+// the block's real tables built per (column, ambient row) as in grad_pair_kernel.
+// Stacks whose column is not lossless, whose ratios leave their bound or whose
+// phases leave the fast range are marked in p.redo and left to grad_pair_kernel.
 template <int POL, int SEG, int WAVES>
 __global__ void __launch_bounds__(WAVES * kWave) grad_inv_kernel(GradParams p) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -1300,8 +1380,8 @@ __global__ void __launch_bounds__(WAVES * kWave) grad_inv_kernel(GradParams p) {
     const TabPhase<double> phase = phase_of<double>(smem);
     unsigned char* const lds = smem + phase_tab_bytes<double>();
     double* red = reinterpret_cast<double*>(lds) + wave * (3 * SEG) * kWave;
-    double2* mtab = reinterpret_cast<double2*>(lds + (size_t)WAVES * (3 * SEG) * kWave * sizeof(double));
-    unsigned char* pairs = reinterpret_cast<unsigned char*>(mtab + (size_t)p.n_mat * kPairFields * kWave);
+    double2* mt = reinterpret_cast<double2*>(lds + (size_t)WAVES * (3 * SEG) * kWave * sizeof(double));
+    double2* pr = mt + (size_t)p.n_mat * kInvRows * kWave;
     const int L2 = p.L + 2;
     const int64_t nbs = p.b_end - p.b_begin;
     const int64_t groups = (nbs + WAVES - 1) / WAVES;
@@ -1340,7 +1420,7 @@ __global__ void __launch_bounds__(WAVES * kWave) grad_inv_kernel(GradParams p) {
                 double n0r, n0i;
                 load_n(p.nk, p.dispersive, p.n_wl, r, i, n0r, n0i);
                 const bool used = active && lam_ok && make_ambient(n0r, n0i, st, ct).ok;
-                build_pair_table(p, mtab, pairs, r, i, used, st, ct, wave, lane, s_bad, s_cmax, s_lossy, WAVES);
+                build_inv_table(p, mt, pr, r, i, used, st, ct, wave, lane, s_bad, s_cmax, s_lossy, WAVES);
                 tab_row = r;
                 tab_col = col;
             }
@@ -1357,9 +1437,9 @@ __global__ void __launch_bounds__(WAVES * kWave) grad_inv_kernel(GradParams p) {
                 load_n(p.nk, p.dispersive, p.n_wl, a_row, i, n0r, n0i);
                 const Ambient amb = make_ambient(n0r, n0i, st, ct);
                 const bool ok = lam_ok && amb.ok && !bad;
-                PairLayers src;
-                src.mtab = mtab + lane;
-                src.pair_lane = pairs + lane * 16;
+                InvLayers src;
+                src.mt = mt + lane;
+                src.pr = pr + lane;
                 src.my_d = lane < p.L ? drow[lane] : 0.0;
                 int m_row = lane < L2 ? mrow[lane] : 0;
                 m_row = m_row < 0 ? 0 : (m_row >= p.n_mat ? p.n_mat - 1 : m_row);
@@ -1368,11 +1448,10 @@ __global__ void __launch_bounds__(WAVES * kWave) grad_inv_kernel(GradParams p) {
                 m_nx = m_nx < 0 ? 0 : (m_nx >= p.n_mat ? p.n_mat - 1 : m_nx);
                 const int m_cur = __shfl_down(m_row, 1, kWave);
                 const int m_nxt = __shfl_down(m_nx, 1, kWave);
-                src.my_code = (m_cur * p.n_mat + m_nxt) * kGradPairBlockBytes;
+                src.my_code = (m_cur * p.n_mat + m_nxt) | (m_nxt * p.n_mat + m_cur) << 5 | m_cur << 10;
                 const bool far = __any(lane < p.L && !(src.my_d <= (0.5 * kScFastRange) / cm));
                 const bool mine = any_bad == 0 && any_lossy == 0 && !far;
-                if (mine)
-                    grad_stack_inv<POL, SEG>(p, src, amb, b, tk_k, i, lane, active, ok, p.n_mat, red, part, phase);
+                if (mine) grad_stack_inv<POL, SEG>(p, src, amb, b, tk_k, i, lane, active, ok, red, part, phase);
                 if (lane == 0) p.redo[(size_t)col * nbs + (b - p.b_begin)] = mine ? 0 : 1;
                 done = true;
             }
@@ -1557,14 +1636,10 @@ static hipError_t launch_grad_inv_t(GradParams p, int n_cu, hipStream_t s) {
 
 // Sixteen-wave blocks while the table leaves room (at most four rows), else eight.
 static hipError_t launch_grad_inv(const GradParams& p, uint32_t pol, int n_cu, hipStream_t s) {
-    if (p.n_mat <= kGradPairLongSegMaxMat) {
-        if (pol == 1u) return launch_grad_inv_t<1, 3, 16>(p, n_cu, s);
-        if (pol == 2u) return launch_grad_inv_t<2, 3, 16>(p, n_cu, s);
-        return launch_grad_inv_t<3, 3, 16>(p, n_cu, s);
-    }
-    if (pol == 1u) return launch_grad_inv_t<1, 3, 8>(p, n_cu, s);
-    if (pol == 2u) return launch_grad_inv_t<2, 3, 8>(p, n_cu, s);
-    return launch_grad_inv_t<3, 3, 8>(p, n_cu, s);
+    static_assert(grad_inv_lds_bytes(kGradPairMaxMat, 3, 16) <= 160 * 1024, "inverse-walk tables exceed LDS");
+    if (pol == 1u) return launch_grad_inv_t<1, 3, 16>(p, n_cu, s);
+    if (pol == 2u) return launch_grad_inv_t<2, 3, 16>(p, n_cu, s);
+    return launch_grad_inv_t<3, 3, 16>(p, n_cu, s);
 }
 
 // Checks and the cases without gradient kernels, shared by the entry points.
