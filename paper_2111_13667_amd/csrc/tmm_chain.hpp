@@ -70,6 +70,39 @@ struct Chain {
         }
     }
 
+    // The same step when the caller knows (wave-uniformly) that the current
+    // medium (CR) and / or the next one (NR) is lossless and propagating in
+    // every lane: Im q = Im eta = 0, so their products with the state are real
+    // scalings, |q|^2 = (Re q)^2 and the step adds nothing to S.  The results
+    // are those of step() (the dropped terms are exact zeros).
+    template <bool CR, bool NR>
+    __device__ __forceinline__ void step_known(const Layer<R>& cur, const Layer<R>& nxt, double cd,
+                                               const TabPhase<R>& phase) {
+        const double phr = cd * cur.pr;
+        const double phi = CR ? 0.0 : cd * cur.pi;
+        const cx<R> E = phase(phr, phi, !CR);
+        if (POL & 1) {
+            const cx<R> A = CR ? cscale(cur.q.re, ss) : cmul(cur.q, ss);
+            const cx<R> Bv = NR ? cscale(nxt.q.re, ts) : cmul(nxt.q, ts);
+            const cx<R> a = cadd(A, Bv), b = csub(A, Bv);
+            const cx<R> Eb = cmul(E, b);
+            ss = cadd(a, Eb);
+            ts = csub(a, Eb);
+        }
+        if (POL & 2) {
+            const cx<R> A = NR ? cscale(nxt.e.re, sp) : cmul(nxt.e, sp);
+            const cx<R> Bv = CR ? cscale(cur.e.re, tp) : cmul(cur.e, tp);
+            const cx<R> a = cadd(A, Bv), b = csub(A, Bv);
+            const cx<R> Eb = cmul(E, b);
+            sp = cadd(a, Eb);
+            tp = csub(a, Eb);
+        }
+        static_assert(!AMP, "amplitude chains use step()");
+        if (POL & 1) pis *= CR ? cur.q.re * cur.q.re : cur.q2;
+        if (POL & 2) pip *= CR ? cur.e.re * cur.e.re : cur.e2;
+        if (!CR) S += phi;
+    }
+
     __device__ __forceinline__ void renorm() {
         if (POL & 1) renorm_pair(ss, ts, es);
         if (POL & 2) renorm_pair(sp, tp, ep);

@@ -115,6 +115,25 @@ __device__ __forceinline__ Medium make_medium(double nr, double ni, double kx) {
     return m;
 }
 
+// make_medium for a real index with n^2 > kx^2 (a lossless, propagating
+// medium in this lane): the same operations with Im n = 0 and the complex
+// square root reduced to a real one (sqrt(z^2) = |z| exactly), so the same
+// values, at a third of the cost.
+__device__ __forceinline__ Medium make_medium_lossless(double nr, double kx) {
+    const double ur = nr * nr;
+    const double zr = ur - kx * kx;
+    const double qr = sqrt(zr);
+    Medium m;
+    m.qr = qr;
+    m.qi = 0.0;
+    m.q2 = qr * qr;
+    const double inv = 1.0 / m.q2;
+    m.er = (ur * qr) * inv;
+    m.ei = 0.0;
+    m.e2 = m.er * m.er;
+    return m;
+}
+
 // Values of one medium as the chain consumes them, in the kernel's real type R,
 // plus q in double for the phase.
 template <typename R>

@@ -252,9 +252,14 @@ __global__ void __launch_bounds__(kMaxThreads) ragged_kernel(Params<R> p) {
             uint32_t lossy_mask = 0;
             for (int m = 0; m < p.n_mat; ++m) {
                 const int64_t e = (int64_t)m * p.nk_stride + col;
-                const Medium md = make_medium((double)p.nk[2 * e], (double)p.nk[2 * e + 1], amb.kx);
-                tab.put(m, lane, md);
-                if (__any(md.qi != 0.0)) lossy_mask |= 1u << m;
+                const double nr = (double)p.nk[2 * e], ni = (double)p.nk[2 * e + 1];
+                if (__all(ni == 0.0 && nr * nr - amb.kx * amb.kx > 0.0)) {
+                    tab.put(m, lane, make_medium_lossless(nr, amb.kx));
+                } else {
+                    const Medium md = make_medium(nr, ni, amb.kx);
+                    tab.put(m, lane, md);
+                    if (__any(md.qi != 0.0)) lossy_mask |= 1u << m;
+                }
             }
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
@@ -289,7 +294,20 @@ __global__ void __launch_bounds__(kMaxThreads) ragged_kernel(Params<R> p) {
                         const int m = __builtin_amdgcn_readlane(my_m, sl);
                         const double dj = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(my_d), sl),
                                                            __builtin_amdgcn_readlane(__double2loint(my_d), sl));
-                        c.step(tab.get(m, lane), tab.get(nxt_row, lane), dj * c4lam, (lossy_mask >> m) & 1u, phase);
+                        const Layer<R> cur = tab.get(m, lane), nx = tab.get(nxt_row, lane);
+                        const double cd = dj * c4lam;
+                        // lossless rows (bit clear) step with real q and eta
+                        if (((lossy_mask >> m) & 1u) == 0) {
+                            if (((lossy_mask >> nxt_row) & 1u) == 0)
+                                c.template step_known<true, true>(cur, nx, cd, phase);
+                            else
+                                c.template step_known<true, false>(cur, nx, cd, phase);
+                        } else {
+                            if (((lossy_mask >> nxt_row) & 1u) == 0)
+                                c.template step_known<false, true>(cur, nx, cd, phase);
+                            else
+                                c.template step_known<false, false>(cur, nx, cd, phase);
+                        }
                         nxt_row = m;
                     };
                     // renormalisation blocks at the points of a running step count
