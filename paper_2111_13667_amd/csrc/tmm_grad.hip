@@ -1101,6 +1101,11 @@ grad_pair_kernel(GradParams p) {
 // units of 1/kScSteps half-turn); the ordered pair (m, m') holds {rho_s, rho_p}.
 constexpr int kInvRows = 4;
 constexpr int kInvRenormSegs = 2;  // segments between rescalings: growth <= 2^9 per step either way
+// Share vectors of the inverse walk are kInvRedStride doubles apart (64 values +
+// 8 of padding): with each lane quad reading its vector in interleaved 16-byte
+// pieces, any eight consecutive lanes then read 128 distinct bytes (no bank
+// conflicts in the segment reduction).
+constexpr int kInvRedStride = kWave + 8;
 
 struct InvLayers {
     const double2* mt;  // material rows + lane: mt[(m * kInvRows + f) * kWave]
@@ -1119,7 +1124,7 @@ struct InvLayers {
 };
 
 __host__ __device__ constexpr size_t grad_inv_lds_bytes(int n_mat, int seg, int waves) {
-    return phase_tab_bytes<double>() + (size_t)waves * 3 * seg * kWave * sizeof(double) +
+    return phase_tab_bytes<double>() + (size_t)waves * 3 * seg * kInvRedStride * sizeof(double) +
            (size_t)n_mat * kInvRows * kWave * sizeof(double2) + (size_t)n_mat * n_mat * kWave * sizeof(double2);
 }
 
@@ -1268,7 +1273,8 @@ __device__ void grad_stack_inv(const GradParams& p, const InvLayers& src, const 
     // ---- pass B: from the ambient to the substrate -------------------------
     const int n_seg = (L + SEG - 1) / SEG;
     const int v_red = lane >> 2 < (3 * SEG) ? lane >> 2 : (3 * SEG) - 1;  // share this lane sums
-    const double2* red_in = reinterpret_cast<const double2*>(red + v_red * kWave + (lane & 3) * 16);
+    // quarter (lane & 3) of that share: values 8u + 2 (lane & 3) and the next, u = 0..7
+    const double2* red_in = reinterpret_cast<const double2*>(red + v_red * kInvRedStride) + (lane & 3);
     for (int s = n_seg - 1; s >= 0; --s) {
         const int top = L - s * SEG;
         const int lo = top - SEG + 1 > 1 ? top - SEG + 1 : 1;
@@ -1320,9 +1326,9 @@ __device__ void grad_stack_inv(const GradParams& p, const InvLayers& src, const 
             wprev_s = w_s;
             wprev_p = w_p;
             pend_nb = {0.0, 0.0};
-            red[(3 * t + 0) * kWave + lane] = gd;
-            red[(3 * t + 1) * kWave + lane] = nb.re;
-            red[(3 * t + 2) * kWave + lane] = nb.im;
+            red[(3 * t + 0) * kInvRedStride + lane] = gd;
+            red[(3 * t + 1) * kInvRedStride + lane] = nb.re;
+            red[(3 * t + 2) * kInvRedStride + lane] = nb.im;
         }
         // keep the walked state near 1: scale it and its adjoint inversely
         if (s % kInvRenormSegs == 0) {
@@ -1347,7 +1353,7 @@ __device__ void grad_stack_inv(const GradParams& p, const InvLayers& src, const 
         double acc = 0.0;
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
-            const double2 x = red_in[u];
+            const double2 x = red_in[4 * u];
             acc += x.x;
             acc += x.y;
         }
@@ -1379,8 +1385,8 @@ __global__ void __launch_bounds__(WAVES * kWave) grad_inv_kernel(GradParams p) {
     __syncthreads();
     const TabPhase<double> phase = phase_of<double>(smem);
     unsigned char* const lds = smem + phase_tab_bytes<double>();
-    double* red = reinterpret_cast<double*>(lds) + wave * (3 * SEG) * kWave;
-    double2* mt = reinterpret_cast<double2*>(lds + (size_t)WAVES * (3 * SEG) * kWave * sizeof(double));
+    double* red = reinterpret_cast<double*>(lds) + wave * (3 * SEG) * kInvRedStride;
+    double2* mt = reinterpret_cast<double2*>(lds + (size_t)WAVES * (3 * SEG) * kInvRedStride * sizeof(double));
     double2* pr = mt + (size_t)p.n_mat * kInvRows * kWave;
     const int L2 = p.L + 2;
     const int64_t nbs = p.b_end - p.b_begin;

@@ -292,6 +292,24 @@ def test_ratio_form_mixed_ambients_and_near_critical_fallback():
     _check_against_oracle(w, rng.normal(size=shape), rng.normal(size=shape))
 
 
+@pytest.mark.parametrize("L", [9, 62])
+def test_inverse_walk_columns_next_to_redone_columns(L):
+    # One material starts to absorb inside the wavelength grid: the 64-wavelength
+    # column below the edge is lossless everywhere and takes the inverse walk, the
+    # column holding the edge and those above it are flagged and redone by the
+    # checkpointed kernel, and both kinds of column feed the same fixed-order sum.
+    from dataclasses import replace
+    w = _material_workload(86 + L, B=5, L=L, n_wl=200, n_theta=2, n_inner=3, k_max=0.0)
+    nk = w.nk.copy()
+    nk[1] = nk[1].real + 1j * np.where(w.wl > w.wl[100], 5e-3, 0.0)
+    mat = w.mat.copy()
+    mat[:, 1 + np.arange(0, L, 3)] = 1   # every stack holds the absorbing material
+    w = replace(w, nk=nk, mat=mat)
+    rng = np.random.default_rng(87)
+    shape = (w.B, 2, w.theta.size, w.wl.size)
+    _check_against_oracle(w, rng.normal(size=shape), rng.normal(size=shape))
+
+
 @pytest.mark.parametrize("L", [7, 13, 60])
 def test_ratio_form_five_layer_kernel_fallback(L):
     # Four table rows (air, one dielectric, ambient 1.5, substrate 1.52): the
