@@ -329,7 +329,7 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py: this build measures one GPU only; every point is independent and "
+        print("bench.py measures one GPU only; every point is independent and "
               "stacks would shard across GPUs with no exchange, but no multi-GPU run is "
               "provided. Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)

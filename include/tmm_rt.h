@@ -47,7 +47,7 @@ extern "C" {
 typedef enum tmm_status {
     TMM_OK = 0,
     TMM_ERR_INVALID_ARG = 1, /* a size, pointer or flag is out of its documented range */
-    TMM_ERR_UNSUPPORTED = 2, /* a valid request this build does not handle           */
+    TMM_ERR_UNSUPPORTED = 2, /* a valid request the library does not handle          */
     TMM_ERR_NONFINITE = 3,   /* TMM_CHECK_FINITE found a NaN or infinity in an input   */
     TMM_ERR_HIP = 4,         /* the HIP runtime reported an error on launch            */
     TMM_ERR_WORKSPACE = 5    /* a caller-provided workspace is missing or too small    */
