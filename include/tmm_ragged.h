@@ -96,9 +96,11 @@ tmm_status tmm_rt_ragged(tmm_ragged_plan *plan, const tmm_ragged_data *data, tmm
  * workgroup, lanes per point}.  TMM_ERR_INVALID_ARG before tuning. */
 tmm_status tmm_ragged_plan_shape(const tmm_ragged_plan *plan, tmm_dtype dtype, int32_t *host_shape);
 
-/* Set the launch shape for dtype instead of tuning (same layout as above).
- * The LDS of a workgroup must fit the CU (8 KiB phase table plus 2 KiB per
- * index-table row and wave); an oversized shape fails at launch with
+/* Set the launch shape for dtype instead of tuning (same layout as above):
+ * at most 12 waves per workgroup in TMM_F64 and 16 in TMM_F32 (the kernels'
+ * register limits), at most 32 waves per CU.  The LDS of a workgroup must fit
+ * the CU (TMM_F64: 8 KiB phase table plus 2 KiB per index-table row and wave;
+ * TMM_F32: 4 KiB plus 1.5 KiB); an oversized shape fails at launch with
  * TMM_ERR_HIP. */
 tmm_status tmm_ragged_plan_set_shape(tmm_ragged_plan *plan, tmm_dtype dtype, const int32_t *host_shape);
 

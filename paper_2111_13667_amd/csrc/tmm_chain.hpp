@@ -19,6 +19,8 @@ template <> struct RenormPeriod<float> { static constexpr int value = 4; };
 template <typename R, int POL, bool AMP>
 struct Chain {
     static constexpr bool kRatio = false;
+    static constexpr double kSLog2 = kNegPiLog2e;  // S times this is log2 of the attenuation
+    __device__ __forceinline__ static double exp2_ext(double y) { return exp2_d<true>(y); }
     cx<R> ss, ts, sp, tp;  // sigma, tau of s and p
     int es, ep;            // power-of-two exponents taken out of (ss, ts), (sp, tp)
     R pis, pip;            // prod |q_j|^2, prod |eta_j|^2 (R, T only)
@@ -137,6 +139,8 @@ template <> struct PairRenormPeriod<float> { static constexpr int value = 8; };
 template <typename R, int POL, bool AMP>
 struct PairChain {
     static constexpr bool kRatio = true;
+    static constexpr double kSLog2 = 1.0;
+    __device__ __forceinline__ static double exp2_ext(double y) { return exp2_d<true>(y); }
     cx<R> ss, ts, sp, tp;
     int es, ep;
     double S;  // sum of y_j = -pi Im(phi_j) / ln 2: log2 of the attenuation
@@ -192,18 +196,19 @@ struct PointOut {
 };
 
 // Ambient step (j = 0, no phase) and extraction of r, t, R, T (Eq. (3), (7)).
-// C is Chain (division-free) or PairChain (ratio form: the products are 1 and S
-// is already the base-2 exponent).
+// C is Chain (division-free) or PairChain (ratio form: the products are 1);
+// C::kSLog2 turns its S into the base-2 exponent of the attenuation, and
+// C::exp2_ext is the 2^y the extraction uses.
 template <typename R, int POL, bool AMP, class C>
 __device__ __forceinline__ void finish(const C& c, const Ambient& amb,
                                        const Layer<R>& first, const Layer<R>& sub,
                                        double nsub_r, double nsub_i, int L, PointOut* out,
                                        const TabPhase<R>& phase) {
-    const double ly = C::kRatio ? c.S : c.S * kNegPiLog2e;
+    const double ly = c.S * C::kSLog2;
     const double Fh = C::kRatio ? c.F * (1.0 / kScSteps) : c.F;  // half-turns
     // the layer loop's own 2^y and table sin/cos (their constants are already
     // resident; library versions would add their own per stack)
-    const double eS = exp2_d<true>(ly);
+    const double eS = C::exp2_ext(ly);
     const int two_L1 = 2 * (L + 1);
     if (POL & 1) {
         const cx<double> q0 = {amb.q0r, amb.q0i};
@@ -234,7 +239,7 @@ __device__ __forceinline__ void finish(const C& c, const Ambient& amb,
             o.r = cdiv(b, a);
             const cx<R> rot = phase.cis_g(sc_exact_g(0.5 * Fh));
             const double cs = (double)rot.re, sn = (double)rot.im;
-            const double m = exp2_d<true>(0.5 * ly);
+            const double m = C::exp2_ext(0.5 * ly);
             const cx<double> ph = {m * cs, m * sn};
             cx<double> num = cmul(cmul(q0, Pq), ph);
             cx<double> tt = cdiv(num, a);
@@ -271,7 +276,7 @@ __device__ __forceinline__ void finish(const C& c, const Ambient& amb,
             o.r = cdiv(b, a);
             const cx<R> rot = phase.cis_g(sc_exact_g(0.5 * Fh));
             const double cs = (double)rot.re, sn = (double)rot.im;
-            const double m = exp2_d<true>(0.5 * ly);
+            const double m = C::exp2_ext(0.5 * ly);
             const cx<double> ph = {m * cs, m * sn};
             // P_p = 2^{L+1} n_0 n_sub / q_sub prod eta_j
             const cx<double> n0 = {amb.n0r, amb.n0i};

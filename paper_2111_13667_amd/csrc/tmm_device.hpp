@@ -197,8 +197,8 @@ struct TabPhase<float> {
         sincospi_g_f(g, tab, s, c);
         return {c, s};
     }
-    __device__ __forceinline__ float atten(double yd) const {
-        const float y = (float)yd;
+    __device__ __forceinline__ float atten(double yd) const { return atten_f((float)yd); }
+    __device__ __forceinline__ float atten_f(float y) const {
         return __all(__builtin_fabsf(y) <= (float)kExp2WeakRange) ? horner<true>(kExp2SF, y) : exp2_f(y);
     }
     __device__ __forceinline__ cx<float> operator()(double phr, double phi_im, bool lossy) const {

@@ -8,10 +8,16 @@
 // four lanes share a point (layer split, below).  Units are ordered by
 // decreasing layer count (longest chains first) and handed out through an
 // atomic counter, so a wave that finishes early takes the next unit.  For
-// every unit each lane computes q, eta of each index-table row at its own
-// (wavelength, angle) into the wave's LDS slice, then runs the layer loop of
+// every unit each lane computes q, eta of the index-table rows the stack uses
+// (its layers' materials and the substrate) at its own (wavelength, angle)
+// into the wave's LDS slice, then runs the division-free layer recursion of
 // the dense kernels (tmm_chain.hpp) on table lookups; the stack's layer data
 // are wave-uniform.
+//
+// Phase of a layer of thickness d in units of 1/256 half-turn:
+// g = d (1024 / lambda) Re q, reduced to a table point by the rounding-constant
+// add of tmm_math.hpp (exact for |g| < 2^50; a unit whose thickness and
+// indices could exceed that first reduces g modulo 512 exactly).
 //
 // Layer split (LPP = 2 or 4 lanes per point): the stack's layers are cut into
 // LPP contiguous segments; lane s of a point's group runs segment s as a 2x2
@@ -42,12 +48,20 @@ namespace tmm {
 namespace ragged {
 
 // Every wave works on its own units with its own media table; a workgroup is
-// 1-12 such waves plus the shared phase table, sized at launch so that the
-// CU's resident waves fit its LDS.
-constexpr int kMaxThreads = 768;
+// 1-16 such waves plus the shared phase table, sized at launch so that the
+// CU's resident waves fit its LDS.  Resident waves per CU that the kernels'
+// registers allow: 3 per SIMD in double (up to 168 VGPRs), 4 in float (128).
+template <typename R> struct Occupancy;
+template <> struct Occupancy<double> { static constexpr int kWavesPerCU = 12; };
+template <> struct Occupancy<float> { static constexpr int kWavesPerCU = 16; };
+constexpr int kMaxWavesPerCU = 16;
 constexpr int kMaxMat = 8;
 constexpr size_t kLdsPerCU = 160 * 1024;
 constexpr int kLppChoices[3] = {1, 2, 4};
+// A unit whose largest phase coefficient is below 2^kPhaseCoefExp (per unit
+// thickness, units of 1/256 half-turn) takes the direct reduction for every
+// layer thinner than 2^(49 - kPhaseCoefExp).
+constexpr int kPhaseCoefExp = 20;
 
 template <typename R>
 struct Params {
@@ -74,10 +88,17 @@ struct Params {
     int grain;
 };
 
-// Per-wave media table: q and eta of every index-table row at each lane's own
-// point (|q|^2 and |eta|^2 are recomputed in the loop, which keeps the slice at
-// 32 bytes per (row, lane) and the occupancy up).  One block per row:
-// FP64 [q (double2)][eta (double2)]; FP32 [q in double (double2)][q (float2)][eta (float2)].
+// One index-table row at a lane's point, as the layer step consumes it.
+//   FP64: q, eta; the step forms the phase from d (1024 / lambda) and q.
+//   FP32: q, eta in float and c = 1024 Re(q) / lambda in double for the phase
+//         (reduced in double, evaluated in float, as in the dense kernels).
+template <typename R> struct Row;
+template <> struct Row<double> { cx<double> q, e; };
+template <> struct Row<float> { cx<float> q, e; double c; };
+
+// Per-wave media table in LDS, one block per index-table row, structure of arrays:
+//   FP64 [q (double2) x 64][eta (double2) x 64]                     32 bytes per (row, lane)
+//   FP32 [c (double) x 64][q.re, q.im, eta.re, eta.im (float4) x 64] 24 bytes per (row, lane)
 template <typename R> struct WaveTable;
 
 template <>
@@ -85,54 +106,199 @@ struct WaveTable<double> {
     static constexpr int kBlockBytes = kWave * 32;
     unsigned char* base;
     __device__ WaveTable(unsigned char* b) : base(b) {}
-    __device__ __forceinline__ void put(int m, int lane, const Medium& md) {
+    __device__ __forceinline__ void put(int m, int lane, double qr, double qi, double er, double ei, double) {
         double2* blk = reinterpret_cast<double2*>(base + m * kBlockBytes);
-        blk[lane] = make_double2(md.qr, md.qi);
-        blk[kWave + lane] = make_double2(md.er, md.ei);
+        blk[lane] = make_double2(qr, qi);
+        blk[kWave + lane] = make_double2(er, ei);
     }
-    __device__ __forceinline__ Layer<double> get(int m, int lane) const {
+    __device__ __forceinline__ Row<double> get(int m, int lane) const {
         const double2* blk = reinterpret_cast<const double2*>(base + m * kBlockBytes) + lane;
         const double2 a = blk[0], b = blk[kWave];
-        Layer<double> v;
-        v.q = {a.x, a.y};
-        v.e = {b.x, b.y};
-        v.q2 = a.x * a.x + a.y * a.y;
-        v.e2 = b.x * b.x + b.y * b.y;
-        v.pr = a.x;
-        v.pi = a.y;
-        return v;
+        return {{a.x, a.y}, {b.x, b.y}};
     }
+    __device__ __forceinline__ Row<double> get_qe(int m, int lane) const { return get(m, lane); }
 };
 
 template <>
 struct WaveTable<float> {
-    static constexpr int kBlockBytes = kWave * 32;
+    static constexpr int kBlockBytes = kWave * 24;
     unsigned char* base;
     __device__ WaveTable(unsigned char* b) : base(b) {}
-    __device__ __forceinline__ void put(int m, int lane, const Medium& md) {
+    __device__ __forceinline__ void put(int m, int lane, double qr, double qi, double er, double ei, double c) {
         unsigned char* blk = base + m * kBlockBytes;
-        reinterpret_cast<double2*>(blk)[lane] = make_double2(md.qr, md.qi);
-        float2* f = reinterpret_cast<float2*>(blk + kWave * 16);
-        f[lane] = make_float2((float)md.qr, (float)md.qi);
-        f[kWave + lane] = make_float2((float)md.er, (float)md.ei);
+        reinterpret_cast<double*>(blk)[lane] = c;
+        reinterpret_cast<float4*>(blk + kWave * 8)[lane] = make_float4((float)qr, (float)qi, (float)er, (float)ei);
     }
-    __device__ __forceinline__ Layer<float> get(int m, int lane) const {
-        const unsigned char* blk = base + m * kBlockBytes;
-        const double2 p = reinterpret_cast<const double2*>(blk)[lane];
-        const float2* f = reinterpret_cast<const float2*>(blk + kWave * 16) + lane;
-        const float2 a = f[0], b = f[kWave];
-        Layer<float> v;
-        v.q = {a.x, a.y};
-        v.e = {b.x, b.y};
-        v.q2 = a.x * a.x + a.y * a.y;
-        v.e2 = b.x * b.x + b.y * b.y;
-        v.pr = p.x;
-        v.pi = p.y;
-        return v;
+    __device__ __forceinline__ Row<float> get_qe(int m, int lane) const {
+        const float4 v = reinterpret_cast<const float4*>(base + m * kBlockBytes + kWave * 8)[lane];
+        return {{v.x, v.y}, {v.z, v.w}, 0.0};
+    }
+    __device__ __forceinline__ Row<float> get(int m, int lane) const {
+        Row<float> r = get_qe(m, lane);
+        r.c = reinterpret_cast<const double*>(base + m * kBlockBytes)[lane];
+        return r;
     }
 };
 
-__host__ __device__ constexpr size_t wave_lds_bytes(int n_mat) { return (size_t)n_mat * kWave * 32; }
+template <typename R>
+__host__ __device__ constexpr size_t wave_lds_bytes(int n_mat) {
+    return (size_t)n_mat * WaveTable<R>::kBlockBytes;
+}
+
+// The Layer view of a row for the extraction (q in double for the s terms).
+template <typename R>
+__device__ __forceinline__ Layer<R> as_layer(const Row<R>& r) {
+    Layer<R> v;
+    v.q = r.q;
+    v.e = r.e;
+    v.q2 = r.q.re * r.q.re + r.q.im * r.q.im;
+    v.e2 = r.e.re * r.e.re + r.e.im * r.e.im;
+    v.pr = (double)r.q.re;
+    v.pi = (double)r.q.im;
+    return v;
+}
+
+// Per-lane constants of a unit's point.
+struct LaneK {
+    double c1024;  // 1024 / lambda
+    float kim;     // -(pi / ln 2) 4 / lambda: log2 of the attenuation per unit thickness and unit Im q
+};
+
+// g modulo 512 (one full turn in units of 1/256 half-turn), exactly, for any finite g.
+__device__ __forceinline__ double reduce512(double g) {
+    return __builtin_fma(-512.0, __builtin_rint(g * (1.0 / 512)), g);
+}
+
+// 1 / x from the hardware reciprocal and two Newton steps (within about an ulp;
+// x = 0 gives NaN, as a division's inf times the zero it multiplies would).
+__device__ __forceinline__ double rcp_nr(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = __builtin_fma(-x, r, 1.0);
+    r = __builtin_fma(r, e, r);
+    e = __builtin_fma(-x, r, 1.0);
+    return __builtin_fma(r, e, r);
+}
+
+// q and eta of one row (Snell invariant kx) in double; the forward branch as
+// make_medium.  Lossless and propagating in every lane: one real square root.
+__device__ __forceinline__ void row_lossless(double nr, double kx, double& qr, double& er) {
+    const double ur = nr * nr;
+    qr = __builtin_sqrt(ur - kx * kx);
+    er = ur * rcp_nr(qr);
+}
+
+__device__ __forceinline__ void row_general(double nr, double ni, double kx, double& qr, double& qi, double& er,
+                                            double& ei) {
+    const double ur = nr * nr - ni * ni, ui = 2.0 * nr * ni;
+    const double zr = ur - kx * kx, zi = ui;
+    const double az = __builtin_sqrt(zr * zr + zi * zi);
+    if (zr >= 0.0) {
+        const double t = __builtin_sqrt(0.5 * (az + zr));
+        qr = t;
+        qi = t > 0.0 ? zi * (0.5 * rcp_nr(t)) : 0.0;
+    } else {
+        const double t = __builtin_sqrt(0.5 * (az - zr));
+        qr = __builtin_fabs(zi) * (0.5 * rcp_nr(t));
+        qi = __builtin_copysign(t, zi);
+    }
+    const bool flip = __builtin_fabs(qi) > kBranchEps ? (qi < 0.0) : (qr < 0.0);
+    if (flip) {
+        qr = -qr;
+        qi = -qi;
+    }
+    const double inv = rcp_nr(qr * qr + qi * qi);
+    er = (ur * qr + ui * qi) * inv;
+    ei = (ui * qr - ur * qi) * inv;
+}
+
+// 2^y on the short series of weak attenuation alone (its coefficients are the
+// only exp2 constants resident in the loop): directly when every lane has
+// |y| <= 1/16, else 2^y = 2^k (2^(f/8))^8 with k = rint(y), |f| <= 1/2, three
+// squarings (relative error within about 10 ulp).  y is clamped as in exp2_d.
+__device__ __forceinline__ double exp2_weak_sq(double y) {
+    if (__all(__builtin_fabs(y) <= kExp2WeakRange)) return horner<true>(kExp2SD, y);
+    y = __builtin_fmin(__builtin_fmax(y, -1100.0), 1100.0);
+    const double k = __builtin_rint(y);
+    double v = horner<true>(kExp2SD, (y - k) * 0.125);
+    v *= v;
+    v *= v;
+    v *= v;
+    return __builtin_amdgcn_ldexp(v, (int)k);
+}
+
+// Division-free recursion (tmm_device.hpp) on table rows.  S sums
+// d (1024 / lambda) Im q in double (FP64) or the base-2 exponents of the
+// attenuation (FP32); kSLog2 turns it into the latter for the extraction.
+template <typename R, int POL>
+struct RChain : Chain<R, POL, false> {
+    static constexpr double kSLog2 = sizeof(R) == 8 ? kNegPiLog2e / kScSteps : 1.0;
+    __device__ __forceinline__ static double exp2_ext(double y) { return exp2_weak_sq(y); }
+
+    // E_j for the current row (dl = d (1024 / lambda), df = d in the kernel's type).
+    template <bool CR>
+    __device__ __forceinline__ cx<R> phase_of(const Row<R>& cur, double dl, R df, const LaneK& k, bool huge,
+                                              const TabPhase<R>& phase) {
+        double g;
+        if constexpr (sizeof(R) == 8) g = dl * cur.q.re;
+        else g = dl * cur.c;
+        if (huge) {
+            // rare (wave-uniform): an empty side-effecting asm keeps this a branch
+            // rather than a select that would run the reduction on every step
+            asm volatile("");
+            g = reduce512(g);
+        }
+        cx<R> E = phase.cis_g(g);
+        if (!CR) attenuate(E, cur, dl, df, k);
+        return E;
+    }
+
+    // Attenuation of a lossy current row: E scaled by 2^y, y added to S.
+    __device__ __forceinline__ void attenuate(cx<R>& E, const Row<R>& cur, double dl, R df, const LaneK& k) {
+        R att;
+        if constexpr (sizeof(R) == 8) {
+            const double ph = dl * cur.q.im;
+            this->S += ph;
+            att = exp2_weak_sq(ph * kSLog2);
+        } else {
+            const float y = (df * k.kim) * cur.q.im;
+            this->S += (double)y;
+            att = __all(__builtin_fabsf(y) <= (float)kExp2WeakRange) ? horner<true>(kExp2SF, y) : exp2_f(y);
+        }
+        E.re *= att;
+        E.im *= att;
+    }
+
+    // One layer step; CR / NR: the current / next row is lossless and
+    // propagating in every lane (real q and eta), wave-uniform.
+    template <bool CR, bool NR>
+    __device__ __forceinline__ void step(const Row<R>& cur, const Row<R>& nxt, double dl, R df, const LaneK& k,
+                                         bool huge, const TabPhase<R>& phase) {
+        step_E<CR, NR>(cur, nxt, phase_of<CR>(cur, dl, df, k, huge, phase));
+    }
+
+    // The chain update of a step whose phase factor E is known.
+    template <bool CR, bool NR>
+    __device__ __forceinline__ void step_E(const Row<R>& cur, const Row<R>& nxt, const cx<R>& E) {
+        if (POL & 1) {
+            const cx<R> A = CR ? cscale(cur.q.re, this->ss) : cmul(cur.q, this->ss);
+            const cx<R> Bv = NR ? cscale(nxt.q.re, this->ts) : cmul(nxt.q, this->ts);
+            const cx<R> a = cadd(A, Bv), b = csub(A, Bv);
+            const cx<R> Eb = cmul(E, b);
+            this->ss = cadd(a, Eb);
+            this->ts = csub(a, Eb);
+        }
+        if (POL & 2) {
+            const cx<R> A = NR ? cscale(nxt.e.re, this->sp) : cmul(nxt.e, this->sp);
+            const cx<R> Bv = CR ? cscale(cur.e.re, this->tp) : cmul(cur.e, this->tp);
+            const cx<R> a = cadd(A, Bv), b = csub(A, Bv);
+            const cx<R> Eb = cmul(E, b);
+            this->sp = cadd(a, Eb);
+            this->tp = csub(a, Eb);
+        }
+        if (POL & 1) this->pis *= CR ? cur.q.re * cur.q.re : cur.q.re * cur.q.re + cur.q.im * cur.q.im;
+        if (POL & 2) this->pip *= CR ? cur.e.re * cur.e.re : cur.e.re * cur.e.re + cur.e.im * cur.e.im;
+    }
+};
 
 __global__ void reset_counter(unsigned long long* c) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *c = 0ull;
@@ -143,25 +309,23 @@ __global__ void reset_counter(unsigned long long* c) {
 // both columns.
 template <typename R, int POL>
 struct Operator {
-    Chain<R, POL, false> c0, c1;  // column 0 from (1, 0), column 1 from (0, 1); c0 holds es, ep, pis, pip, S
+    RChain<R, POL> c0, c1;  // column 0 from (1, 0), column 1 from (0, 1); c0 holds es, ep, pis, pip, S
     __device__ __forceinline__ void init() {
         c0.init();
         c1.init();
         c0.ts = c0.tp = {(R)0, (R)0};
         c1.ss = c1.sp = {(R)0, (R)0};
     }
-    __device__ __forceinline__ void step(const Layer<R>& cur, const Layer<R>& nxt, double cd, bool lossy,
-                                         const TabPhase<R>& phase) {
-        const double phr = cd * cur.pr;
-        const double phi = cd * cur.pi;
-        const cx<R> E = phase(phr, phi, lossy);
+    __device__ __forceinline__ void step(const Row<R>& cur, const Row<R>& nxt, double dl, R df, const LaneK& k,
+                                         bool huge, bool lossy, const TabPhase<R>& phase) {
+        const cx<R> E = lossy ? c0.template phase_of<false>(cur, dl, df, k, huge, phase)
+                              : c0.template phase_of<true>(cur, dl, df, k, huge, phase);
         col(c0, cur, nxt, E);
         col(c1, cur, nxt, E);
-        if (POL & 1) c0.pis *= cur.q2;
-        if (POL & 2) c0.pip *= cur.e2;
-        c0.S += phi;
+        if (POL & 1) c0.pis *= cur.q.re * cur.q.re + cur.q.im * cur.q.im;
+        if (POL & 2) c0.pip *= cur.e.re * cur.e.re + cur.e.im * cur.e.im;
     }
-    __device__ __forceinline__ static void col(Chain<R, POL, false>& c, const Layer<R>& cur, const Layer<R>& nxt,
+    __device__ __forceinline__ static void col(RChain<R, POL>& c, const Row<R>& cur, const Row<R>& nxt,
                                                const cx<R>& E) {
         if (POL & 1) {
             const cx<R> A = cmul(cur.q, c.ss), Bv = cmul(nxt.q, c.ts);
@@ -201,15 +365,31 @@ __device__ __forceinline__ cx<R> shfl_down_cx(cx<R> v, int d) {
     return {__shfl_down(v.re, d, kWave), __shfl_down(v.im, d, kWave)};
 }
 
+// Steps between renormalisations for a unit whose rows' q and eta components
+// all lie in [2^(emin-1), 2^emax) (wave-uniform): per step the state grows by
+// less than 2^(emax + 2.5) and |q|^2, |eta|^2 lie within 2^(+-(2 |e| + 1)), so
+// the chosen period keeps the state and the running products far from
+// overflow and underflow.  Powers of two, so that the 64-layer chunks hold
+// whole blocks.
+template <typename R>
+__device__ __forceinline__ int renorm_period(bool small, bool medium);
+template <>
+__device__ __forceinline__ int renorm_period<double>(bool small, bool medium) { return small ? 64 : (medium ? 32 : 16); }
+template <>
+__device__ __forceinline__ int renorm_period<float>(bool small, bool medium) { return small ? 16 : (medium ? 8 : 4); }
+template <typename R> struct PeriodBounds;
+template <> struct PeriodBounds<double> { static constexpr int kSmall = 6, kMedium = 14; };
+template <> struct PeriodBounds<float> { static constexpr int kSmall = 3, kMedium = 6; };
+
 template <typename R, int POL, int LPP>
-__global__ void __launch_bounds__(kMaxThreads) ragged_kernel(Params<R> p) {
+__global__ void __launch_bounds__(Occupancy<R>::kWavesPerCU * kWave) ragged_kernel(Params<R> p) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     fill_phase_tab<R>(smem, threadIdx.x, blockDim.x);
     __syncthreads();
     const TabPhase<R> phase = phase_of<R>(smem);
-    unsigned char* my = smem + phase_tab_bytes<R>() + (size_t)wave * wave_lds_bytes(p.n_mat);
+    unsigned char* my = smem + phase_tab_bytes<R>() + (size_t)wave * wave_lds_bytes<R>(p.n_mat);
     WaveTable<R> tab(my);
     constexpr int P = (POL == 3) ? 2 : 1;
     constexpr int PPW = kWave / LPP;  // points per unit (the tile)
@@ -235,12 +415,22 @@ __global__ void __launch_bounds__(kMaxThreads) ragged_kernel(Params<R> p) {
             const int64_t f_raw = tile * PPW + pt;
             const bool active = f_raw < npts;
             const int64_t f = active ? f_raw : npts - 1;
-            const int k = (int)(f / nwl);
-            const int i = (int)(f - (int64_t)k * nwl);
+            int k, i;
+            if (npts <= 0x7fffffff) {  // wave-uniform: 32-bit division
+                const uint32_t fu = (uint32_t)f, nw = (uint32_t)nwl;
+                const uint32_t ku = fu / nw;
+                k = (int)ku;
+                i = (int)(fu - ku * nw);
+            } else {
+                k = (int)(f / nwl);
+                i = (int)(f - (int64_t)k * nwl);
+            }
             const int64_t col = w0 + i;  // column of this lane's wavelength in nk
             const double lam = (double)p.wl[col];
             const bool lam_ok = lam > 0.0 && lam < __builtin_inf();
-            const double c4lam = 4.0 / lam;
+            LaneK kk;
+            kk.c1024 = (double)(4 * kScSteps) / lam;
+            kk.kim = (float)(kk.c1024 * (kNegPiLog2e / kScSteps));
             const double st = (double)p.sin_t[t0 + k], ct = (double)p.cos_t[t0 + k];
             int a_row = p.ends[2 * b], s_row = p.ends[2 * b + 1];
             bool bad = (uint32_t)a_row >= (uint32_t)p.n_mat || (uint32_t)s_row >= (uint32_t)p.n_mat;
@@ -248,73 +438,100 @@ __global__ void __launch_bounds__(kMaxThreads) ragged_kernel(Params<R> p) {
             s_row = min(max(s_row, 0), p.n_mat - 1);
             const Ambient amb = make_ambient((double)p.nk[2 * ((int64_t)a_row * p.nk_stride + col)],
                                              (double)p.nk[2 * ((int64_t)a_row * p.nk_stride + col) + 1], st, ct);
-            // this unit's media table: every row at this lane's point
+            const R* drow = p.d + l0;
+            const int32_t* mrow = p.mat + l0;
+            // rows the stack uses: its layers' materials and the substrate
+            uint32_t used = 1u << s_row;
+            {
+                uint32_t lane_used = 0;
+                for (int j = lane; j < L; j += kWave) lane_used |= 1u << min(max(mrow[j], 0), p.n_mat - 1);
+                for (int m = 0; m < p.n_mat; ++m)
+                    if (__any((lane_used >> m) & 1u)) used |= 1u << m;
+            }
+            // this unit's media table: the used rows at this lane's point
             uint32_t lossy_mask = 0;
+            int ex_max = -1100, ex_min = 1100, ex_c = -1100;
             for (int m = 0; m < p.n_mat; ++m) {
+                if (!((used >> m) & 1u)) continue;
                 const int64_t e = (int64_t)m * p.nk_stride + col;
                 const double nr = (double)p.nk[2 * e], ni = (double)p.nk[2 * e + 1];
+                double qr, qi = 0.0, er, ei = 0.0;
                 if (__all(ni == 0.0 && nr * nr - amb.kx * amb.kx > 0.0)) {
-                    tab.put(m, lane, make_medium_lossless(nr, amb.kx));
+                    row_lossless(nr, amb.kx, qr, er);
                 } else {
-                    const Medium md = make_medium(nr, ni, amb.kx);
-                    tab.put(m, lane, md);
-                    if (__any(md.qi != 0.0)) lossy_mask |= 1u << m;
+                    row_general(nr, ni, amb.kx, qr, qi, er, ei);
+                    if (__any(qi != 0.0)) lossy_mask |= 1u << m;
                 }
+                tab.put(m, lane, qr, qi, er, ei, kk.c1024 * qr);
+                const double qa = fmax(fabs(qr), fabs(qi)), ea = fmax(fabs(er), fabs(ei));
+                ex_max = max(ex_max, max(frexp_exp(qa), frexp_exp(ea)));
+                ex_min = min(ex_min, min(frexp_exp(qa), frexp_exp(ea)));
+                ex_c = max(ex_c, frexp_exp(kk.c1024 * fabs(qr)));
             }
+            // renormalisation period and phase-range check (wave-uniform)
+            constexpr int kS = PeriodBounds<R>::kSmall, kM = PeriodBounds<R>::kMedium;
+            const int RPu = renorm_period<R>(__all(ex_max <= kS && ex_min >= -kS),
+                                             __all(ex_max <= kM && ex_min >= -kM));
+            const bool c_ok = __all(ex_c <= kPhaseCoefExp);
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            const R* drow = p.d + l0;
-            const int32_t* mrow = p.mat + l0;
-            const Layer<R> sub = tab.get(s_row, lane);
-            Chain<R, POL, false> c;
+            const Row<R> sub = tab.get_qe(s_row, lane);
+            RChain<R, POL> c;
             int first_row = s_row;  // table row of layer 1 (the substrate for L = 0)
-            constexpr int RP = RenormPeriod<R>::value;
             if constexpr (LPP == 1) {
                 int nxt_row = s_row;  // the layer below, as its table row (re-read from LDS per step)
                 c.init();
-                static_assert(kWave % RP == 0, "chunks must hold whole renormalisation blocks");
                 for (int top = L; top >= 1; top -= kWave) {
                     const int lo = top - kWave + 1 > 1 ? top - kWave + 1 : 1;
                     // lane l holds layer lo + l (thickness, table row); the loop broadcasts them
                     const int j = lo + lane;
-                    double my_d = 0.0;
+                    R my_d = (R)0;
                     int my_m = 0;
                     bool lane_bad = false;
                     if (j <= top) {
                         const R dj = drow[j - 1];
                         const int m = mrow[j - 1];
                         lane_bad = bad_thickness(dj) || (uint32_t)m >= (uint32_t)p.n_mat;
-                        my_d = (double)dj;
+                        my_d = dj;
                         my_m = min(max(m, 0), p.n_mat - 1);
                     }
                     bad = bad || __any(lane_bad);
+                    const bool huge = !c_ok || __any(my_d >= (R)0x1p29);
                     auto step = [&](int jj) {
                         const int sl = jj - lo;
                         const int m = __builtin_amdgcn_readlane(my_m, sl);
-                        const double dj = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(my_d), sl),
-                                                           __builtin_amdgcn_readlane(__double2loint(my_d), sl));
-                        const Layer<R> cur = tab.get(m, lane), nx = tab.get(nxt_row, lane);
-                        const double cd = dj * c4lam;
+                        R df;
+                        double dl;
+                        if constexpr (sizeof(R) == 8) {
+                            df = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(my_d), sl),
+                                                  __builtin_amdgcn_readlane(__double2loint(my_d), sl));
+                            dl = df * kk.c1024;
+                        } else {
+                            df = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(my_d), sl));
+                            dl = (double)df;
+                        }
+                        const Row<R> cur = tab.get(m, lane), nx = tab.get_qe(nxt_row, lane);
                         // lossless rows (bit clear) step with real q and eta
                         if (((lossy_mask >> m) & 1u) == 0) {
                             if (((lossy_mask >> nxt_row) & 1u) == 0)
-                                c.template step_known<true, true>(cur, nx, cd, phase);
+                                c.template step<true, true>(cur, nx, dl, df, kk, huge, phase);
                             else
-                                c.template step_known<true, false>(cur, nx, cd, phase);
+                                c.template step<true, false>(cur, nx, dl, df, kk, huge, phase);
                         } else {
                             if (((lossy_mask >> nxt_row) & 1u) == 0)
-                                c.template step_known<false, true>(cur, nx, cd, phase);
+                                c.template step<false, true>(cur, nx, dl, df, kk, huge, phase);
                             else
-                                c.template step_known<false, false>(cur, nx, cd, phase);
+                                c.template step<false, false>(cur, nx, dl, df, kk, huge, phase);
                         }
                         nxt_row = m;
                     };
-                    // renormalisation blocks at the points of a running step count
-                    for (int bt = top; bt >= lo; bt -= RP) {
-                        if (bt - lo >= RP - 1) {
+                    // renormalisation blocks of RPu steps (a power of two <= 64:
+                    // whole blocks in every chunk but the last)
+                    for (int bt = top; bt >= lo; bt -= RPu) {
+                        if (bt - lo >= RPu - 1) {
 #pragma unroll 2
-                            for (int uu = 0; uu < RP; ++uu) step(bt - uu);
+                            for (int uu = 0; uu < RPu; ++uu) step(bt - uu);
                             c.renorm();
                         } else {
                             for (int jj = bt; jj >= lo; --jj) step(jj);
@@ -325,6 +542,7 @@ __global__ void __launch_bounds__(kMaxThreads) ragged_kernel(Params<R> p) {
                 first_row = nxt_row;
             } else {
                 // segment seg of the layers: [lo_s, hi_s], equal lengths from the top
+                constexpr int RP = RenormPeriod<R>::value;
                 const int ns = (L + LPP - 1) / LPP;
                 const int lo_s = 1 + seg * ns;
                 const int hi_s = min(L, lo_s + ns - 1);
@@ -344,7 +562,9 @@ __global__ void __launch_bounds__(kMaxThreads) ragged_kernel(Params<R> p) {
                         const int m_raw = mrow[j - 1];
                         bad = bad || bad_thickness(dj) || (uint32_t)m_raw >= (uint32_t)p.n_mat;
                         const int m = min(max(m_raw, 0), p.n_mat - 1);
-                        op.step(tab.get(m, lane), tab.get(nxt_row, lane), (double)dj * c4lam,
+                        const bool huge = !c_ok || dj >= (R)0x1p29;
+                        const double dl = sizeof(R) == 8 ? (double)dj * kk.c1024 : (double)dj;
+                        op.step(tab.get(m, lane), tab.get_qe(nxt_row, lane), dl, dj, kk, huge,
                                 (lossy_mask >> m) & 1u, phase);
                         nxt_row = m;
                         if (++cnt == RP) {
@@ -368,7 +588,7 @@ __global__ void __launch_bounds__(kMaxThreads) ragged_kernel(Params<R> p) {
                 }
                 for (int r = LPP - 2; r >= 0; --r) {
                     // lane seg = r takes the state reached below it (lane seg + 1) through its operator
-                    Chain<R, POL, false> v = c;
+                    RChain<R, POL> v = c;
                     if (POL & 1) {
                         v.ss = shfl_down_cx(c.ss, 1);
                         v.ts = shfl_down_cx(c.ts, 1);
@@ -409,7 +629,8 @@ __global__ void __launch_bounds__(kMaxThreads) ragged_kernel(Params<R> p) {
                 }
             }
             PointOut out[2];
-            finish<R, POL, false>(c, amb, tab.get(first_row, lane), sub, 0.0, 0.0, L, out, phase);
+            finish<R, POL, false>(c, amb, as_layer(tab.get_qe(first_row, lane)), as_layer(sub), 0.0, 0.0, L, out,
+                                  phase);
             if (active && seg == 0) {
                 const bool valid = lam_ok && amb.ok && !bad;
                 const double nan = __builtin_nan("");
@@ -441,21 +662,22 @@ inline int lpp_index(int lpp) { return lpp == 1 ? 0 : (lpp == 2 ? 1 : 2); }
 
 template <typename R>
 size_t shape_lds(int n_mat, int waves) {
-    return phase_tab_bytes<R>() + (size_t)waves * wave_lds_bytes(n_mat);
+    return phase_tab_bytes<R>() + (size_t)waves * wave_lds_bytes<R>(n_mat);
 }
 
-// Workgroup shapes that hold the most resident waves per CU (at most 12: 3 per
-// SIMD at the kernel's register count) within the CU's LDS; the three with the
-// largest workgroups.
+// Workgroup shapes that hold the most resident waves per CU (at most the
+// kernel's register limit, Occupancy<R>) within the CU's LDS; the three with
+// the largest workgroups.
 template <typename R>
 std::vector<Shape> candidate_shapes(int n_mat) {
     const size_t granule = 2048;
+    constexpr int kMax = Occupancy<R>::kWavesPerCU;
     int best = 0;
     std::vector<Shape> out;
-    for (int waves = 12; waves >= 1; --waves) {
+    for (int waves = kMax; waves >= 1; --waves) {
         const size_t lds = (shape_lds<R>(n_mat, waves) + granule - 1) / granule * granule;
         int per_cu = (int)(kLdsPerCU / lds);
-        if (per_cu > 12 / waves) per_cu = 12 / waves;
+        if (per_cu > kMax / waves) per_cu = kMax / waves;
         if (per_cu < 1) continue;
         const int total = per_cu * waves;
         if (total > best) {
@@ -830,11 +1052,13 @@ tmm_status tmm_ragged_plan_set_shape(tmm_ragged_plan* pl, tmm_dtype dtype, const
     if (dtype != TMM_F64 && dtype != TMM_F32)
         return fail(TMM_ERR_INVALID_ARG, "tmm_ragged_plan_set_shape: unknown dtype");
     const int bpc = host_shape[0], grain = host_shape[1], waves = host_shape[2], lpp = host_shape[3];
-    if (bpc < 1 || grain < 1 || grain > 64 || waves < 1 || waves > tmm::ragged::kMaxThreads / tmm::kWave ||
-        (lpp != 1 && lpp != 2 && lpp != 4) || bpc * waves > 32)
+    const int max_waves = dtype == TMM_F64 ? tmm::ragged::Occupancy<double>::kWavesPerCU
+                                           : tmm::ragged::Occupancy<float>::kWavesPerCU;
+    if (bpc < 1 || grain < 1 || grain > 64 || waves < 1 || waves > max_waves || (lpp != 1 && lpp != 2 && lpp != 4) ||
+        bpc * waves > 32)
         return fail(TMM_ERR_INVALID_ARG,
-                    "tmm_ragged_plan_set_shape: need workgroups per CU >= 1, 1 <= grain <= 64, 1 <= waves <= 12, "
-                    "lanes per point 1, 2 or 4, and at most 32 waves per CU");
+                    "tmm_ragged_plan_set_shape: need workgroups per CU >= 1, 1 <= grain <= 64, 1 <= waves <= %d "
+                    "for this dtype, lanes per point 1, 2 or 4, and at most 32 waves per CU", max_waves);
     const int di = dtype == TMM_F64 ? 0 : 1;
     pl->shape[di] = {bpc, grain, waves, lpp};
     pl->tuned[di] = true;

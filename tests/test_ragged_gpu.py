@@ -163,3 +163,50 @@ def test_first_run_of_a_plan_with_a_cached_shape_computes_its_output():
     run(rw)                                   # tunes and caches the shape
     plan, _, R, T = run(rw)                   # new plan, cached shape
     check_stacks(rw, plan, R, T, range(rw.B))
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_scaled_lengths_take_the_exact_phase_reduction(dtype):
+    # Only d / lambda matters.  Thicknesses and wavelengths scaled by 1e-6 leave
+    # every phase as it was, but the phase coefficient per unit thickness
+    # (1024 Re q / lambda) exceeds 2^20, so every unit reduces its phases
+    # modulo a full turn before the table lookup; every stack against the oracle.
+    import dataclasses
+    rw = workloads.ragged_batch(seed=70, B=21, L_range=(0, 80), wl_range=(1, 120), th_range=(1, 6))
+    rw = dataclasses.replace(rw, d=rw.d * 1e-6, wl=rw.wl * 1e-6)
+    plan, _, R, T = run(rw, dtype)
+    check_stacks(rw, plan, R, T, range(rw.B), dtype)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_ambient_and_substrate_rows_as_layer_materials(dtype):
+    # Layers made of the ambient's or the substrate's table row (rows 4, 5):
+    # the unit builds exactly the rows its stack uses.
+    rw = workloads.ragged_batch(seed=71, B=17, L_range=(1, 70), wl_range=(20, 150), th_range=(1, 5))
+    rng = np.random.default_rng(71)
+    pick = rng.random(rw.mat.size) < 0.3
+    rw.mat[pick] = rng.integers(4, 6, int(pick.sum())).astype(np.int32)
+    plan, _, R, T = run(rw, dtype)
+    check_stacks(rw, plan, R, T, range(rw.B), dtype)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_metal_rows_and_grazing_angles(dtype):
+    # Strongly absorbing rows (metal-like 0.2+3.5i and 1.5+5.8i in place of
+    # materials 1 and 3), 5-40 nm films and angles up to 89.9 deg, where eta
+    # grows to hundreds and the units fall back to the shorter renormalisation
+    # period; every stack against the oracle.
+    import dataclasses
+    rw = workloads.ragged_batch(seed=72, B=15, L_range=(1, 60), wl_range=(10, 120), th_range=(2, 7))
+    rng = np.random.default_rng(72)
+    nk = rw.nk.copy()
+    nk[1] = 0.2 + 3.5j
+    nk[3] = 1.5 + 5.8j
+    d = rw.d.copy()
+    metal = np.isin(rw.mat, [1, 3])
+    d[metal] = rng.uniform(5.0, 40.0, int(metal.sum()))
+    theta = np.concatenate([np.deg2rad(np.linspace(0.0, 89.9, n)) for n in np.diff(rw.th_off)])
+    s, c = workloads.angles(theta)
+    rw = dataclasses.replace(rw, nk=nk, d=d, theta=theta, sin_t=s, cos_t=c)
+    plan, _, R, T = run(rw, dtype)
+    check_stacks(rw, plan, R, T, range(rw.B), dtype)
