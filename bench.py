@@ -205,6 +205,38 @@ PAPER_CONTEXT = {
 }
 
 
+def _surrogate_record(rep):
+    tp = rep["throughput_stacks_per_s"]
+    per = {}
+    for k, r in rep["bounds"].items():
+        per[k] = {"err_scale": r["err_scale"], "accepted_fraction_cal": r["accepted_fraction_cal"],
+                  "accepted_fraction_test": r["accepted_fraction_test"],
+                  "max_abs_accepted_test": r["max_abs_accepted_test"],
+                  "fallback_fraction_outputs": r["fallback_fraction_eval_batch"],
+                  "max_abs_after_fallback_vs_f64": r["max_abs_after_fallback_vs_f64"],
+                  "surrogate_fallback_stacks_per_s": round(r["surrogate_fallback_stacks_per_s"], 1),
+                  "gain_vs_tmm_f32": round(r["gain_vs_tmm_f32"], 3), "gain_vs_tmm_f64": round(r["gain_vs_tmm_f64"], 3)}
+    first = per[next(iter(per))]
+    return {"bound": rep["config"]["bounds"][0], "calibration_margin": rep["config"]["margin"],
+            "spread_factor": rep["config"]["spread_factor"], "sigma_window": rep["config"]["sigma_window"],
+            "surrogate_fallback_stacks_per_s": first["surrogate_fallback_stacks_per_s"],
+            "surrogate_only_stacks_per_s": round(tp["surrogate_only"], 1),
+            "tmm_f32_stacks_per_s": round(tp["tmm_f32"], 1),
+            "tmm_f64_stacks_per_s": round(tp["tmm_f64"], 1),
+            "gain_vs_tmm_f32": first["gain_vs_tmm_f32"], "gain_vs_tmm_f64": first["gain_vs_tmm_f64"],
+            "accepted_fraction_cal": first["accepted_fraction_cal"],
+            "accepted_fraction_test": first["accepted_fraction_test"],
+            "fallback_fraction_outputs": first["fallback_fraction_outputs"],
+            "max_abs_accepted_test": first["max_abs_accepted_test"],
+            "max_abs_after_fallback_vs_f64": first["max_abs_after_fallback_vs_f64"],
+            "per_bound": per,
+            "test_mae": round(rep["test_mae"], 6), "test_max_abs": round(rep["test_max_abs"], 6),
+            "test_frac_within": rep["test_frac_within"],
+            "baseline_mean_spectrum_mae": round(rep["baseline_mean_spectrum_mae"], 4),
+            "train_s": round(rep["train_s"], 1), "datagen_s": round(rep["datagen_s"], 2),
+            "train_tflops": round(rep["train_tflops"], 1)}
+
+
 def time_surrogate():
     """Surrogate + transfer-matrix fallback against plain TMM on the 30-layer
     surrogate task (256 wavelengths x 16 angles x s,p R outputs per stack):
@@ -213,26 +245,27 @@ def time_surrogate():
     to test it, which are also the throughput batch)."""
     from paper_2111_13667_amd import surrogate
     rep = surrogate.run(n_train=2_000_000, n_cal=34_464, n_test=65_536, epochs=20, log=lambda *_: None)
-    tp = rep["throughput_stacks_per_s"]
-    return {"workload": "surrogate_batch: 30 layers, 256 wl x 16 angles x s,p R; ensemble of 5 MLPs "
-                        "30 -> 5 x 1024 GELU -> 8192, BF16 MFMA; 2000000 training stacks x 20 epochs, "
-                        "100000 held-out (34464 calibration, 65536 test and throughput batch)",
-            "bound": rep["config"]["bound"], "calibration_margin": rep["config"]["margin"],
-            "surrogate_fallback_stacks_per_s": round(tp["surrogate_fallback"], 1),
-            "surrogate_only_stacks_per_s": round(tp["surrogate_only"], 1),
-            "tmm_f32_stacks_per_s": round(tp["tmm_f32"], 1),
-            "tmm_f64_stacks_per_s": round(tp["tmm_f64"], 1),
-            "gain_vs_tmm_f32": round(rep["gain_vs_tmm_f32"], 3),
-            "gain_vs_tmm_f64": round(rep["gain_vs_tmm_f64"], 3),
-            "accepted_fraction_cal": rep["accepted_fraction_cal"],
-            "accepted_fraction_test": rep["accepted_fraction_test"],
-            "fallback_fraction_outputs": rep["fallback_fraction_eval_batch"],
-            "max_abs_accepted_test": rep["max_abs_accepted_test"],
-            "max_abs_after_fallback_vs_f64": rep["max_abs_after_fallback_vs_f64"],
-            "test_mae": round(rep["test_mae"], 4),
-            "baseline_mean_spectrum_mae": round(rep["baseline_mean_spectrum_mae"], 4),
-            "train_s": round(rep["train_s"], 1), "datagen_s": round(rep["datagen_s"], 2),
-            "train_tflops": round(rep["train_tflops"], 1)}
+    rec = {"workload": "surrogate_batch: 30 layers, 256 wl x 16 angles x s,p R; ensemble of 5 MLPs "
+                       "30 -> 5 x 1024 GELU -> 8192, BF16 MFMA; 2000000 training stacks x 20 epochs, "
+                       "100000 held-out (34464 calibration, 65536 test and throughput batch)"}
+    rec.update(_surrogate_record(rep))
+    return rec
+
+
+def time_surrogate_dataset():
+    """The same surrogate and fallback on the paper's dataset-generation shape
+    (App. A.2: ten layers 2.0 / 1.4 between 2.5 and 1.0, d ~ U[5,180] nm, s-polarised
+    R at normal incidence, 128 wavelengths 1000-1700 nm): 1 000 000 training
+    stacks (the paper's dataset size), 100 epochs at a 3e-4 peak learning rate,
+    100 000 held-out; bounds 1e-3 and 1e-2."""
+    from paper_2111_13667_amd import surrogate
+    rep = surrogate.run(n_train=1_000_000, n_cal=34_464, n_test=65_536, epochs=100, lr_max=3e-4,
+                        bounds=(1e-3, 1e-2), instance="dataset_example", log=lambda *_: None)
+    rec = {"workload": "dataset_example (App. A.2 shape): 10 layers, 128 wl x 1 angle x s R; ensemble of 5 MLPs "
+                       "10 -> 5 x 1024 GELU -> 128, BF16 MFMA; 1000000 training stacks x 100 epochs, "
+                       "100000 held-out (34464 calibration, 65536 test and throughput batch)"}
+    rec.update(_surrogate_record(rep))
+    return rec
 
 
 def roofline(w, dtype, kernel_ms, out_bytes, traffic=None):
@@ -321,7 +354,8 @@ def main():
     ap.add_argument("--cpu-stacks", type=int, default=128,
                     help="stacks of the CPU oracle sample (median of 3 runs after a warm-up)")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"))
-    ap.add_argument("--only", choices=["adjoint", "ragged_f64", "ragged_f32", "surrogate", "materials"],
+    ap.add_argument("--only", choices=["adjoint", "ragged_f64", "ragged_f32", "surrogate", "surrogate_dataset",
+                                       "materials"],
                     default=None, help="run only this extra measurement and print its record (for profiling)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="first run a plain N-MiB elementwise copy kernel (profiler calibration)")
@@ -344,6 +378,8 @@ def main():
             rec = time_grad(max(1, args.steps))
         elif args.only == "surrogate":
             rec = time_surrogate()
+        elif args.only == "surrogate_dataset":
+            rec = time_surrogate_dataset()
         elif args.only == "materials":
             rec = {"7": material_variant(7, max(1, args.steps)), "12": material_variant(12, max(1, args.steps))}
         else:
@@ -420,6 +456,7 @@ def main():
         extra["material_pool_7"] = material_variant(7)
         extra["material_pool_12"] = material_variant(12)
         extra["surrogate"] = time_surrogate()
+        extra["surrogate_dataset_example"] = time_surrogate_dataset()
         rec["extra"] = extra
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(w, args.cpu_stacks)

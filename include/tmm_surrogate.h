@@ -51,6 +51,12 @@ typedef struct tmm_surrogate_config {
     int32_t gemm_tile;  /* GEMM workgroup tile: 0 automatic; 1 = 256 x 256 (eight waves), 2 = 256 x 128
                            (eight waves), 3 = 128 x 128 (four waves).  A forced tile that does not
                            divide a product's M and N falls back to the automatic choice for it.   */
+    int32_t sigma_window; /* 0 .. 4096: half-width, in wavelengths, of the window over which
+                           tmm_surrogate_predict_fallback takes the largest sigma of a spectrum
+                           row (one stack, angle, polarisation) before comparing it with the
+                           bound; 0 = each output's own sigma.  The members' curves can cross at
+                           an isolated wavelength where their spread is tiny and the error is
+                           not; the window maximum closes those gaps.                          */
 } tmm_surrogate_config;
 
 /* Allocate and initialise (weights U(-a, a), a = sqrt(6/fan_in) for hidden layers
@@ -92,9 +98,11 @@ tmm_status tmm_surrogate_predict(tmm_surrogate *h, const float *x, int32_t B, fl
                                  float *members, void *stream);
 
 /* Surrogate with transfer-matrix fallback at point granularity: predict as
- * above, then every output whose error estimate err_scale * sigma exceeds bound
- * (or whose sigma is NaN) is recomputed by the transfer-matrix kernels
- * (float32) and replaced in out.  A unit is one (stack, angle, wavelength) with
+ * above, then every output whose error estimate err_scale * sigma_w exceeds
+ * bound (or whose sigma_w is NaN) is recomputed by the transfer-matrix kernels,
+ * where sigma_w is the largest sigma of the output's spectrum row within
+ * cfg.sigma_window wavelengths of it (the output's own sigma for a window of 0)
+ * (float32), and replaced in out.  A unit is one (stack, angle, wavelength) with
  * its P polarisation outputs; a unit is recomputed when any of its outputs is
  * flagged.  A stack whose units are all flagged goes through tmm_rt on the
  * gathered stacks; the flagged units of the other stacks go through the

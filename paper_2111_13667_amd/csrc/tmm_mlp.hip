@@ -246,19 +246,33 @@ __global__ void ensemble_stats(const float* Y, int E, int B, int n_out, int64_t 
 // Fallback selection, one workgroup of 256 threads per stack row b.  A unit is
 // one (angle k, wavelength i) of the row, u = k * n_wl + i, with its P outputs
 // at sigma[b][q * units + u]; it is flagged when some output has
-// scale * sigma > bound (or a NaN sigma).  A row whose units are all flagged is
+// scale * sigma_w > bound (or a NaN sigma_w), sigma_w being the largest sigma of
+// the output's (k, q) spectrum within win wavelengths of i.  A row whose units are all flagged is
 // appended to stacks (recomputed by the dense kernel); otherwise its flagged
 // units are appended to points as b * units + u (recomputed one by one).  Order
 // within the lists is unspecified.  counts[0] = stacks, counts[1] = points.
-__global__ void flag_units(const float* sigma, int units, int P, float scale, float bound, int* stacks,
-                           uint32_t* points, int* counts) {
+__global__ void flag_units(const float* sigma, int units, int n_wl, int win, int P, float scale, float bound,
+                           int* stacks, uint32_t* points, int* counts) {
     __shared__ int s_cnt;
     const int b = blockIdx.x;
     const int lane = threadIdx.x & 63;
     const float* sg = sigma + (int64_t)b * units * P;
     auto flagged = [&](int u) {
+        const int i = u % n_wl;
+        const int lo = i - win > 0 ? i - win : 0, hi = i + win < n_wl - 1 ? i + win : n_wl - 1;
         bool f = false;
-        for (int q = 0; q < P; ++q) f = f || !(scale * sg[(int64_t)q * units + u] <= bound);
+        for (int q = 0; q < P; ++q) {
+            const float* row = sg + (int64_t)q * units + (u - i);
+            // a NaN anywhere in the window flags the unit (fmaxf would drop it)
+            float m = 0.0f;
+            bool nan = false;
+            for (int j = lo; j <= hi; ++j) {
+                const float v = row[j];
+                nan = nan || (v != v);
+                m = fmaxf(m, v);
+            }
+            f = f || nan || !(scale * m <= bound);
+        }
         return f;
     };
     if (threadIdx.x == 0) s_cnt = 0;
@@ -546,6 +560,8 @@ tmm_status tmm_surrogate_create(const tmm_surrogate_config* c, tmm_surrogate** o
         return fail(TMM_ERR_INVALID_ARG, "tmm_surrogate_create: max_batch * n_out must stay below 2^32");
     if (c->gemm_tile < 0 || c->gemm_tile > 3)
         return fail(TMM_ERR_INVALID_ARG, "tmm_surrogate_create: gemm_tile must be 0 (automatic), 1, 2 or 3");
+    if (c->sigma_window < 0 || c->sigma_window > 4096)
+        return fail(TMM_ERR_INVALID_ARG, "tmm_surrogate_create: sigma_window must be in 0 .. 4096");
     if (!(c->in_scale == c->in_scale) || !(c->lr >= 0.0f) || !(c->beta1 >= 0.0f && c->beta1 < 1.0f) ||
         !(c->beta2 >= 0.0f && c->beta2 < 1.0f) || !(c->eps > 0.0f))
         return fail(TMM_ERR_INVALID_ARG, "tmm_surrogate_create: bad optimiser or input scaling parameters");
@@ -793,8 +809,8 @@ tmm_status tmm_surrogate_predict_fallback(tmm_surrogate* h, const float* x, int3
         hipLaunchKernelGGL(tmm::mlp::ensemble_stats, dim3(grid1((int64_t)nb * No / 4)), dim3(256), 0, s, h->Y, h->E, nb,
                            No, (int64_t)h->Bt * No, oc, h->sigma_buf);
         hipLaunchKernelGGL(tmm::mlp::zero_int, dim3(1), dim3(64), 0, s, h->count, 2);
-        hipLaunchKernelGGL(tmm::mlp::flag_units, dim3(nb), dim3(256), 0, s, h->sigma_buf, units, P, err_scale, bound,
-                           h->list, h->plist, h->count);
+        hipLaunchKernelGGL(tmm::mlp::flag_units, dim3(nb), dim3(256), 0, s, h->sigma_buf, units, tmpl->n_wl,
+                           h->cfg.sigma_window, P, err_scale, bound, h->list, h->plist, h->count);
         int cnt[2] = {0, 0};
         if (hipMemcpyAsync(cnt, h->count, sizeof(cnt), hipMemcpyDeviceToHost, s) != hipSuccess ||
             hipStreamSynchronize(s) != hipSuccess)

@@ -24,7 +24,7 @@ class SurrogateConfig(ctypes.Structure):
         ("in_shift", ctypes.c_float), ("in_scale", ctypes.c_float),
         ("lr", ctypes.c_float), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float),
         ("eps", ctypes.c_float), ("weight_decay", ctypes.c_float),
-        ("gemm_tile", ctypes.c_int32),
+        ("gemm_tile", ctypes.c_int32), ("sigma_window", ctypes.c_int32),
     ]
 
 
@@ -68,13 +68,16 @@ class Surrogate:
     """Ensemble MLP surrogate living in device memory (one handle)."""
 
     def __init__(self, n_in, n_out, *, n_hidden=1024, n_layers=5, n_members=5, max_batch=4096, seed=0,
-                 in_shift=0.0, in_scale=1.0, beta1=0.9, beta2=0.999, eps=1e-8, weight_decay=0.0, gemm_tile=0):
+                 in_shift=0.0, in_scale=1.0, beta1=0.9, beta2=0.999, eps=1e-8, weight_decay=0.0, gemm_tile=0,
+                 sigma_window=0):
         self.cfg = SurrogateConfig(n_in, n_hidden, n_layers, n_out, n_members, max_batch, seed,
-                                   in_shift, in_scale, 0.0, beta1, beta2, eps, weight_decay, gemm_tile)
+                                   in_shift, in_scale, 0.0, beta1, beta2, eps, weight_decay, gemm_tile,
+                                   sigma_window)
         h = ctypes.c_void_p()
         tmm._check(_lib().tmm_surrogate_create(ctypes.byref(self.cfg), ctypes.byref(h)))
         self.h = h
         self.n_in, self.n_out, self.E = n_in, n_out, n_members
+        self.sigma_window = sigma_window
 
     def close(self):
         if self.h:
@@ -155,7 +158,16 @@ class Surrogate:
 
 
 # ---------------------------------------------------------------------------
-# The thin-film surrogate task: 30 alternating Cauchy layers -> R over 256 wl x 16 angles x 2 pol.
+# Surrogate tasks: a fixed material sequence and grids; the thicknesses vary.
+#   "surrogate_batch"  30 alternating Cauchy layers -> R over 256 wl x 16 angles x s, p
+#   "dataset_example"  the paper's App. A.2 dataset shape: 10 layers 2.0 / 1.4 between
+#                      2.5 and 1.0 -> s-polarised R over 128 wl at normal incidence
+
+INSTANCES = {
+    "surrogate_batch": dict(pol="both", d_range=(20.0, 250.0), n_wl=256),
+    "dataset_example": dict(pol="s", d_range=(5.0, 180.0), n_wl=128),
+}
+
 
 @dataclass
 class Task:
@@ -168,10 +180,15 @@ class Task:
     cos_t: object
     n_wl: int
     n_theta: int
+    pol_mask: int = 3    # tmm.POL: 1 s, 2 p, 3 both
+
+    @property
+    def P(self):
+        return 2 if self.pol_mask == 3 else 1
 
     @property
     def n_out(self):
-        return 2 * self.n_theta * self.n_wl
+        return self.P * self.n_theta * self.n_wl
 
     def mat(self, B):
         """Material ids [B, L+2] (a contiguous device tensor with exactly B rows)."""
@@ -187,21 +204,31 @@ class Task:
         mat = self.mat(B)
         return tmm.TmmRtArgs(B, self.n_layers, self.n_wl, self.n_theta, tmm._ptr(d), tmm._ptr(self.nk),
                              self.nk.shape[0], int(self.nk.dim() == 2), tmm._ptr(mat),
-                             tmm._ptr(self.wl), tmm._ptr(self.sin_t), tmm._ptr(self.cos_t), 3,
+                             tmm._ptr(self.wl), tmm._ptr(self.sin_t), tmm._ptr(self.cos_t), self.pol_mask,
                              tmm._ptr(R), None, None, None)
 
 
-def make_task(dtype="f32", device="cuda", L=30, n_wl=256, n_theta=16):
-    """The surrogate workload's fixed part (default: 30 alternating layers, 256 wl x 16 angles)."""
+def make_task(dtype="f32", device="cuda", L=30, n_wl=None, n_theta=16, instance="surrogate_batch"):
+    """The fixed part of a surrogate instance ("surrogate_batch": L alternating
+    layers over n_wl x n_theta, s and p; "dataset_example": the paper's App. A.2
+    shape over n_wl wavelengths, s only; L and n_theta do not apply to it)."""
     import torch
-    w = workloads.surrogate_batch(B=1, L=L, n_wl=n_wl, n_theta=n_theta)
+    if n_wl is None:
+        n_wl = INSTANCES[instance]["n_wl"]
+    if instance == "surrogate_batch":
+        w = workloads.surrogate_batch(B=1, L=L, n_wl=n_wl, n_theta=n_theta)
+    elif instance == "dataset_example":
+        w = workloads.dataset_example(B=1, n_wl=n_wl)
+    else:
+        raise ValueError(f"unknown surrogate instance {instance!r}")
     real = torch.float32 if dtype == "f32" else torch.float64
     cplx = torch.complex64 if dtype == "f32" else torch.complex128
     mat_row = torch.as_tensor(w.mat[:1], dtype=torch.int32, device=device)
     return Task(w.L, torch.as_tensor(w.nk, dtype=cplx, device=device), mat_row,
                 torch.as_tensor(w.wl, dtype=real, device=device),
                 torch.as_tensor(w.sin_t, dtype=real, device=device),
-                torch.as_tensor(w.cos_t, dtype=real, device=device), w.wl.size, w.theta.size)
+                torch.as_tensor(w.cos_t, dtype=real, device=device), w.wl.size, w.theta.size,
+                tmm.POL[INSTANCES[instance]["pol"]])
 
 
 def generate(task: Task, d, chunk=65536):
@@ -214,25 +241,45 @@ def generate(task: Task, d, chunk=65536):
     for b0 in range(0, B, chunk):
         b1 = min(B, b0 + chunk)
         dd = d[b0:b1].to(real).contiguous()
-        tmm.tmm_rt(dd, task.nk, task.wl, task.sin_t, task.cos_t, mat=task.mat(b1 - b0), pol_mask=3,
-                   R=out[b0:b1].view(b1 - b0, 2, task.n_theta, task.n_wl))
+        tmm.tmm_rt(dd, task.nk, task.wl, task.sin_t, task.cos_t, mat=task.mat(b1 - b0), pol_mask=task.pol_mask,
+                   R=out[b0:b1].view(b1 - b0, task.P, task.n_theta, task.n_wl))
     return out
 
 
-def calibrate(mean, sigma, truth, bound, margin=1.0):
+def window_sigma(sigma, task, window):
+    """sigma [B, n_out] -> the largest sigma of each output's spectrum row (one
+    stack, polarisation and angle) within `window` wavelengths of it, the
+    estimate tmm_surrogate_predict_fallback compares with the bound for a handle
+    whose sigma_window is `window` (NaN propagates)."""
+    import torch
+    if window <= 0:
+        return sigma
+    B = sigma.shape[0]
+    rows = sigma.reshape(B * task.P * task.n_theta, 1, task.n_wl)
+    nan = torch.isnan(rows)
+    m = torch.nn.functional.max_pool1d(torch.nan_to_num(rows, nan=0.0), 2 * window + 1, stride=1, padding=window)
+    if bool(nan.any()):
+        nanw = torch.nn.functional.max_pool1d(nan.float(), 2 * window + 1, stride=1, padding=window) > 0
+        m = torch.where(nanw, torch.full_like(m, float("nan")), m)
+    return m.reshape(B, -1)
+
+
+def calibrate(mean, sigma, truth, bound, margin=1.0, spread_factor=1.0):
     """Point-level error scale: tau is the smallest sigma among the outputs of this
     set whose error |mean - truth| exceeds margin * bound; err_scale = bound / tau'
-    with tau' just below tau, so that accepting the outputs with
+    with tau' just below tau / spread_factor, so that accepting the outputs with
     err_scale * sigma <= bound (sigma <= tau') keeps every accepted error of this
     set within margin * bound.  Returns (err_scale, accepted fraction of outputs);
     err_scale is inf (nothing accepted) when the smallest-sigma output is bad, 0
-    (everything accepted) when no output is bad.  margin < 1 leaves room for the
-    held-out data the scale is then used on."""
+    (everything accepted) when no output is bad.  margin < 1 leaves room in the
+    error and spread_factor > 1 in the spread for the held-out data the scale is
+    then used on: on new data an output can fall below every bad calibration
+    output's spread and still miss the bound."""
     import torch
     bad = (mean - truth).abs() > margin * bound
     if not bool(bad.any()):
         return 0.0, 1.0
-    tau = float(sigma[bad].min())
+    tau = float(sigma[bad].min()) / spread_factor
     tau = float(np.nextafter(np.float32(tau), np.float32(0)))
     if not tau > 0:
         return float("inf"), 0.0
@@ -290,8 +337,9 @@ def _timeit(fn, reps=3):
 
 
 def run(n_train=2_000_000, n_cal=34_464, n_test=65_536, epochs=20, batch=4096, hidden=1024, layers=5,
-        members=5, lr_max=1e-3, lr_min=1e-5, eval_batch=65536, bound=1e-3, margin=0.5, seed=0,
-        infer_batch=16384, log=_log):
+        members=5, lr_max=1e-3, lr_min=1e-5, eval_batch=65536, bounds=(1e-3,), margin=0.5, seed=0,
+        infer_batch=16384, instance="surrogate_batch", n_wl=None, sigma_window=4, spread_factor=2.0,
+        log=_log):
     """Train the surrogate on tmm_rt data and report accuracy and throughput.
     The held-out stacks (n_cal + n_test, 100 000 by default) are split into a
     calibration part, on which the point-level error scale is fitted with the
@@ -299,18 +347,30 @@ def run(n_train=2_000_000, n_cal=34_464, n_test=65_536, epochs=20, batch=4096, h
     eval_batch stacks), on which the accepted fraction and the errors are
     measured.  Inference runs on a second handle whose internal batch is
     infer_batch rows (larger GEMMs than the training batch), loaded with the
-    trained weights."""
+    trained weights.  instance: "surrogate_batch" (30 layers, 256 wl x 16 angles x
+    s, p) or "dataset_example" (the paper's App. A.2 shape, 128 wl, s);
+    thicknesses are drawn uniformly over the instance's range.  Every bound of
+    `bounds` gets its own calibrated scale, accepted fractions, fallback check
+    and fallback throughput (the first also at the top level of the report);
+    the error estimate is the ensemble spread maximised over sigma_window
+    wavelengths of each spectrum row (window_sigma), calibrated with the given
+    margin and spread_factor (calibrate)."""
     import torch
     dev = "cuda"
-    report = {"config": dict(n_train=n_train, n_cal=n_cal, n_test=n_test, epochs=epochs, batch=batch,
-                             hidden=hidden, layers=layers, members=members, bound=bound, margin=margin,
-                             infer_batch=infer_batch)}
-    task = make_task("f32")
-    task64 = make_task("f64")
+    bounds = tuple(float(b) for b in bounds)
+    report = {"config": dict(instance=instance, n_train=n_train, n_cal=n_cal, n_test=n_test, epochs=epochs,
+                             batch=batch, hidden=hidden, layers=layers, members=members, bounds=list(bounds),
+                             margin=margin, spread_factor=spread_factor, infer_batch=infer_batch,
+                             sigma_window=sigma_window, lr_max=lr_max)}
+    kw = {} if n_wl is None else {"n_wl": n_wl}
+    task = make_task("f32", instance=instance, **kw)
+    task64 = make_task("f64", instance=instance, **kw)
+    lo, hi = INSTANCES[instance]["d_range"]
     g = torch.Generator(device=dev)
     g.manual_seed(seed)
     N = n_train + n_cal + n_test
-    d = (20.0 + 230.0 * torch.rand((N, task.n_layers), generator=g, device=dev, dtype=torch.float32)).contiguous()
+    d = (lo + (hi - lo) * torch.rand((N, task.n_layers), generator=g, device=dev, dtype=torch.float32)).contiguous()
+    in_shift, in_scale = 0.5 * (lo + hi), float(np.sqrt(12.0) / (hi - lo))  # zero mean, unit variance
     t0 = time.perf_counter()
     y = generate(task, d)
     torch.cuda.synchronize()
@@ -320,7 +380,7 @@ def run(n_train=2_000_000, n_cal=34_464, n_test=65_536, epochs=20, batch=4096, h
     xcal, ycal = d[n_train:n_train + n_cal], y[n_train:n_train + n_cal]
     xte, yte = d[n_train + n_cal:], y[n_train + n_cal:]
     sur = Surrogate(task.n_layers, task.n_out, n_hidden=hidden, n_layers=layers, n_members=members,
-                    max_batch=max(batch, 4096), seed=seed + 1, in_shift=135.0, in_scale=1.0 / 66.4)
+                    max_batch=max(batch, 4096), seed=seed + 1, in_shift=in_shift, in_scale=in_scale)
     t0 = time.perf_counter()
     hist = train(sur, xtr, ytr, epochs=epochs, batch=batch, lr_max=lr_max, lr_min=lr_min, seed=seed,
                  log_every=1, log=log)
@@ -336,7 +396,8 @@ def run(n_train=2_000_000, n_cal=34_464, n_test=65_536, epochs=20, batch=4096, h
     params = sur.export()
     sur.close()
     sur = Surrogate(task.n_layers, task.n_out, n_hidden=hidden, n_layers=layers, n_members=members,
-                    max_batch=infer_batch, seed=seed + 1, in_shift=135.0, in_scale=1.0 / 66.4)
+                    max_batch=infer_batch, seed=seed + 1, in_shift=in_shift, in_scale=in_scale,
+                    sigma_window=sigma_window)
     sur.load(params)
     # accuracy on held-out stacks
     mean, sigma, _ = sur.predict(xte)
@@ -345,25 +406,35 @@ def run(n_train=2_000_000, n_cal=34_464, n_test=65_536, epochs=20, batch=4096, h
     report["test_mae"] = err.mean().item()
     report["test_rmse"] = err.pow(2).mean().sqrt().item()
     report["test_max_abs"] = err.max().item()
+    report["test_frac_within"] = {f"{b:g}": float((err <= b).double().mean()) for b in bounds}
     report["baseline_mean_spectrum_mae"] = base.mean().item()
+    report["sigma_window"] = sigma_window
+    sw = window_sigma(sigma, task, sigma_window)
     mcal, scal, _ = sur.predict(xcal)
-    scale, frac_cal = calibrate(mcal, scal, ycal, bound, margin)
-    del mcal, scal
-    report["err_scale"] = scale
-    report["accepted_fraction_cal"] = frac_cal
-    acc = sigma * scale <= bound
-    report["accepted_fraction_test"] = float(acc.double().mean())
-    report["max_abs_accepted_test"] = float(err[acc].max()) if bool(acc.any()) else None
-    del mean, sigma, err, base, acc
-    out, nf = sur.predict_fallback(xte, task, scale, bound)
+    scal = window_sigma(scal, task, sigma_window)
     y64 = generate(task64, xte.double())
-    report["fallback_fraction_test"] = nf / (n_test * task.n_out)
-    report["max_abs_after_fallback_vs_f64"] = (out.double() - y64).abs().max().item()
-    del out, y64
+    per = {}
+    for bnd in bounds:
+        r = {}
+        scale, r["accepted_fraction_cal"] = calibrate(mcal, scal, ycal, bnd, margin, spread_factor)
+        r["err_scale"] = scale
+        acc = sw * scale <= bnd
+        r["accepted_fraction_test"] = float(acc.double().mean())
+        r["max_abs_accepted_test"] = float(err[acc].max()) if bool(acc.any()) else None
+        out, nf = sur.predict_fallback(xte, task, scale, bnd)
+        r["fallback_fraction_test"] = nf / (n_test * task.n_out)
+        r["max_abs_after_fallback_vs_f64"] = (out.double() - y64).abs().max().item()
+        del out, acc
+        per[f"{bnd:g}"] = r
+        log(json.dumps({"stage": "accuracy", "bound": bnd, **r}))
+    del mcal, scal, sw, mean, sigma, err, base, y64
+    report["bounds"] = per
+    first = per[f"{bounds[0]:g}"]
+    report.update({k: first[k] for k in ("err_scale", "accepted_fraction_cal", "accepted_fraction_test",
+                                        "max_abs_accepted_test", "fallback_fraction_test",
+                                        "max_abs_after_fallback_vs_f64")})
     log(json.dumps({"stage": "accuracy", **{k: report[k] for k in (
-        "test_mae", "test_rmse", "test_max_abs", "baseline_mean_spectrum_mae", "accepted_fraction_cal",
-        "accepted_fraction_test", "max_abs_accepted_test", "fallback_fraction_test",
-        "max_abs_after_fallback_vs_f64")}}))
+        "test_mae", "test_rmse", "test_max_abs", "baseline_mean_spectrum_mae", "test_frac_within")}}))
     # throughput on one batch of eval_batch stacks
     xb = xte[:eval_batch] if n_test >= eval_batch else d[:eval_batch]
     B = xb.shape[0]
@@ -371,19 +442,27 @@ def run(n_train=2_000_000, n_cal=34_464, n_test=65_536, epochs=20, batch=4096, h
     Rd = torch.empty((B, task.n_out), dtype=torch.float64, device=dev)
     x64 = xb.double().contiguous()
     t_tmm32 = _timeit(lambda: tmm.tmm_rt(xb, task.nk, task.wl, task.sin_t, task.cos_t, mat=task.mat(B),
-                                         R=Rf.view(B, 2, task.n_theta, task.n_wl)))
+                                         pol_mask=task.pol_mask, R=Rf.view(B, task.P, task.n_theta, task.n_wl)))
     t_tmm64 = _timeit(lambda: tmm.tmm_rt(x64, task64.nk, task64.wl, task64.sin_t, task64.cos_t,
-                                         mat=task64.mat(B), R=Rd.view(B, 2, task.n_theta, task.n_wl)))
+                                         mat=task64.mat(B), pol_mask=task.pol_mask,
+                                         R=Rd.view(B, task.P, task.n_theta, task.n_wl)))
     t_pred = _timeit(lambda: sur.predict(xb))
-    nfs = []
-    t_fb = _timeit(lambda: nfs.append(sur.predict_fallback(xb, task, scale, bound)[1]))
-    report["throughput_stacks_per_s"] = {"tmm_f32": B / t_tmm32, "tmm_f64": B / t_tmm64,
-                                         "surrogate_only": B / t_pred, "surrogate_fallback": B / t_fb}
-    report["fallback_fraction_eval_batch"] = nfs[-1] / (B * task.n_out)
-    report["gain_vs_tmm_f32"] = t_tmm32 / t_fb
-    report["gain_vs_tmm_f64"] = t_tmm64 / t_fb
-    log(json.dumps({"stage": "throughput", **report["throughput_stacks_per_s"],
-                    "gain_vs_tmm_f32": report["gain_vs_tmm_f32"], "gain_vs_tmm_f64": report["gain_vs_tmm_f64"]}))
+    thr = {"tmm_f32": B / t_tmm32, "tmm_f64": B / t_tmm64, "surrogate_only": B / t_pred}
+    for bnd in bounds:
+        r = per[f"{bnd:g}"]
+        nfs = []
+        t_fb = _timeit(lambda: nfs.append(sur.predict_fallback(xb, task, r["err_scale"], bnd)[1]))
+        r["surrogate_fallback_stacks_per_s"] = B / t_fb
+        r["fallback_fraction_eval_batch"] = nfs[-1] / (B * task.n_out)
+        r["gain_vs_tmm_f32"] = t_tmm32 / t_fb
+        r["gain_vs_tmm_f64"] = t_tmm64 / t_fb
+    thr["surrogate_fallback"] = first["surrogate_fallback_stacks_per_s"]
+    report["throughput_stacks_per_s"] = thr
+    report["fallback_fraction_eval_batch"] = first["fallback_fraction_eval_batch"]
+    report["gain_vs_tmm_f32"] = first["gain_vs_tmm_f32"]
+    report["gain_vs_tmm_f64"] = first["gain_vs_tmm_f64"]
+    log(json.dumps({"stage": "throughput", **thr, "gains": {k: (v["gain_vs_tmm_f32"], v["gain_vs_tmm_f64"])
+                                                            for k, v in per.items()}}))
     sur.close()
     return report
 
@@ -400,14 +479,18 @@ if __name__ == "__main__":
     ap.add_argument("--layers", type=int, default=5)
     ap.add_argument("--members", type=int, default=5)
     ap.add_argument("--lr", type=float, default=1e-3)
-    ap.add_argument("--bound", type=float, default=1e-3)
+    ap.add_argument("--bound", type=float, nargs="+", default=[1e-3])
+    ap.add_argument("--sigma-window", type=int, default=4)
+    ap.add_argument("--spread-factor", type=float, default=2.0)
     ap.add_argument("--margin", type=float, default=0.5, help="calibration margin (fraction of the bound)")
     ap.add_argument("--infer-batch", type=int, default=16384, help="internal batch of the inference handle")
+    ap.add_argument("--instance", choices=sorted(INSTANCES), default="surrogate_batch")
     ap.add_argument("--out", default=None)
     a = ap.parse_args()
     rep = run(n_train=a.n_train, n_cal=a.n_cal, n_test=a.n_test, epochs=a.epochs, batch=a.batch, hidden=a.hidden,
-              layers=a.layers, members=a.members, lr_max=a.lr, bound=a.bound, margin=a.margin,
-              infer_batch=a.infer_batch)
+              layers=a.layers, members=a.members, lr_max=a.lr, bounds=a.bound, margin=a.margin,
+              infer_batch=a.infer_batch, instance=a.instance, sigma_window=a.sigma_window,
+              spread_factor=a.spread_factor)
     print(json.dumps(rep), flush=True)
     if a.out:
         with open(a.out, "w") as f:

@@ -203,6 +203,27 @@ def surrogate_batch(seed: int = 0, B: int = 65536, L: int = 30, n_wl: int = 256,
     return Workload("surrogate_batch_30", d, nk, mat, wl, theta, s, c)
 
 
+def dataset_example(seed: int = 0, B: int = 65536, n_wl: int = 128) -> Workload:
+    """Shape of the paper's dataset-generation example (App. A.2): ten finite
+    layers alternating n = 2.0 / 1.4 between an injection medium n = 2.5 and an
+    exit medium n = 1.0, d ~ U[5,180] nm, wavelengths 1000-1700 nm at normal
+    incidence (the paper's example takes s-polarised R at 100 wavelengths;
+    128 here, the surrogate's output tile).  Table rows: 0 high, 1 low,
+    2 injection, 3 exit."""
+    rng = np.random.default_rng(seed)
+    L = 10
+    d = rng.uniform(5.0, 180.0, (B, L))
+    wl = np.linspace(1000.0, 1700.0, n_wl)
+    nk = np.array([2.0, 1.4, 2.5, 1.0], dtype=np.complex128)
+    mat = np.empty((B, L + 2), dtype=np.int32)
+    mat[:, 0] = 2
+    mat[:, 1:L + 1] = np.arange(L) % 2
+    mat[:, L + 1] = 3
+    theta = np.zeros(1)
+    s, c = angles(theta)
+    return Workload("dataset_example_10", d, nk, mat, wl, theta, s, c)
+
+
 @dataclass
 class RaggedWorkload:
     """Stacks with their own layer counts and grids, packed flat (CSR style).
