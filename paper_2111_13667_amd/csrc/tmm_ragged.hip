@@ -377,9 +377,18 @@ template <>
 __device__ __forceinline__ int renorm_period<double>(bool small, bool medium) { return small ? 64 : (medium ? 32 : 16); }
 template <>
 __device__ __forceinline__ int renorm_period<float>(bool small, bool medium) { return small ? 16 : (medium ? 8 : 4); }
+// Exponent bounds (frexp) for the two longer periods: the largest component
+// below 2^hi, each row's largest component at least 2^(lo - 1).  FP64: 64 steps
+// keep the state below 2^544 and the products within 2^(+-896); 32 steps below
+// 2^(32 x 16.5) and within 2^(+-960).  FP32: 16 steps below 2^96 and within
+// 2^(+-112); 8 steps below 2^72 and within 2^(+-112) (normal range 2^-126).
 template <typename R> struct PeriodBounds;
-template <> struct PeriodBounds<double> { static constexpr int kSmall = 6, kMedium = 14; };
-template <> struct PeriodBounds<float> { static constexpr int kSmall = 3, kMedium = 6; };
+template <> struct PeriodBounds<double> {
+    static constexpr int kSmallHi = 6, kSmallLo = -6, kMediumHi = 14, kMediumLo = -14;
+};
+template <> struct PeriodBounds<float> {
+    static constexpr int kSmallHi = 3, kSmallLo = -2, kMediumHi = 6, kMediumLo = -6;
+};
 
 template <typename R, int POL, int LPP>
 __global__ void __launch_bounds__(Occupancy<R>::kWavesPerCU * kWave) ragged_kernel(Params<R> p) {
@@ -469,9 +478,9 @@ __global__ void __launch_bounds__(Occupancy<R>::kWavesPerCU * kWave) ragged_kern
                 ex_c = max(ex_c, frexp_exp(kk.c1024 * fabs(qr)));
             }
             // renormalisation period and phase-range check (wave-uniform)
-            constexpr int kS = PeriodBounds<R>::kSmall, kM = PeriodBounds<R>::kMedium;
-            const int RPu = renorm_period<R>(__all(ex_max <= kS && ex_min >= -kS),
-                                             __all(ex_max <= kM && ex_min >= -kM));
+            using PB = PeriodBounds<R>;
+            const int RPu = renorm_period<R>(__all(ex_max <= PB::kSmallHi && ex_min >= PB::kSmallLo),
+                                             __all(ex_max <= PB::kMediumHi && ex_min >= PB::kMediumLo));
             const bool c_ok = __all(ex_c <= kPhaseCoefExp);
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
