@@ -268,16 +268,37 @@ def time_surrogate_dataset():
     return rec
 
 
-def roofline(w, dtype, kernel_ms, out_bytes, traffic=None):
-    """kernel_ms: the average launch duration of the forward kernel."""
+# Arithmetic the forward pair kernel executes on the benchmark batch, from its
+# instruction counters (profiles/fwd_pair_kernel_large_batch_4096x40.md: 64 lanes x
+# (2 FMA + MUL + ADD) per launch): FP64 72.6 flops per lane-step, 36.3 per point and
+# interface; FP32 kernel 2.1e10 float and 2.1e9 double instructions' worth.
+EXECUTED_FLOPS_PER_LAUNCH = {
+    "f64": {"fp64": 64 * (2 * 5.018e9 + 3.454e9 + 4.246e9)},
+    "f32": {"fp32": 64 * (2 * 3.35e9 + 3.12e9 + 3.82e9), "fp64": 64 * (2 * 8.33e8 + 4.29e8)},
+}
+
+
+def roofline(w, dtype, kernel_ms, out_bytes, traffic=None, executed=None):
+    """kernel_ms: the average launch duration of the forward kernel.  executed:
+    the kernel's executed flops per launch by precision (instruction counters of
+    the same kernel on the same batch), reported beside the algorithmic figure."""
     flops = w.n_points * (w.L + 1) * FLOPS_PER_POINT_STEP
     achieved = flops / (kernel_ms * 1e-3) / 1e12
     peak = PEAK_TFLOPS[dtype]
-    return {"bound": "alu", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
-            "frac": round(achieved / peak, 4), "traffic": traffic,
-            "algorithmic_flops_per_launch": flops,
-            "output_GBps": round(out_bytes / (kernel_ms * 1e-3) / 1e9, 1),
-            "output_frac_of_hbm": round(out_bytes / (kernel_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)}
+    rec = {"bound": "alu", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+           "frac": round(achieved / peak, 4), "traffic": traffic,
+           "algorithmic_flops_per_launch": flops,
+           "output_GBps": round(out_bytes / (kernel_ms * 1e-3) / 1e9, 1),
+           "output_frac_of_hbm": round(out_bytes / (kernel_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)}
+    if executed:
+        ex = {}
+        for prec, f in executed.items():
+            tf = f / (kernel_ms * 1e-3) / 1e12
+            ex[prec] = {"flops_per_launch": f, "TFLOPs": round(tf, 3),
+                        "frac_of_peak": round(tf / PEAK_TFLOPS["f64" if prec == "fp64" else "f32"], 4)}
+        rec["executed"] = ex
+        rec["executed_source"] = "instruction counters, profiles/fwd_pair_kernel_large_batch_4096x40.md"
+    return rec
 
 
 def time_oracle(w, runs=3, amplitudes=False):
@@ -433,14 +454,15 @@ def main():
                                "1024 wavelengths 300-1200 nm x 91 angles 0-90 deg, s+p, R and T",
                    "stacks": w.B, "layers": w.L, "n_wl": int(w.wl.size), "n_theta": int(w.theta.size),
                    "points": w.n_points, "outputs": "R,T"},
-        "roofline": roofline(w, args.dtype, mean, out_bytes, traffic),
+        "roofline": roofline(w, args.dtype, mean, out_bytes, traffic, EXECUTED_FLOPS_PER_LAUNCH[args.dtype]),
     }
     if not args.no_extra:
         extra = {}
         other = "f32" if args.dtype == "f64" else "f64"
         oms, _, ob = time_gpu(w, other, max(10, args.steps // 2), 1)
         extra[other] = {"value": round(w.n_points / (np.median(oms) * 1e-3), 1), **summary(oms),
-                        "roofline": roofline(w, other, float(np.mean(oms)), ob, traffic_all.get(other))}
+                        "roofline": roofline(w, other, float(np.mean(oms)), ob, traffic_all.get(other),
+                                             EXECUTED_FLOPS_PER_LAUNCH[other])}
         ams, _, ob = time_gpu(w, args.dtype, max(10, args.steps // 2), 1, amplitudes=True)
         extra[args.dtype + "_with_r_t"] = {"value": round(w.n_points / (np.median(ams) * 1e-3), 1), **summary(ams),
                                            "roofline": roofline(w, args.dtype, float(np.mean(ams)), ob)}

@@ -373,6 +373,93 @@ struct PairTab<float> {
     }
 };
 
+// Row blocks (tables of 7 to 16 rows, where a block per ordered pair no longer
+// fits the LDS): one block per table row m with, for the 64 lanes, q_m, eta_m,
+// 1 / q_m, 1 / eta_m and (cre, cim) as in PairTab; a step forms the ratios
+// rho_s = q_{m'} (1 / q_m) and rho_p = eta_{m'} (1 / eta_m) from the blocks of the
+// current row m and the next row m'.
+template <typename R> struct RowTab;
+
+template <>
+struct RowTab<double> {
+    static constexpr int kBlockBytes = 5 * kWave * 16;  // q, eta, 1/q, 1/eta, (cre, cim)
+    __device__ static void put(unsigned char* blk, int lane, cx<double> q, cx<double> e, cx<double> iq,
+                               cx<double> ie, double cre, double cim) {
+        double2* b = reinterpret_cast<double2*>(blk);
+        b[lane] = make_double2(q.re, q.im);
+        b[kWave + lane] = make_double2(e.re, e.im);
+        b[2 * kWave + lane] = make_double2(iq.re, iq.im);
+        b[3 * kWave + lane] = make_double2(ie.re, ie.im);
+        b[4 * kWave + lane] = make_double2(cre, cim);
+    }
+    // `at` is the block address plus lane * 16
+    __device__ __forceinline__ static void get_cur(const unsigned char* at, cx<double>& iq, cx<double>& ie,
+                                                   double& cre, double& cim) {
+        const double2* b = reinterpret_cast<const double2*>(at);
+        const double2 x = b[2 * kWave], y = b[3 * kWave], z = b[4 * kWave];
+        iq = {x.x, x.y};
+        ie = {y.x, y.y};
+        cre = z.x;
+        cim = z.y;
+    }
+    __device__ __forceinline__ static void get_next(const unsigned char* at, cx<double>& q, cx<double>& e) {
+        const double2* b = reinterpret_cast<const double2*>(at);
+        const double2 x = b[0], y = b[kWave];
+        q = {x.x, x.y};
+        e = {y.x, y.y};
+    }
+    __device__ __forceinline__ static Layer<double> layer(const unsigned char* at) {
+        cx<double> q, e;
+        get_next(at, q, e);
+        Layer<double> v;
+        v.q = q;
+        v.e = e;
+        v.q2 = cnorm(q);
+        v.e2 = cnorm(e);
+        v.pr = q.re;
+        v.pi = q.im;
+        return v;
+    }
+};
+
+template <>
+struct RowTab<float> {
+    static constexpr int kBlockBytes = 3 * kWave * 16;  // (q, eta) float4, (1/q, 1/eta) float4, (cre, cim)
+    __device__ static void put(unsigned char* blk, int lane, cx<double> q, cx<double> e, cx<double> iq,
+                               cx<double> ie, double cre, double cim) {
+        reinterpret_cast<float4*>(blk)[lane] = make_float4((float)q.re, (float)q.im, (float)e.re, (float)e.im);
+        reinterpret_cast<float4*>(blk + kWave * 16)[lane] =
+            make_float4((float)iq.re, (float)iq.im, (float)ie.re, (float)ie.im);
+        reinterpret_cast<double2*>(blk + 2 * kWave * 16)[lane] = make_double2(cre, cim);
+    }
+    __device__ __forceinline__ static void get_cur(const unsigned char* at, cx<float>& iq, cx<float>& ie,
+                                                   double& cre, double& cim) {
+        const float4 x = *reinterpret_cast<const float4*>(at + kWave * 16);
+        const double2 z = *reinterpret_cast<const double2*>(at + 2 * kWave * 16);
+        iq = {x.x, x.y};
+        ie = {x.z, x.w};
+        cre = z.x;
+        cim = z.y;
+    }
+    __device__ __forceinline__ static void get_next(const unsigned char* at, cx<float>& q, cx<float>& e) {
+        const float4 x = *reinterpret_cast<const float4*>(at);
+        q = {x.x, x.y};
+        e = {x.z, x.w};
+    }
+    __device__ __forceinline__ static Layer<float> layer(const unsigned char* at) {
+        cx<float> q, e;
+        get_next(at, q, e);
+        Layer<float> v;
+        v.q = q;
+        v.e = e;
+        v.q2 = cnorm(q);
+        v.e2 = cnorm(e);
+        v.pr = (double)q.re;
+        v.pi = (double)q.im;
+        return v;
+    }
+};
+
 // Waves per workgroup at most: 16 (4 per SIMD, at most 128 VGPRs) for every
 // variant but the double-precision two-polarisation amplitude one, which needs
 // more registers and runs 12 (3 per SIMD).
@@ -390,6 +477,17 @@ __host__ __device__ constexpr size_t pair_lds_bytes(int n_mat) {
     return phase_tab_bytes<R>() + (size_t)n_mat * Table<R>::kBlockBytes +
            (size_t)n_mat * n_mat * PairTab<R>::kBlockBytes + kPairFlagBytes;
 }
+// Row-block layout: phase table | one RowTab block per row | flags.
+constexpr int kRowMaxMat = 16;
+constexpr size_t kRowFlagBytes = 4 * kRowMaxMat + 4 * kPairMaxWaves + 8 * kPairMaxWaves + 16;
+template <typename R>
+__host__ __device__ constexpr size_t row_lds_bytes(int n_mat) {
+    return phase_tab_bytes<R>() + (size_t)n_mat * RowTab<R>::kBlockBytes + kRowFlagBytes;
+}
+template <typename R, bool ROWS>
+__host__ __device__ constexpr size_t pair_kernel_lds_bytes(int n_mat) {
+    return ROWS ? row_lds_bytes<R>(n_mat) : pair_lds_bytes<R>(n_mat);
+}
 
 template <typename R>
 constexpr int pair_max_mat() {
@@ -401,7 +499,9 @@ constexpr int pair_max_mat() {
 // One stack on the pair table.  Returns false, having stored nothing, when a
 // layer's phase could leave the range of the fast reduction (thickness above
 // dmax, or not a number); the caller then evaluates the stack on the exact path.
-template <typename R, int POL, bool AMP>
+// ROWS: pair_base holds row blocks (RowTab) and the ratios are formed per step
+// from the current and the next row; tab is not used.
+template <typename R, int POL, bool AMP, bool ROWS>
 __device__ __forceinline__ bool run_stack_pair(const FwdParams<R>& p, const unsigned char* pair_base,
                                                const Table<R>& tab, uint32_t lossy_mask, double dmax,
                                                const Ambient& amb, int b, int k, int i, int lane, bool active,
@@ -415,6 +515,7 @@ __device__ __forceinline__ bool run_stack_pair(const FwdParams<R>& p, const unsi
     bool bad = (uint32_t)m_sub_raw >= (uint32_t)n_mat;
     const int m_sub = bad ? 0 : m_sub_raw;
     const unsigned char* const lane_base = pair_base + lane * 16;
+    int nxt_off = m_sub * RowTab<R>::kBlockBytes;  // ROWS: block of the layer below (the substrate first)
     PairChain<R, POL, AMP> c;
     c.init();
     constexpr int RP = PairRenormPeriod<R>::value;
@@ -429,12 +530,14 @@ __device__ __forceinline__ bool run_stack_pair(const FwdParams<R>& p, const unsi
         if (j <= top) {
             const R dj = drow[j - 1];
             const int m = mrow[j], mn = mrow[j + 1];
-            const bool mbad = (uint32_t)m >= (uint32_t)n_mat || (uint32_t)mn >= (uint32_t)n_mat;
+            // ROWS: the next row was checked as the current one of the step below (or as the substrate)
+            const bool mbad = (uint32_t)m >= (uint32_t)n_mat || (!ROWS && (uint32_t)mn >= (uint32_t)n_mat);
             lane_bad = mbad || bad_thickness(dj);
             lane_far = !((double)dj <= dmax);
             const int mc = mbad ? 0 : m, mnc = mbad ? 0 : mn;
             my_d = (double)dj;
-            my_code = (mc * n_mat + mnc) * PairTab<R>::kBlockBytes | (int)(((lossy_mask >> mc) & 1u) << 31);
+            const int off = ROWS ? mc * RowTab<R>::kBlockBytes : (mc * n_mat + mnc) * PairTab<R>::kBlockBytes;
+            my_code = off | (int)(((lossy_mask >> mc) & 1u) << 31);
         }
         if (__any(lane_far)) return false;
         bad = bad || __any(lane_bad);
@@ -445,7 +548,17 @@ __device__ __forceinline__ bool run_stack_pair(const FwdParams<R>& p, const unsi
                                                __builtin_amdgcn_readlane(__double2loint(my_d), sl));
             cx<R> rs, rp;
             double cre, cim;
-            PairTab<R>::get(lane_base + (code & 0x7fffffff), rs, rp, cre, cim);
+            if constexpr (ROWS) {
+                const int cur_off = code & 0x7fffffff;
+                cx<R> iq, ie, qn, en;
+                RowTab<R>::get_cur(lane_base + cur_off, iq, ie, cre, cim);
+                RowTab<R>::get_next(lane_base + nxt_off, qn, en);
+                rs = cmul(qn, iq);
+                rp = cmul(en, ie);
+                nxt_off = cur_off;
+            } else {
+                PairTab<R>::get(lane_base + (code & 0x7fffffff), rs, rp, cre, cim);
+            }
             c.step(rs, rp, cre, cim, dj, code < 0, phase);
         };
         for (int bt = top; bt >= lo; bt -= RP) {
@@ -462,7 +575,12 @@ __device__ __forceinline__ bool run_stack_pair(const FwdParams<R>& p, const unsi
     const int m_first_raw = L >= 1 ? mrow[1] : m_sub;
     const int m_first = (uint32_t)m_first_raw < (uint32_t)n_mat ? m_first_raw : 0;
     PointOut out[2];
-    finish<R, POL, AMP>(c, amb, tab.get(m_first, lane), tab.get(m_sub, lane), nsub_r, nsub_i, L, out, phase);
+    if constexpr (ROWS)
+        finish<R, POL, AMP>(c, amb, RowTab<R>::layer(lane_base + m_first * RowTab<R>::kBlockBytes),
+                            RowTab<R>::layer(lane_base + m_sub * RowTab<R>::kBlockBytes), nsub_r, nsub_i, L, out,
+                            phase);
+    else
+        finish<R, POL, AMP>(c, amb, tab.get(m_first, lane), tab.get(m_sub, lane), nsub_r, nsub_i, L, out, phase);
     if (active) {
         const bool valid = lane_ok && !bad;
         constexpr int P = (POL == 3) ? 2 : 1;
@@ -472,7 +590,7 @@ __device__ __forceinline__ bool run_stack_pair(const FwdParams<R>& p, const unsi
     return true;
 }
 
-template <typename R, int POL, bool AMP>
+template <typename R, int POL, bool AMP, bool ROWS>
 __global__ void __launch_bounds__((pair_max_waves<R, POL, AMP>() * kWave)) fwd_pair_kernel(FwdParams<R> p) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int nthr = blockDim.x;  // a multiple of kWave, at most pair_max_waves * kWave
@@ -497,10 +615,12 @@ __global__ void __launch_bounds__((pair_max_waves<R, POL, AMP>() * kWave)) fwd_p
     const int n_mat = p.n_mat;
     fill_phase_tab<R>(smem, threadIdx.x, nthr);
     unsigned char* const tab_base = smem + phase_tab_bytes<R>();
-    unsigned char* const pair_base = tab_base + (size_t)n_mat * Table<R>::kBlockBytes;
-    unsigned char* const flag_base = pair_base + (size_t)n_mat * n_mat * PairTab<R>::kBlockBytes;
+    // ROWS: no media table; the row blocks start where it would
+    unsigned char* const pair_base = ROWS ? tab_base : tab_base + (size_t)n_mat * Table<R>::kBlockBytes;
+    unsigned char* const flag_base =
+        pair_base + (ROWS ? (size_t)n_mat * RowTab<R>::kBlockBytes : (size_t)n_mat * n_mat * PairTab<R>::kBlockBytes);
     int* const lossy_f = reinterpret_cast<int*>(flag_base);
-    int* const bad_w = lossy_f + kPairMaxMat;
+    int* const bad_w = lossy_f + (ROWS ? kRowMaxMat : kPairMaxMat);  // one lossy flag per row
     double* const cmax_w = reinterpret_cast<double*>(bad_w + kPairMaxWaves);
     int* const next_b = reinterpret_cast<int*>(cmax_w + kPairMaxWaves);
 
@@ -510,6 +630,23 @@ __global__ void __launch_bounds__((pair_max_waves<R, POL, AMP>() * kWave)) fwd_p
     load_n(p.nk, p.dispersive, p.n_wl, amb_row, i, n0r, n0i);
     const Ambient amb = make_ambient(n0r, n0i, st, ct);
     Table<R> tab(tab_base, n_mat);
+    const bool lane_used = active && lam_ok && amb.ok;
+    bool bad_lane = false;
+    double cmax = 0.0;
+    if constexpr (ROWS) {
+        // row blocks: q, eta, their reciprocals and the phase coefficients of every row
+        for (int m = wave; m < n_mat; m += nwaves) {
+            double nr, ni;
+            load_n(p.nk, p.dispersive, p.n_wl, m, i, nr, ni);
+            const Medium md = make_medium(nr, ni, amb.kx);
+            const cx<double> q = {md.qr, md.qi}, e = {md.er, md.ei};
+            const cx<double> iq = cdiv({1.0, 0.0}, q), ie = cdiv({1.0, 0.0}, e);
+            const double cre = (c4lam * kScSteps) * md.qr, cim = c4lam * md.qi * kNegPiLog2e;
+            RowTab<R>::put(pair_base + (size_t)m * RowTab<R>::kBlockBytes, lane, q, e, iq, ie, cre, cim);
+            const bool lossy = __any(md.qi != 0.0);
+            if (lane == 0) lossy_f[m] = lossy ? 1 : 0;
+        }
+    } else {
     for (int m = wave; m < n_mat; m += nwaves) {
         double nr, ni;
         load_n(p.nk, p.dispersive, p.n_wl, m, i, nr, ni);
@@ -520,9 +657,6 @@ __global__ void __launch_bounds__((pair_max_waves<R, POL, AMP>() * kWave)) fwd_p
     }
     // pair blocks; lanes whose results are stored check the ratio bound and
     // give the largest phase coefficient
-    const bool lane_used = active && lam_ok && amb.ok;
-    bool bad_lane = false;
-    double cmax = 0.0;
     for (int pi = wave; pi < n_mat * n_mat; pi += nwaves) {
         const int mc = pi / n_mat, mn = pi - mc * n_mat;
         double ar, ai, br, bi;
@@ -537,6 +671,37 @@ __global__ void __launch_bounds__((pair_max_waves<R, POL, AMP>() * kWave)) fwd_p
             const double mag = fmax(fmax(fabs(rs.re), fabs(rs.im)), fmax(fabs(rp.re), fabs(rp.im)));
             bad_lane = bad_lane || !(mag <= kPairRatioMax);
             cmax = fmax(cmax, fabs(cre));
+        }
+    }
+    }
+    if constexpr (ROWS) {
+        // every ratio of two rows is bounded by the largest over the smallest modulus;
+        // each wave reads all rows for its lanes after the blocks are written
+        __syncthreads();
+        if (lane_used) {
+            double qmax = 0.0, qmin = __builtin_inf(), emax = 0.0, emin = __builtin_inf();
+            for (int m = 0; m < n_mat; ++m) {
+                const double2* b = reinterpret_cast<const double2*>(pair_base + (size_t)m * RowTab<R>::kBlockBytes);
+                cx<double> q, e;
+                if constexpr (sizeof(R) == 8) {
+                    const double2 x = b[lane], y = b[kWave + lane];
+                    q = {x.x, x.y};
+                    e = {y.x, y.y};
+                } else {
+                    const float4 x = reinterpret_cast<const float4*>(b)[lane];
+                    q = {(double)x.x, (double)x.y};
+                    e = {(double)x.z, (double)x.w};
+                }
+                const double aq = sqrt(cnorm(q)), ae = sqrt(cnorm(e));
+                qmax = fmax(qmax, aq);
+                qmin = fmin(qmin, aq);
+                emax = fmax(emax, ae);
+                emin = fmin(emin, ae);
+                const double cre = reinterpret_cast<const double2*>(
+                    pair_base + (size_t)m * RowTab<R>::kBlockBytes + (RowTab<R>::kBlockBytes - kWave * 16))[lane].x;
+                cmax = fmax(cmax, fabs(cre));
+            }
+            bad_lane = !(qmax <= kPairRatioMax * qmin) || !(emax <= kPairRatioMax * emin);
         }
     }
     const bool wave_bad = __any(bad_lane);
@@ -576,8 +741,8 @@ __global__ void __launch_bounds__((pair_max_waves<R, POL, AMP>() * kWave)) fwd_p
         double nsr = 0.0, nsi = 0.0;
         if (AMP) load_n(p.nk, p.dispersive, p.n_wl, sub_row, i, nsr, nsi);
         if (pair_ok && mrow[0] == amb_row &&
-            run_stack_pair<R, POL, AMP>(p, pair_base, tab, mask, dmax, amb, bb, k, i, lane, active, lam_ok && amb.ok,
-                                        nsr, nsi, phase))
+            run_stack_pair<R, POL, AMP, ROWS>(p, pair_base, tab, mask, dmax, amb, bb, k, i, lane, active,
+                                              lam_ok && amb.ok, nsr, nsi, phase))
             continue;
         // per-step media: any ambient, any ratio, any finite phase
         int a_row = mrow[0];
@@ -612,37 +777,39 @@ static hipError_t dispatch_pol(const FwdParams<R>& p, unsigned pol, bool amp, in
     return launch_fwd<R, 3, false, TABLE>(p, blocks, lds, s);
 }
 
-template <typename R, int POL, bool AMP>
+template <typename R, int POL, bool AMP, bool ROWS>
 static hipError_t launch_pair(const FwdParams<R>& p, int blocks, int threads, size_t lds, hipStream_t s) {
     // dynamic LDS above 64 KiB: raise the kernel's limit once per device
     static std::atomic<size_t> raised[64];
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
     if (raised[dev].load() < lds) {
-        (void)hipFuncSetAttribute((const void*)&fwd_pair_kernel<R, POL, AMP>,
+        (void)hipFuncSetAttribute((const void*)&fwd_pair_kernel<R, POL, AMP, ROWS>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         (void)hipGetLastError();
         raised[dev].store(lds);
     }
-    hipLaunchKernelGGL((fwd_pair_kernel<R, POL, AMP>), dim3(blocks), dim3(threads), lds, s, p);
+    hipLaunchKernelGGL((fwd_pair_kernel<R, POL, AMP, ROWS>), dim3(blocks), dim3(threads), lds, s, p);
     return hipGetLastError();
 }
 
 // Launch shape of the pair kernel: as many workgroups per CU as the LDS holds
-// (at most 4), and waves per workgroup so that the CU holds its maximum of
+// (1, 2 or 4), and waves per workgroup so that the CU holds its maximum of
 // resident waves.  Stacks per workgroup: enough layer steps to amortise the
 // workgroup's table build (about 320 VALU instructions per material pair and
 // 150 per material, against about 60 per layer step) twenty times over, more
 // while the grid keeps at least 64 workgroups per resident slot (a short last
 // round of workgroups), at most 32 per wave.
-template <typename R, int POL, bool AMP>
+template <typename R, int POL, bool AMP, bool ROWS>
 static tmm_status run_pair(FwdParams<R> p, int64_t B, int64_t cols, hipStream_t s) {
-    const size_t lds = pair_lds_bytes<R>(p.n_mat);
+    const size_t lds = pair_kernel_lds_bytes<R, ROWS>(p.n_mat);
     const size_t granule = 2048;
     int per_cu = (int)(kLdsPerCU / ((lds + granule - 1) / granule * granule));
-    per_cu = per_cu < 1 ? 1 : (per_cu > 4 ? 4 : per_cu);
+    // 1, 2 or 4 workgroups per CU, so that each holds a multiple of the four SIMDs'
+    // waves (three would give five-wave workgroups that do not divide over them)
+    per_cu = per_cu >= 4 ? 4 : (per_cu >= 2 ? 2 : 1);
     const int waves = pair_max_waves<R, POL, AMP>() / per_cu;
-    const int64_t table_cost = 320 * (int64_t)p.n_mat * p.n_mat + 150 * (int64_t)p.n_mat;
+    const int64_t table_cost = ROWS ? 450 * (int64_t)p.n_mat : 320 * (int64_t)p.n_mat * p.n_mat + 150 * (int64_t)p.n_mat;
     const int64_t amortise = ceil_div(20 * table_cost, 60 * ((int64_t)p.L + 1));
     const int64_t fill = ceil_div(B * cols, 256 * (int64_t)per_cu * 64);
     int64_t chunk = amortise > fill ? amortise : fill;
@@ -652,22 +819,22 @@ static tmm_status run_pair(FwdParams<R> p, int64_t B, int64_t cols, hipStream_t 
     const int64_t blocks = cols * ceil_div(B, (int64_t)p.chunk);
     if (blocks > 0x7fffffff)
         return fail(TMM_ERR_UNSUPPORTED, "tmm_rt: grid of %lld workgroups is too large", (long long)blocks);
-    const hipError_t e = launch_pair<R, POL, AMP>(p, (int)blocks, waves * kWave, lds, s);
+    const hipError_t e = launch_pair<R, POL, AMP, ROWS>(p, (int)blocks, waves * kWave, lds, s);
     if (e != hipSuccess) return fail(TMM_ERR_HIP, "tmm_rt: launch failed: %s", hipGetErrorString(e));
     return ok();
 }
 
-template <typename R>
+template <typename R, bool ROWS>
 static tmm_status dispatch_pair(const FwdParams<R>& p, unsigned pol, bool amp, int64_t B, int64_t cols,
                                 hipStream_t s) {
     if (amp) {
-        if (pol == 1) return run_pair<R, 1, true>(p, B, cols, s);
-        if (pol == 2) return run_pair<R, 2, true>(p, B, cols, s);
-        return run_pair<R, 3, true>(p, B, cols, s);
+        if (pol == 1) return run_pair<R, 1, true, ROWS>(p, B, cols, s);
+        if (pol == 2) return run_pair<R, 2, true, ROWS>(p, B, cols, s);
+        return run_pair<R, 3, true, ROWS>(p, B, cols, s);
     }
-    if (pol == 1) return run_pair<R, 1, false>(p, B, cols, s);
-    if (pol == 2) return run_pair<R, 2, false>(p, B, cols, s);
-    return run_pair<R, 3, false>(p, B, cols, s);
+    if (pol == 1) return run_pair<R, 1, false, ROWS>(p, B, cols, s);
+    if (pol == 2) return run_pair<R, 2, false, ROWS>(p, B, cols, s);
+    return run_pair<R, 3, false, ROWS>(p, B, cols, s);
 }
 
 // Stacks per workgroup: enough workgroups to fill 256 CUs many times over,
@@ -704,7 +871,9 @@ static tmm_status run_fwd(const tmm_rt_args* a, hipStream_t s) {
     const int64_t cols = (int64_t)p.n_tiles * a->n_theta;
     const bool amp = a->r != nullptr || a->t != nullptr;
     (void)hipGetLastError();
-    if (a->mat != nullptr && a->n_mat <= pair_max_mat<R>()) return dispatch_pair<R>(p, a->pol_mask, amp, a->B, cols, s);
+    if (a->mat != nullptr && a->n_mat <= pair_max_mat<R>())
+        return dispatch_pair<R, false>(p, a->pol_mask, amp, a->B, cols, s);
+    if (a->mat != nullptr && a->n_mat <= kRowMaxMat) return dispatch_pair<R, true>(p, a->pol_mask, amp, a->B, cols, s);
     p.chunk = pick_chunk(a->B, cols);
     const int64_t blocks = cols * ceil_div(a->B, p.chunk);
     if (blocks > 0x7fffffff)

@@ -514,3 +514,53 @@ def test_long_stacks_many_renormalisation_blocks(dtype):
             assert_close64(run_gpu(ww, amplitudes=True), run_oracle(ww, amplitudes=True), ("R", "T", "r", "t"))
         else:
             assert_close32(run_gpu(ww, dtype="f32"), run_oracle(ww.rounded_f32()))
+
+
+@pytest.mark.parametrize("n_inner,L", [(5, 31), (10, 64), (14, 45)])
+def test_row_blocks_f64(n_inner, L):
+    # 7, 12 and 16 table rows (above the pair blocks' six in double): one block per
+    # row with q, eta, their reciprocals and the phase coefficients, the ratios
+    # formed per step; ragged wavelength tile, angles to 89 deg, r and t.
+    w = _material_workload(140 + n_inner, B=23, L=L, n_wl=97, n_theta=4, n_inner=n_inner)
+    assert_close64(run_gpu(w, amplitudes=True), run_oracle(w, amplitudes=True), ("R", "T", "r", "t"))
+    assert_close64(run_gpu(w), run_oracle(w))
+
+
+@pytest.mark.parametrize("n_inner,L", [(7, 40), (14, 66)])
+def test_row_blocks_f32(n_inner, L):
+    # 9 and 16 rows in float (above the pair blocks' eight), with r and t
+    w = _material_workload(150 + n_inner, B=19, L=L, n_wl=70, n_theta=3, n_inner=n_inner)
+    assert_close32(run_gpu(w, dtype="f32"), run_oracle(w.rounded_f32()))
+    assert_close32(run_gpu(w, dtype="f32", amplitudes=True), run_oracle(w.rounded_f32(), amplitudes=True))
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_row_blocks_metal_rows_and_critical_fallback(dtype):
+    # Ten rows: metal-like media (0.15+3.5i, 0.9+5.8i) in thin films with the
+    # strong-attenuation path, under a dense ambient (n = 1.5) with one air layer
+    # per stack at 4e-6 from its critical angle (q ~ 2.5e-3: the row ratios exceed
+    # their bound and those workgroups take the division-free recursion), beside an
+    # angle that stays on the row blocks.
+    from dataclasses import replace
+    rng = np.random.default_rng(160)
+    w = _material_workload(160, B=8, L=10, n_wl=66, n_theta=3, n_inner=8, n_amb=1.5, k_max=0.005)
+    nk = w.nk.copy()
+    nk[0] = 1.0
+    nk[1] = workloads.cauchy(np.array([0.15]), np.array([0.0]), np.array([3.5]), w.wl)[0]
+    nk[2] = workloads.cauchy(np.array([0.9]), np.array([0.0]), np.array([5.8]), w.wl)[0]
+    mat = w.mat.copy()
+    inner = mat[:, 1:-1]
+    inner[inner == 0] = 3
+    inner[np.arange(w.B), np.arange(w.B) % w.L] = 0
+    d = w.d.copy()
+    metal = np.isin(inner, [1, 2])
+    d[metal] = rng.uniform(5.0, 40.0, int(metal.sum()))
+    th_c = np.arcsin(1.0 / 1.5)
+    theta = np.array([0.3, th_c * (1 + 4e-6), th_c * (1 - 4e-6)])
+    s, c = workloads.angles(theta)
+    w = replace(w, nk=nk, mat=mat, d=d, theta=theta, sin_t=s, cos_t=c)
+    if dtype == "f64":
+        assert_close64(run_gpu(w, amplitudes=True), run_oracle(w, amplitudes=True), ("R", "T", "r", "t"))
+    else:
+        ww = replace(w, theta=theta[:1], sin_t=s[:1], cos_t=c[:1])  # float: away from the critical angle
+        assert_close32(run_gpu(ww, dtype="f32"), run_oracle(ww.rounded_f32()))
