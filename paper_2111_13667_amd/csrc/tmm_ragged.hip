@@ -27,8 +27,10 @@
 // the point.  Twice the arithmetic per layer, a fraction of the latency: for
 // batches with few points per stack.
 //
-// The plan keeps its own device copies of the offsets it was created with,
-// so the kernel never reads a caller's offset array.
+// The plan keeps one 64-byte record per stack on the device (its offsets,
+// sizes and unit range, built from the offsets it was created with), so the
+// kernel never reads a caller's offset array and a wave reads a stack's
+// description with one scalar load when its units move on to the next stack.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <string.h>
@@ -63,13 +65,23 @@ constexpr int kLppChoices[3] = {1, 2, 4};
 // layer thinner than 2^(49 - kPhaseCoefExp).
 constexpr int kPhaseCoefExp = 20;
 
+// What a wave needs of a stack, in one 64-byte record (one scalar load),
+// per lanes-per-point choice since the unit ranges differ.
+struct StackInfo {
+    int64_t l0;          // first layer in d, mat
+    int64_t w0;          // first wavelength column
+    int64_t t0;          // first angle
+    int64_t out0;        // first output element
+    int64_t first_unit;  // units [first_unit, end_unit) are this stack's tiles
+    int64_t end_unit;
+    int32_t L, n_wl, n_th, pad;
+};
+static_assert(sizeof(StackInfo) == 64, "one 64-byte scalar load per stack");
+
 template <typename R>
 struct Params {
     int B;
-    const int64_t* layer_off;
-    const int64_t* wl_off;
-    const int64_t* th_off;
-    const int64_t* out_off;
+    const StackInfo* info;  // [B]
     const R* d;
     const int32_t* mat;
     const int32_t* ends;
@@ -81,8 +93,7 @@ struct Params {
     int64_t nk_stride;  // wl_off[B]
     R* R_out;
     R* T_out;
-    const int32_t* unit_stack;   // stack of each unit (units of a stack are consecutive)
-    const int64_t* stack_first;  // [B] first unit of each stack
+    const int32_t* unit_stack;  // stack of each unit (units of a stack are consecutive)
     int64_t n_units;
     unsigned long long* counter;
     int grain;
@@ -117,6 +128,15 @@ struct WaveTable<double> {
         return {{a.x, a.y}, {b.x, b.y}};
     }
     __device__ __forceinline__ Row<double> get_qe(int m, int lane) const { return get(m, lane); }
+    // The row's refractive index parked in its q slot until put() replaces it.
+    __device__ __forceinline__ void stage(int m, int lane, double nr, double ni) {
+        reinterpret_cast<double2*>(base + m * kBlockBytes)[lane] = make_double2(nr, ni);
+    }
+    __device__ __forceinline__ void staged(int m, int lane, double& nr, double& ni) const {
+        const double2 v = reinterpret_cast<const double2*>(base + m * kBlockBytes)[lane];
+        nr = v.x;
+        ni = v.y;
+    }
 };
 
 template <>
@@ -137,6 +157,15 @@ struct WaveTable<float> {
         Row<float> r = get_qe(m, lane);
         r.c = reinterpret_cast<const double*>(base + m * kBlockBytes)[lane];
         return r;
+    }
+    // The row's refractive index parked in its c slot until put() replaces it.
+    __device__ __forceinline__ void stage(int m, int lane, float nr, float ni) {
+        reinterpret_cast<float2*>(base + m * kBlockBytes)[lane] = make_float2(nr, ni);
+    }
+    __device__ __forceinline__ void staged(int m, int lane, double& nr, double& ni) const {
+        const float2 v = reinterpret_cast<const float2*>(base + m * kBlockBytes)[lane];
+        nr = (double)v.x;
+        ni = (double)v.y;
     }
 };
 
@@ -390,6 +419,45 @@ template <> struct PeriodBounds<float> {
     static constexpr int kSmallHi = 3, kSmallLo = -2, kMediumHi = 6, kMediumLo = -6;
 };
 
+// Read of a plan or input array at a wave-uniform index through the constant
+// address space: a scalar load straight into scalar registers (none of these
+// arrays is written while the kernel runs).
+template <typename T>
+__device__ __forceinline__ T uread(const T* a, int64_t i) {
+    return ((const __attribute__((address_space(4))) T*)a)[i];
+}
+
+// A stack's record, field by field through uread (one 64-byte scalar load).
+__device__ __forceinline__ StackInfo uread_info(const StackInfo* a, int64_t b) {
+    const int64_t* w = reinterpret_cast<const int64_t*>(a + b);
+    const int32_t* v = reinterpret_cast<const int32_t*>(w + 6);
+    StackInfo r;
+    r.l0 = uread(w, 0);
+    r.w0 = uread(w, 1);
+    r.t0 = uread(w, 2);
+    r.out0 = uread(w, 3);
+    r.first_unit = uread(w, 4);
+    r.end_unit = uread(w, 5);
+    r.L = uread(v, 0);
+    r.n_wl = uread(v, 1);
+    r.n_th = uread(v, 2);
+    r.pad = 0;
+    return r;
+}
+
+// Claims the next batch of units; the old counter value arrives in lane 0.
+__device__ __forceinline__ unsigned long long claim(unsigned long long* counter, int grain, int lane) {
+    unsigned long long v = 0;
+    if (lane == 0) v = atomicAdd(counter, (unsigned long long)grain);
+    return v;
+}
+
+__device__ __forceinline__ int64_t first_lane(unsigned long long v) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
 template <typename R, int POL, int LPP>
 __global__ void __launch_bounds__(Occupancy<R>::kWavesPerCU * kWave) ragged_kernel(Params<R> p) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -404,22 +472,31 @@ __global__ void __launch_bounds__(Occupancy<R>::kWavesPerCU * kWave) ragged_kern
     constexpr int PPW = kWave / LPP;  // points per unit (the tile)
     const int pt = lane / LPP;        // this lane's point within the unit
     const int seg = lane % LPP;       // and its layer segment (0 = ambient side)
+    // The next batch is claimed while the current one's first unit runs, so
+    // the atomic's round trip overlaps that work.
+    int64_t next = first_lane(claim(p.counter, p.grain, lane));
+    // the current stack's record and end rows, kept while the units stay in it
+    StackInfo si;
+    si.first_unit = 1;
+    si.end_unit = 0;
+    int b = 0, a_raw = 0, s_raw = 0;
     for (;;) {
-        unsigned long long base = 0;
-        if (lane == 0) base = atomicAdd(p.counter, (unsigned long long)p.grain);
-        base = __shfl(base, 0, kWave);
-        if ((int64_t)base >= p.n_units) break;
+        const int64_t base = next;
+        if (base >= p.n_units) break;
         for (int g = 0; g < p.grain; ++g) {
-            const int64_t u = (int64_t)base + g;
+            const int64_t u = base + g;
             if (u >= p.n_units) break;
-            const int b = __builtin_amdgcn_readfirstlane(p.unit_stack[u]);
-            const int64_t tile = u - p.stack_first[b];
-            const int64_t l0 = p.layer_off[b];
-            const int L = (int)(p.layer_off[b + 1] - l0);
-            const int64_t w0 = p.wl_off[b];
-            const int nwl = (int)(p.wl_off[b + 1] - w0);
-            const int64_t t0 = p.th_off[b];
-            const int nth = (int)(p.th_off[b + 1] - t0);
+            // the stack's description (wave-uniform), read when the unit leaves the last one
+            if (u < si.first_unit || u >= si.end_unit) {
+                b = uread(p.unit_stack, u);
+                si = uread_info(p.info, b);
+                a_raw = uread(p.ends, 2 * (int64_t)b);
+                s_raw = uread(p.ends, 2 * (int64_t)b + 1);
+            }
+            const int64_t tile = u - si.first_unit;
+            const int64_t l0 = si.l0, w0 = si.w0, t0 = si.t0;
+            const int L = si.L, nwl = si.n_wl, nth = si.n_th;
+            int a_row = a_raw, s_row = s_raw;
             const int64_t npts = (int64_t)nth * nwl;
             const int64_t f_raw = tile * PPW + pt;
             const bool active = f_raw < npts;
@@ -435,35 +512,60 @@ __global__ void __launch_bounds__(Occupancy<R>::kWavesPerCU * kWave) ragged_kern
                 i = (int)(f - (int64_t)k * nwl);
             }
             const int64_t col = w0 + i;  // column of this lane's wavelength in nk
-            const double lam = (double)p.wl[col];
-            const bool lam_ok = lam > 0.0 && lam < __builtin_inf();
-            LaneK kk;
-            kk.c1024 = (double)(4 * kScSteps) / lam;
-            kk.kim = (float)(kk.c1024 * (kNegPiLog2e / kScSteps));
-            const double st = (double)p.sin_t[t0 + k], ct = (double)p.cos_t[t0 + k];
-            int a_row = p.ends[2 * b], s_row = p.ends[2 * b + 1];
             bool bad = (uint32_t)a_row >= (uint32_t)p.n_mat || (uint32_t)s_row >= (uint32_t)p.n_mat;
             a_row = min(max(a_row, 0), p.n_mat - 1);
             s_row = min(max(s_row, 0), p.n_mat - 1);
-            const Ambient amb = make_ambient((double)p.nk[2 * ((int64_t)a_row * p.nk_stride + col)],
-                                             (double)p.nk[2 * ((int64_t)a_row * p.nk_stride + col) + 1], st, ct);
             const R* drow = p.d + l0;
             const int32_t* mrow = p.mat + l0;
+            // Every per-lane read of the unit is issued here, before any of them
+            // is used, so that they share one memory round trip: the point's
+            // wavelength and angle, the ambient's and every table row's index
+            // (rows past n_mat repeat the last one), and the layer list of the
+            // top 64-layer chunk (lane l: layer lo1 + l).
+            const R lam_r = p.wl[col];
+            const R st_r = p.sin_t[t0 + k], ct_r = p.cos_t[t0 + k];
+            const R* nkc = p.nk + 2 * col;
+            const R an_r = nkc[2 * (int64_t)a_row * p.nk_stride], an_i = nkc[2 * (int64_t)a_row * p.nk_stride + 1];
+            R raw_r[kMaxMat], raw_i[kMaxMat];
+#pragma unroll
+            for (int m = 0; m < kMaxMat; ++m) {
+                const int64_t e = 2 * (int64_t)min(m, p.n_mat - 1) * p.nk_stride;
+                raw_r[m] = nkc[e];
+                raw_i[m] = nkc[e + 1];
+            }
+            const int lo1 = max(L - kWave + 1, 1);
+            const int j1 = lo1 + lane;
+            R d1 = (R)0;
+            int m1 = 0;
+            if (j1 <= L) {
+                d1 = drow[j1 - 1];
+                m1 = mrow[j1 - 1];
+            }
+            const double lam = (double)lam_r;
+            const bool lam_ok = lam > 0.0 && lam < __builtin_inf();
+            LaneK kk;
+            kk.c1024 = (double)(4 * kScSteps) * rcp_nr(lam);
+            kk.kim = (float)(kk.c1024 * (kNegPiLog2e / kScSteps));
+            const Ambient amb = make_ambient((double)an_r, (double)an_i, (double)st_r, (double)ct_r);
             // rows the stack uses: its layers' materials and the substrate
             uint32_t used = 1u << s_row;
             {
-                uint32_t lane_used = 0;
-                for (int j = lane; j < L; j += kWave) lane_used |= 1u << min(max(mrow[j], 0), p.n_mat - 1);
+                uint32_t lane_used = j1 <= L ? 1u << min(max(m1, 0), p.n_mat - 1) : 0u;
+                for (int j = lane; j < lo1 - 1; j += kWave) lane_used |= 1u << min(max(mrow[j], 0), p.n_mat - 1);
                 for (int m = 0; m < p.n_mat; ++m)
                     if (__any((lane_used >> m) & 1u)) used |= 1u << m;
             }
-            // this unit's media table: the used rows at this lane's point
+            // this unit's media table: the indices staged in each row's block,
+            // then q and eta of the used rows at this lane's point
+#pragma unroll
+            for (int m = 0; m < kMaxMat; ++m)
+                if (m < p.n_mat) tab.stage(m, lane, raw_r[m], raw_i[m]);
             uint32_t lossy_mask = 0;
             int ex_max = -1100, ex_min = 1100, ex_c = -1100;
             for (int m = 0; m < p.n_mat; ++m) {
                 if (!((used >> m) & 1u)) continue;
-                const int64_t e = (int64_t)m * p.nk_stride + col;
-                const double nr = (double)p.nk[2 * e], ni = (double)p.nk[2 * e + 1];
+                double nr, ni;
+                tab.staged(m, lane, nr, ni);
                 double qr, qi = 0.0, er, ei = 0.0;
                 if (__all(ni == 0.0 && nr * nr - amb.kx * amb.kx > 0.0)) {
                     row_lossless(nr, amb.kx, qr, er);
@@ -477,6 +579,12 @@ __global__ void __launch_bounds__(Occupancy<R>::kWavesPerCU * kWave) ragged_kern
                 ex_min = min(ex_min, min(frexp_exp(qa), frexp_exp(ea)));
                 ex_c = max(ex_c, frexp_exp(kk.c1024 * fabs(qr)));
             }
+            // The next batch is claimed now that the unit's reads are consumed
+            // (vector memory operations complete in order, so an atomic issued
+            // before them would hold up their wait) and read back once the
+            // unit is done.
+            unsigned long long claimed = 0;
+            if (g == 0) claimed = claim(p.counter, p.grain, lane);
             // renormalisation period and phase-range check (wave-uniform)
             using PB = PeriodBounds<R>;
             const int RPu = renorm_period<R>(__all(ex_max <= PB::kSmallHi && ex_min >= PB::kSmallLo),
@@ -495,15 +603,19 @@ __global__ void __launch_bounds__(Occupancy<R>::kWavesPerCU * kWave) ragged_kern
                     const int lo = top - kWave + 1 > 1 ? top - kWave + 1 : 1;
                     // lane l holds layer lo + l (thickness, table row); the loop broadcasts them
                     const int j = lo + lane;
+                    R dj = d1;  // the top chunk was read with the unit's other reads
+                    int mj = m1;
+                    if (top != L && j <= top) {
+                        dj = drow[j - 1];
+                        mj = mrow[j - 1];
+                    }
                     R my_d = (R)0;
                     int my_m = 0;
                     bool lane_bad = false;
                     if (j <= top) {
-                        const R dj = drow[j - 1];
-                        const int m = mrow[j - 1];
-                        lane_bad = bad_thickness(dj) || (uint32_t)m >= (uint32_t)p.n_mat;
+                        lane_bad = bad_thickness(dj) || (uint32_t)mj >= (uint32_t)p.n_mat;
                         my_d = dj;
-                        my_m = min(max(m, 0), p.n_mat - 1);
+                        my_m = min(max(mj, 0), p.n_mat - 1);
                     }
                     bad = bad || __any(lane_bad);
                     const bool huge = !c_ok || __any(my_d >= (R)0x1p29);
@@ -644,10 +756,14 @@ __global__ void __launch_bounds__(Occupancy<R>::kWavesPerCU * kWave) ragged_kern
                 const bool valid = lam_ok && amb.ok && !bad;
                 const double nan = __builtin_nan("");
                 for (int q = 0; q < P; ++q) {
-                    const int64_t o = p.out_off[b] + (int64_t)q * npts + f;
+                    const int64_t o = si.out0 + (int64_t)q * npts + f;
                     if (p.R_out) p.R_out[o] = (R)(valid ? out[q].R : nan);
                     if (p.T_out) p.T_out[o] = (R)(valid ? out[q].T : nan);
                 }
+            }
+            if (g == 0) {
+                asm volatile("" : "+v"(claimed));  // keeps the read here, after the unit
+                next = first_lane(claimed);
             }
             // the next unit rewrites this wave's table slice
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -712,9 +828,8 @@ struct tmm_ragged_plan {
     std::vector<int64_t> layer_off, wl_off, th_off, out_off;
     int64_t n_units[3];     // per lanes-per-point choice (1, 2, 4)
     int64_t out_size;
-    int64_t*d_layer_off, *d_wl_off, *d_th_off, *d_out_off;
     int32_t* d_unit_stack[3];
-    int64_t* d_stack_first[3];
+    tmm::ragged::StackInfo* d_info[3];
     unsigned long long* d_counter;
     int n_cu;
     bool tuned[2];
@@ -733,10 +848,7 @@ template <typename R>
 tmm::ragged::Params<R> make_params(const tmm_ragged_plan* pl, const tmm_ragged_data* a) {
     tmm::ragged::Params<R> p;
     p.B = pl->B;
-    p.layer_off = pl->d_layer_off;
-    p.wl_off = pl->d_wl_off;
-    p.th_off = pl->d_th_off;
-    p.out_off = pl->d_out_off;
+    p.info = pl->d_info[0];
     p.d = static_cast<const R*>(a->d);
     p.mat = a->mat;
     p.ends = a->ends;
@@ -749,7 +861,6 @@ tmm::ragged::Params<R> make_params(const tmm_ragged_plan* pl, const tmm_ragged_d
     p.R_out = static_cast<R*>(a->R);
     p.T_out = static_cast<R*>(a->T);
     p.unit_stack = pl->d_unit_stack[0];
-    p.stack_first = pl->d_stack_first[0];
     p.n_units = pl->n_units[0];
     p.counter = pl->d_counter;
     p.grain = 1;
@@ -773,7 +884,7 @@ hipError_t launch(const tmm_ragged_plan* pl, tmm::ragged::Params<R> p, tmm::ragg
     const int li = tmm::ragged::lpp_index(sh.lpp);
     p.grain = sh.grain;
     p.unit_stack = pl->d_unit_stack[li];
-    p.stack_first = pl->d_stack_first[li];
+    p.info = pl->d_info[li];
     p.n_units = pl->n_units[li];
     const size_t lds = tmm::ragged::shape_lds<R>(p.n_mat, sh.waves);
     const int blocks = pl->n_cu * sh.blocks_per_cu;
@@ -927,11 +1038,11 @@ tmm_status tmm_ragged_plan_create(int32_t B, const int64_t* layer_off, const int
     // work lists per lanes-per-point choice: the tiles of consecutive points of
     // each stack, stacks in the sorted order; unit -> stack, stack -> first unit
     std::vector<int32_t> unit_stack[3];
-    std::vector<int64_t> stack_first[3];
+    std::vector<tmm::ragged::StackInfo> info[3];
     int64_t n_units[3];
     for (int li = 0; li < 3; ++li) {
         const int64_t ppw = tmm::kWave / tmm::ragged::kLppChoices[li];
-        stack_first[li].assign((size_t)B, 0);
+        info[li].assign((size_t)B, tmm::ragged::StackInfo{});
         int64_t n = 0;
         for (int b : order) n += ((wl_off[b + 1] - wl_off[b]) * (th_off[b + 1] - th_off[b]) + ppw - 1) / ppw;
         if (n > ((int64_t)1 << 31) - 1)
@@ -939,7 +1050,17 @@ tmm_status tmm_ragged_plan_create(int32_t B, const int64_t* layer_off, const int
         unit_stack[li].reserve((size_t)n);
         for (int b : order) {
             const int64_t tiles = ((wl_off[b + 1] - wl_off[b]) * (th_off[b + 1] - th_off[b]) + ppw - 1) / ppw;
-            stack_first[li][b] = (int64_t)unit_stack[li].size();
+            tmm::ragged::StackInfo& r = info[li][b];
+            r.l0 = layer_off[b];
+            r.w0 = wl_off[b];
+            r.t0 = th_off[b];
+            r.out0 = oo[b];
+            r.first_unit = (int64_t)unit_stack[li].size();
+            r.end_unit = r.first_unit + tiles;
+            r.L = (int32_t)(layer_off[b + 1] - layer_off[b]);
+            r.n_wl = (int32_t)(wl_off[b + 1] - wl_off[b]);
+            r.n_th = (int32_t)(th_off[b + 1] - th_off[b]);
+            r.pad = 0;
             unit_stack[li].insert(unit_stack[li].end(), (size_t)tiles, b);
         }
         n_units[li] = n;
@@ -955,13 +1076,12 @@ tmm_status tmm_ragged_plan_create(int32_t B, const int64_t* layer_off, const int
     for (int li = 0; li < 3; ++li) {
         pl->n_units[li] = n_units[li];
         pl->d_unit_stack[li] = nullptr;
-        pl->d_stack_first[li] = nullptr;
+        pl->d_info[li] = nullptr;
     }
     pl->out_size = oo[B];
     pl->tuned[0] = pl->tuned[1] = false;
     pl->graph = nullptr;
     pl->graph_exec = nullptr;
-    pl->d_layer_off = pl->d_wl_off = pl->d_th_off = pl->d_out_off = nullptr;
     pl->d_counter = nullptr;
     pl->mean_layers = B > 0 ? (int)(layer_off[B] / B) : 0;
     int dev = 0;
@@ -971,23 +1091,16 @@ tmm_status tmm_ragged_plan_create(int32_t B, const int64_t* layer_off, const int
         return fail(TMM_ERR_HIP, "tmm_ragged_plan_create: no device");
     }
     pl->n_cu = prop.multiProcessorCount;
-    const size_t nb = (size_t)(B + 1) * sizeof(int64_t);
-    bool okk = hipMalloc((void**)&pl->d_layer_off, nb) == hipSuccess && hipMalloc((void**)&pl->d_wl_off, nb) == hipSuccess &&
-               hipMalloc((void**)&pl->d_th_off, nb) == hipSuccess && hipMalloc((void**)&pl->d_out_off, nb) == hipSuccess &&
-               hipMalloc((void**)&pl->d_counter, sizeof(unsigned long long)) == hipSuccess;
-    okk = okk && hipMemcpy(pl->d_layer_off, layer_off, nb, hipMemcpyHostToDevice) == hipSuccess &&
-          hipMemcpy(pl->d_wl_off, wl_off, nb, hipMemcpyHostToDevice) == hipSuccess &&
-          hipMemcpy(pl->d_th_off, th_off, nb, hipMemcpyHostToDevice) == hipSuccess &&
-          hipMemcpy(pl->d_out_off, oo.data(), nb, hipMemcpyHostToDevice) == hipSuccess;
+    bool okk = hipMalloc((void**)&pl->d_counter, sizeof(unsigned long long)) == hipSuccess;
     for (int li = 0; okk && li < 3; ++li) {
         const size_t nu = std::max<size_t>(1, unit_stack[li].size()) * sizeof(int32_t);
-        const size_t ns = std::max<size_t>(1, (size_t)B) * sizeof(int64_t);
+        const size_t ns = std::max<size_t>(1, (size_t)B) * sizeof(tmm::ragged::StackInfo);
         okk = hipMalloc((void**)&pl->d_unit_stack[li], nu) == hipSuccess &&
-              hipMalloc((void**)&pl->d_stack_first[li], ns) == hipSuccess &&
+              hipMalloc((void**)&pl->d_info[li], ns) == hipSuccess &&
               (unit_stack[li].empty() || hipMemcpy(pl->d_unit_stack[li], unit_stack[li].data(),
                                                    unit_stack[li].size() * sizeof(int32_t),
                                                    hipMemcpyHostToDevice) == hipSuccess) &&
-              (B == 0 || hipMemcpy(pl->d_stack_first[li], stack_first[li].data(), (size_t)B * sizeof(int64_t),
+              (B == 0 || hipMemcpy(pl->d_info[li], info[li].data(), (size_t)B * sizeof(tmm::ragged::StackInfo),
                                    hipMemcpyHostToDevice) == hipSuccess);
     }
     if (!okk) {
@@ -1003,9 +1116,8 @@ tmm_status tmm_ragged_plan_destroy(tmm_ragged_plan* pl) {
     (void)hipDeviceSynchronize();
     if (pl->graph_exec) (void)hipGraphExecDestroy(pl->graph_exec);
     if (pl->graph) (void)hipGraphDestroy(pl->graph);
-    void* ptrs[] = {pl->d_layer_off,      pl->d_wl_off,         pl->d_th_off,         pl->d_out_off,
-                    pl->d_counter,        pl->d_unit_stack[0],  pl->d_unit_stack[1],  pl->d_unit_stack[2],
-                    pl->d_stack_first[0], pl->d_stack_first[1], pl->d_stack_first[2]};
+    void* ptrs[] = {pl->d_counter,   pl->d_unit_stack[0], pl->d_unit_stack[1], pl->d_unit_stack[2],
+                    pl->d_info[0],  pl->d_info[1],       pl->d_info[2]};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     delete pl;
