@@ -191,6 +191,29 @@ def time_ragged(dtype="f64", steps=10):
                                        / PEAK_TFLOPS[dtype], 4)}
 
 
+def time_ragged_layers(dtype="f64", steps=5, layer_counts=(2, 50, 100)):
+    """The ragged batch's shape (8192 stacks, 256-2048 wl, 1-64 angles, s+p) with
+    every stack at one layer count, in the launch shape the full batch tunes to
+    (one workgroup per CU of 12 (FP64) or 16 (FP32) waves, 4 units per claim): the
+    time per unit of 64 points against the time per layer step."""
+    import torch
+    from paper_2111_13667_amd import ragged, workloads
+    out = {"workload": f"ragged_batch shape, fixed layer counts {list(layer_counts)}, s+p, {dtype}",
+           "shape": {"workgroups_per_cu": 1, "grain": 4, "waves_per_workgroup": 12 if dtype == "f64" else 16}}
+    for L in layer_counts:
+        rw = workloads.ragged_batch(L_range=(L, L))
+        plan = ragged.RaggedPlan(rw.layer_off, rw.wl_off, rw.th_off)
+        dev = ragged.to_device(rw, dtype)
+        R = torch.empty(plan.output_size, dtype=dev[3].dtype, device="cuda")
+        T = torch.empty_like(R)
+        plan.set_shape(dtype, **out["shape"])
+        rms, _ = launch_times(lambda: plan.run(*dev, R=R, T=T), steps, 1)
+        npts = np.diff(rw.wl_off) * np.diff(rw.th_off)
+        out[f"L={L}"] = {"ms": round(float(np.median(rms)), 3), "units": int(((npts + 63) // 64).sum())}
+        plan.close()
+    return out
+
+
 # The paper's own timings (section "Core functionality speedup and dataset
 # generation"): CPU only, hardware model not stated, polarisations not stated.
 # Points counted as stack x wavelength x angle (one polarisation).  Other
@@ -375,8 +398,8 @@ def main():
     ap.add_argument("--cpu-stacks", type=int, default=128,
                     help="stacks of the CPU oracle sample (median of 3 runs after a warm-up)")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"))
-    ap.add_argument("--only", choices=["adjoint", "ragged_f64", "ragged_f32", "surrogate", "surrogate_dataset",
-                                       "materials"],
+    ap.add_argument("--only", choices=["adjoint", "ragged_f64", "ragged_f32", "ragged_layers_f64", "ragged_layers_f32",
+                                       "surrogate", "surrogate_dataset", "materials"],
                     default=None, help="run only this extra measurement and print its record (for profiling)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="first run a plain N-MiB elementwise copy kernel (profiler calibration)")
@@ -401,6 +424,8 @@ def main():
             rec = time_surrogate()
         elif args.only == "surrogate_dataset":
             rec = time_surrogate_dataset()
+        elif args.only.startswith("ragged_layers_"):
+            rec = time_ragged_layers(args.only.split("_")[2], max(1, args.steps))
         elif args.only == "materials":
             rec = {"7": material_variant(7, max(1, args.steps)), "12": material_variant(12, max(1, args.steps))}
         else:
