@@ -210,3 +210,30 @@ def test_metal_rows_and_grazing_angles(dtype):
     rw = dataclasses.replace(rw, nk=nk, d=d, theta=theta, sin_t=s, cos_t=c)
     plan, _, R, T = run(rw, dtype)
     check_stacks(rw, plan, R, T, range(rw.B), dtype)
+
+
+@pytest.mark.parametrize("grain", [1, 3, 16])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_eight_rows_and_claim_batches_across_stacks(dtype, grain):
+    # The most rows a unit's table holds (8: two more rows, one of them
+    # absorbing), stacks of one to four units so that a claimed batch of units
+    # spans several stacks and the wave's kept stack record changes within the
+    # batch, empty stacks, and layer counts to 90 (top 64-layer chunks that
+    # start above layer 1); every stack against the oracle.
+    import dataclasses
+    from paper_2111_13667_amd import ragged
+    rw = workloads.ragged_batch(seed=73, B=45, L_range=(0, 90), wl_range=(1, 120), th_range=(1, 3))
+    rng = np.random.default_rng(73)
+    extra = np.stack([np.full(rw.wl.size, 1.8 + 0.0j), np.full(rw.wl.size, 2.1 + 0.02j)])
+    mat = rw.mat.copy()
+    pick = rng.random(mat.size) < 0.3
+    mat[pick] = rng.integers(6, 8, int(pick.sum())).astype(np.int32)
+    rw = dataclasses.replace(rw, nk=np.concatenate([rw.nk, extra]), mat=mat)
+    plan = ragged.RaggedPlan(rw.layer_off, rw.wl_off, rw.th_off)
+    plan.set_shape(dtype, workgroups_per_cu=1, grain=grain, waves_per_workgroup=8)
+    dev = ragged.to_device(rw, dtype)
+    R = torch.empty(plan.output_size, dtype=dev[3].dtype, device="cuda")
+    T = torch.empty_like(R)
+    plan.run(*dev, R=R, T=T)
+    torch.cuda.synchronize()
+    check_stacks(rw, plan, R, T, range(rw.B), dtype)
