@@ -606,7 +606,7 @@ __global__ void __launch_bounds__(kGradBlock) __attribute__((amdgpu_waves_per_eu
 }
 
 // ---------------------------------------------------------------------------
-// Ratio form (material ids, small tables, L + 2 <= 64).  The forward steps are
+// Ratio form (material ids, small tables, L + 2 <= 128).  The forward steps are
 // those of the forward kernel's pair path: step j divided by q_j (s) or eta_j
 // (p), with rho_s = q_{j+1}/q_j and rho_p = eta_{j+1}/eta_j tabulated per
 // ordered material pair, and the normalisation products gone from T.
@@ -632,19 +632,72 @@ __host__ __device__ constexpr size_t grad_pair_lds_bytes(int n_mat, int seg) {
            (size_t)n_mat * kPairFields * kWave * sizeof(double2) + (size_t)n_mat * n_mat * kGradPairBlockBytes;
 }
 
-// Layer data of the stack, one value per lane (L + 2 <= 64), broadcast by readlane.
+// Per-layer values of a stack held N to a lane (lane l of register r: element
+// 64 r + l), broadcast at a wave-uniform index x: one register for stacks with
+// L + 2 <= 64, two for L + 2 <= 128.
+template <int N>
+__device__ __forceinline__ int lane_bcast(const int (&v)[N], int x) {
+    if (N == 1 || x < kWave) return __builtin_amdgcn_readlane(v[0], x);
+    return __builtin_amdgcn_readlane(v[N - 1], x - kWave);
+}
+template <int N>
+__device__ __forceinline__ double lane_bcast(const double (&v)[N], int x) {
+    const int r = (N == 1 || x < kWave) ? 0 : N - 1;
+    const int y = r == 0 ? x : x - kWave;
+    if (N == 1 || r == 0)
+        return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v[0]), y),
+                                __builtin_amdgcn_readlane(__double2loint(v[0]), y));
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v[N - 1]), y),
+                            __builtin_amdgcn_readlane(__double2loint(v[N - 1]), y));
+}
+
+// A stack's layer data for the ratio-form kernels: lane l of register r holds
+// layer 64 r + l + 1 (its thickness, and the table rows of media 64 r + l + 1
+// and + 2, from which the kernel forms the layer's code) and the row of medium
+// 64 r + l; rows clamped into the table.
+template <int N>
+__device__ __forceinline__ void load_layers(const GradParams& p, const double* drow, ciptr mrow, int lane,
+                                            double (&d)[N], int (&row)[N], int (&cur)[N], int (&nxt)[N]) {
+    const int L2 = p.L + 2;
+    auto clamp_row = [&](int m) { return m < 0 ? 0 : (m >= p.n_mat ? p.n_mat - 1 : m); };
+    if (N == 1) {
+        // rows of media l and l + 1 per lane; the layer's two from the lane above
+        d[0] = lane < p.L ? drow[lane] : 0.0;
+        row[0] = clamp_row(lane < L2 ? mrow[lane] : 0);
+        const int m_nx = clamp_row(lane + 1 < L2 ? mrow[lane + 1] : 0);
+        cur[0] = __shfl_down(row[0], 1, kWave);
+        nxt[0] = __shfl_down(m_nx, 1, kWave);
+        return;
+    }
+    for (int r = 0; r < N; ++r) {
+        const int l = lane + r * kWave;
+        d[r] = l < p.L ? drow[l] : 0.0;
+        row[r] = clamp_row(l < L2 ? mrow[l] : 0);
+        cur[r] = clamp_row(l + 1 < L2 ? mrow[l + 1] : 0);
+        nxt[r] = clamp_row(l + 2 < L2 ? mrow[l + 2] : 0);
+    }
+}
+
+// Whether a layer of the stack is thicker than the fast phase reduction allows
+// at the largest phase coefficient cm (wave-uniform).
+template <int N>
+__device__ __forceinline__ bool any_far(const double (&d)[N], int L, int lane, double cm) {
+    bool far = false;
+    for (int r = 0; r < N; ++r) far = far || (lane + r * kWave < L && !(d[r] <= (0.5 * kScFastRange) / cm));
+    return __any(far);
+}
+
+// Layer data of the stack, N per lane (L + 2 <= 64 N), broadcast by readlane.
+template <int N>
 struct PairLayers {
     const double2* mtab;            // material table + lane: mtab[(row * kPairFields + f) * kWave]
     const unsigned char* pair_lane; // pair blocks + lane * 16
-    double my_d;   // lane l: thickness of layer l + 1
-    int my_code;   // lane l: pair block offset of layer l + 1 | lossy << 31
-    int my_row;    // lane l: material row of medium l
-    __device__ __forceinline__ double d(int j) const {
-        return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(my_d), j - 1),
-                                __builtin_amdgcn_readlane(__double2loint(my_d), j - 1));
-    }
-    __device__ __forceinline__ int code(int j) const { return __builtin_amdgcn_readlane(my_code, j - 1); }
-    __device__ __forceinline__ int row(int j) const { return __builtin_amdgcn_readlane(my_row, j); }
+    double my_d[N];   // lane l, register r: thickness of layer 64 r + l + 1
+    int my_code[N];   // pair block offset of that layer | lossy << 31
+    int my_row[N];    // material row of medium 64 r + l
+    __device__ __forceinline__ double d(int j) const { return lane_bcast(my_d, j - 1); }
+    __device__ __forceinline__ int code(int j) const { return lane_bcast(my_code, j - 1); }
+    __device__ __forceinline__ int row(int j) const { return lane_bcast(my_row, j); }
     __device__ __forceinline__ cx<double> field(int m, int f) const {
         const double2 v = mtab[(m * kPairFields + f) * kWave];
         return {v.x, v.y};
@@ -693,8 +746,8 @@ __device__ __forceinline__ cx<double> pair_phase(double dj, double cre, double c
     return E;
 }
 
-template <int POL, int SEG>
-__device__ void grad_stack_pair(const GradParams& p, const PairLayers& src, const Ambient& amb, int b, int k, int i,
+template <int POL, int SEG, class LY>
+__device__ void grad_stack_pair(const GradParams& p, const LY& src, const Ambient& amb, int b, int k, int i,
                                 int lane, bool active, bool valid, double* ws, double* red, double* part,
                                 const TabPhase<double>& phase) {
     const int L = p.L;
@@ -960,7 +1013,7 @@ __device__ void build_pair_table(const GradParams& p, double2* mtab, unsigned ch
     }
 }
 
-template <int POL, int SEG>
+template <int POL, int SEG, int N>
 __global__ void __launch_bounds__(kGradPairBlock) __attribute__((amdgpu_waves_per_eu(2)))
 grad_pair_kernel(GradParams p) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -1039,22 +1092,17 @@ grad_pair_kernel(GradParams p) {
                 load_n(p.nk, p.dispersive, p.n_wl, a_row, i, n0r, n0i);
                 const Ambient amb = make_ambient(n0r, n0i, st, ct);
                 const bool ok = lam_ok && amb.ok && !bad;
-                // layer data one per lane; a layer thicker than 2^49 / (256 max cre) would
+                // layer data N per lane; a layer thicker than 2^49 / (256 max cre) would
                 // leave the fast phase reduction's range
-                PairLayers src;
+                PairLayers<N> src;
                 src.mtab = mtab + lane;
                 src.pair_lane = pairs + lane * 16;
-                src.my_d = lane < p.L ? drow[lane] : 0.0;
-                int m_row = lane < L2 ? mrow[lane] : 0;
-                m_row = m_row < 0 ? 0 : (m_row >= p.n_mat ? p.n_mat - 1 : m_row);
-                src.my_row = m_row;
-                int m_nx = lane + 1 < L2 ? mrow[lane + 1] : 0;
-                m_nx = m_nx < 0 ? 0 : (m_nx >= p.n_mat ? p.n_mat - 1 : m_nx);
-                // lane l holds layer l + 1: its row is medium l + 1, the next one l + 2
-                const int m_cur = __shfl_down(m_row, 1, kWave);
-                const int m_nxt = __shfl_down(m_nx, 1, kWave);
-                src.my_code = (m_cur * p.n_mat + m_nxt) * kGradPairBlockBytes | (int)(((mask >> m_cur) & 1u) << 31);
-                const bool far = __any(lane < p.L && !(src.my_d <= (0.5 * kScFastRange) / cm));
+                int m_cur[N], m_nxt[N];
+                load_layers(p, drow, mrow, lane, src.my_d, src.my_row, m_cur, m_nxt);
+                for (int r = 0; r < N; ++r)
+                    src.my_code[r] =
+                        (m_cur[r] * p.n_mat + m_nxt[r]) * kGradPairBlockBytes | (int)(((mask >> m_cur[r]) & 1u) << 31);
+                const bool far = any_far(src.my_d, p.L, lane, cm);
                 if (any_bad == 0 && !far) {
                     grad_stack_pair<POL, SEG>(p, src, amb, b, tk_k, i, lane, active, ok, ws, red, part, phase);
                 } else {
@@ -1107,18 +1155,16 @@ constexpr int kInvRenormSegs = 2;  // segments between rescalings: growth <= 2^9
 // conflicts in the segment reduction).
 constexpr int kInvRedStride = kWave + 8;
 
+template <int N>
 struct InvLayers {
     const double2* mt;  // material rows + lane: mt[(m * kInvRows + f) * kWave]
     const double2* pr;  // pair ratios + lane: pr[pair * kWave]
-    double my_d;        // lane l: thickness of layer l + 1
-    int my_code;        // lane l: layer l + 1: pair | reversed pair << 5 | material << 10
-    int my_row;         // lane l: material row of medium l
-    __device__ __forceinline__ double d(int j) const {
-        return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(my_d), j - 1),
-                                __builtin_amdgcn_readlane(__double2loint(my_d), j - 1));
-    }
-    __device__ __forceinline__ int code(int j) const { return __builtin_amdgcn_readlane(my_code, j - 1); }
-    __device__ __forceinline__ int row(int j) const { return __builtin_amdgcn_readlane(my_row, j); }
+    double my_d[N];     // lane l, register r: thickness of layer 64 r + l + 1
+    int my_code[N];     // that layer: pair | reversed pair << 5 | material << 10
+    int my_row[N];      // material row of medium 64 r + l
+    __device__ __forceinline__ double d(int j) const { return lane_bcast(my_d, j - 1); }
+    __device__ __forceinline__ int code(int j) const { return lane_bcast(my_code, j - 1); }
+    __device__ __forceinline__ int row(int j) const { return lane_bcast(my_row, j); }
     __device__ __forceinline__ double2 ratio(int pair) const { return pr[pair * kWave]; }
     __device__ __forceinline__ double2 mat(int m, int f) const { return mt[(m * kInvRows + f) * kWave]; }
 };
@@ -1174,8 +1220,8 @@ __device__ void build_inv_table(const GradParams& p, double2* mt, double2* pr, i
     }
 }
 
-template <int POL, int SEG>
-__device__ void grad_stack_inv(const GradParams& p, const InvLayers& src, const Ambient& amb, int b, int k, int i,
+template <int POL, int SEG, class LY>
+__device__ void grad_stack_inv(const GradParams& p, const LY& src, const Ambient& amb, int b, int k, int i,
                                int lane, bool active, bool valid, double* red, double* part,
                                const TabPhase<double>& phase) {
     const int L = p.L;
@@ -1372,7 +1418,7 @@ __device__ void grad_stack_inv(const GradParams& p, const InvLayers& src, const 
 // the block's real tables built per (column, ambient row) as in grad_pair_kernel.
 // Stacks whose column is not lossless, whose ratios leave their bound or whose
 // phases leave the fast range are marked in p.redo and left to grad_pair_kernel.
-template <int POL, int SEG, int WAVES>
+template <int POL, int SEG, int WAVES, int N>
 __global__ void __launch_bounds__(WAVES * kWave) grad_inv_kernel(GradParams p) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int s_rows[WAVES];
@@ -1443,19 +1489,15 @@ __global__ void __launch_bounds__(WAVES * kWave) grad_inv_kernel(GradParams p) {
                 load_n(p.nk, p.dispersive, p.n_wl, a_row, i, n0r, n0i);
                 const Ambient amb = make_ambient(n0r, n0i, st, ct);
                 const bool ok = lam_ok && amb.ok && !bad;
-                InvLayers src;
+                InvLayers<N> src;
                 src.mt = mt + lane;
                 src.pr = pr + lane;
-                src.my_d = lane < p.L ? drow[lane] : 0.0;
-                int m_row = lane < L2 ? mrow[lane] : 0;
-                m_row = m_row < 0 ? 0 : (m_row >= p.n_mat ? p.n_mat - 1 : m_row);
-                src.my_row = m_row;
-                int m_nx = lane + 1 < L2 ? mrow[lane + 1] : 0;
-                m_nx = m_nx < 0 ? 0 : (m_nx >= p.n_mat ? p.n_mat - 1 : m_nx);
-                const int m_cur = __shfl_down(m_row, 1, kWave);
-                const int m_nxt = __shfl_down(m_nx, 1, kWave);
-                src.my_code = (m_cur * p.n_mat + m_nxt) | (m_nxt * p.n_mat + m_cur) << 5 | m_cur << 10;
-                const bool far = __any(lane < p.L && !(src.my_d <= (0.5 * kScFastRange) / cm));
+                int m_cur[N], m_nxt[N];
+                load_layers(p, drow, mrow, lane, src.my_d, src.my_row, m_cur, m_nxt);
+                for (int r = 0; r < N; ++r)
+                    src.my_code[r] =
+                        (m_cur[r] * p.n_mat + m_nxt[r]) | (m_nxt[r] * p.n_mat + m_cur[r]) << 5 | m_cur[r] << 10;
+                const bool far = any_far(src.my_d, p.L, lane, cm);
                 const bool mine = any_bad == 0 && any_lossy == 0 && !far;
                 if (mine) grad_stack_inv<POL, SEG>(p, src, amb, b, tk_k, i, lane, active, ok, red, part, phase);
                 if (lane == 0) p.redo[(size_t)col * nbs + (b - p.b_begin)] = mine ? 0 : 1;
@@ -1558,7 +1600,7 @@ static int occupancy_blocks(size_t lds) {
     return n;
 }
 
-template <int POL, int SEG>
+template <int POL, int SEG, int N>
 static int occupancy_pair_blocks(size_t lds) {
     static std::mutex mu;
     static std::map<size_t, int> cache;
@@ -1566,18 +1608,18 @@ static int occupancy_pair_blocks(size_t lds) {
     auto it = cache.find(lds);
     if (it != cache.end()) return it->second;
     // dynamic LDS above 64 KiB: raise the kernel's limit first
-    (void)hipFuncSetAttribute((const void*)&grad_pair_kernel<POL, SEG>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    (void)hipFuncSetAttribute((const void*)&grad_pair_kernel<POL, SEG, N>, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)lds);
     (void)hipGetLastError();
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, grad_pair_kernel<POL, SEG>, kGradPairBlock, lds) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, grad_pair_kernel<POL, SEG, N>, kGradPairBlock, lds) != hipSuccess ||
         n < 1)
         n = 1;
     cache[lds] = n;
     return n;
 }
 
-template <int POL, int SEG>
+template <int POL, int SEG, int N>
 static hipError_t launch_grad_pair(GradParams p, int n_cu, size_t lds, hipStream_t s) {
     p.n_tasks = p.n_tasks_pair;
     // The ratio-form stacks walk segments of SEG layers; stacks that fall back to
@@ -1585,13 +1627,13 @@ static hipError_t launch_grad_pair(GradParams p, int n_cu, size_t lds, hipStream
     // kSeg, and p.n_seg + 1 stays the per-wave checkpoint stride (SEG >= kSeg).
     static_assert(SEG >= kSeg, "checkpoint slots are sized for segments of kSeg layers");
     p.n_seg_pair = (int)ceil_div(p.L, SEG);
-    int64_t grid = (int64_t)n_cu * occupancy_pair_blocks<POL, SEG>(lds);
+    int64_t grid = (int64_t)n_cu * occupancy_pair_blocks<POL, SEG, N>(lds);
     if (grid > kGradPairMaxBlocks) grid = kGradPairMaxBlocks;
     if (grid > p.slots / kGradPairWaves) grid = p.slots / kGradPairWaves;
     if (grid > p.n_tasks) grid = p.n_tasks;
     p.per_block = ceil_div(p.n_tasks, grid);
     grid = ceil_div(p.n_tasks, p.per_block);
-    hipLaunchKernelGGL((grad_pair_kernel<POL, SEG>), dim3((unsigned)grid), dim3(kGradPairBlock), lds, s, p);
+    hipLaunchKernelGGL((grad_pair_kernel<POL, SEG, N>), dim3((unsigned)grid), dim3(kGradPairBlock), lds, s, p);
     return hipGetLastError();
 }
 
@@ -1607,7 +1649,7 @@ static hipError_t launch_grad(GradParams p, int n_cu, size_t lds, hipStream_t s)
     return hipGetLastError();
 }
 
-template <int POL, int SEG, int WAVES>
+template <int POL, int SEG, int WAVES, int N>
 static hipError_t launch_grad_inv_t(GradParams p, int n_cu, hipStream_t s) {
     const size_t lds = grad_inv_lds_bytes(p.n_mat, SEG, WAVES);
     static std::mutex mu;
@@ -1619,10 +1661,10 @@ static hipError_t launch_grad_inv_t(GradParams p, int n_cu, hipStream_t s) {
         if (it != cache.end()) {
             occ = it->second;
         } else {
-            (void)hipFuncSetAttribute((const void*)&grad_inv_kernel<POL, SEG, WAVES>,
+            (void)hipFuncSetAttribute((const void*)&grad_inv_kernel<POL, SEG, WAVES, N>,
                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
             (void)hipGetLastError();
-            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, grad_inv_kernel<POL, SEG, WAVES>, WAVES * kWave,
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, grad_inv_kernel<POL, SEG, WAVES, N>, WAVES * kWave,
                                                              lds) != hipSuccess ||
                 occ < 1)
                 occ = 1;
@@ -1636,16 +1678,29 @@ static hipError_t launch_grad_inv_t(GradParams p, int n_cu, hipStream_t s) {
     if (grid > n_tasks) grid = n_tasks;
     p.per_block = ceil_div(n_tasks, grid);
     grid = ceil_div(n_tasks, p.per_block);
-    hipLaunchKernelGGL((grad_inv_kernel<POL, SEG, WAVES>), dim3((unsigned)grid), dim3(WAVES * kWave), lds, s, p);
+    hipLaunchKernelGGL((grad_inv_kernel<POL, SEG, WAVES, N>), dim3((unsigned)grid), dim3(WAVES * kWave), lds, s, p);
     return hipGetLastError();
 }
 
-// Sixteen-wave blocks while the table leaves room (at most four rows), else eight.
+// Sixteen-wave blocks (four waves per SIMD at 128 VGPRs); stacks of 63-126
+// layers (two registers of layer data) in twelve-wave blocks.
 static hipError_t launch_grad_inv(const GradParams& p, uint32_t pol, int n_cu, hipStream_t s) {
     static_assert(grad_inv_lds_bytes(kGradPairMaxMat, 3, 16) <= 160 * 1024, "inverse-walk tables exceed LDS");
-    if (pol == 1u) return launch_grad_inv_t<1, 3, 16>(p, n_cu, s);
-    if (pol == 2u) return launch_grad_inv_t<2, 3, 16>(p, n_cu, s);
-    return launch_grad_inv_t<3, 3, 16>(p, n_cu, s);
+    if (p.L + 2 > kWave) {
+        if (pol == 1u) return launch_grad_inv_t<1, 3, 12, 2>(p, n_cu, s);
+        if (pol == 2u) return launch_grad_inv_t<2, 3, 12, 2>(p, n_cu, s);
+        return launch_grad_inv_t<3, 3, 12, 2>(p, n_cu, s);
+    }
+    if (pol == 1u) return launch_grad_inv_t<1, 3, 16, 1>(p, n_cu, s);
+    if (pol == 2u) return launch_grad_inv_t<2, 3, 16, 1>(p, n_cu, s);
+    return launch_grad_inv_t<3, 3, 16, 1>(p, n_cu, s);
+}
+
+template <int SEG, int N>
+static hipError_t launch_grad_pair_pol(const GradParams& p, uint32_t pol, int n_cu, size_t lds, hipStream_t s) {
+    if (pol == 1u) return launch_grad_pair<1, SEG, N>(p, n_cu, lds, s);
+    if (pol == 2u) return launch_grad_pair<2, SEG, N>(p, n_cu, lds, s);
+    return launch_grad_pair<3, SEG, N>(p, n_cu, lds, s);
 }
 
 // Checks and the cases without gradient kernels, shared by the entry points.
@@ -1714,8 +1769,10 @@ static tmm_status grad_launch(const tmm_rt_args* a, const void* dl_dR, const voi
     p.n_seg_pair = g.n_seg;
     p.slots = g.slots;
     const bool table = a->mat != nullptr && a->n_mat <= kGradMaxTableMat;
-    // ratio form: material ids, a small table, and the stack's layer data one per lane
-    const bool pair = a->mat != nullptr && a->n_mat <= kGradPairMaxMat && a->L + 2 <= kWave;
+    // ratio form: material ids, a small table, and the stack's layer data one
+    // (L + 2 <= 64) or two (<= 128) per lane
+    const bool pair = a->mat != nullptr && a->n_mat <= kGradPairMaxMat && a->L + 2 <= 2 * kWave;
+    const bool two = a->L + 2 > kWave;
     // segments of five layers where their larger share buffer still fits the LDS
     // beside the table (at most four rows; 15 shares fill 60 reduction lanes), else of three
     const bool seg5 = pair && a->n_mat <= kGradPairLongSegMaxMat;
@@ -1737,13 +1794,11 @@ static tmm_status grad_launch(const tmm_rt_args* a, const void* dl_dR, const voi
             if (e != hipSuccess) return check_launch(who);
         }
         if (pair && seg5)
-            e = a->pol_mask == 1u   ? launch_grad_pair<1, 5>(p, n_cu, lds, s)
-                : a->pol_mask == 2u ? launch_grad_pair<2, 5>(p, n_cu, lds, s)
-                                    : launch_grad_pair<3, 5>(p, n_cu, lds, s);
+            e = two ? launch_grad_pair_pol<5, 2>(p, a->pol_mask, n_cu, lds, s)
+                    : launch_grad_pair_pol<5, 1>(p, a->pol_mask, n_cu, lds, s);
         else if (pair)
-            e = a->pol_mask == 1u   ? launch_grad_pair<1, kSeg>(p, n_cu, lds, s)
-                : a->pol_mask == 2u ? launch_grad_pair<2, kSeg>(p, n_cu, lds, s)
-                                    : launch_grad_pair<3, kSeg>(p, n_cu, lds, s);
+            e = two ? launch_grad_pair_pol<kSeg, 2>(p, a->pol_mask, n_cu, lds, s)
+                    : launch_grad_pair_pol<kSeg, 1>(p, a->pol_mask, n_cu, lds, s);
         else if (a->pol_mask == 1u)
             e = table ? launch_grad<1, true>(p, n_cu, lds, s) : launch_grad<1, false>(p, n_cu, lds, s);
         else if (a->pol_mask == 2u)

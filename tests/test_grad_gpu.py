@@ -224,7 +224,7 @@ def test_table_path_with_mixed_ambient_rows():
     assert (rel_err(gn, on) <= REL).all(), rel_err(gn, on)
 
 
-# --- ratio form (material ids, at most 5 table rows, L + 2 <= 64) -------------
+# --- ratio form (material ids, at most 5 table rows, L + 2 <= 128) ------------
 
 def _material_workload(seed, B, L, n_wl, n_theta, n_inner, *, theta_max_deg=80.0, n_amb=1.0, k_max=0.02):
     from dataclasses import replace
@@ -292,7 +292,17 @@ def test_ratio_form_mixed_ambients_and_near_critical_fallback():
     _check_against_oracle(w, rng.normal(size=shape), rng.normal(size=shape))
 
 
-@pytest.mark.parametrize("L", [9, 62])
+@pytest.mark.parametrize("n_inner,L", [(2, 63), (3, 100), (1, 126)])
+def test_ratio_form_long_stacks(n_inner, L):
+    # 65 <= L + 2 <= 128: the layer data two per lane (layers 65-126 in the second
+    # register), lossy and lossless materials, both ratio-form kernels
+    w = _material_workload(140 + L, B=4, L=L, n_wl=70, n_theta=2, n_inner=n_inner)
+    rng = np.random.default_rng(141)
+    shape = (w.B, 2, w.theta.size, w.wl.size)
+    _check_against_oracle(w, rng.normal(size=shape), rng.normal(size=shape))
+
+
+@pytest.mark.parametrize("L", [9, 62, 100])
 def test_inverse_walk_columns_next_to_redone_columns(L):
     # One material starts to absorb inside the wavelength grid: the 64-wavelength
     # column below the edge is lossless everywhere and takes the inverse walk, the
@@ -310,7 +320,7 @@ def test_inverse_walk_columns_next_to_redone_columns(L):
     _check_against_oracle(w, rng.normal(size=shape), rng.normal(size=shape))
 
 
-@pytest.mark.parametrize("L", [7, 13, 60])
+@pytest.mark.parametrize("L", [7, 13, 60, 90])
 def test_ratio_form_five_layer_kernel_fallback(L):
     # Four table rows (air, one dielectric, ambient 1.5, substrate 1.52): the
     # kernel with five-layer segments.  Two angles send their blocks to the
