@@ -124,13 +124,14 @@ def _event_time(fn, steps, warmup, stream=None):
 GRAD_FLOPS_PER_POINT_STEP = 129.0
 
 
-def time_grad(steps=10, L=60):
+def time_grad(steps=10, L=60, n_pool=2):
     """Adjoint gradients on the 1024 x 60-layer batch (512 wl x 31 angles, s+p):
     dl/dd and dl/dn of an MSE against a long-pass target, float64.  L: the same
-    batch with L layers (120 for the long-stack record)."""
+    batch with L layers (120 for the long-stack record); n_pool: layers cycling
+    through n_pool materials (5 for the seven-row record)."""
     import torch
     from paper_2111_13667_amd import tmm, workloads
-    w = workloads.adjoint_batch(L=L)
+    w = workloads.adjoint_batch(L=L, n_pool=n_pool)
     (d, nk, wl, s, c), mat, _, _ = device_inputs(w, "f64")
     shape = (w.B, 2, w.theta.size, w.wl.size)
     R = torch.empty(shape, dtype=torch.float64, device="cuda")
@@ -147,7 +148,8 @@ def time_grad(steps=10, L=60):
     units = w.n_points * (w.L + 1)
     flops = units * GRAD_FLOPS_PER_POINT_STEP
     achieved = flops / (float(np.mean(gms)) * 1e-3) / 1e12
-    return {"workload": f"adjoint_batch: 1024 stacks x {L} layers, 512 wl x 31 angles, s+p, float64",
+    return {"workload": f"adjoint_batch: 1024 stacks x {L} layers, {n_pool + 2} table rows, 512 wl x 31 angles, s+p, "
+                        "float64",
             "points": w.n_points, "grad_ms": round(g_med, 3), "forward_ms": round(f_med, 3),
             "grad_timing": summary(gms),
             "grad_points_per_s": round(w.n_points / (g_med * 1e-3), 1), "grad_over_forward": round(g_med / f_med, 2),
@@ -399,7 +401,7 @@ def main():
     ap.add_argument("--cpu-stacks", type=int, default=128,
                     help="stacks of the CPU oracle sample (median of 3 runs after a warm-up)")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"))
-    ap.add_argument("--only", choices=["adjoint", "adjoint_long", "ragged_f64", "ragged_f32", "ragged_layers_f64", "ragged_layers_f32",
+    ap.add_argument("--only", choices=["adjoint", "adjoint_long", "adjoint_rows", "ragged_f64", "ragged_f32", "ragged_layers_f64", "ragged_layers_f32",
                                        "surrogate", "surrogate_dataset", "materials"],
                     default=None, help="run only this extra measurement and print its record (for profiling)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -423,6 +425,8 @@ def main():
             rec = time_grad(max(1, args.steps))
         elif args.only == "adjoint_long":
             rec = time_grad(max(1, args.steps), L=120)
+        elif args.only == "adjoint_rows":
+            rec = time_grad(max(1, args.steps), n_pool=5)
         elif args.only == "surrogate":
             rec = time_surrogate()
         elif args.only == "surrogate_dataset":
@@ -502,6 +506,7 @@ def main():
             "100 wl 400-700 nm x 20 angles 0-90 deg (points counted with both polarisations)", paper_s=0.168)
         extra["adjoint_f64"] = time_grad()
         extra["adjoint_f64_120_layers"] = time_grad(L=120)
+        extra["adjoint_f64_7_rows"] = time_grad(n_pool=5)
         extra["ragged_f64"] = time_ragged("f64")
         extra["ragged_f32"] = time_ragged("f32")
         extra["material_pool_7"] = material_variant(7)

@@ -539,10 +539,13 @@ __global__ void __launch_bounds__(kGradBlock) __attribute__((amdgpu_waves_per_eu
         const double lam = p.wl[i];
         const bool lam_ok = lam > 0.0 && lam < __builtin_inf();
         const double st = p.sin_t[tk.k], ct = p.cos_t[tk.k];
-        const bool has = tk.b < p.b_end;
-        const int b = has ? tk.b : p.b_end - 1;
-        const ciptr mrow = p.mat ? (ciptr)(p.mat + (int64_t)b * L2) : nullptr;
         const int64_t col = (int64_t)tk.k * p.n_tiles + tk.tile;
+        // after the inverse-walk kernel: only the stacks it left
+        const bool has = tk.b < p.b_end &&
+                         (!p.redo || p.redo[(size_t)col * nbs + (tk.b - p.b_begin)] != 0);
+        if (p.redo && __syncthreads_or(has ? 1 : 0) == 0) continue;
+        const int b = tk.b < p.b_end ? tk.b : p.b_end - 1;
+        const ciptr mrow = p.mat ? (ciptr)(p.mat + (int64_t)b * L2) : nullptr;
         double* part = p.partial + ((size_t)col * nbs + (b - p.b_begin)) * (size_t)p.L * 3;
         const bool bad = stack_bad(p, p.d + (int64_t)b * p.L, mrow, lane);
         if (TABLE) {
@@ -1148,6 +1151,9 @@ grad_pair_kernel(GradParams p) {
 // with cre = 4 kScSteps q / lambda (the phase of layer thickness d is d cre in
 // units of 1/kScSteps half-turn); the ordered pair (m, m') holds {rho_s, rho_p}.
 constexpr int kInvRows = 4;
+// Table rows the inverse walk takes: seven at twelve waves per block (146 KiB
+// of LDS), six at sixteen; pair codes of 6 bits.
+constexpr int kGradInvMaxMat = 7;
 constexpr int kInvRenormSegs = 2;  // segments between rescalings: growth <= 2^9 per step either way
 // Share vectors of the inverse walk are kInvRedStride doubles apart (64 values +
 // 8 of padding): with each lane quad reading its vector in interleaved 16-byte
@@ -1160,7 +1166,7 @@ struct InvLayers {
     const double2* mt;  // material rows + lane: mt[(m * kInvRows + f) * kWave]
     const double2* pr;  // pair ratios + lane: pr[pair * kWave]
     double my_d[N];     // lane l, register r: thickness of layer 64 r + l + 1
-    int my_code[N];     // that layer: pair | reversed pair << 5 | material << 10
+    int my_code[N];     // that layer: pair | reversed pair << 6 | material << 12
     int my_row[N];      // material row of medium 64 r + l
     __device__ __forceinline__ double d(int j) const { return lane_bcast(my_d, j - 1); }
     __device__ __forceinline__ int code(int j) const { return lane_bcast(my_code, j - 1); }
@@ -1238,8 +1244,8 @@ __device__ void grad_stack_inv(const GradParams& p, const LY& src, const Ambient
         const int lo = top - RPA + 1 > 1 ? top - RPA + 1 : 1;
         for (int j = top; j >= lo; --j) {
             const int c = src.code(j);
-            const double2 r = src.ratio(c & 31);
-            const cx<double> E = phase.cis_g(src.d(j) * src.mat(c >> 10, 0).x);
+            const double2 r = src.ratio(c & 63);
+            const cx<double> E = phase.cis_g(src.d(j) * src.mat(c >> 12, 0).x);
             if (POL & 1) {
                 const cx<double> X = cscale(r.x, z.ts);
                 const cx<double> a = cadd(z.ss, X), bd = csub(z.ss, X);
@@ -1328,8 +1334,8 @@ __device__ void grad_stack_inv(const GradParams& p, const LY& src, const Ambient
         for (int j = lo; j <= top; ++j) {
             const int t = top - j;  // share slot, as in grad_stack_pair
             const int c = src.code(j);
-            const double2 r = src.ratio(c & 31), rr = src.ratio((c >> 5) & 31);
-            const double2 f0 = src.mat(c >> 10, 0), f1 = src.mat(c >> 10, 1);  // {cre, dq/dn}, {dlog q, dlog eta}
+            const double2 r = src.ratio(c & 63), rr = src.ratio((c >> 6) & 63);
+            const double2 f0 = src.mat(c >> 12, 0), f1 = src.mat(c >> 12, 1);  // {cre, dq/dn}, {dlog q, dlog eta}
             const double dj = src.d(j);
             const cx<double> E = phase.cis_g(dj * f0.x);
             const cx<double> Eq = {0.25 * E.re, -0.25 * E.im};  // conj(E) / 4
@@ -1417,14 +1423,15 @@ __device__ void grad_stack_inv(const GradParams& p, const LY& src, const Ambient
 // Persistent blocks of WAVES waves over tasks (column, group of WAVES stacks),
 // the block's real tables built per (column, ambient row) as in grad_pair_kernel.
 // Stacks whose column is not lossless, whose ratios leave their bound or whose
-// phases leave the fast range are marked in p.redo and left to grad_pair_kernel.
+// phases leave the fast range are marked in p.redo and left to grad_pair_kernel
+// (at most five rows) or to grad_kernel.
 template <int POL, int SEG, int WAVES, int N>
 __global__ void __launch_bounds__(WAVES * kWave) grad_inv_kernel(GradParams p) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int s_rows[WAVES];
     __shared__ int s_bad[WAVES];
     __shared__ double s_cmax[WAVES];
-    __shared__ int s_lossy[kGradPairMaxMat];
+    __shared__ int s_lossy[kGradInvMaxMat];
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     fill_phase_tab<double>(smem, threadIdx.x, WAVES * kWave);
@@ -1496,7 +1503,7 @@ __global__ void __launch_bounds__(WAVES * kWave) grad_inv_kernel(GradParams p) {
                 load_layers(p, drow, mrow, lane, src.my_d, src.my_row, m_cur, m_nxt);
                 for (int r = 0; r < N; ++r)
                     src.my_code[r] =
-                        (m_cur[r] * p.n_mat + m_nxt[r]) | (m_nxt[r] * p.n_mat + m_cur[r]) << 5 | m_cur[r] << 10;
+                        (m_cur[r] * p.n_mat + m_nxt[r]) | (m_nxt[r] * p.n_mat + m_cur[r]) << 6 | m_cur[r] << 12;
                 const bool far = any_far(src.my_d, p.L, lane, cm);
                 const bool mine = any_bad == 0 && any_lossy == 0 && !far;
                 if (mine) grad_stack_inv<POL, SEG>(p, src, amb, b, tk_k, i, lane, active, ok, red, part, phase);
@@ -1683,10 +1690,13 @@ static hipError_t launch_grad_inv_t(GradParams p, int n_cu, hipStream_t s) {
 }
 
 // Sixteen-wave blocks (four waves per SIMD at 128 VGPRs); stacks of 63-126
-// layers (two registers of layer data) in twelve-wave blocks.
+// layers (two registers of layer data) and seven-row tables in twelve-wave
+// blocks.
 static hipError_t launch_grad_inv(const GradParams& p, uint32_t pol, int n_cu, hipStream_t s) {
-    static_assert(grad_inv_lds_bytes(kGradPairMaxMat, 3, 16) <= 160 * 1024, "inverse-walk tables exceed LDS");
-    if (p.L + 2 > kWave) {
+    static_assert(grad_inv_lds_bytes(kGradInvMaxMat - 1, 3, 16) <= 160 * 1024, "inverse-walk tables exceed LDS");
+    static_assert(grad_inv_lds_bytes(kGradInvMaxMat, 3, 12) <= 160 * 1024, "inverse-walk tables exceed LDS");
+    static_assert(kGradInvMaxMat * kGradInvMaxMat <= 64, "pair codes are 6 bits");
+    if (p.L + 2 > kWave || grad_inv_lds_bytes(p.n_mat, 3, 16) > 160 * 1024) {
         if (pol == 1u) return launch_grad_inv_t<1, 3, 12, 2>(p, n_cu, s);
         if (pol == 2u) return launch_grad_inv_t<2, 3, 12, 2>(p, n_cu, s);
         return launch_grad_inv_t<3, 3, 12, 2>(p, n_cu, s);
@@ -1773,6 +1783,9 @@ static tmm_status grad_launch(const tmm_rt_args* a, const void* dl_dR, const voi
     // (L + 2 <= 64) or two (<= 128) per lane
     const bool pair = a->mat != nullptr && a->n_mat <= kGradPairMaxMat && a->L + 2 <= 2 * kWave;
     const bool two = a->L + 2 > kWave;
+    // the inverse walk first (lossless columns) up to seven rows; the columns it
+    // leaves go to the ratio-form kernel (at most five rows) or the division-free one
+    const bool inv = a->mat != nullptr && a->n_mat <= kGradInvMaxMat && a->L + 2 <= 2 * kWave;
     // segments of five layers where their larger share buffer still fits the LDS
     // beside the table (at most four rows; 15 shares fill 60 reduction lanes), else of three
     const bool seg5 = pair && a->n_mat <= kGradPairLongSegMaxMat;
@@ -1787,7 +1800,7 @@ static tmm_status grad_launch(const tmm_rt_args* a, const void* dl_dR, const voi
         p.n_tasks_pair = g.cols * ceil_div(p.b_end - p.b_begin, kGradPairWaves);
         hipError_t e = hipSuccess;
         p.redo = nullptr;
-        if (pair) {
+        if (inv) {
             // lossless columns by the inverse walk; the rest marked for the kernels below
             p.redo = redo;
             e = launch_grad_inv(p, a->pol_mask, n_cu, s);

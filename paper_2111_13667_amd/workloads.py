@@ -157,18 +157,24 @@ def large_batch(seed: int = 0, B: int = 4096, L: int = 40, n_wl: int = 1024,
 
 
 def adjoint_batch(seed: int = 0, B: int = 1024, L: int = 60, n_wl: int = 512,
-                  n_theta: int = 31) -> Workload:
+                  n_theta: int = 31, n_pool: int = 2) -> Workload:
     """Gradient workload: 1024 stacks x 60 alternating high/low layers (high first,
     n_H = 2.35, n_L = 1.46, k = 0), d ~ U[30,200] nm, 512 wavelengths 400-800 nm x
     31 angles 0-60 deg, ambient 1.0, substrate 1.52.  Table rows: 0 high, 1 low,
-    2 ambient, 3 substrate."""
+    2 ambient, 3 substrate.  n_pool > 2: the layers cycle through a pool of
+    n_pool lossless indices (2.35, 1.46, then 2.0, 1.7, 2.2, 1.6, ...), rows
+    n_pool and n_pool + 1 the ambient and the substrate (the thicknesses are the
+    same draws)."""
     rng = np.random.default_rng(seed)
     d = rng.uniform(30.0, 200.0, (B, L))
-    nk = np.array([2.35, 1.46, 1.0, 1.52], dtype=np.complex128)
+    pool = [2.35, 1.46, 2.0, 1.7, 2.2, 1.6, 1.9, 2.5, 1.55, 2.1][:n_pool]
+    if len(pool) < n_pool:
+        raise ValueError("n_pool <= 10")
+    nk = np.array(pool + [1.0, 1.52], dtype=np.complex128)
     mat = np.empty((B, L + 2), dtype=np.int32)
-    mat[:, 0] = 2
-    mat[:, 1:L + 1] = np.arange(L) % 2
-    mat[:, L + 1] = 3
+    mat[:, 0] = n_pool
+    mat[:, 1:L + 1] = np.arange(L) % n_pool
+    mat[:, L + 1] = n_pool + 1
     wl = np.linspace(400.0, 800.0, n_wl)
     theta = np.deg2rad(np.linspace(0.0, 60.0, n_theta))
     s, c = angles(theta)

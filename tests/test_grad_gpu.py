@@ -320,6 +320,25 @@ def test_inverse_walk_columns_next_to_redone_columns(L):
     _check_against_oracle(w, rng.normal(size=shape), rng.normal(size=shape))
 
 
+@pytest.mark.parametrize("n_inner,L", [(4, 11), (5, 24), (5, 80)])
+def test_six_and_seven_rows_inverse_walk_and_division_free_redo(n_inner, L):
+    # Six and seven table rows: the inverse walk takes the lossless columns (below
+    # an absorption edge of one material) and the division-free adjoint redoes
+    # the columns it leaves; a lossless batch of the same shape runs on the
+    # inverse walk alone.
+    from dataclasses import replace
+    w = _material_workload(150 + L, B=5, L=L, n_wl=200, n_theta=2, n_inner=n_inner, k_max=0.0)
+    rng = np.random.default_rng(151)
+    shape = (w.B, 2, w.theta.size, w.wl.size)
+    _check_against_oracle(w, rng.normal(size=shape), rng.normal(size=shape))
+    nk = w.nk.copy()
+    nk[1] = nk[1].real + 1j * np.where(w.wl > w.wl[100], 5e-3, 0.0)
+    mat = w.mat.copy()
+    mat[:, 1 + np.arange(0, L, 3)] = 1   # every stack holds the absorbing material
+    w = replace(w, nk=nk, mat=mat)
+    _check_against_oracle(w, rng.normal(size=shape), rng.normal(size=shape))
+
+
 @pytest.mark.parametrize("L", [7, 13, 60, 90])
 def test_ratio_form_five_layer_kernel_fallback(L):
     # Four table rows (air, one dielectric, ambient 1.5, substrate 1.52): the
