@@ -237,3 +237,22 @@ def test_eight_rows_and_claim_batches_across_stacks(dtype, grain):
     plan.run(*dev, R=R, T=T)
     torch.cuda.synchronize()
     check_stacks(rw, plan, R, T, range(rw.B), dtype)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_one_row_table_and_empty_stacks(dtype):
+    # A one-row table (ambient, every layer and the substrate the same medium):
+    # R = 0 and T = 1 at every point, against the oracle too; then a batch in
+    # which every stack is empty (L = 0: the bare interface).
+    import dataclasses
+    rw = workloads.ragged_batch(seed=74, B=12, L_range=(0, 70), wl_range=(1, 90), th_range=(1, 4))
+    one = dataclasses.replace(rw, nk=rw.nk[5:6].copy(), mat=np.zeros_like(rw.mat),
+                              ends=np.zeros_like(rw.ends))
+    plan, _, R, T = run(one, dtype)
+    check_stacks(one, plan, R, T, range(one.B), dtype)
+    tol = 1e-12 if dtype == "f64" else 2e-5
+    assert np.abs(R.cpu().numpy()).max() <= tol
+    assert np.abs(T.cpu().numpy() - 1.0).max() <= tol
+    empty = workloads.ragged_batch(seed=75, B=20, L_range=(0, 0), wl_range=(1, 130), th_range=(1, 5))
+    plan, _, R, T = run(empty, dtype)
+    check_stacks(empty, plan, R, T, range(empty.B), dtype)
