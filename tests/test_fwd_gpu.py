@@ -534,6 +534,20 @@ def test_row_blocks_f32(n_inner, L):
     assert_close32(run_gpu(w, dtype="f32", amplitudes=True), run_oracle(w.rounded_f32(), amplitudes=True))
 
 
+@pytest.mark.parametrize("pol", ["s", "p"])
+def test_row_blocks_single_polarisation(pol):
+    # The row-block kernels for one polarisation (11 rows), R, T, r and t in
+    # double, R and T in float; then 18 rows (above the row blocks' 16: the
+    # per-step media path) for the same polarisation.
+    w = _material_workload(170, B=13, L=26, n_wl=75, n_theta=3, n_inner=9)
+    assert_close64(run_gpu(w, amplitudes=True, pol=pol), run_oracle(w, amplitudes=True, pol=pol),
+                   ("R", "T", "r", "t"))
+    assert_close32(run_gpu(w, dtype="f32", pol=pol), run_oracle(w.rounded_f32(), pol=pol))
+    w = _material_workload(171, B=7, L=21, n_wl=40, n_theta=2, n_inner=16)
+    assert_close64(run_gpu(w, amplitudes=True, pol=pol), run_oracle(w, amplitudes=True, pol=pol),
+                   ("R", "T", "r", "t"))
+
+
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_row_blocks_metal_rows_and_critical_fallback(dtype):
     # Ten rows: metal-like media (0.15+3.5i, 0.9+5.8i) in thin films with the
