@@ -168,6 +168,11 @@ struct PairChain {
             E.im *= att;
         }
         if (AMP) F = reduce1024(F + g);
+        update(rs, rp, E);
+    }
+
+    // The ratio-form update of the state for the step's ratios and phase factor.
+    __device__ __forceinline__ void update(cx<R> rs, cx<R> rp, const cx<R>& E) {
         if (POL & 1) {
             const cx<R> X = cmul(rs, ts);
             const cx<R> a = cadd(ss, X), b = csub(ss, X);
@@ -182,6 +187,27 @@ struct PairChain {
             sp = cadd(a, Eb);
             tp = csub(a, Eb);
         }
+    }
+
+    // The same step in float with the phase coefficient as a float pair
+    // (c_hi + c_lo, per unit d) and a float thickness: the phase d c is formed
+    // as an exact float pair (d c_hi and its FMA error, plus d c_lo) and reduced
+    // in float (|d c_hi| < 2^21); R and T only (the phase sum F is not kept).
+    __device__ __forceinline__ void step_ff(cx<R> rs, cx<R> rp, float c_hi, float c_lo, float cim, float d,
+                                            bool lossy, const TabPhase<R>& phase) {
+#pragma clang fp contract(off)  // hi must stay the rounded product its FMA error term refers to
+        static_assert(sizeof(R) == 4 && !AMP, "float pair phase: float R and T only");
+        const float hi = d * c_hi;
+        const float lo = __builtin_fmaf(d, c_lo, __builtin_fmaf(d, c_hi, -hi));
+        cx<R> E = phase.cis_ff(hi, lo);
+        if (lossy) {
+            const float y = d * cim;
+            S += (double)y;
+            const R att = phase.atten_f(y);
+            E.re *= att;
+            E.im *= att;
+        }
+        update(rs, rp, E);
     }
 
     __device__ __forceinline__ void renorm() {

@@ -197,6 +197,13 @@ struct TabPhase<float> {
         sincospi_g_f(g, tab, s, c);
         return {c, s};
     }
+    // e^{i pi g / 256} for g = hi + lo given as a float pair, |hi| < 2^21:
+    // the index and residual in float, exactly up to the final addition of lo.
+    __device__ __forceinline__ cx<float> cis_ff(float hi, float lo) const {
+        float s, c;
+        sincospi_ff(hi, lo, tab, s, c);
+        return {c, s};
+    }
     __device__ __forceinline__ float atten(double yd) const { return atten_f((float)yd); }
     __device__ __forceinline__ float atten_f(float y) const {
         return __all(__builtin_fabsf(y) <= (float)kExp2WeakRange) ? horner<true>(kExp2SF, y) : exp2_f(y);

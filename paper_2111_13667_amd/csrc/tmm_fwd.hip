@@ -355,21 +355,38 @@ struct PairTab<double> {
     }
 };
 
+// The phase coefficient cre as a float pair (hi, lo: hi + lo = cre to about
+// 48 bits) beside cim in float, in one 16-byte slot.
+__device__ __forceinline__ float4 phase_slot_f(double cre, double cim) {
+    const float hi = (float)cre;
+    return make_float4(hi, (float)(cre - (double)hi), (float)cim, 0.0f);
+}
+
 template <>
 struct PairTab<float> {
-    static constexpr int kBlockBytes = 2 * kWave * 16;  // (rho_s, rho_p)[64] as float4, (cre, cim)[64]
+    static constexpr int kBlockBytes = 2 * kWave * 16;  // (rho_s, rho_p)[64] as float4, (cre hi, lo, cim)[64]
     __device__ static void put(unsigned char* blk, int lane, cx<double> rs, cx<double> rp, double cre, double cim) {
         reinterpret_cast<float4*>(blk)[lane] = make_float4((float)rs.re, (float)rs.im, (float)rp.re, (float)rp.im);
-        reinterpret_cast<double2*>(blk + kWave * 16)[lane] = make_double2(cre, cim);
+        reinterpret_cast<float4*>(blk + kWave * 16)[lane] = phase_slot_f(cre, cim);
     }
     __device__ __forceinline__ static void get(const unsigned char* at, cx<float>& rs, cx<float>& rp, double& cre,
                                                double& cim) {
         const float4 x = *reinterpret_cast<const float4*>(at);
-        const double2 z = *reinterpret_cast<const double2*>(at + kWave * 16);
+        const float4 z = *reinterpret_cast<const float4*>(at + kWave * 16);
         rs = {x.x, x.y};
         rp = {x.z, x.w};
-        cre = z.x;
-        cim = z.y;
+        cre = (double)z.x + (double)z.y;
+        cim = (double)z.z;
+    }
+    __device__ __forceinline__ static void get_ff(const unsigned char* at, cx<float>& rs, cx<float>& rp, float& c_hi,
+                                                  float& c_lo, float& cim) {
+        const float4 x = *reinterpret_cast<const float4*>(at);
+        const float4 z = *reinterpret_cast<const float4*>(at + kWave * 16);
+        rs = {x.x, x.y};
+        rp = {x.z, x.w};
+        c_hi = z.x;
+        c_lo = z.y;
+        cim = z.z;
     }
 };
 
@@ -424,22 +441,32 @@ struct RowTab<double> {
 
 template <>
 struct RowTab<float> {
-    static constexpr int kBlockBytes = 3 * kWave * 16;  // (q, eta) float4, (1/q, 1/eta) float4, (cre, cim)
+    static constexpr int kBlockBytes = 3 * kWave * 16;  // (q, eta) float4, (1/q, 1/eta) float4, (cre hi, lo, cim)
     __device__ static void put(unsigned char* blk, int lane, cx<double> q, cx<double> e, cx<double> iq,
                                cx<double> ie, double cre, double cim) {
         reinterpret_cast<float4*>(blk)[lane] = make_float4((float)q.re, (float)q.im, (float)e.re, (float)e.im);
         reinterpret_cast<float4*>(blk + kWave * 16)[lane] =
             make_float4((float)iq.re, (float)iq.im, (float)ie.re, (float)ie.im);
-        reinterpret_cast<double2*>(blk + 2 * kWave * 16)[lane] = make_double2(cre, cim);
+        reinterpret_cast<float4*>(blk + 2 * kWave * 16)[lane] = phase_slot_f(cre, cim);
     }
     __device__ __forceinline__ static void get_cur(const unsigned char* at, cx<float>& iq, cx<float>& ie,
                                                    double& cre, double& cim) {
         const float4 x = *reinterpret_cast<const float4*>(at + kWave * 16);
-        const double2 z = *reinterpret_cast<const double2*>(at + 2 * kWave * 16);
+        const float4 z = *reinterpret_cast<const float4*>(at + 2 * kWave * 16);
         iq = {x.x, x.y};
         ie = {x.z, x.w};
-        cre = z.x;
-        cim = z.y;
+        cre = (double)z.x + (double)z.y;
+        cim = (double)z.z;
+    }
+    __device__ __forceinline__ static void get_cur_ff(const unsigned char* at, cx<float>& iq, cx<float>& ie,
+                                                      float& c_hi, float& c_lo, float& cim) {
+        const float4 x = *reinterpret_cast<const float4*>(at + kWave * 16);
+        const float4 z = *reinterpret_cast<const float4*>(at + 2 * kWave * 16);
+        iq = {x.x, x.y};
+        ie = {x.z, x.w};
+        c_hi = z.x;
+        c_lo = z.y;
+        cim = z.z;
     }
     __device__ __forceinline__ static void get_next(const unsigned char* at, cx<float>& q, cx<float>& e) {
         const float4 x = *reinterpret_cast<const float4*>(at);
@@ -514,6 +541,8 @@ __device__ __forceinline__ bool run_stack_pair(const FwdParams<R>& p, const unsi
     const int m_sub_raw = mrow[L + 1];
     bool bad = (uint32_t)m_sub_raw >= (uint32_t)n_mat;
     const int m_sub = bad ? 0 : m_sub_raw;
+    // float R and T: the phase reduced as a float pair (dmax keeps it below 2^21)
+    constexpr bool kFF = sizeof(R) == 4 && !AMP;
     const unsigned char* const lane_base = pair_base + lane * 16;
     int nxt_off = m_sub * RowTab<R>::kBlockBytes;  // ROWS: block of the layer below (the substrate first)
     PairChain<R, POL, AMP> c;
@@ -525,6 +554,7 @@ __device__ __forceinline__ bool run_stack_pair(const FwdParams<R>& p, const unsi
         // lane l holds layer lo + l: thickness and pair block offset | lossy << 31
         const int j = lo + lane;
         double my_d = 0.0;
+        float my_df = 0.0f;  // the same thickness in float (exact for float inputs)
         int my_code = 0;
         bool lane_bad = false, lane_far = false;
         if (j <= top) {
@@ -536,6 +566,7 @@ __device__ __forceinline__ bool run_stack_pair(const FwdParams<R>& p, const unsi
             lane_far = !((double)dj <= dmax);
             const int mc = mbad ? 0 : m, mnc = mbad ? 0 : mn;
             my_d = (double)dj;
+            my_df = (float)dj;
             const int off = ROWS ? mc * RowTab<R>::kBlockBytes : (mc * n_mat + mnc) * PairTab<R>::kBlockBytes;
             my_code = off | (int)(((lossy_mask >> mc) & 1u) << 31);
         }
@@ -544,6 +575,25 @@ __device__ __forceinline__ bool run_stack_pair(const FwdParams<R>& p, const unsi
         auto step = [&](int jj) {
             const int sl = jj - lo;
             const int code = __builtin_amdgcn_readlane(my_code, sl);
+            if constexpr (kFF) {
+                // float: the thickness is exact in float, the phase a float pair
+                const float df = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(my_df), sl));
+                cx<R> rs, rp;
+                float c_hi, c_lo, cim;
+                if constexpr (ROWS) {
+                    const int cur_off = code & 0x7fffffff;
+                    cx<R> iq, ie, qn, en;
+                    RowTab<R>::get_cur_ff(lane_base + cur_off, iq, ie, c_hi, c_lo, cim);
+                    RowTab<R>::get_next(lane_base + nxt_off, qn, en);
+                    rs = cmul(qn, iq);
+                    rp = cmul(en, ie);
+                    nxt_off = cur_off;
+                } else {
+                    PairTab<R>::get_ff(lane_base + (code & 0x7fffffff), rs, rp, c_hi, c_lo, cim);
+                }
+                c.step_ff(rs, rp, c_hi, c_lo, cim, df, code < 0, phase);
+                return;
+            }
             const double dj = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(my_d), sl),
                                                __builtin_amdgcn_readlane(__double2loint(my_d), sl));
             cx<R> rs, rp;
@@ -723,7 +773,8 @@ __global__ void __launch_bounds__((pair_max_waves<R, POL, AMP>() * kWave)) fwd_p
     }
     const bool pair_ok = __builtin_amdgcn_readfirstlane(any_bad) == 0;
     // every layer of a stack with d <= dmax keeps |phi| below the fast range
-    const double dmax = (0.5 * kScFastRange) / cm;
+    // (the float-pair reduction's in float R and T)
+    const double dmax = (sizeof(R) == 4 && !AMP ? kScFastRangeF : 0.5 * kScFastRange) / cm;
     const TabPhase<R> phase = phase_of<R>(smem);
     // stacks are handed out one at a time from an LDS counter (the first one
     // per wave statically): waves that run faster take more stacks, so the

@@ -154,6 +154,27 @@ __device__ __forceinline__ void sincospi_g_f(double g, const float2* tab, float&
     s = __builtin_fmaf(t.y, ch, t.x * sh);
 }
 
+// The same for g = hi + lo held as two floats (hi carries g to 24 bits, lo
+// the rest), |hi| < 2^21: adding 1.5 * 2^23 rounds hi to an integer n (exact,
+// ulp 1), whose low bits index the table; hi - n is exact (Sterbenz), and lo
+// is added to it once.  No double arithmetic.
+constexpr float kScRoundF = 12582912.0f;  // 1.5 * 2^23
+__device__ __forceinline__ void sincospi_ff(float hi, float lo, const float2* tab, float& s, float& c) {
+#pragma clang fp contract(off)  // hi is a rounded product: no FMA may re-form it exactly
+    const float t = hi + kScRoundF;
+    const uint32_t idx = __float_as_uint(t) & (uint32_t)(kScEntries - 1);
+    const float r = (hi - (t - kScRoundF)) + lo;
+    const float2 e = tab[idx];
+    const float r2 = r * r;
+    const float sh = r * horner<true>(kSinGF, r2);
+    const float ch = horner<true>(kCosGF, r2);
+    c = __builtin_fmaf(e.x, ch, -(e.y * sh));
+    s = __builtin_fmaf(e.y, ch, e.x * sh);
+}
+// Largest |hi| sincospi_ff takes (with room below the 2^22 where the rounding
+// constant stops giving integers).
+constexpr double kScFastRangeF = 2097152.0;  // 2^21
+
 // Any finite x (half-turns): x is first reduced modulo 2, exactly
 // (x - 2 rint(x/2)), then scaled by 256 (exact).
 __device__ __forceinline__ double sc_exact_g(double x) {

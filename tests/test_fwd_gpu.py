@@ -397,6 +397,20 @@ def test_thick_lossless_layer_conserves_energy(d_thick):
     assert np.abs(got["R"] + got["T"] - 1.0).max() <= 1e-12
 
 
+def test_float_pair_phase_range_f32():
+    # Float R and T reduce the phase d * 1024 Re q / lambda as a float pair below
+    # 2^21: a 0.1 mm layer stays on it, a 1 mm layer (phase about 2^22) sends its
+    # stack to the exact reduction; both against the oracle element by element,
+    # and R + T = 1 (no absorption).
+    w = _material_workload(63, B=6, L=8, n_wl=64, n_theta=3, n_inner=3, k_max=0.0)
+    w.d[0:2, 3] = 1e5
+    w.d[2:4, 5] = 1e6
+    w = w.rounded_f32()
+    got = run_gpu(w, dtype="f32")
+    assert_close32(got, run_oracle(w))
+    assert np.abs(got["R"] + got["T"] - 1.0).max() <= 2e-5
+
+
 @pytest.mark.parametrize("pol", ["s", "p"])
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_material_table_single_polarisation_rt(pol, dtype):
