@@ -300,7 +300,7 @@ def time_surrogate_dataset():
 # interface; FP32 kernel 2.1e10 float and 2.1e9 double instructions' worth.
 EXECUTED_FLOPS_PER_LAUNCH = {
     "f64": {"fp64": 64 * (2 * 5.018e9 + 3.454e9 + 4.246e9)},
-    "f32": {"fp32": 64 * (2 * 3.35e9 + 3.12e9 + 3.82e9), "fp64": 64 * (2 * 8.33e8 + 4.29e8)},
+    "f32": {"fp32": 64 * (2 * 3.822e9 + 3.472e9 + 4.761e9), "fp64": 64 * (2 * 3.62e8 + 2.20e8 + 1.93e8)},
 }
 
 
