@@ -142,6 +142,24 @@ def _units_flagged(sigma, scale, bound, task):
     return flag.view(-1, P, task.n_theta * task.n_wl).any(dim=1)
 
 
+def _assert_transfer_matrix_values(out, y, uf, x, task):
+    # Flagged outputs are float32 transfer-matrix values: those of the dense
+    # kernel (stacks flagged whole, y) or of the point kernel (stacks flagged in
+    # part).  The two reduce the layer phase differently (float pair / double),
+    # so each output must match one of them; both stay within the float32 error
+    # of the 30-layer task against float64 (1.2e-4 at most measured on 1500
+    # stacks).
+    from paper_2111_13667_amd import surrogate as S, tmm
+    n = x.shape[0]
+    yp = torch.zeros((n, 2, task.n_theta, task.n_wl), dtype=torch.float32, device="cuda")
+    pts = torch.arange(n * task.n_theta * task.n_wl, dtype=torch.int64, device="cuda")
+    tmm.tmm_rt_points(x, task.nk, task.wl, task.sin_t, task.cos_t, pts, mat=task.mat(n), pol_mask=3, R=yp)
+    near = torch.minimum((out - y).abs(), (out - yp.view(n, -1)).abs())
+    assert near[uf].max().item() <= 1e-6
+    y64 = S.generate(S.make_task("f64"), x.double())
+    assert (out[uf].double() - y64[uf]).abs().max().item() <= 2e-4
+
+
 def test_fallback_keeps_the_bound():
     # 30-layer task, untrained ensemble.  (a) The point-level scale calibrated
     # on a set keeps max |out - tmm| <= bound on that set.  (b) The mechanism at
@@ -173,7 +191,7 @@ def test_fallback_keeps_the_bound():
     assert nf == 2 * int(units.sum().item())
     uf = units[:, None, :].expand(n, 2, units.shape[1]).reshape(n, -1)
     assert torch.equal(out[~uf], mean[~uf])
-    assert (out[uf] - y[uf]).abs().max().item() <= 4e-5
+    _assert_transfer_matrix_values(out, y, uf, x, task)
     out_all, nf_all = sur.predict_fallback(x, task, float("inf"), bound)
     assert nf_all == n * task.n_out and torch.equal(out_all, y)
     out_none, nf_none = sur.predict_fallback(x, task, 0.0, bound)
@@ -244,7 +262,7 @@ def test_windowed_spread_flags_exactly_the_units_it_defines():
     assert nf == 2 * int(units.sum().item())
     uf = units[:, None, :].expand(n, 2, units.shape[1]).reshape(n, -1)
     assert torch.equal(out[~uf], mean[~uf])
-    assert (out[uf] - y[uf]).abs().max().item() <= 4e-5
+    _assert_transfer_matrix_values(out, y, uf, x, task)
     sur.close()
 
 
