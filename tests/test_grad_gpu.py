@@ -449,7 +449,8 @@ def test_metal_layers_gradient_both_forms():
 
 
 def test_long_stack_gradient_division_free_form():
-    # 130 layers (L + 2 > 64: the division-free adjoint), 44 checkpoint segments
+    # 130 layers (L + 2 > 128, past the ratio form's two registers of layer data:
+    # the division-free adjoint), 44 checkpoint segments
     w = _material_workload(96, B=2, L=130, n_wl=12, n_theta=2, n_inner=3, k_max=0.002)
     rng = np.random.default_rng(97)
     shape = (w.B, 2, w.theta.size, w.wl.size)
