@@ -46,8 +46,14 @@ typedef struct tmm_ragged_plan tmm_ragged_plan;
  *  nk         [n_mat][wl_off[B]] complex interleaved: row m, column wl_off[b]+i
  *             is the index of material m at stack b's i-th wavelength.
  *  n_mat      1 .. 8.
- *  R, T       [output_size] real (either may be NULL, not both): stack b's
- *             block starts at its output offset and is [P][n_theta_b][n_wl_b].
+ *  R, T       [output_size] real: stack b's block starts at its output
+ *             offset and is [P][n_theta_b][n_wl_b].
+ *  r, t       [output_size] complex interleaved, the same layout: the
+ *             amplitudes of tmm_rt (Eq. (7); the same phase convention).
+ * Any of R, T, r, t may be NULL, not all four.  A run that asks for r or t uses
+ * the amplitude kernels: one lane per point, with a launch shape tuned (and
+ * cached) for them separately from the R and T runs' shape, which is the one
+ * tmm_ragged_plan_shape reports and tmm_ragged_plan_set_shape fixes.
  * Invalid values (negative / non-finite thickness, row out of range, absorbing
  * ambient at oblique incidence) give NaN, as in tmm_rt.
  */
@@ -61,6 +67,7 @@ typedef struct tmm_ragged_data {
     const void *nk;
     int32_t n_mat;
     void *R, *T;
+    void *r, *t;
 } tmm_ragged_data;
 
 /* Build a plan.  layer_off, wl_off, th_off: HOST arrays [B+1] starting at 0

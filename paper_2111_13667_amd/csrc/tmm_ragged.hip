@@ -53,9 +53,13 @@ namespace ragged {
 // 1-16 such waves plus the shared phase table, sized at launch so that the
 // CU's resident waves fit its LDS.  Resident waves per CU that the kernels'
 // registers allow: 3 per SIMD in double (up to 168 VGPRs), 4 in float (128).
-template <typename R> struct Occupancy;
-template <> struct Occupancy<double> { static constexpr int kWavesPerCU = 12; };
-template <> struct Occupancy<float> { static constexpr int kWavesPerCU = 16; };
+template <typename R, bool AMP = false> struct Occupancy;
+template <> struct Occupancy<double, false> { static constexpr int kWavesPerCU = 12; };
+template <> struct Occupancy<float, false> { static constexpr int kWavesPerCU = 16; };
+// r and t wanted: the running products of q and eta are complex and the phase
+// sum rides along
+template <> struct Occupancy<double, true> { static constexpr int kWavesPerCU = 8; };
+template <> struct Occupancy<float, true> { static constexpr int kWavesPerCU = 16; };
 constexpr int kMaxWavesPerCU = 16;
 constexpr int kMaxMat = 8;
 constexpr size_t kLdsPerCU = 160 * 1024;
@@ -97,6 +101,8 @@ struct Params {
     int64_t n_units;
     unsigned long long* counter;
     int grain;
+    R* r_out;  // complex interleaved, or null (read by the amplitude kernels only)
+    R* t_out;
 };
 
 // One index-table row at a lane's point, as the layer step consumes it.
@@ -258,8 +264,8 @@ __device__ __forceinline__ double exp2_weak_sq(double y) {
 // Division-free recursion (tmm_device.hpp) on table rows.  S sums
 // d (1024 / lambda) Im q in double (FP64) or the base-2 exponents of the
 // attenuation (FP32); kSLog2 turns it into the latter for the extraction.
-template <typename R, int POL>
-struct RChain : Chain<R, POL, false> {
+template <typename R, int POL, bool AMP = false>
+struct RChain : Chain<R, POL, AMP> {
     static constexpr double kSLog2 = sizeof(R) == 8 ? kNegPiLog2e / kScSteps : 1.0;
     __device__ __forceinline__ static double exp2_ext(double y) { return exp2_weak_sq(y); }
 
@@ -274,8 +280,11 @@ struct RChain : Chain<R, POL, false> {
             // rare (wave-uniform): an empty side-effecting asm keeps this a branch
             // rather than a select that would run the reduction on every step
             asm volatile("");
-            g = reduce512(g);
+            // one turn is enough for E; the phase sum of t needs two (its half
+            // enters the extraction)
+            g = AMP ? reduce1024(g) : reduce512(g);
         }
+        if constexpr (AMP) this->F = reduce1024(this->F + g);  // in 1/256 half-turn until the extraction
         cx<R> E = phase.cis_g(g);
         if (!CR) attenuate(E, cur, dl, df, k);
         return E;
@@ -324,8 +333,13 @@ struct RChain : Chain<R, POL, false> {
             this->sp = cadd(a, Eb);
             this->tp = csub(a, Eb);
         }
-        if (POL & 1) this->pis *= CR ? cur.q.re * cur.q.re : cur.q.re * cur.q.re + cur.q.im * cur.q.im;
-        if (POL & 2) this->pip *= CR ? cur.e.re * cur.e.re : cur.e.re * cur.e.re + cur.e.im * cur.e.im;
+        if constexpr (AMP) {
+            if (POL & 1) this->Pq = CR ? cscale(cur.q.re, this->Pq) : cmul(this->Pq, cur.q);
+            if (POL & 2) this->Pe = CR ? cscale(cur.e.re, this->Pe) : cmul(this->Pe, cur.e);
+        } else {
+            if (POL & 1) this->pis *= CR ? cur.q.re * cur.q.re : cur.q.re * cur.q.re + cur.q.im * cur.q.im;
+            if (POL & 2) this->pip *= CR ? cur.e.re * cur.e.re : cur.e.re * cur.e.re + cur.e.im * cur.e.im;
+        }
     }
 };
 
@@ -458,8 +472,9 @@ __device__ __forceinline__ int64_t first_lane(unsigned long long v) {
     return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
-template <typename R, int POL, int LPP>
-__global__ void __launch_bounds__(Occupancy<R>::kWavesPerCU * kWave) ragged_kernel(Params<R> p) {
+template <typename R, int POL, int LPP, bool AMP = false>
+__global__ void __launch_bounds__((Occupancy<R, AMP>::kWavesPerCU * kWave)) ragged_kernel(Params<R> p) {
+    static_assert(!AMP || LPP == 1, "r and t come from the one-lane-per-point chain");
     extern __shared__ __align__(16) unsigned char smem[];
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
@@ -533,6 +548,12 @@ __global__ void __launch_bounds__(Occupancy<R>::kWavesPerCU * kWave) ragged_kern
                 raw_r[m] = nkc[e];
                 raw_i[m] = nkc[e + 1];
             }
+            R ns_r = (R)0, ns_i = (R)0;  // the substrate's index (t of p)
+            if constexpr (AMP) {
+                const int64_t e = 2 * (int64_t)s_row * p.nk_stride;
+                ns_r = nkc[e];
+                ns_i = nkc[e + 1];
+            }
             const int lo1 = max(L - kWave + 1, 1);
             const int j1 = lo1 + lane;
             R d1 = (R)0;
@@ -594,7 +615,7 @@ __global__ void __launch_bounds__(Occupancy<R>::kWavesPerCU * kWave) ragged_kern
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             const Row<R> sub = tab.get_qe(s_row, lane);
-            RChain<R, POL> c;
+            RChain<R, POL, AMP> c;
             int first_row = s_row;  // table row of layer 1 (the substrate for L = 0)
             if constexpr (LPP == 1) {
                 int nxt_row = s_row;  // the layer below, as its table row (re-read from LDS per step)
@@ -750,8 +771,9 @@ __global__ void __launch_bounds__(Occupancy<R>::kWavesPerCU * kWave) ragged_kern
                 }
             }
             PointOut out[2];
-            finish<R, POL, false>(c, amb, as_layer(tab.get_qe(first_row, lane)), as_layer(sub), 0.0, 0.0, L, out,
-                                  phase);
+            if constexpr (AMP) c.F *= 1.0 / kScSteps;  // half-turns, as the extraction takes them
+            finish<R, POL, AMP>(c, amb, as_layer(tab.get_qe(first_row, lane)), as_layer(sub), (double)ns_r,
+                                (double)ns_i, L, out, phase);
             if (active && seg == 0) {
                 const bool valid = lam_ok && amb.ok && !bad;
                 const double nan = __builtin_nan("");
@@ -759,6 +781,16 @@ __global__ void __launch_bounds__(Occupancy<R>::kWavesPerCU * kWave) ragged_kern
                     const int64_t o = si.out0 + (int64_t)q * npts + f;
                     if (p.R_out) p.R_out[o] = (R)(valid ? out[q].R : nan);
                     if (p.T_out) p.T_out[o] = (R)(valid ? out[q].T : nan);
+                    if constexpr (AMP) {
+                        if (p.r_out) {
+                            p.r_out[2 * o] = (R)(valid ? out[q].r.re : nan);
+                            p.r_out[2 * o + 1] = (R)(valid ? out[q].r.im : nan);
+                        }
+                        if (p.t_out) {
+                            p.t_out[2 * o] = (R)(valid ? out[q].t.re : nan);
+                            p.t_out[2 * o + 1] = (R)(valid ? out[q].t.im : nan);
+                        }
+                    }
                 }
             }
             if (g == 0) {
@@ -793,10 +825,10 @@ size_t shape_lds(int n_mat, int waves) {
 // Workgroup shapes that hold the most resident waves per CU (at most the
 // kernel's register limit, Occupancy<R>) within the CU's LDS; the three with
 // the largest workgroups.
-template <typename R>
+template <typename R, bool AMP>
 std::vector<Shape> candidate_shapes(int n_mat) {
     const size_t granule = 2048;
-    constexpr int kMax = Occupancy<R>::kWavesPerCU;
+    constexpr int kMax = Occupancy<R, AMP>::kWavesPerCU;
     int best = 0;
     std::vector<Shape> out;
     for (int waves = kMax; waves >= 1; --waves) {
@@ -814,9 +846,9 @@ std::vector<Shape> candidate_shapes(int n_mat) {
     return out;
 }
 
-// Autotune cache: (dtype, pol, mean-layer bucket, unit-count bucket) -> shape.
+// Autotune cache: (dtype, r and t wanted, pol, mean-layer bucket, unit-count bucket) -> shape.
 std::mutex g_tune_mutex;
-std::map<std::tuple<int, int, int, int>, Shape> g_tune_cache;
+std::map<std::tuple<int, int, int, int, int>, Shape> g_tune_cache;
 
 }  // namespace ragged
 }  // namespace tmm
@@ -832,8 +864,8 @@ struct tmm_ragged_plan {
     tmm::ragged::StackInfo* d_info[3];
     unsigned long long* d_counter;
     int n_cu;
-    bool tuned[2];
-    tmm::ragged::Shape shape[2];  // per dtype
+    bool tuned[4];
+    tmm::ragged::Shape shape[4];  // per dtype (0 F64, 1 F32), + 2 with r and t
     hipGraph_t graph;
     hipGraphExec_t graph_exec;
     int mean_layers;
@@ -864,23 +896,31 @@ tmm::ragged::Params<R> make_params(const tmm_ragged_plan* pl, const tmm_ragged_d
     p.n_units = pl->n_units[0];
     p.counter = pl->d_counter;
     p.grain = 1;
+    p.r_out = static_cast<R*>(a->r);
+    p.t_out = static_cast<R*>(a->t);
     return p;
 }
 
-template <typename R, int POL, int LPP>
+// Shape slot of a run: the dtype, plus 2 when r or t is wanted (those runs
+// have their own kernels and tuned shape).
+int shape_slot(const tmm_ragged_data* a, tmm_dtype dt) { return (dt == TMM_F64 ? 0 : 1) + (a->r || a->t ? 2 : 0); }
+
+template <typename R, int POL, int LPP, bool AMP = false>
 void launch_one(const tmm::ragged::Params<R>& p, int blocks, dim3 threads, size_t lds, hipStream_t s) {
-    hipLaunchKernelGGL((tmm::ragged::ragged_kernel<R, POL, LPP>), dim3(blocks), threads, lds, s, p);
+    hipLaunchKernelGGL((tmm::ragged::ragged_kernel<R, POL, LPP, AMP>), dim3(blocks), threads, lds, s, p);
 }
 
 template <typename R, int POL>
 void launch_pol(const tmm::ragged::Params<R>& p, int lpp, int blocks, dim3 threads, size_t lds, hipStream_t s) {
-    if (lpp == 1) launch_one<R, POL, 1>(p, blocks, threads, lds, s);
+    if (p.r_out || p.t_out) launch_one<R, POL, 1, true>(p, blocks, threads, lds, s);  // one lane per point
+    else if (lpp == 1) launch_one<R, POL, 1>(p, blocks, threads, lds, s);
     else if (lpp == 2) launch_one<R, POL, 2>(p, blocks, threads, lds, s);
     else launch_one<R, POL, 4>(p, blocks, threads, lds, s);
 }
 
 template <typename R>
 hipError_t launch(const tmm_ragged_plan* pl, tmm::ragged::Params<R> p, tmm::ragged::Shape sh, hipStream_t s) {
+    if (p.r_out || p.t_out) sh.lpp = 1;  // the amplitude kernels run one lane per point
     const int li = tmm::ragged::lpp_index(sh.lpp);
     p.grain = sh.grain;
     p.unit_stack = pl->d_unit_stack[li];
@@ -903,9 +943,9 @@ hipError_t launch(const tmm_ragged_plan* pl, tmm::ragged::Params<R> p, tmm::ragg
 // valid output) and keeps the fastest; the result is cached per
 // (dtype, pol, layer bucket, unit bucket) for later plans.
 // Dynamic LDS above 64 KiB: raise the kernels' limit (outside any capture).
-template <typename R, int POL, int LPP>
+template <typename R, int POL, int LPP, bool AMP = false>
 void raise_one() {
-    (void)hipFuncSetAttribute((const void*)&tmm::ragged::ragged_kernel<R, POL, LPP>,
+    (void)hipFuncSetAttribute((const void*)&tmm::ragged::ragged_kernel<R, POL, LPP, AMP>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)tmm::ragged::kLdsPerCU);
 }
 
@@ -914,30 +954,34 @@ void raise_lds_limit() {
     raise_one<R, 1, 1>(); raise_one<R, 2, 1>(); raise_one<R, 3, 1>();
     raise_one<R, 1, 2>(); raise_one<R, 2, 2>(); raise_one<R, 3, 2>();
     raise_one<R, 1, 4>(); raise_one<R, 2, 4>(); raise_one<R, 3, 4>();
+    raise_one<R, 1, 1, true>(); raise_one<R, 2, 1, true>(); raise_one<R, 3, 1, true>();
     (void)hipGetLastError();
 }
 
+// si: the shape slot (shape_slot).
 template <typename R>
-tmm_status tune(tmm_ragged_plan* pl, const tmm::ragged::Params<R>& p, int di, hipStream_t s) {
+tmm_status tune(tmm_ragged_plan* pl, const tmm::ragged::Params<R>& p, int si, hipStream_t s) {
     raise_lds_limit<R>();
     const int lb = pl->mean_layers / 16;
     int ub = 0;
     for (int64_t u = pl->n_units[0]; u > 1; u >>= 2) ++ub;
-    const auto key = std::make_tuple(di, (int)pl->pol_mask, lb, ub);
+    const bool amp = si >= 2;
+    const auto key = std::make_tuple(si & 1, (int)amp, (int)pl->pol_mask, lb, ub);
     {
         std::lock_guard<std::mutex> g(tmm::ragged::g_tune_mutex);
         auto it = tmm::ragged::g_tune_cache.find(key);
         if (it != tmm::ragged::g_tune_cache.end()) {
             // shape known from an earlier plan of the same kind: this run's output
             // still has to be computed
-            pl->shape[di] = it->second;
-            pl->tuned[di] = true;
-            if (launch<R>(pl, p, pl->shape[di], s) != hipSuccess)
+            pl->shape[si] = it->second;
+            pl->tuned[si] = true;
+            if (launch<R>(pl, p, pl->shape[si], s) != hipSuccess)
                 return fail(TMM_ERR_HIP, "tmm_ragged_run: launch failed");
             return ok();
         }
     }
-    const std::vector<tmm::ragged::Shape> shapes = tmm::ragged::candidate_shapes<R>(p.n_mat);
+    const std::vector<tmm::ragged::Shape> shapes = amp ? tmm::ragged::candidate_shapes<R, true>(p.n_mat)
+                                                       : tmm::ragged::candidate_shapes<R, false>(p.n_mat);
     const int grains[] = {1, 4};
     hipEvent_t e0 = nullptr, e1 = nullptr;
     auto release = [&]() {
@@ -953,9 +997,10 @@ tmm_status tune(tmm_ragged_plan* pl, const tmm::ragged::Params<R>& p, int di, hi
     std::vector<tmm::ragged::Shape> trials;
     for (const tmm::ragged::Shape& base : shapes)
         for (int g : grains) trials.push_back({base.blocks_per_cu, g, base.waves, 1});
-    // lanes per point 2 and 4 (16- and 32-point tiles) at the largest workgroup shape
-    for (int lpp : {2, 4})
-        for (int g : grains) trials.push_back({shapes.front().blocks_per_cu, g, shapes.front().waves, lpp});
+    // lanes per point 2 and 4 (16- and 32-point tiles) at the largest workgroup shape (R and T only)
+    if (!amp)
+        for (int lpp : {2, 4})
+            for (int g : grains) trials.push_back({shapes.front().blocks_per_cu, g, shapes.front().waves, lpp});
     {
         for (const tmm::ragged::Shape& sh : trials) {
             if (hipEventRecord(e0, s) != hipSuccess || launch<R>(pl, p, sh, s) != hipSuccess ||
@@ -975,8 +1020,8 @@ tmm_status tune(tmm_ragged_plan* pl, const tmm::ragged::Params<R>& p, int di, hi
         }
     }
     release();
-    pl->shape[di] = best_sh;
-    pl->tuned[di] = true;
+    pl->shape[si] = best_sh;
+    pl->tuned[si] = true;
     // the shapes differ in arithmetic order (lanes per point), so the run's
     // output comes from the chosen one: launch it once more unless it ran last
     const tmm::ragged::Shape& last = trials.back();
@@ -995,7 +1040,7 @@ tmm_status check_data(const tmm_ragged_plan* pl, const tmm_ragged_data* a, tmm_d
     if (a->n_mat < 1) return fail(TMM_ERR_INVALID_ARG, "%s: n_mat must be >= 1", who);
     if (a->n_mat > tmm::ragged::kMaxMat)
         return fail(TMM_ERR_UNSUPPORTED, "%s: at most %d index-table rows are supported", who, tmm::ragged::kMaxMat);
-    if (!a->R && !a->T) return fail(TMM_ERR_INVALID_ARG, "%s: no output requested", who);
+    if (!a->R && !a->T && !a->r && !a->t) return fail(TMM_ERR_INVALID_ARG, "%s: no output requested", who);
     if (pl->B > 0 && (!a->ends || !a->wl || !a->sin_theta || !a->cos_theta || !a->nk))
         return fail(TMM_ERR_INVALID_ARG, "%s: ends, wl, sin_theta, cos_theta and nk must be non-NULL", who);
     if (pl->layer_off[pl->B] > 0 && (!a->d || !a->mat))
@@ -1079,7 +1124,7 @@ tmm_status tmm_ragged_plan_create(int32_t B, const int64_t* layer_off, const int
         pl->d_info[li] = nullptr;
     }
     pl->out_size = oo[B];
-    pl->tuned[0] = pl->tuned[1] = false;
+    for (int i = 0; i < 4; ++i) pl->tuned[i] = false;
     pl->graph = nullptr;
     pl->graph_exec = nullptr;
     pl->d_counter = nullptr;
@@ -1137,7 +1182,7 @@ tmm_status tmm_ragged_run(tmm_ragged_plan* pl, const tmm_ragged_data* a, tmm_dty
     if (st != TMM_OK) return st;
     if (pl->n_units[0] == 0) return ok();
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const int di = dtype == TMM_F64 ? 0 : 1;
+    const int di = shape_slot(a, dtype);
     (void)hipGetLastError();
     if (dtype == TMM_F64) {
         const auto p = make_params<double>(pl, a);
@@ -1191,7 +1236,7 @@ tmm_status tmm_ragged_capture(tmm_ragged_plan* pl, const tmm_ragged_data* a, tmm
     if (st != TMM_OK) return st;
     if (!stream) return fail(TMM_ERR_INVALID_ARG, "tmm_ragged_capture: needs a non-default stream");
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const int di = dtype == TMM_F64 ? 0 : 1;
+    const int di = shape_slot(a, dtype);
     if (!pl->tuned[di]) {
         st = tmm_ragged_run(pl, a, dtype, stream);  // tunes (and computes the outputs once)
         if (st != TMM_OK) return st;

@@ -15,7 +15,8 @@ from . import tmm
 class RaggedData(ctypes.Structure):
     _fields_ = [("d", ctypes.c_void_p), ("mat", ctypes.c_void_p), ("ends", ctypes.c_void_p),
                 ("wl", ctypes.c_void_p), ("sin_theta", ctypes.c_void_p), ("cos_theta", ctypes.c_void_p),
-                ("nk", ctypes.c_void_p), ("n_mat", ctypes.c_int32), ("R", ctypes.c_void_p), ("T", ctypes.c_void_p)]
+                ("nk", ctypes.c_void_p), ("n_mat", ctypes.c_int32), ("R", ctypes.c_void_p), ("T", ctypes.c_void_p),
+                ("r", ctypes.c_void_p), ("t", ctypes.c_void_p)]
 
 
 _bound = False
@@ -85,7 +86,7 @@ class RaggedPlan:
         tmm._check(_lib().tmm_ragged_plan_output_offsets(self.h, out.ctypes.data))
         return out
 
-    def _pack(self, d, mat, ends, wl, sin_t, cos_t, nk, R, T):
+    def _pack(self, d, mat, ends, wl, sin_t, cos_t, nk, R, T, r=None, t=None):
         import torch
         n_layers, n_wl, n_th = int(self.layer_off[-1]), int(self.wl_off[-1]), int(self.th_off[-1])
         real = wl.dtype
@@ -93,7 +94,8 @@ class RaggedPlan:
         checks = [("d", d, (n_layers,), real), ("mat", mat, (n_layers,), torch.int32),
                   ("ends", ends, (self.B, 2), torch.int32), ("wl", wl, (n_wl,), real),
                   ("sin_theta", sin_t, (n_th,), real), ("cos_theta", cos_t, (n_th,), real),
-                  ("R", R, (self.output_size,), real), ("T", T, (self.output_size,), real)]
+                  ("R", R, (self.output_size,), real), ("T", T, (self.output_size,), real),
+                  ("r", r, (self.output_size,), cplx), ("t", t, (self.output_size,), cplx)]
         for name, x, shape, dt in checks:
             if x is None:
                 continue
@@ -101,8 +103,8 @@ class RaggedPlan:
                 raise ValueError(f"{name} must be a contiguous {dt} device tensor of shape {shape}")
         if nk.dim() != 2 or nk.shape[1] != n_wl or nk.dtype != cplx or not nk.is_cuda or not nk.is_contiguous():
             raise ValueError(f"nk must be a contiguous {cplx} device tensor [n_mat, {n_wl}]")
-        if R is None and T is None:
-            raise ValueError("at least one of R, T")
+        if R is None and T is None and r is None and t is None:
+            raise ValueError("at least one of R, T, r, t")
         if real == torch.float64:
             dt = tmm.TMM_F64
         elif real == torch.float32:
@@ -110,10 +112,13 @@ class RaggedPlan:
         else:
             raise TypeError("real tensors must be float64 or float32")
         p = tmm._ptr
-        return RaggedData(p(d), p(mat), p(ends), p(wl), p(sin_t), p(cos_t), p(nk), nk.shape[0], p(R), p(T)), dt
+        return RaggedData(p(d), p(mat), p(ends), p(wl), p(sin_t), p(cos_t), p(nk), nk.shape[0], p(R), p(T), p(r),
+                          p(t)), dt
 
-    def run(self, d, mat, ends, wl, sin_t, cos_t, nk, R=None, T=None, stream=None):
-        data, dt = self._pack(d, mat, ends, wl, sin_t, cos_t, nk, R, T)
+    def run(self, d, mat, ends, wl, sin_t, cos_t, nk, R=None, T=None, r=None, t=None, stream=None):
+        """Evaluate every stack into R, T (real) and / or r, t (complex), each
+        [output_size] in the plan's output layout."""
+        data, dt = self._pack(d, mat, ends, wl, sin_t, cos_t, nk, R, T, r, t)
         tmm._check(_lib().tmm_rt_ragged(self.h, ctypes.byref(data), dt, tmm._stream_handle(stream)))
 
     def shape(self, dtype="f64") -> dict:
@@ -130,10 +135,10 @@ class RaggedPlan:
         tmm._check(_lib().tmm_ragged_plan_set_shape(self.h, tmm.TMM_F64 if dtype == "f64" else tmm.TMM_F32,
                                                     sh.ctypes.data))
 
-    def capture(self, d, mat, ends, wl, sin_t, cos_t, nk, R=None, T=None, stream=None):
+    def capture(self, d, mat, ends, wl, sin_t, cos_t, nk, R=None, T=None, r=None, t=None, stream=None):
         """Capture a run into the plan's HIP graph (stream: a non-default torch stream)."""
-        data, dt = self._pack(d, mat, ends, wl, sin_t, cos_t, nk, R, T)
-        self._data = (d, mat, ends, wl, sin_t, cos_t, nk, R, T)  # keep the captured buffers alive
+        data, dt = self._pack(d, mat, ends, wl, sin_t, cos_t, nk, R, T, r, t)
+        self._data = (d, mat, ends, wl, sin_t, cos_t, nk, R, T, r, t)  # keep the captured buffers alive
         tmm._check(_lib().tmm_ragged_capture(self.h, ctypes.byref(data), dt, tmm._stream_handle(stream)))
 
     def replay(self, stream=None):

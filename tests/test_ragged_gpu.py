@@ -256,3 +256,115 @@ def test_one_row_table_and_empty_stacks(dtype):
     empty = workloads.ragged_batch(seed=75, B=20, L_range=(0, 0), wl_range=(1, 130), th_range=(1, 5))
     plan, _, R, T = run(empty, dtype)
     check_stacks(empty, plan, R, T, range(empty.B), dtype)
+
+
+# --- r and t (the amplitude kernels: one lane per point, their own shape) ---
+
+def run_amp(rw, dtype="f64", pol="both", outputs=("R", "T", "r", "t")):
+    from paper_2111_13667_amd import ragged
+    plan = ragged.RaggedPlan(rw.layer_off, rw.wl_off, rw.th_off, pol=pol)
+    dev = ragged.to_device(rw, dtype)
+    real = dev[3].dtype
+    cplx = torch.complex128 if real == torch.float64 else torch.complex64
+    out = {k: torch.full((plan.output_size,), float("nan"), dtype=real if k in ("R", "T") else cplx, device="cuda")
+           for k in outputs}
+    plan.run(*dev, **out)
+    torch.cuda.synchronize()
+    return plan, dev, out
+
+
+def check_amplitudes(rw, plan, out, stacks, dtype="f64", pol="both"):
+    # tmm_rt's bounds: R, T absolute; r, t relative to max(1, |ref|)
+    off = plan.output_offsets()
+    host = {k: v.cpu().numpy() for k, v in out.items()}
+    tol = 1e-12 if dtype == "f64" else 2e-5
+    for b in stacks:
+        w = rw.stack(b)
+        if dtype == "f32":
+            w = w.rounded_f32()
+        ref = oracle.rt(w.d, w.nk, w.wl, w.sin_t, w.cos_t, mat=w.mat, pol=pol, want_amplitudes=True)
+        for k, v in host.items():
+            want = ref[k][0]
+            got = v[off[b]:off[b + 1]].reshape(want.shape).astype(want.dtype)
+            err = np.abs(got - want)
+            bound = tol * (np.maximum(1.0, np.abs(want)) if k in ("r", "t") else 1.0)
+            assert (err <= bound).all(), (k, b, float(err.max()))
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_amplitudes_every_stack(dtype):
+    # R, T, r, t in one run: empty stacks, stacks of one and of two 64-layer
+    # chunks, absorbing and lossless rows; every stack against the oracle.
+    rw = workloads.ragged_batch(seed=80, B=31, L_range=(0, 100), wl_range=(1, 140), th_range=(1, 5))
+    plan, _, out = run_amp(rw, dtype)
+    check_amplitudes(rw, plan, out, range(rw.B), dtype)
+
+
+@pytest.mark.parametrize("pol", ["s", "p"])
+def test_amplitudes_single_polarisation(pol):
+    rw = workloads.ragged_batch(seed=81, B=13, L_range=(0, 40), wl_range=(10, 90), th_range=(1, 4))
+    plan, _, out = run_amp(rw, "f64", pol)
+    check_amplitudes(rw, plan, out, range(rw.B), "f64", pol)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_amplitudes_exact_phase_reduction_and_metals(dtype):
+    # Thicknesses and wavelengths scaled by 1e-6 (every unit reduces its phases
+    # exactly before the table lookup: t's phase sum must keep two turns), then
+    # metal-like rows at angles up to 89.9 deg; every stack against the oracle.
+    import dataclasses
+    rw = workloads.ragged_batch(seed=82, B=17, L_range=(0, 80), wl_range=(1, 100), th_range=(1, 5))
+    scaled = dataclasses.replace(rw, d=rw.d * 1e-6, wl=rw.wl * 1e-6)
+    plan, _, out = run_amp(scaled, dtype)
+    check_amplitudes(scaled, plan, out, range(scaled.B), dtype)
+    rng = np.random.default_rng(83)
+    nk = rw.nk.copy()
+    nk[1] = 0.2 + 3.5j
+    nk[3] = 1.5 + 5.8j
+    d = rw.d.copy()
+    metal = np.isin(rw.mat, [1, 3])
+    d[metal] = rng.uniform(5.0, 40.0, int(metal.sum()))
+    theta = np.concatenate([np.deg2rad(np.linspace(0.0, 89.9, n)) for n in np.diff(rw.th_off)])
+    s, c = workloads.angles(theta)
+    metals = dataclasses.replace(rw, nk=nk, d=d, theta=theta, sin_t=s, cos_t=c)
+    plan, _, out = run_amp(metals, dtype)
+    check_amplitudes(metals, plan, out, range(metals.B), dtype)
+
+
+def test_amplitude_outputs_alone_and_rt_runs_unchanged():
+    # r alone, then t alone (the other outputs untouched); an R, T run of the
+    # same plan afterwards keeps its own tuned shape and its bits.
+    rw = workloads.ragged_batch(seed=84, B=19, L_range=(1, 70), wl_range=(20, 150), th_range=(1, 4))
+    plan, dev, R0, T0 = run(rw)
+    shape0 = plan.shape("f64")
+    for k in ("r", "t"):
+        x = torch.full((plan.output_size,), complex(7.0, 7.0), dtype=torch.complex128, device="cuda")
+        plan.run(*dev, **{k: x})
+        torch.cuda.synchronize()
+        check_amplitudes(rw, plan, {k: x}, range(rw.B))
+    R1, T1 = torch.empty_like(R0), torch.empty_like(T0)
+    plan.run(*dev, R=R1, T=T1)
+    torch.cuda.synchronize()
+    assert plan.shape("f64") == shape0
+    assert torch.equal(R0, R1) and torch.equal(T0, T1)
+
+
+def test_amplitude_graph_replay_matches_eager():
+    rw = workloads.ragged_batch(seed=85, B=60, L_range=(2, 70), wl_range=(32, 200), th_range=(1, 6))
+    plan, dev, out0 = run_amp(rw)
+    out = {k: torch.empty_like(v) for k, v in out0.items()}
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        plan.capture(*dev, stream=s, **out)
+    s.synchronize()
+    for rep in range(3):
+        for v in out.values():
+            v.fill_(-1.0)
+        torch.cuda.synchronize()
+        plan.replay(stream=s)
+        s.synchronize()
+        for k in out:
+            assert torch.equal(out[k], out0[k]), (k, rep)
+        x = torch.randn(1000, device="cuda").sum()  # eager work between replays
+        torch.cuda.synchronize()
+    check_amplitudes(rw, plan, out, [0, rw.B // 2, rw.B - 1])
