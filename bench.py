@@ -160,7 +160,7 @@ def time_grad(steps=10, L=60, n_pool=2):
             "workspace_MB": round(ws.numel() / 1e6, 1)}
 
 
-def time_ragged(dtype="f64", steps=10):
+def time_ragged(dtype="f64", steps=10, amplitudes=False):
     """Ragged batch: 8192 stacks, 2-100 layers, 256-2048 wl, 1-64 angles, s+p, R and T,
     one persistent launch (autotuned on the first run) and its HIP-graph replay."""
     import torch
@@ -169,23 +169,29 @@ def time_ragged(dtype="f64", steps=10):
     plan = ragged.RaggedPlan(rw.layer_off, rw.wl_off, rw.th_off)
     dev = ragged.to_device(rw, dtype)
     real = dev[3].dtype
-    R = torch.empty(plan.output_size, dtype=real, device="cuda")
-    T = torch.empty(plan.output_size, dtype=real, device="cuda")
+    out = {"R": torch.empty(plan.output_size, dtype=real, device="cuda"),
+           "T": torch.empty(plan.output_size, dtype=real, device="cuda")}
+    if amplitudes:
+        cplx = torch.complex128 if dtype == "f64" else torch.complex64
+        out["r"] = torch.empty(plan.output_size, dtype=cplx, device="cuda")
+        out["t"] = torch.empty(plan.output_size, dtype=cplx, device="cuda")
     t0 = time.perf_counter()
-    plan.run(*dev, R=R, T=T)  # tunes
+    plan.run(*dev, **out)  # tunes
     torch.cuda.synchronize()
     tune_s = time.perf_counter() - t0
-    shape = plan.shape(dtype)
-    rms, _ = launch_times(lambda: plan.run(*dev, R=R, T=T), steps, 1)
+    # the amplitude kernels tune their own shape (one lane per point), which the plan does not report
+    shape = None if amplitudes else plan.shape(dtype)
+    rms, _ = launch_times(lambda: plan.run(*dev, **out), steps, 1)
     ms = float(np.median(rms))
     st = torch.cuda.Stream()
     with torch.cuda.stream(st):
-        plan.capture(*dev, R=R, T=T, stream=st)
+        plan.capture(*dev, stream=st, **out)
     st.synchronize()
     gms = _event_time(lambda: plan.replay(stream=st), steps, 1, stream=st)
     layer_steps = int(((np.diff(rw.layer_off) + 1) * np.diff(rw.wl_off) * np.diff(rw.th_off)).sum()) * 2
     plan.close()
-    return {"workload": f"ragged_batch: 8192 stacks, 2-100 layers, 256-2048 wl, 1-64 angles, s+p, {dtype}",
+    outputs = "R,T,r,t" if amplitudes else "R,T"
+    return {"workload": f"ragged_batch: 8192 stacks, 2-100 layers, 256-2048 wl, 1-64 angles, s+p, {outputs}, {dtype}",
             "points": rw.n_points, "ms": round(ms, 3), "timing": summary(rms), "graph_ms": round(gms, 3),
             "autotuned_shape": shape, "first_run_with_tuning_s": round(tune_s, 3),
             "points_per_s": round(rw.n_points / (ms * 1e-3), 1),
@@ -401,7 +407,7 @@ def main():
     ap.add_argument("--cpu-stacks", type=int, default=128,
                     help="stacks of the CPU oracle sample (median of 3 runs after a warm-up)")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"))
-    ap.add_argument("--only", choices=["adjoint", "adjoint_long", "adjoint_rows", "ragged_f64", "ragged_f32", "ragged_layers_f64", "ragged_layers_f32",
+    ap.add_argument("--only", choices=["adjoint", "adjoint_long", "adjoint_rows", "ragged_f64", "ragged_f32", "ragged_rt_f64", "ragged_rt_f32", "ragged_layers_f64", "ragged_layers_f32",
                                        "surrogate", "surrogate_dataset", "materials"],
                     default=None, help="run only this extra measurement and print its record (for profiling)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -435,6 +441,8 @@ def main():
             rec = time_ragged_layers(args.only.split("_")[2], max(1, args.steps))
         elif args.only == "materials":
             rec = {"7": material_variant(7, max(1, args.steps)), "12": material_variant(12, max(1, args.steps))}
+        elif args.only.startswith("ragged_rt_"):
+            rec = time_ragged(args.only.split("_")[2], max(1, args.steps), amplitudes=True)
         else:
             rec = time_ragged(args.only.split("_")[1], max(1, args.steps))
         print(json.dumps({"only": args.only, **rec}), flush=True)
@@ -509,6 +517,7 @@ def main():
         extra["adjoint_f64_7_rows"] = time_grad(n_pool=5)
         extra["ragged_f64"] = time_ragged("f64")
         extra["ragged_f32"] = time_ragged("f32")
+        extra["ragged_f64_with_r_t"] = time_ragged("f64", amplitudes=True)
         extra["material_pool_7"] = material_variant(7)
         extra["material_pool_12"] = material_variant(12)
         extra["surrogate"] = time_surrogate()

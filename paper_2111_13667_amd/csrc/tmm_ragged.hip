@@ -57,8 +57,9 @@ template <typename R, bool AMP = false> struct Occupancy;
 template <> struct Occupancy<double, false> { static constexpr int kWavesPerCU = 12; };
 template <> struct Occupancy<float, false> { static constexpr int kWavesPerCU = 16; };
 // r and t wanted: the running products of q and eta are complex and the phase
-// sum rides along
-template <> struct Occupancy<double, true> { static constexpr int kWavesPerCU = 8; };
+// sum rides along (FP64: two values spill at 168 registers, still 7 % faster
+// than 8 waves without spills)
+template <> struct Occupancy<double, true> { static constexpr int kWavesPerCU = 12; };
 template <> struct Occupancy<float, true> { static constexpr int kWavesPerCU = 16; };
 constexpr int kMaxWavesPerCU = 16;
 constexpr int kMaxMat = 8;
