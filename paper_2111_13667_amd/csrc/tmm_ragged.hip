@@ -27,6 +27,11 @@
 // the point.  Twice the arithmetic per layer, a fraction of the latency: for
 // batches with few points per stack.
 //
+// Amplitudes r, t (Eq. (7)): separate instantiations (AMP) of the one-lane-
+// per-point kernel keep the complex running products of q and eta and the
+// phase sum (modulo 1024 in units of 1/256 half-turn, two turns: half of it is
+// the phase of t), and the shared extraction returns r and t with R and T.
+//
 // The plan keeps one 64-byte record per stack on the device (its offsets,
 // sizes and unit range, built from the offsets it was created with), so the
 // kernel never reads a caller's offset array and a wave reads a stack's
