@@ -179,16 +179,15 @@ tmm_status tmm_rt_grad(const tmm_rt_args *a, const void *dl_dR, const void *dl_d
                        void *stream);
 
 /*
- * tmm_rt at an explicit list of points: R and T (for the polarisations of
+ * tmm_rt at an explicit list of points: R, T, r, t (for the polarisations of
  * a->pol_mask) of the listed (stack, angle, wavelength) points of the batch a
  * describes -- the same quantities as tmm_rt (Eq. (1)-(7)), for callers that
  * need only scattered points, such as a surrogate model's fallback, which
  * recomputes exactly the outputs it does not trust (paper: App. A.2, datasets
  * of reflectance spectra for machine learning).
- *  a        as for tmm_rt; a->R and a->T (either may be NULL, not both) are laid
- *           out as tmm_rt's outputs, [B][P][n_theta][n_wl], and only the
- *           elements of the listed points are written; r and t must be NULL
- *           (TMM_ERR_UNSUPPORTED otherwise).
+ *  a        as for tmm_rt; a->R, a->T, a->r, a->t (any of them NULL, not all
+ *           four) are laid out as tmm_rt's outputs, [B][P][n_theta][n_wl], and
+ *           only the elements of the listed points are written.
  *  points   [n_points] int64 device array of flat indices
  *           (b * n_theta + k) * n_wl + i.  An index outside [0, B*n_theta*n_wl)
  *           is skipped (nothing written); a repeated index is evaluated twice.

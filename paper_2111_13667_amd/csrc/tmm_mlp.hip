@@ -852,6 +852,7 @@ tmm_status tmm_surrogate_predict_fallback(tmm_surrogate* h, const float* x, int3
             p.cos_t = static_cast<const float*>(tmpl->cos_theta);
             p.R_out = oc;
             p.T_out = nullptr;
+            p.r_out = p.t_out = nullptr;
             p.pts64 = nullptr;
             p.pts32 = h->plist;
             p.n_pts = npt;

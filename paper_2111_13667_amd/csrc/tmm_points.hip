@@ -55,7 +55,7 @@ __device__ __forceinline__ int64_t point_index(const PtParams<R>& p, int64_t t) 
     return p.pts64 ? p.pts64[t] : (int64_t)p.pts32[t];
 }
 
-template <typename R, int POL, bool TABLE>
+template <typename R, int POL, bool TABLE, bool AMP>
 __global__ void __launch_bounds__(kPtBlock) points_kernel(PtParams<R> p) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int lane = threadIdx.x & (kWave - 1);
@@ -113,7 +113,7 @@ __global__ void __launch_bounds__(kPtBlock) points_kernel(PtParams<R> p) {
         const R* drow = p.d + (int64_t)b * L;
         const Layer<R> sub = medium(L + 1);
         Layer<R> nxt = sub;
-        Chain<R, POL, false> c;
+        Chain<R, POL, AMP> c;
         c.init();
         constexpr int RP = RenormPeriod<R>::value;
         int since = 0;
@@ -129,8 +129,10 @@ __global__ void __launch_bounds__(kPtBlock) points_kernel(PtParams<R> p) {
             }
         }
         c.renorm();
+        double ns_r = 0.0, ns_i = 0.0;  // the substrate's index (t of p)
+        if constexpr (AMP) load_n(p.nk, p.dispersive, p.n_wl, row_of(L + 1), i, ns_r, ns_i);
         PointOut out[2];
-        finish<R, POL, false>(c, amb, nxt, sub, 0.0, 0.0, L, out, phase);
+        finish<R, POL, AMP>(c, amb, nxt, sub, ns_r, ns_i, L, out, phase);
         if (in_range) {
             const bool valid = lam_ok && amb.ok && !bad;
             const double nan = __builtin_nan("");
@@ -138,12 +140,22 @@ __global__ void __launch_bounds__(kPtBlock) points_kernel(PtParams<R> p) {
                 const int64_t o = (((int64_t)b * P + q) * p.n_theta + k) * p.n_wl + i;
                 if (p.R_out) p.R_out[o] = (R)(valid ? out[q].R : nan);
                 if (p.T_out) p.T_out[o] = (R)(valid ? out[q].T : nan);
+                if constexpr (AMP) {
+                    if (p.r_out) {
+                        p.r_out[2 * o] = (R)(valid ? out[q].r.re : nan);
+                        p.r_out[2 * o + 1] = (R)(valid ? out[q].r.im : nan);
+                    }
+                    if (p.t_out) {
+                        p.t_out[2 * o] = (R)(valid ? out[q].t.re : nan);
+                        p.t_out[2 * o + 1] = (R)(valid ? out[q].t.im : nan);
+                    }
+                }
             }
         }
     }
 }
 
-template <typename R, int POL, bool TABLE>
+template <typename R, int POL, bool TABLE, bool AMP>
 static hipError_t launch_pol(const PtParams<R>& p, int64_t max_points, hipStream_t s) {
     const size_t lds = phase_tab_bytes<R>() + (TABLE ? (size_t)kPtWaves * lane_table_bytes(p.n_mat) : 0);
     int dev = 0, n_cu = 256;
@@ -156,20 +168,28 @@ static hipError_t launch_pol(const PtParams<R>& p, int64_t max_points, hipStream
     if (blocks > cap) blocks = cap;
     if (blocks < 1) blocks = 1;
     if (lds > 64 * 1024) {
-        (void)hipFuncSetAttribute((const void*)&points_kernel<R, POL, TABLE>,
+        (void)hipFuncSetAttribute((const void*)&points_kernel<R, POL, TABLE, AMP>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         (void)hipGetLastError();
     }
-    hipLaunchKernelGGL((points_kernel<R, POL, TABLE>), dim3((unsigned)blocks), dim3(kPtBlock), lds, s, p);
+    hipLaunchKernelGGL((points_kernel<R, POL, TABLE, AMP>), dim3((unsigned)blocks), dim3(kPtBlock), lds, s, p);
     return hipGetLastError();
+}
+
+template <typename R, bool AMP>
+static hipError_t launch_amp(const PtParams<R>& p, unsigned pol_mask, int64_t max_points, hipStream_t s) {
+    const bool table = p.mat != nullptr && p.n_mat <= kPtMaxMat;
+    if (pol_mask == 1u)
+        return table ? launch_pol<R, 1, true, AMP>(p, max_points, s) : launch_pol<R, 1, false, AMP>(p, max_points, s);
+    if (pol_mask == 2u)
+        return table ? launch_pol<R, 2, true, AMP>(p, max_points, s) : launch_pol<R, 2, false, AMP>(p, max_points, s);
+    return table ? launch_pol<R, 3, true, AMP>(p, max_points, s) : launch_pol<R, 3, false, AMP>(p, max_points, s);
 }
 
 template <typename R>
 hipError_t launch_points(const PtParams<R>& p, unsigned pol_mask, int64_t max_points, hipStream_t s) {
-    const bool table = p.mat != nullptr && p.n_mat <= kPtMaxMat;
-    if (pol_mask == 1u) return table ? launch_pol<R, 1, true>(p, max_points, s) : launch_pol<R, 1, false>(p, max_points, s);
-    if (pol_mask == 2u) return table ? launch_pol<R, 2, true>(p, max_points, s) : launch_pol<R, 2, false>(p, max_points, s);
-    return table ? launch_pol<R, 3, true>(p, max_points, s) : launch_pol<R, 3, false>(p, max_points, s);
+    return (p.r_out || p.t_out) ? launch_amp<R, true>(p, pol_mask, max_points, s)
+                                : launch_amp<R, false>(p, pol_mask, max_points, s);
 }
 
 template hipError_t launch_points<double>(const PtParams<double>&, unsigned, int64_t, hipStream_t);
@@ -192,6 +212,8 @@ static tmm_status run(const tmm_rt_args* a, const int64_t* points, int64_t n_poi
     p.cos_t = static_cast<const R*>(a->cos_theta);
     p.R_out = static_cast<R*>(a->R);
     p.T_out = static_cast<R*>(a->T);
+    p.r_out = static_cast<R*>(a->r);
+    p.t_out = static_cast<R*>(a->t);
     p.pts64 = points;
     p.pts32 = nullptr;
     p.n_pts = n_points;
@@ -214,8 +236,7 @@ tmm_status tmm_rt_points(const tmm_rt_args* a, const int64_t* points, int64_t n_
     if (dtype != TMM_F64 && dtype != TMM_F32)
         return fail(TMM_ERR_INVALID_ARG, "tmm_rt_points: unknown dtype %d", (int)dtype);
     if (n_points < 0) return fail(TMM_ERR_INVALID_ARG, "tmm_rt_points: negative point count");
-    if (a->r || a->t) return fail(TMM_ERR_UNSUPPORTED, "tmm_rt_points: r and t are not produced here");
-    if (!a->R && !a->T) return fail(TMM_ERR_INVALID_ARG, "tmm_rt_points: no output requested");
+    if (!a->R && !a->T && !a->r && !a->t) return fail(TMM_ERR_INVALID_ARG, "tmm_rt_points: no output requested");
     if (n_points > 0 && !points) return fail(TMM_ERR_INVALID_ARG, "tmm_rt_points: points is NULL");
     if (n_points == 0 || a->B == 0 || a->n_wl == 0 || a->n_theta == 0) return tmm::ok();
     hipStream_t s = static_cast<hipStream_t>(stream);

@@ -26,6 +26,8 @@ struct PtParams {
     const uint32_t* pts32;  // the same in 32 bits (exactly one of the two is set)
     int64_t n_pts;          // number of points, unless
     const int* n_dev;       // a device count is given (read by the kernel)
+    R* r_out = nullptr;     // complex interleaved, the layout of R_out, or null;
+    R* t_out = nullptr;     // either set: the amplitude kernels
 };
 
 // Launch on the stream; max_points bounds the count (sizes the grid).

@@ -147,10 +147,11 @@ def tmm_rt(d, nk, wl, sin_theta, cos_theta, *, mat=None, n_mat=None, dispersive=
 
 
 def tmm_rt_points(d, nk, wl, sin_theta, cos_theta, points, *, mat=None, n_mat=None, dispersive=None,
-                  pol_mask: int = 3, R=None, T=None, flags: int = 0, stream=None) -> None:
-    """Launch tmm_rt_points: R and T at the listed points (int64 device tensor of
-    flat indices (b * n_theta + k) * n_wl + i), written into R, T laid out as
-    tmm_rt's outputs [B, P, n_theta, n_wl]; other elements are left as they are."""
+                  pol_mask: int = 3, R=None, T=None, r=None, t=None, flags: int = 0, stream=None) -> None:
+    """Launch tmm_rt_points: R, T (real) and / or r, t (complex) at the listed
+    points (int64 device tensor of flat indices (b * n_theta + k) * n_wl + i),
+    written into outputs laid out as tmm_rt's [B, P, n_theta, n_wl]; other
+    elements are left as they are."""
     import torch
     real = d.dtype
     if real == torch.float64:
@@ -164,9 +165,12 @@ def tmm_rt_points(d, nk, wl, sin_theta, cos_theta, points, *, mat=None, n_mat=No
             raise TypeError(f"{name} must be {real}")
     if nk.dtype != cdt:
         raise TypeError(f"nk must be {cdt}")
+    for name, x in (("r", r), ("t", t)):
+        if x is not None and x.dtype != cdt:
+            raise TypeError(f"{name} must be {cdt}")
     if points.dtype != torch.int64 or points.dim() != 1:
         raise TypeError("points must be a 1-D int64 tensor")
-    for x in (d, nk, wl, sin_theta, cos_theta, mat, R, T, points):
+    for x in (d, nk, wl, sin_theta, cos_theta, mat, R, T, r, t, points):
         if x is not None and (not x.is_cuda or not x.is_contiguous()):
             raise ValueError("every tensor must be a contiguous device tensor")
     if mat is not None and mat.dtype != torch.int32:
@@ -175,10 +179,10 @@ def tmm_rt_points(d, nk, wl, sin_theta, cos_theta, points, *, mat=None, n_mat=No
     n_mat = _check_shapes(d, nk, wl, sin_theta, cos_theta, mat, n_mat, dispersive)
     P = 2 if pol_mask == 3 else 1
     shape = (B, P, sin_theta.numel(), wl.numel())
-    for name, x in (("R", R), ("T", T)):
+    for name, x in (("R", R), ("T", T), ("r", r), ("t", t)):
         if x is not None and tuple(x.shape) != shape:
             raise ValueError(f"{name} must have shape {shape}")
-    a = _rt_args(d, nk, wl, sin_theta, cos_theta, mat, n_mat, dispersive, pol_mask, R, T, flags=flags)
+    a = _rt_args(d, nk, wl, sin_theta, cos_theta, mat, n_mat, dispersive, pol_mask, R, T, r, t, flags=flags)
     _check(library().tmm_rt_points(ctypes.byref(a), _ptr(points), points.numel(), dt, _stream_handle(stream)))
 
 

@@ -140,7 +140,7 @@ def test_edge_cases():
     untouched[0, :, 0, 7] = False
     untouched[2, :, 0, 5] = False
     assert (R[untouched] == SENTINEL).all()
-    # no points: a no-op; r and t are not produced here
+    # no points: a no-op; no output at all: an error
     R2, _ = run_points(w, np.zeros(0, np.int64))
     assert (R2 == SENTINEL).all()
     d = dev(w.d, torch.float64)
@@ -148,3 +148,75 @@ def test_edge_cases():
         tmm.tmm_rt_points(d, dev(w.nk, torch.complex128), dev(w.wl, torch.float64), dev(w.sin_t, torch.float64),
                           dev(w.cos_t, torch.float64), dev(flat[3:4], torch.int64), mat=dev(w.mat, torch.int32))
     assert e.value.status == tmm.TMM_ERR_INVALID_ARG   # no output requested
+
+
+def run_point_amplitudes(w, flat, dtype="f64", pol="both"):
+    from paper_2111_13667_amd import tmm
+    real = torch.float64 if dtype == "f64" else torch.float32
+    cplx = torch.complex128 if dtype == "f64" else torch.complex64
+    P = 2 if pol == "both" else 1
+    shape = (w.B, P, w.theta.size, w.wl.size)
+    out = {k: torch.full(shape, SENTINEL, dtype=real if k in ("R", "T") else cplx, device="cuda")
+           for k in ("R", "T", "r", "t")}
+    tmm.tmm_rt_points(dev(w.d, real), dev(w.nk, cplx), dev(w.wl, real), dev(w.sin_t, real), dev(w.cos_t, real),
+                      dev(flat, torch.int64), mat=None if w.mat is None else dev(w.mat, torch.int32),
+                      pol_mask=tmm.POL[pol], **out)
+    torch.cuda.synchronize()
+    return {k: v.cpu().numpy() for k, v in out.items()}
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("kind", ["table", "per_layer", "tir"])
+def test_point_amplitudes(dtype, kind):
+    # R, T, r, t at listed points against the oracle's whole grid: material ids
+    # with the LDS media table (lossy rows, grazing angles), per-layer
+    # dispersive rows (media per step), and the appendix example's evanescent
+    # layers and total internal reflection; r, t within tol * max(1, |ref|).
+    # Unlisted elements keep their sentinel.
+    if kind == "table":
+        w = workloads.large_batch(B=24, L=40, n_wl=70, n_theta=9)
+    elif kind == "per_layer":
+        w = workloads.random_stacks(32, B=10, L=23, n_wl=60, n_theta=5, dispersive=True)
+    else:
+        w = workloads.appendix_example(B=2, n_wl=41, n_theta=31)
+    rng = np.random.default_rng(90)
+    total = w.B * w.theta.size * w.wl.size
+    flat = rng.choice(total, size=total // 3, replace=False)
+    got = run_point_amplitudes(w, flat, dtype)
+    wr = w.rounded_f32() if dtype == "f32" else w
+    ref = oracle.rt(wr.d, wr.nk, wr.wl, wr.sin_t, wr.cos_t, mat=wr.mat, want_amplitudes=True)
+    i, k, b = flat % w.wl.size, (flat // w.wl.size) % w.theta.size, flat // (w.wl.size * w.theta.size)
+    tol = 1e-12 if dtype == "f64" else 2e-5
+    if kind == "tir" and dtype == "f64":
+        tol = 2e-12  # the oracle's own product loses about 1e-12 at some TIR points (test above)
+    listed = np.zeros(got["R"].shape, bool)
+    listed[b, :, k, i] = True
+    for key in ("R", "T", "r", "t"):
+        g = got[key][b, :, k, i]
+        r = ref[key][b, :, k, i]
+        bound = tol * (np.maximum(1.0, np.abs(r)) if key in ("r", "t") else 1.0)
+        err = np.abs(g.astype(r.dtype) - r)
+        assert (err <= bound).all(), (key, float(err.max()))
+        assert (got[key][~listed] == SENTINEL).all(), key
+
+
+@pytest.mark.parametrize("pol", ["s", "p"])
+def test_point_amplitudes_single_polarisation_and_alone(pol):
+    # one polarisation; then t alone (nothing else written)
+    from paper_2111_13667_amd import tmm
+    w = workloads.large_batch(B=9, L=17, n_wl=50, n_theta=7)
+    flat = np.random.default_rng(91).choice(w.B * w.theta.size * w.wl.size, 1500, replace=False)
+    got = run_point_amplitudes(w, flat, "f64", pol)
+    q = 0 if pol == "s" else 1
+    ref = oracle.rt(w.d, w.nk, w.wl, w.sin_t, w.cos_t, mat=w.mat, want_amplitudes=True)
+    i, k, b = flat % w.wl.size, (flat // w.wl.size) % w.theta.size, flat // (w.wl.size * w.theta.size)
+    for key in ("r", "t"):
+        r = ref[key][b, q, k, i]
+        assert (np.abs(got[key][b, 0, k, i] - r) <= 1e-12 * np.maximum(1.0, np.abs(r))).all(), key
+    t = torch.full((w.B, 2, w.theta.size, w.wl.size), SENTINEL, dtype=torch.complex128, device="cuda")
+    tmm.tmm_rt_points(dev(w.d, torch.float64), dev(w.nk, torch.complex128), dev(w.wl, torch.float64),
+                      dev(w.sin_t, torch.float64), dev(w.cos_t, torch.float64), dev(flat, torch.int64),
+                      mat=dev(w.mat, torch.int32), t=t)
+    th = t.cpu().numpy()
+    r = ref["t"][b, :, k, i]
+    assert (np.abs(th[b, :, k, i] - r) <= 1e-12 * np.maximum(1.0, np.abs(r))).all()
