@@ -123,3 +123,39 @@ def test_surrogate_config_rejected_on_host():
         h = ctypes.c_void_p()
         assert lib.tmm_surrogate_create(ctypes.byref(cfg), ctypes.byref(h)) == tmm.TMM_ERR_INVALID_ARG, bad
         assert not h.value
+
+
+def test_binding_structs_match_the_c_headers(tmp_path):
+    # Every struct the ctypes bindings mirror (tmm_rt_args, tmm_ragged_data,
+    # tmm_surrogate_config): field names, offsets and total size as the C
+    # compiler lays them out from include/*.h, so that a field added to a header
+    # cannot go unnoticed by its binding.
+    import ctypes
+    import shutil
+    import subprocess
+    from paper_2111_13667_amd import ragged, surrogate, tmm
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("gcc not available")
+    structs = {"tmm_rt_args": tmm.TmmRtArgs, "tmm_ragged_data": ragged.RaggedData,
+               "tmm_surrogate_config": surrogate.SurrogateConfig}
+    lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "tmm_rt.h"', '#include "tmm_ragged.h"',
+             '#include "tmm_surrogate.h"', "int main(void) {"]
+    for cname, cls in structs.items():
+        lines.append(f'    printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in cls._fields_:
+            lines.append(f'    printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["    return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    include = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    subprocess.run([gcc, "-std=c11", "-I", include, str(src), "-o", str(exe)], check=True)
+    got = {}
+    for line in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.splitlines():
+        cname, key, value = line.split()
+        got[(cname, key)] = int(value)
+    for cname, cls in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(cls), cname
+        for fname, _ in cls._fields_:
+            assert got[(cname, fname)] == getattr(cls, fname).offset, (cname, fname)
