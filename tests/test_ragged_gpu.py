@@ -368,3 +368,20 @@ def test_amplitude_graph_replay_matches_eager():
         x = torch.randn(1000, device="cuda").sum()  # eager work between replays
         torch.cuda.synchronize()
     check_amplitudes(rw, plan, out, [0, rw.B // 2, rw.B - 1])
+
+
+def test_fixed_rt_shape_leaves_amplitude_runs_their_own():
+    # A plan whose R, T shape is fixed at four lanes per point: an amplitude run
+    # of the same plan still takes the one-lane-per-point kernels (its own
+    # tuned shape), and the R, T shape stays as set.
+    from paper_2111_13667_amd import ragged
+    rw = workloads.ragged_batch(seed=86, B=14, L_range=(0, 50), wl_range=(8, 90), th_range=(1, 4))
+    plan = ragged.RaggedPlan(rw.layer_off, rw.wl_off, rw.th_off)
+    plan.set_shape("f64", workgroups_per_cu=2, grain=2, waves_per_workgroup=6, lanes_per_point=4)
+    dev = ragged.to_device(rw, "f64")
+    out = {k: torch.empty(plan.output_size, dtype=torch.float64 if k in ("R", "T") else torch.complex128,
+                          device="cuda") for k in ("R", "r", "t")}
+    plan.run(*dev, **out)
+    torch.cuda.synchronize()
+    check_amplitudes(rw, plan, out, range(rw.B))
+    assert plan.shape("f64")["lanes_per_point"] == 4
